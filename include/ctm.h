@@ -1,0 +1,197 @@
+/*
+ * ctm.h -- C interface of the MI355X (gfx950) corner-transfer-matrix library.
+ *
+ * The library approximates the environment of an infinite PEPS on the square
+ * lattice of block sites obtained from the ruby lattice (Sec. II B and the
+ * caption of Fig. 2: a 2x2 cell of tensors A, B in a checkerboard, physical
+ * dimension d = 2^3 = 8), by the directional corner-transfer-matrix method
+ * named in Sec. II C: four chi x chi corners C1..C4 and chi x chi x D^2 edges
+ * around the cell (caption of Fig. 3(b)).  From the converged environment it
+ * returns the norm per site, nearest-neighbour reduced density matrices and
+ * expectation values (Sec. II C, Sec. VI) and the fidelity per lattice site
+ * (Sec. III, Eq. "fidelity").
+ *
+ * Conventions (shared by every entry point):
+ *   - PEPS tensors are float64, C order, legs [s, u, l, d, r] (physical index
+ *     first; x points right, y points down).  Site (x, y) of an Lx x Ly cell
+ *     carries tensor pattern[y * Lx + x].
+ *   - One "column step" is the unit of work called a move below: in a move in
+ *     direction L/U/R/D the environment absorbs one column (or row) of the cell
+ *     and is truncated back to chi.  A sweep is L, R, U, D moves, i.e. 2*Lx +
+ *     2*Ly column steps.
+ *   - Singular-value decompositions, the truncated pseudo-inverse square roots
+ *     of singular values and all normalisations are float64 on the GPU in every
+ *     precision mode; `prec` selects only the arithmetic of the bulk tensor
+ *     contractions (enlarged corners, half-system products, absorption).
+ *
+ * Ownership and errors:
+ *   - The caller owns the tensor buffers (device memory); they are copied at
+ *     ctm_init and never kept.  The caller owns the device workspace, which must
+ *     stay alive until ctm_destroy.  Host outputs go to caller buffers.
+ *   - All device work is enqueued on the caller's HIP stream.  Calls that
+ *     return host data synchronise that stream.
+ *   - No call throws.  Each returns a ctm_status; ctm_last_error() gives a
+ *     thread-local message for the last non-OK status.  A context is not
+ *     thread-safe; distinct contexts are independent.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctm_ctx_s* ctm_ctx;
+
+typedef enum {
+  CTM_OK = 0,
+  CTM_E_INVALID = 1,   /* bad argument, shape or size                      */
+  CTM_E_NONFINITE = 2, /* NaN/Inf in an input or in the environment         */
+  CTM_E_NOMEM = 3,     /* workspace too small                               */
+  CTM_E_NOCONV = 4,    /* not converged within max_sweeps (state is valid)  */
+  CTM_E_SOLVER = 5,    /* projector solver failed (e.g. zero half-system)   */
+  CTM_E_HIP = 6,       /* a HIP runtime call failed                         */
+  CTM_E_STATE = 7      /* call not valid in the context's current state     */
+} ctm_status;
+
+typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16 = 2 } ctm_prec;
+
+typedef enum { CTM_LEFT = 0, CTM_UP = 1, CTM_RIGHT = 2, CTM_DOWN = 3, CTM_SWEEP = 4 } ctm_dir;
+
+typedef enum { CTM_INIT_TRIVIAL = 0, CTM_INIT_DIAG = 1 } ctm_init_kind;
+
+typedef struct {
+  int32_t n_inst;          /* independent instances (1 = plain CTM)                */
+  int32_t Lx, Ly;          /* unit cell, 1..4 each                                 */
+  int32_t n_tensors;       /* distinct tensors per instance                        */
+  const int32_t* pattern;  /* host [Lx*Ly]: tensor id of site (x, y) at y*Lx+x     */
+  const int32_t* d;        /* host [n_inst]: physical dimension                    */
+  const int32_t* D;        /* host [n_inst]: bond dimension (all legs)             */
+  const int32_t* chi;      /* host [n_inst]: environment dimension                 */
+  int32_t prec;            /* ctm_prec of the bulk contractions                    */
+  int32_t svd_oversample;  /* extra subspace columns p (default 16)                */
+  int32_t svd_max_iters;   /* subspace iterations per projector (default 30)       */
+  double svd_resid_tol;    /* stop when every kept residual < tol*sigma_1; 0 = run
+                              exactly svd_max_iters iterations (default 1e-13)     */
+  double svd_cutoff;       /* keep sigma_i > cutoff*sigma_1 (default 1e-12)         */
+  uint64_t seed;           /* seeds the random start of the subspace iteration     */
+} ctm_config;
+
+/* Fills *cfg with the defaults above for one instance (caller sets the rest). */
+void ctm_config_default(ctm_config* cfg);
+
+/* Bytes of device workspace that ctm_init / ctm_fidelity need for `cfg`. */
+ctm_status ctm_workspace_size(const ctm_config* cfg, size_t* bytes);
+
+/*
+ * Creates a context: copies the tensors, forms the double-layer tensors
+ * a = sum_s A_s (x) conj(B_s) (caption of Fig. 3(a); with B = NULL the bra
+ * layer is A itself; with B given it is the mixed network of the fidelity,
+ * caption of Fig. 4(a)) and initialises the environment.
+ *   A_dev, B_dev: host arrays of n_inst*n_tensors device pointers, instance-
+ *                 major, each tensor float64 [d][D][D][D][D].  B_dev may be NULL.
+ *   ws_dev, ws_bytes: caller-owned device workspace of at least
+ *                 ctm_workspace_size() bytes, 256-byte aligned.
+ *   stream:       hipStream_t on which all work is enqueued (NULL = default).
+ *   init:         CTM_INIT_TRIVIAL: C = e0 e0^T, T = delta_a0 delta_b0
+ *                 delta_uu' (open boundary, boundary ket/bra bonds traced),
+ *                 zero-padded to chi.  CTM_INIT_DIAG: C_i = diag(s_i) from
+ *                 spectrum_host, T = delta_ab delta_uu', Frobenius-normalised.
+ *   spectrum_host: for CTM_INIT_DIAG, float64 [n_inst][Lx*Ly][4][chi_max] with
+ *                 chi_max the largest chi; else NULL.
+ * Returns CTM_E_NONFINITE if a tensor holds NaN/Inf (nothing is allocated).
+ */
+ctm_status ctm_init(const ctm_config* cfg, const double* const* A_dev,
+                    const double* const* B_dev, void* ws_dev, size_t ws_bytes,
+                    void* stream, int32_t init, const double* spectrum_host,
+                    ctm_ctx* out);
+
+/*
+ * `count` column steps in direction `dir` (Sec. II C; see the conventions
+ * above), continuing from where the previous call in that direction stopped;
+ * with dir = CTM_SWEEP, `count` full sweeps.  Each column step computes, for
+ * every row of the column, the four enlarged corners of the plaquette, the
+ * truncating projectors from the float64 truncated SVD of the half-system
+ * product, then the renormalised corners and edges, each divided by its
+ * Frobenius norm.  Asynchronous.
+ */
+ctm_status ctm_move(ctm_ctx ctx, int32_t dir, int32_t count);
+
+/*
+ * Sweeps until the largest l1 change of the normalised corner spectra
+ * sigma(C)/sum sigma(C), over all corners and positions of an instance, is
+ * below tol, or max_sweeps sweeps were done.  The change is read back to the
+ * host every check_every sweeps.  sweeps_out, delta_out: host [n_inst] or NULL.
+ * Returns CTM_E_NOCONV (state valid) if some instance did not converge.
+ */
+ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,
+                        int32_t check_every, int32_t* sweeps_out, double* delta_out);
+
+/* Normalised corner spectra of instance `inst`, float64
+ * [Lx*Ly][4][chi] (position y*Lx+x, corner C1..C4), zero-padded.  Syncs. */
+ctm_status ctm_spectra(ctm_ctx ctx, int32_t inst, double* out_host);
+
+/* Norm per site kappa = (Z11 Z00 / (Z10 Z01))^(1/(Lx Ly)) of instance `inst`:
+ * the cell in its environment, the corners alone, and the two strip pairs
+ * joined directly (Sec. III, Eq. "fidelity" and the paragraph after it).  Syncs. */
+ctm_status ctm_norm(ctm_ctx ctx, int32_t inst, double* kappa_out);
+
+/*
+ * Two-site reduced density matrix of the bond from site (x, y) to its right
+ * (vertical = 0) or lower (vertical = 1) neighbour, divided by its trace,
+ * not symmetrised.  rho_host: float64 [(s1,s2)][(s1',s2')] (d^2 x d^2, row =
+ * ket indices, column = bra indices, first site = left/upper).  herm_defect
+ * (may be NULL): ||rho - rho^T||_F / ||rho||_F.  Syncs.
+ */
+ctm_status ctm_rdm(ctm_ctx ctx, int32_t inst, int32_t x, int32_t y,
+                   int32_t vertical, double* rho_host, double* herm_defect);
+
+/*
+ * Expectation value tr(rho h) of a two-site operator on the same bond, with
+ * h_host float64 [(s1,s2)][(s1',s2')] (Sec. II B: H is a sum of such
+ * nearest-neighbour terms).  Computed on the device.  Syncs.
+ */
+ctm_status ctm_expect(ctm_ctx ctx, int32_t inst, int32_t x, int32_t y,
+                      int32_t vertical, const double* h_host, double* value_out);
+
+/*
+ * Fidelity per lattice site between the states of A_dev and B_dev (Sec. III,
+ * Eq. "fidelity"): three CTM runs on the networks A(x)A*, B(x)B* and the mixed
+ * A(x)B*, each from the trivial start until converged; then
+ *   d = |kappa_AB| / sqrt(kappa_AA kappa_BB), all per site.
+ * cfg must describe both tensor sets (n_inst must be 1).  d_out, ln_d_out:
+ * host scalars.  sweeps_out (may be NULL): host [3] sweeps of the three runs.
+ */
+ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev,
+                        const double* const* B_dev, void* ws_dev, size_t ws_bytes,
+                        void* stream, double tol, int32_t max_sweeps,
+                        double* d_out, double* ln_d_out, int32_t* sweeps_out);
+
+/* Checkpoint: all corners and edges of instance `inst` as float64, in the
+ * order C1..C4 then T1..T4, each for positions y*Lx+x; `bytes` must equal
+ * ctm_env_bytes().  Import restores them exactly.  Both sync. */
+size_t ctm_env_bytes(ctm_ctx ctx, int32_t inst);
+ctm_status ctm_env_export(ctm_ctx ctx, int32_t inst, void* host_buf, size_t bytes);
+ctm_status ctm_env_import(ctm_ctx ctx, int32_t inst, const void* host_buf, size_t bytes);
+
+/* Kernel-time accounting of the last calls: seconds spent in enlarged-corner
+ * contractions, projector solver, absorption (HIP events on the context's
+ * stream; only filled when timing is enabled with ctm_set_timing). */
+ctm_status ctm_set_timing(ctm_ctx ctx, int32_t enable);
+ctm_status ctm_get_timing(ctm_ctx ctx, double* corner_s, double* solver_s,
+                          double* absorb_s, int64_t* corner_launches);
+
+/* Releases the context (not the workspace). */
+void ctm_destroy(ctm_ctx ctx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* ctm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_H */

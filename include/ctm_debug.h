@@ -1,0 +1,42 @@
+/*
+ * ctm_debug.h -- unit-test entry points of the gfx950 CTM library.
+ *
+ * These expose two internal building blocks so that their numerics can be
+ * checked in isolation against a CPU reference.  They are not needed to use
+ * the library.  All pointers are device pointers; all calls are enqueued on
+ * `stream` and synchronise it before returning.
+ */
+#ifndef CTM_DEBUG_H
+#define CTM_DEBUG_H
+
+#include <stdint.h>
+#include "ctm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * C = op(A) op(B) on the MFMA GEMM kernel.  A is M x K (K x M if transA),
+ * B is K x N (N x K if transB), C is M x N, all row-major and dense.
+ * ta: element type of A and B, tc: of C (0 = float64, 1 = float32,
+ * 2 = bfloat16); supported pairs: (0,0), (1,1), (1,0), (2,1), (2,0), (2,2), (1,2).
+ * Returns CTM_E_INVALID for other pairs or non-positive sizes.
+ */
+ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t K,
+                          const void* A, int32_t transA, const void* B, int32_t transB,
+                          void* C, void* stream);
+
+/*
+ * One-sided Jacobi SVD of the k x k float64 row-major matrix M (1 <= k <= 256):
+ * M W = U diag(S), singular values descending.  U, W: k x k row-major; S: k.
+ * work: 2 k^2 doubles.
+ */
+ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W,
+                         double* work, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_DEBUG_H */

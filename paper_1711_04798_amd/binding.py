@@ -1,0 +1,275 @@
+"""Thin ctypes binding of libctm.so (argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels; torch only
+supplies device memory (the workspace and the tensor copies) and the stream.
+The binding raises if the shared library is missing: there is no CPU path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctm.so")
+
+CTM_OK, CTM_E_INVALID, CTM_E_NONFINITE, CTM_E_NOMEM, CTM_E_NOCONV, CTM_E_SOLVER, CTM_E_HIP, CTM_E_STATE = range(8)
+STATUS_NAMES = ["OK", "INVALID", "NONFINITE", "NOMEM", "NOCONV", "SOLVER", "HIP", "STATE"]
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+DIRS = {"L": 0, "U": 1, "R": 2, "D": 3, "SWEEP": 4}
+INIT = {"trivial": 0, "diag": 1}
+
+EXPORTS = [
+    "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
+    "ctm_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
+    "ctm_env_export", "ctm_env_import", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
+    "ctm_last_error",
+]
+
+
+class CtmConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_inst", ctypes.c_int32), ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+        ("n_tensors", ctypes.c_int32),
+        ("pattern", ctypes.POINTER(ctypes.c_int32)), ("d", ctypes.POINTER(ctypes.c_int32)),
+        ("D", ctypes.POINTER(ctypes.c_int32)), ("chi", ctypes.POINTER(ctypes.c_int32)),
+        ("prec", ctypes.c_int32), ("svd_oversample", ctypes.c_int32),
+        ("svd_max_iters", ctypes.c_int32), ("svd_resid_tol", ctypes.c_double),
+        ("svd_cutoff", ctypes.c_double), ("seed", ctypes.c_uint64),
+    ]
+
+
+class CtmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ctm status %s: %s" % (STATUS_NAMES[status] if 0 <= status < 8 else status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libctm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libctm.so not built (run __graft_entry__.build()): %s" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, F64, SZ, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+    cfgp = P(CtmConfig)
+    dpp = P(ctypes.c_void_p)
+    lib.ctm_config_default.argtypes = [cfgp]
+    lib.ctm_config_default.restype = None
+    lib.ctm_workspace_size.argtypes = [cfgp, P(SZ)]
+    lib.ctm_init.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, I32, P(F64), P(VP)]
+    lib.ctm_move.argtypes = [VP, I32, I32]
+    lib.ctm_converge.argtypes = [VP, F64, I32, I32, P(I32), P(F64)]
+    lib.ctm_spectra.argtypes = [VP, I32, P(F64)]
+    lib.ctm_norm.argtypes = [VP, I32, P(F64)]
+    lib.ctm_rdm.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
+    lib.ctm_expect.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
+    lib.ctm_fidelity.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, F64, I32, P(F64), P(F64), P(I32)]
+    lib.ctm_env_bytes.argtypes = [VP, I32]
+    lib.ctm_env_bytes.restype = SZ
+    lib.ctm_env_export.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_env_import.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_set_timing.argtypes = [VP, I32]
+    lib.ctm_get_timing.argtypes = [VP, P(F64), P(F64), P(F64), P(ctypes.c_int64)]
+    lib.ctm_destroy.argtypes = [VP]
+    lib.ctm_destroy.restype = None
+    lib.ctm_last_error.argtypes = []
+    lib.ctm_last_error.restype = ctypes.c_char_p
+    for name in ("ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge", "ctm_spectra",
+                 "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_export",
+                 "ctm_env_import", "ctm_set_timing", "ctm_get_timing"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st, allow=()):
+    if st != CTM_OK and st not in allow:
+        raise CtmError(st, _lib.ctm_last_error().decode())
+    return st
+
+
+def _i32arr(v):
+    return (ctypes.c_int32 * len(v))(*[int(t) for t in v])
+
+
+def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=16,
+                max_iters=30, resid_tol=1e-13, cutoff=1e-12, seed=12345):
+    """ctm_config plus the ctypes arrays it points into (keep both alive)."""
+    lib = load()
+    cfg = CtmConfig()
+    lib.ctm_config_default(ctypes.byref(cfg))
+    d, D, chi = list(d), list(D), list(chi)
+    keep = [_i32arr(pattern), _i32arr(d), _i32arr(D), _i32arr(chi)]
+    cfg.n_inst = len(d)
+    cfg.Lx, cfg.Ly, cfg.n_tensors = Lx, Ly, n_tensors
+    cfg.pattern, cfg.d, cfg.D, cfg.chi = [ctypes.cast(k, ctypes.POINTER(ctypes.c_int32)) for k in keep]
+    cfg.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    cfg.svd_oversample = oversample
+    cfg.svd_max_iters = max_iters
+    cfg.svd_resid_tol = resid_tol
+    cfg.svd_cutoff = cutoff
+    cfg.seed = seed
+    return cfg, keep
+
+
+def workspace_size(cfg):
+    lib = load()
+    n = ctypes.c_size_t(0)
+    _check(lib.ctm_workspace_size(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def _dev_tensors(torch, arrays, device):
+    ts = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device) for a in arrays]
+    ptrs = (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+    return ts, ptrs
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class CTM:
+    """One CTM context: `kets` is a list (instances) of lists (tensors) of
+    numpy arrays [s, u, l, d, r]; `bras` the same or None."""
+
+    def __init__(self, kets, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", bras=None,
+                 init="trivial", spectrum=None, device="cuda:0", **solver):
+        import torch
+        self._torch = torch
+        lib = load()
+        if isinstance(kets[0], np.ndarray):
+            kets = [kets]
+            bras = [bras] if bras is not None else None
+        self.n_inst = len(kets)
+        nt = len(kets[0])
+        if pattern is None:
+            pattern = [0] * (Lx * Ly)
+        chis = chi if isinstance(chi, (list, tuple)) else [chi] * self.n_inst
+        d = [k[0].shape[0] for k in kets]
+        D = [k[0].shape[1] for k in kets]
+        self.Lx, self.Ly, self.d, self.D, self.chi = Lx, Ly, d, D, list(chis)
+        self.cfg, self._keep = make_config(Lx, Ly, pattern, nt, d, D, chis, prec, **solver)
+        self.device = torch.device(device)
+        nbytes = workspace_size(self.cfg)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        flat_k = [a for inst in kets for a in inst]
+        self._kt, kp = _dev_tensors(torch, flat_k, self.device)
+        bp = None
+        if bras is not None:
+            flat_b = [a for inst in bras for a in inst]
+            self._bt, bp = _dev_tensors(torch, flat_b, self.device)
+        sp = None
+        if spectrum is not None:
+            spectrum = np.ascontiguousarray(spectrum, dtype=np.float64)
+            sp = spectrum.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self._spec = spectrum
+        self.ctx = ctypes.c_void_p()
+        self.stream = _stream(torch, self.device)
+        _check(lib.ctm_init(ctypes.byref(self.cfg), ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p)),
+                            ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)) if bp is not None else None,
+                            ctypes.c_void_p(base + off), nbytes, self.stream, INIT[init], sp,
+                            ctypes.byref(self.ctx)))
+
+    def move(self, direction, count=1):
+        _check(load().ctm_move(self.ctx, DIRS[direction] if isinstance(direction, str) else direction, count))
+
+    def sweep(self, count=1):
+        self.move("SWEEP", count)
+
+    def converge(self, tol=1e-10, max_sweeps=500, check_every=1):
+        n = self.n_inst
+        sw = (ctypes.c_int32 * n)()
+        dl = (ctypes.c_double * n)()
+        st = _check(load().ctm_converge(self.ctx, tol, max_sweeps, check_every, sw, dl), allow=(CTM_E_NOCONV,))
+        return list(sw), list(dl), st == CTM_OK
+
+    def spectra(self, inst=0):
+        out = np.zeros((self.Lx * self.Ly, 4, self.chi[inst]))
+        _check(load().ctm_spectra(self.ctx, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def norm(self, inst=0):
+        v = ctypes.c_double()
+        _check(load().ctm_norm(self.ctx, inst, ctypes.byref(v)))
+        return v.value
+
+    def rdm(self, x, y, vertical=False, inst=0):
+        m = self.d[inst] ** 2
+        out = np.zeros((m, m))
+        h = ctypes.c_double()
+        _check(load().ctm_rdm(self.ctx, inst, x, y, int(vertical),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        return out, h.value
+
+    def expect(self, x, y, vertical, op, inst=0):
+        op = np.ascontiguousarray(np.real(op), dtype=np.float64)
+        v = ctypes.c_double()
+        _check(load().ctm_expect(self.ctx, inst, x, y, int(vertical),
+                                 op.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(v)))
+        return v.value
+
+    def export_env(self, inst=0):
+        n = load().ctm_env_bytes(self.ctx, inst)
+        buf = np.zeros(n // 8)
+        _check(load().ctm_env_export(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), n))
+        return buf
+
+    def import_env(self, buf, inst=0):
+        buf = np.ascontiguousarray(buf, dtype=np.float64)
+        _check(load().ctm_env_import(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
+
+    def set_timing(self, on=True):
+        _check(load().ctm_set_timing(self.ctx, int(on)))
+
+    def timing(self):
+        c, s, a = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        nl = ctypes.c_int64()
+        _check(load().ctm_get_timing(self.ctx, ctypes.byref(c), ctypes.byref(s), ctypes.byref(a), ctypes.byref(nl)))
+        return {"corner_s": c.value, "solver_s": s.value, "absorb_s": a.value, "corner_launches": nl.value}
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self._torch.cuda.synchronize(self.device)
+            load().ctm_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=1e-10,
+             max_sweeps=200, device="cuda:0", **solver):
+    """Fidelity per site d and ln d between the states of two tensor sets."""
+    import torch
+    lib = load()
+    if pattern is None:
+        pattern = [0] * (Lx * Ly)
+    d = [A_list[0].shape[0]]
+    D = [A_list[0].shape[1]]
+    cfg, keep = make_config(Lx, Ly, pattern, len(A_list), d, D, [chi], prec, **solver)
+    dev = torch.device(device)
+    nbytes = workspace_size(cfg)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    at, ap = _dev_tensors(torch, A_list, dev)
+    bt, bp = _dev_tensors(torch, B_list, dev)
+    dv, lv = ctypes.c_double(), ctypes.c_double()
+    sw = (ctypes.c_int32 * 3)()
+    _check(lib.ctm_fidelity(ctypes.byref(cfg), ctypes.cast(ap, ctypes.POINTER(ctypes.c_void_p)),
+                            ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)),
+                            ctypes.c_void_p(ws.data_ptr() + off), nbytes, _stream(torch, dev), tol,
+                            max_sweeps, ctypes.byref(dv), ctypes.byref(lv), sw))
+    torch.cuda.synchronize(dev)
+    del at, bt, ws
+    return dv.value, lv.value, list(sw)

@@ -1,0 +1,1658 @@
+// Host orchestration and C ABI of the gfx950 CTM library.
+//
+// Method (paper Sec. II C, captions of Figs. 3 and 4; Sec. III): directional
+// corner-transfer-matrix renormalisation of the double-layer network around
+// an Lx x Ly cell.  A move in direction k (0 = L, 1 = U, 2 = R, 3 = D) is the
+// left move of the picture turned by k counter-clockwise quarter turns: the
+// environment tensors keep their clockwise leg order, so turning only relabels
+// which stored corner/edge plays which role and which rotated copy of the
+// double-layer tensor is used (the rotated copies are built once).
+//
+// Storage (all row-major, float64 master copies):
+//   A[s][u][l][d][r]                   PEPS tensors (ket A, bra B)
+//   b_k[L'][U'][D'][R']                double layer turned by k quarter turns,
+//                                      laid out as a (L',U') x (D',R') matrix
+//   C_i[prev][next]    (chi x chi)     corner i at each site
+//   T_i[prev][inner][next] (chi x D^2 x chi)
+//   Q   [cut_in][cut_out]  (n x n, n = chi D^2) enlarged corner, cut = (chi, D^2)
+#include "ctm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <initializer_list>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "solver.h"
+
+using namespace ctmk;
+
+namespace {
+
+thread_local std::string g_err;
+
+ctm_status fail(ctm_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+ctm_status hip_fail(hipError_t e, const char* what) {
+  if (ctmk::g_reg && ctmk::g_reg->last && ctmk::g_reg->violations)
+    return fail(CTM_E_INVALID, std::string("internal bounds check failed (") + ctmk::g_reg->last + ") in " + what);
+  return fail(CTM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return hip_fail(e_, #x);                                       \
+  } while (0)
+
+#define CHK(x)                          \
+  do {                                  \
+    ctm_status s_ = (x);                \
+    if (s_ != CTM_OK) return s_;        \
+  } while (0)
+
+struct RegGuard {
+  Registry* prev;
+  explicit RegGuard(Registry* r) : prev(g_reg) { g_reg = r; }
+  ~RegGuard() { g_reg = prev; }
+};
+
+hipError_t d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!span_ok(dst, bytes, "copy dst") || !span_ok(src, bytes, "copy src")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+hipError_t d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!span_ok(src, bytes, "readback src")) return hipErrorInvalidValue;
+  if (dry_run()) { std::memset(dst, 0, bytes); return hipSuccess; }
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+}
+hipError_t h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!span_ok(dst, bytes, "upload dst")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+hipError_t dmemset(void* p, int v, size_t bytes, hipStream_t s) {
+  if (!span_ok(p, bytes, "memset")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  return hipMemsetAsync(p, v, bytes, s);
+}
+hipError_t last_err() { return dry_run() ? hipSuccess : hipGetLastError(); }
+hipError_t ssync(hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  return hipStreamSynchronize(s);
+}
+hipError_t spans(std::initializer_list<std::pair<const void*, size_t>> l, const char* what) {
+  for (auto& e : l)
+    if (!span_ok(e.first, e.second, what)) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+constexpr int MAXT = 4;     // distinct tensors per instance
+constexpr int MAXPOS = 16;  // sites per cell (Lx, Ly <= 4)
+constexpr int MAXROWS = 4;  // rows per column step
+
+// ---------------------------------------------------------------------------
+// workspace arena: the same code path sizes (dry run) and assigns the buffers
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  Registry* reg = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    if (reg && base && count) reg->allocs.emplace_back((uintptr_t)p, count * sizeof(T));
+    off += count * sizeof(T);
+    return p;
+  }
+  void* take_bytes(size_t bytes) { return take<char>(bytes); }
+};
+
+struct Inst {
+  int d = 0, D = 0, D2 = 0, chi = 0, n = 0, k = 0;
+  double* A[MAXT] = {};
+  double* B[MAXT] = {};
+  double* b64[MAXT][4] = {};
+  void* bw[MAXT][4] = {};
+  double* C[4][MAXPOS] = {};
+  double* T[4][MAXPOS] = {};
+  void* Cw[4][MAXPOS] = {};
+  void* Tw[4][MAXPOS] = {};
+  double* spec_old = nullptr;  // [pos][4][chi]
+  double* spec_new = nullptr;
+  double* delta = nullptr;     // device scalar
+  int* flag = nullptr;         // device: non-finite flag
+  double* Vkeep[4][MAXPOS] = {};
+  SolveStatus* skeep[4][MAXPOS] = {};
+  bool has_keep[4][MAXPOS] = {};
+  int cursor[4] = {0, 0, 0, 0};
+  uint64_t solves = 0;
+};
+
+struct Row {  // scratch for one row of a column step
+  void* Q[4] = {};
+  void* X[4] = {};
+  void* Y[4] = {};
+  double *V = nullptr, *Yb = nullptr, *Qb = nullptr, *Z = nullptr, *LV = nullptr, *UU = nullptr,
+         *Ub = nullptr, *Vp = nullptr, *tmp = nullptr;
+  void *qin = nullptr, *q1 = nullptr, *q2 = nullptr;  // N-apply scratch in the Q type
+  double *G = nullptr, *Rinv = nullptr, *Rm = nullptr, *UR = nullptr, *WR = nullptr,
+         *S = nullptr, *Wp = nullptr, *Up = nullptr, *jw = nullptr;
+  SolveStatus* st = nullptr;
+  double *P1 = nullptr, *P2T = nullptr;
+  void *P1w = nullptr, *P2Tw = nullptr;
+  void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
+  double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
+  double *red = nullptr, *sums = nullptr;
+};
+
+struct Obs {  // float64 scratch of the observables
+  double *Q[4] = {}, *X = nullptr, *Y = nullptr, *Uh = nullptr, *LhT = nullptr;
+  double *G1 = nullptr, *B1 = nullptr, *H = nullptr, *CT = nullptr, *ab = nullptr;
+  double *Lall = nullptr, *Rall = nullptr, *Rp = nullptr;
+  double *t0 = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  double *rho = nullptr, *red = nullptr, *vals = nullptr;
+  size_t big = 0;
+};
+
+}  // namespace
+
+struct ctm_ctx_s {
+  ctm_config cfg{};
+  std::vector<int> pattern, dv, Dv, chiv;
+  int Lx = 1, Ly = 1, ntens = 1, ninst = 1;
+  int prec = CTM_FP64;
+  int wt = F64, qt = F64;  // contraction operand type, enlarged-corner type
+  hipStream_t stream = nullptr;
+  std::vector<Inst> inst;
+  Row rows[MAXROWS];
+  Obs obs;
+  double* spec_tmp_U = nullptr;  // corner SVD scratch
+  double* spec_tmp_W = nullptr;
+  double* spec_tmp_S = nullptr;
+  double* spec_tmp_J = nullptr;
+  size_t ws_need = 0;
+  bool timing = false;
+  double t_corner = 0, t_solver = 0, t_absorb = 0;
+  int64_t corner_launches = 0;
+  hipEvent_t ev[4] = {};
+  Registry reg;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+int wtype_of(int prec) { return prec == CTM_FP64 ? F64 : (prec == CTM_FP32 ? F32 : BF16); }
+int qtype_of(int prec) { return prec == CTM_FP64 ? F64 : F32; }
+
+int subspace_dim(const ctm_config& c, int chi, int n) {
+  int p = c.svd_oversample > 0 ? c.svd_oversample : 0;
+  return std::min(n, chi + p);
+}
+
+void plan(ctm_ctx_s& x, Arena& ar) {
+  const int npos = x.Lx * x.Ly;
+  const size_t ws = dtype_size(x.wt), qs = dtype_size(x.qt);
+  int rows = std::max(x.Lx, x.Ly);
+  size_t mx_n = 0, mx_k = 0, mx_chi = 0, mx_D2 = 0, mx_d = 0;
+  for (int i = 0; i < x.ninst; ++i) {
+    Inst& I = x.inst[i];
+    mx_n = std::max(mx_n, (size_t)I.n);
+    mx_k = std::max(mx_k, (size_t)I.k);
+    mx_chi = std::max(mx_chi, (size_t)I.chi);
+    mx_D2 = std::max(mx_D2, (size_t)I.D2);
+    mx_d = std::max(mx_d, (size_t)I.d);
+  }
+  for (int i = 0; i < x.ninst; ++i) {
+    Inst& I = x.inst[i];
+    const size_t t5 = (size_t)I.d * I.D2 * I.D2;
+    const size_t a8 = (size_t)I.D2 * I.D2 * I.D2 * I.D2;
+    const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+    for (int t = 0; t < x.ntens; ++t) {
+      I.A[t] = ar.take<double>(t5);
+      I.B[t] = ar.take<double>(t5);
+      for (int r = 0; r < 4; ++r) {
+        I.b64[t][r] = ar.take<double>(a8);
+        I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : ar.take_bytes(a8 * ws);
+      }
+    }
+    for (int c = 0; c < 4; ++c)
+      for (int p = 0; p < npos; ++p) {
+        I.C[c][p] = ar.take<double>(c2);
+        I.T[c][p] = ar.take<double>(t3);
+        I.Cw[c][p] = (x.wt == F64) ? (void*)I.C[c][p] : ar.take_bytes(c2 * ws);
+        I.Tw[c][p] = (x.wt == F64) ? (void*)I.T[c][p] : ar.take_bytes(t3 * ws);
+      }
+    I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi);
+    I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
+    I.delta = ar.take<double>(4);
+    I.flag = ar.take<int>(4);
+    for (int c = 0; c < 4; ++c)
+      for (int p = 0; p < npos; ++p) {
+        I.Vkeep[c][p] = ar.take<double>((size_t)I.n * I.k);
+        I.skeep[c][p] = ar.take<SolveStatus>(1);
+      }
+  }
+  // row scratch sized for the largest instance
+  const size_t n = mx_n, k = mx_k, chi = mx_chi, D2 = mx_D2;
+  const size_t nk = n * k, c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
+  for (int r = 0; r < rows; ++r) {
+    Row& R = x.rows[r];
+    for (int q = 0; q < 4; ++q) {
+      R.Q[q] = ar.take_bytes(n * n * qs);
+      R.X[q] = ar.take_bytes(t3 * ws);
+      R.Y[q] = ar.take_bytes(y4 * ws);
+    }
+    R.V = ar.take<double>(nk); R.Yb = ar.take<double>(nk); R.Qb = ar.take<double>(nk);
+    R.Z = ar.take<double>(nk); R.LV = ar.take<double>(nk); R.UU = ar.take<double>(nk);
+    R.Ub = ar.take<double>(nk); R.Vp = ar.take<double>(nk); R.tmp = ar.take<double>(nk);
+    if (x.qt != F64) {
+      R.qin = ar.take_bytes(nk * qs); R.q1 = ar.take_bytes(nk * qs); R.q2 = ar.take_bytes(nk * qs);
+    }
+    R.G = ar.take<double>(k * k); R.Rinv = ar.take<double>(k * k); R.Rm = ar.take<double>(k * k);
+    R.UR = ar.take<double>(k * k); R.WR = ar.take<double>(k * k); R.S = ar.take<double>(k);
+    R.Wp = ar.take<double>(k * chi); R.Up = ar.take<double>(k * chi); R.jw = ar.take<double>(2 * k * k);
+    R.st = ar.take<SolveStatus>(1);
+    R.P1 = ar.take<double>(n * chi); R.P2T = ar.take<double>(n * chi);
+    R.P1w = (x.wt == F64) ? (void*)R.P1 : ar.take_bytes(n * chi * ws);
+    R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
+    R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
+    R.X6 = ar.take_bytes(t3 * ws);
+    R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
+    R.red = ar.take<double>(256); R.sums = ar.take<double>(8);
+  }
+  // corner-spectrum SVD scratch (8 corners per launch)
+  x.spec_tmp_U = ar.take<double>(8 * c2);
+  x.spec_tmp_W = ar.take<double>(8 * c2);
+  x.spec_tmp_S = ar.take<double>(8 * chi);
+  x.spec_tmp_J = ar.take<double>(8 * 2 * c2);
+  // observables (float64)
+  const size_t d = mx_d, a8 = D2 * D2 * D2 * D2;
+  Obs& O = x.obs;
+  const bool plaq = (x.Lx >= 2 && x.Ly >= 2);
+  if (plaq) {
+    for (int q = 0; q < 4; ++q) O.Q[q] = ar.take<double>(n * n);
+    O.Uh = ar.take<double>(n * n);
+    O.LhT = ar.take<double>(n * n);
+  }
+  O.X = ar.take<double>(t3);
+  O.Y = ar.take<double>(y4);
+  O.G1 = ar.take<double>(y4);
+  O.B1 = ar.take<double>(t3);
+  O.H = ar.take<double>(y4);
+  O.CT = ar.take<double>(t3);
+  O.ab = ar.take<double>(4 * a8);
+  O.Lall = ar.take<double>(d * d * t3);
+  O.Rall = ar.take<double>(d * d * t3);
+  O.Rp = ar.take<double>(d * d * t3);
+  size_t big = std::max(y4, c2 * (size_t)std::pow((double)D2, (double)std::max(x.Lx, x.Ly)));
+  O.big = big;
+  O.t0 = ar.take<double>(big); O.t1 = ar.take<double>(big);
+  O.t2 = ar.take<double>(big); O.t3 = ar.take<double>(big);
+  O.rho = ar.take<double>(d * d * d * d * 2);
+  O.red = ar.take<double>(256);
+  O.vals = ar.take<double>(16);
+}
+
+// ---------------------------------------------------------------------------
+// frames
+// ---------------------------------------------------------------------------
+void frame_dims(int k, int Lx, int Ly, int& lx, int& ly) {
+  if (k % 2 == 0) { lx = Lx; ly = Ly; } else { lx = Ly; ly = Lx; }
+}
+int pmod(int a, int m) { int r = a % m; return r < 0 ? r + m : r; }
+
+// Site (x, y) shown at (xp, yp) after k counter-clockwise quarter turns; one
+// turn maps (x, y) to (y, -x), so undoing it maps (xp, yp) to (-yp, xp).
+void frame_site(int k, int xp, int yp, int Lx, int Ly, int& x, int& y) {
+  int lx, ly;
+  frame_dims(k, Lx, Ly, lx, ly);
+  xp = pmod(xp, lx);
+  yp = pmod(yp, ly);
+  for (int j = k % 4; j > 0; --j) {
+    int ax, ay;
+    frame_dims(j - 1, Lx, Ly, ax, ay);
+    int nx = pmod(-yp, ax), ny = pmod(xp, ay);
+    xp = nx;
+    yp = ny;
+  }
+  x = pmod(xp, Lx);
+  y = pmod(yp, Ly);
+}
+
+// frame coordinates of site (x, y) after k turns
+void to_frame(int k, int x, int y, int Lx, int Ly, int& xp, int& yp) {
+  for (int j = 0; j < k % 4; ++j) {
+    int nx = y, ny = -x;
+    x = nx;
+    y = ny;
+  }
+  int lx, ly;
+  frame_dims(k, Lx, Ly, lx, ly);
+  xp = pmod(x, lx);
+  yp = pmod(y, ly);
+}
+
+struct Roles {
+  const ctm_ctx_s* x;
+  Inst* I;
+  int k;
+  int pos(int xp, int yp) const {
+    int sx, sy;
+    frame_site(k, xp, yp, x->Lx, x->Ly, sx, sy);
+    return sy * x->Lx + sx;
+  }
+  int tid(int xp, int yp) const { return x->pattern[pos(xp, yp)]; }
+  double* C(int i, int xp, int yp) const { return I->C[(i + k) % 4][pos(xp, yp)]; }
+  double* T(int i, int xp, int yp) const { return I->T[(i + k) % 4][pos(xp, yp)]; }
+  void* Cw(int i, int xp, int yp) const { return I->Cw[(i + k) % 4][pos(xp, yp)]; }
+  void* Tw(int i, int xp, int yp) const { return I->Tw[(i + k) % 4][pos(xp, yp)]; }
+  // double layer of the site in this frame, additionally turned by r
+  double* b64(int xp, int yp, int r) const { return I->b64[tid(xp, yp)][(k + r) % 4]; }
+  void* bw(int xp, int yp, int r) const { return I->bw[tid(xp, yp)][(k + r) % 4]; }
+  int cut(int xp, int yp) const { return pos(xp, yp); }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM helpers
+// ---------------------------------------------------------------------------
+struct G {
+  GemmGroup g{};
+  int n = 0;
+  void add(const void* a, const void* b, void* c) {
+    g.A[n] = a; g.B[n] = b; g.C[n] = c; ++n;
+  }
+};
+
+ctm_status gemm_run(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
+                    const View& vb, const View& vc, const G& g, double alpha = 1.0,
+                    double beta = 0.0) {
+  HIPCHK(ctmk::gemm(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g.g, g.n));
+  return CTM_OK;
+}
+
+ctm_status gemm1(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
+                 const void* a, const View& vb, const void* b, const View& vc, void* c,
+                 double alpha = 1.0, double beta = 0.0) {
+  G g;
+  g.add(a, b, c);
+  return gemm_run(s, ta, tc, M, N, K, va, vb, vc, g, alpha, beta);
+}
+
+View view2(int64_t r_ext, int64_t r_ls, int64_t r_hs, int64_t c_ext, int64_t c_ls, int64_t c_hs) {
+  return View{r_ext, r_ls, r_hs, c_ext, c_ls, c_hs};
+}
+const int64_t BIG = INT64_MAX / 4;
+
+// ---------------------------------------------------------------------------
+// enlarged corners: Q[(g,dn),(b,r)] = sum C[p,n] Tn[n,u,b] Tp[g,l,p] a[u,l,dn,r]
+//   X[(g,l), n]     = Tp[(g,l), p] C[p, n]
+//   Y[(g,l), (u,b)] = X[(g,l), n] Tn[n, (u,b)]
+//   Q               = sum_{(l,u)} Y[(g,b),(l,u)] b[(l,u),(dn,r)], written to
+//                     the row-major [W x N] matrix through a two-level view.
+// One grouped launch per stage covers every corner of every row.
+// ---------------------------------------------------------------------------
+struct CornerJob {
+  const void *C, *Tn, *Tp, *b;
+  void *X, *Y, *Q;
+};
+
+ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs) {
+  const int64_t c = chi, n = (int64_t)chi * D2;
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
+    size_t j1 = std::min(jobs.size(), j0 + MAXG);
+    G g1, g2, g3;
+    for (size_t j = j0; j < j1; ++j) {
+      g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
+      g2.add(jobs[j].X, jobs[j].Tn, jobs[j].Y);
+      g3.add(jobs[j].Y, jobs[j].b, jobs[j].Q);
+    }
+    CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
+    CHK(gemm_run(s, tin, tin, n, n, c, rowmajor(c), rowmajor(n), rowmajor(n), g2));
+    // A: rows m = (g, b): b low (extent chi, stride 1), g high (stride D2*D2*chi);
+    //    cols k = (l, u): stride chi
+    View va = view2(c, 1, (int64_t)D2 * D2 * c, BIG, c, 0);
+    // C: rows m = (g, b) -> g*D2*n + b*D2; cols (dn, r) -> dn*n + r
+    View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
+    CHK(gemm_run(s, tin, tq, c * c, (int64_t)D2 * D2, (int64_t)D2 * D2, va, rowmajor((int64_t)D2 * D2),
+                 vc, g3));
+  }
+  return CTM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the solver
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SolveRow {
+  const void* Q[4];
+  Row* R;
+  double* Vkeep;
+  SolveStatus* skeep;
+  bool warm;
+};
+
+// out = op(N) in for all problems, with N = Q2^T Q1^T Q4^T Q3^T (transposeN =
+// false) or N^T = Q3 Q4 Q1 Q2 (true).  `mid` receives the product after the
+// first two factors (Lh^T in, or Uh in).  in/out/mid float64 n x k.
+ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
+                  const std::vector<double*>& in, const std::vector<double*>& out,
+                  const std::vector<double*>& mid, bool transposeN) {
+  hipStream_t s = x.stream;
+  const int qt = x.qt;
+  const View vq = transposeN ? rowmajor(n) : transposed(rowmajor(n));
+  const View vb = rowmajor(k);
+  // factor order
+  const int ord_n[4] = {2, 3, 0, 1};   // Q3^T, Q4^T, Q1^T, Q2^T applied in turn
+  const int ord_t[4] = {1, 0, 3, 2};   // Q2, Q1, Q4, Q3
+  const int* ord = transposeN ? ord_t : ord_n;
+  const size_t P = rows.size();
+  if (qt == F64) {
+    for (int f = 0; f < 4; ++f) {
+      G g;
+      for (size_t r = 0; r < P; ++r) {
+        Row* R = rows[r].R;
+        const double* src = f == 0 ? in[r] : (f == 1 ? R->tmp : (f == 2 ? mid[r] : R->tmp));
+        double* dst = f == 0 ? R->tmp : (f == 1 ? mid[r] : (f == 2 ? R->tmp : out[r]));
+        g.add(rows[r].Q[ord[f]], src, dst);
+      }
+      CHK(gemm_run(s, F64, F64, n, k, n, vq, vb, vb, g));
+    }
+    return CTM_OK;
+  }
+  // reduced precision: cast in, apply in the Q type, mid and out back to float64
+  for (size_t r = 0; r < P; ++r) HIPCHK(convert(s, F64, in[r], qt, rows[r].R->qin, (int64_t)n * k));
+  for (int f = 0; f < 4; ++f) {
+    G g;
+    for (size_t r = 0; r < P; ++r) {
+      Row* R = rows[r].R;
+      const void* src = f == 0 ? R->qin : (f == 1 ? R->q1 : (f == 2 ? R->q2 : R->q1));
+      void* dst = f == 0 ? R->q1 : (f == 1 ? R->q2 : (f == 2 ? R->q1 : (void*)out[r]));
+      g.add(rows[r].Q[ord[f]], src, dst);
+    }
+    CHK(gemm_run(s, qt, f == 3 ? F64 : qt, n, k, n, vq, vb, vb, g));
+    if (f == 1)
+      for (size_t r = 0; r < P; ++r) HIPCHK(convert(s, qt, rows[r].R->q2, F64, mid[r], (int64_t)n * k));
+  }
+  return CTM_OK;
+}
+
+// Y <- Y R^{-1} three times with R from the shifted Cholesky factor of Y^T Y
+// (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020).
+ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
+                          const std::vector<double*>& Y) {
+  hipStream_t s = x.stream;
+  const size_t P = rows.size();
+  const double u = 1.1102230246251565e-16;
+  for (int pass = 0; pass < 3; ++pass) {
+    double coef = pass == 0 ? 11.0 * ((double)n * k + (double)k * (k + 1)) * u : 4.0 * u;
+    G gg;
+    CPtrSet Gs{};
+    PtrSet Ri{};
+    StatSet st{};
+    for (size_t r = 0; r < P; ++r) {
+      gg.add(Y[r], Y[r], rows[r].R->G);
+      Gs.p[r] = rows[r].R->G;
+      Ri.p[r] = rows[r].R->Rinv;
+      st.p[r] = rows[r].R->st;
+    }
+    CHK(gemm_run(s, F64, F64, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
+    HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P));
+    G gm;
+    for (size_t r = 0; r < P; ++r) gm.add(Y[r], rows[r].R->Rinv, rows[r].R->tmp);
+    CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gm));
+    for (size_t r = 0; r < P; ++r)
+      HIPCHK(d2d(Y[r], rows[r].R->tmp, (size_t)n * k * 8, s));
+  }
+  return CTM_OK;
+}
+
+// Truncated SVD of N = (Lh Uh)^T by block subspace iteration with
+// Rayleigh-Ritz, then the projectors
+//   P1 = Lh^T V S^{-1/2},   P2^T = Uh U S^{-1/2}   (kept columns only).
+ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) {
+  hipStream_t s = x.stream;
+  const int n = I.n, k = I.k, chi = I.chi;
+  const size_t P = rows.size();
+  const ctm_config& c = x.cfg;
+  // start block: kept columns of the previous solve on this cut, then normals
+  {
+    PtrSet V0{};
+    CPtrSet Vp{};
+    StatSet pr{};
+    StatSet st{};
+    for (size_t r = 0; r < P; ++r) {
+      V0.p[r] = rows[r].R->V;
+      Vp.p[r] = rows[r].warm ? rows[r].Vkeep : nullptr;
+      pr.p[r] = rows[r].warm ? rows[r].skeep : nullptr;
+      st.p[r] = rows[r].R->st;
+    }
+    HIPCHK(warm_start(s, n, k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (++I.solves), (int)P));
+    HIPCHK(reset_status(s, st, (int)P));
+  }
+  std::vector<double*> V(P), Yb(P), Qb(P), Z(P), LV(P), UU(P), Ub(P), Vpv(P);
+  for (size_t r = 0; r < P; ++r) {
+    Row* R = rows[r].R;
+    V[r] = R->V; Yb[r] = R->Yb; Qb[r] = R->Qb; Z[r] = R->Z; LV[r] = R->LV; UU[r] = R->UU;
+    Ub[r] = R->Ub; Vpv[r] = R->Vp;
+  }
+  CHK(orthonormalize(x, n, k, rows, V));
+  const int maxit = std::max(1, c.svd_max_iters);
+  const bool adaptive = c.svd_resid_tol > 0;
+  std::vector<SolveStatus> hst(P);
+  for (int it = 0; it < maxit; ++it) {
+    CHK(napply(x, n, k, rows, V, Yb, LV, false));          // Y = N V, LV = Lh^T V
+    for (size_t r = 0; r < P; ++r)
+      HIPCHK(d2d(Qb[r], Yb[r], (size_t)n * k * 8, s));
+    CHK(orthonormalize(x, n, k, rows, Qb));                // Q = orth(Y)
+    {
+      G g;
+      for (size_t r = 0; r < P; ++r) g.add(Qb[r], Yb[r], rows[r].R->Rm);
+      CHK(gemm_run(s, F64, F64, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), g));
+    }
+    {
+      CPtrSet M{};
+      PtrSet U{}, S{}, W{}, J{};
+      for (size_t r = 0; r < P; ++r) {
+        Row* R = rows[r].R;
+        M.p[r] = R->Rm; U.p[r] = R->UR; S.p[r] = R->S; W.p[r] = R->WR; J.p[r] = R->jw;
+      }
+      HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P));     // R = U_R S W_R^T
+    }
+    {
+      G gu, gv, gl;
+      for (size_t r = 0; r < P; ++r) {
+        Row* R = rows[r].R;
+        gu.add(Qb[r], R->UR, Ub[r]);   // U  = Q U_R
+        gv.add(V[r], R->WR, Vpv[r]);   // V' = V W_R
+        gl.add(LV[r], R->WR, R->tmp);  // Lh^T V' = (Lh^T V) W_R
+      }
+      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gu));
+      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gv));
+      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gl));
+      for (size_t r = 0; r < P; ++r)
+        HIPCHK(d2d(LV[r], rows[r].R->tmp, (size_t)n * k * 8, s));
+    }
+    CHK(napply(x, n, k, rows, Ub, Z, UU, true));           // Z = N^T U, UU = Uh U
+    {
+      CPtrSet Zs{}, Vs{}, Ss{};
+      StatSet st{};
+      for (size_t r = 0; r < P; ++r) {
+        Zs.p[r] = Z[r]; Vs.p[r] = Vpv[r]; Ss.p[r] = rows[r].R->S; st.p[r] = rows[r].R->st;
+      }
+      HIPCHK(residual_status(s, n, k, chi, c.svd_cutoff, c.svd_resid_tol > 0 ? c.svd_resid_tol : 0.0,
+                             Zs, Vs, Ss, st, (int)P));
+    }
+    if (it + 1 >= maxit) break;
+    if (adaptive) {
+      bool all = true;
+      for (size_t r = 0; r < P; ++r) {
+        HIPCHK(d2h(&hst[r], rows[r].R->st, sizeof(SolveStatus), s));
+      }
+      HIPCHK(ssync(s));
+      for (size_t r = 0; r < P; ++r) all = all && hst[r].converged;
+      if (all) break;
+    }
+    for (size_t r = 0; r < P; ++r)
+      HIPCHK(d2d(V[r], Z[r], (size_t)n * k * 8, s));
+    CHK(orthonormalize(x, n, k, rows, V));
+  }
+  // projectors
+  {
+    CPtrSet W{}, Sv{}, Id{};
+    PtrSet Wp{}, Up{};
+    StatSet st{};
+    for (size_t r = 0; r < P; ++r) {
+      Row* R = rows[r].R;
+      W.p[r] = R->WR; Sv.p[r] = R->S; Id.p[r] = nullptr; Wp.p[r] = R->Wp; Up.p[r] = R->Up; st.p[r] = R->st;
+    }
+    // LV already holds Lh^T V' (rotated); Wp = diag-scaled selector
+    HIPCHK(scale_kept(s, k, chi, Id, Sv, Wp, st, (int)P));
+    HIPCHK(scale_kept(s, k, chi, Id, Sv, Up, st, (int)P));
+    G g1, g2;
+    for (size_t r = 0; r < P; ++r) {
+      Row* R = rows[r].R;
+      g1.add(LV[r], R->Wp, R->P1);
+      g2.add(UU[r], R->Up, R->P2T);
+    }
+    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g1));
+    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g2));
+    // keep the right vectors and status for the next solve on the same cut
+    for (size_t r = 0; r < P; ++r) {
+      HIPCHK(d2d(rows[r].Vkeep, Vpv[r], (size_t)n * k * 8, s));
+      HIPCHK(d2d(rows[r].skeep, rows[r].R->st, sizeof(SolveStatus), s));
+    }
+  }
+  return CTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// absorption for one row (frame roles):
+//   C1'  = P1[y-1]^T (C1 T1)
+//   T4'  = P1[y]^T-contracted ( (T4 P2[y-1]^T) b )
+//   C4'  = (T3 C4) P2[y]^T-contracted
+// ---------------------------------------------------------------------------
+ctm_status frob_normalize(ctm_ctx_s& x, Row& R, double* t, int64_t n) {
+  HIPCHK(sumsq(x.stream, t, n, R.red, R.sums));
+  HIPCHK(scale_by_rsqrt(x.stream, t, n, R.sums));
+  return CTM_OK;
+}
+
+ctm_status absorb_row(ctm_ctx_s& x, Inst& I, const Roles& ro, int xp, int yp, Row& R,
+                      Row& Rprev) {
+  hipStream_t s = x.stream;
+  const int at = x.wt;
+  const int64_t c = I.chi, D2 = I.D2, n = I.n;
+  // C1' [b', r] = sum_(a,U) P1prev[(a,U), b'] CT[(a,U), r]
+  CHK(gemm1(s, at, at, c, D2 * c, c, rowmajor(c), ro.Cw(0, xp, yp), rowmajor(D2 * c), ro.Tw(0, xp, yp),
+            rowmajor(D2 * c), R.CT));
+  CHK(gemm1(s, at, F64, c, c, n, transposed(rowmajor(c)), Rprev.P1w, rowmajor(c), R.CT, rowmajor(c), R.nC1));
+  // W1[(g,l),(u,c2)] = sum_p T4[(g,l),p] P2T_prev[(p,u), c2]
+  CHK(gemm1(s, at, at, c * D2, D2 * c, c, rowmajor(c), ro.Tw(3, xp, yp), rowmajor(D2 * c), Rprev.P2Tw,
+            rowmajor(D2 * c), R.W1));
+  // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)]
+  {
+    View va = view2(c, 1, D2 * D2 * c, BIG, c, 0);
+    CHK(gemm1(s, at, at, c * c, D2 * D2, D2 * D2, va, R.W1, rowmajor(D2 * D2), ro.bw(xp, yp, 0),
+              rowmajor(D2 * D2), R.W2));
+  }
+  // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
+  {
+    // B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
+    // B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
+    View vb = view2(D2, D2, c * D2 * D2, c, D2 * D2, 1);
+    CHK(gemm1(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), R.P1w, vb, R.W2, rowmajor(D2 * c), R.nT4));
+  }
+  // X6[z, (g, dn)] = sum_q T3[(z,dn), q] C4[q, g]  written as [z][g][dn]
+  {
+    View vc = view2(D2, 1, c * D2, BIG, D2, 0);
+    CHK(gemm1(s, at, at, c * D2, c, c, rowmajor(c), ro.Tw(2, xp, yp), rowmajor(c), ro.Cw(3, xp, yp), vc, R.X6));
+  }
+  // C4'[z, c] = sum_(g,dn) X6[z,(g,dn)] P2T[(g,dn), c]
+  CHK(gemm1(s, at, F64, c, c, n, rowmajor(n), R.X6, rowmajor(c), R.P2Tw, rowmajor(c), R.nC4));
+  CHK(frob_normalize(x, R, R.nC1, c * c));
+  CHK(frob_normalize(x, R, R.nT4, c * c * D2));
+  CHK(frob_normalize(x, R, R.nC4, c * c));
+  return CTM_OK;
+}
+
+ctm_status refresh_working(ctm_ctx_s& x, Inst& I) {
+  if (x.wt == F64) return CTM_OK;
+  const int npos = x.Lx * x.Ly;
+  const int64_t c2 = (int64_t)I.chi * I.chi, t3 = c2 * I.D2;
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p) {
+      HIPCHK(convert(x.stream, F64, I.C[c][p], x.wt, I.Cw[c][p], c2));
+      HIPCHK(convert(x.stream, F64, I.T[c][p], x.wt, I.Tw[c][p], t3));
+    }
+  return CTM_OK;
+}
+
+void ev_record(ctm_ctx_s& x, int i) {
+  if (x.timing && !dry_run()) (void)hipEventRecord(x.ev[i], x.stream);
+}
+double ev_ms(ctm_ctx_s& x, int a, int b) {
+  float ms = 0;
+  if (dry_run()) return 0.0;
+  (void)hipEventSynchronize(x.ev[b]);
+  (void)hipEventElapsedTime(&ms, x.ev[a], x.ev[b]);
+  return ms * 1e-3;
+}
+
+// One column step of the move in direction k at frame column xp.
+ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
+  hipStream_t s = x.stream;
+  Roles ro{&x, &I, k};
+  int lx, ly;
+  frame_dims(k, x.Lx, x.Ly, lx, ly);
+  CHK(refresh_working(x, I));
+  ev_record(x, 0);
+  // enlarged corners of every plaquette (xp, yp)
+  std::vector<CornerJob> jobs;
+  for (int yp = 0; yp < ly; ++yp) {
+    Row& R = x.rows[yp];
+    const int cx[4] = {xp, xp + 1, xp + 1, xp};
+    const int cy[4] = {yp, yp, yp + 1, yp + 1};
+    for (int q = 0; q < 4; ++q) {
+      CornerJob j;
+      j.C = ro.Cw(q, cx[q], cy[q]);
+      j.Tn = ro.Tw(q, cx[q], cy[q]);
+      j.Tp = ro.Tw((q + 3) % 4, cx[q], cy[q]);
+      j.b = ro.bw(cx[q], cy[q], q);
+      j.X = R.X[q];
+      j.Y = R.Y[q];
+      j.Q = R.Q[q];
+      jobs.push_back(j);
+    }
+  }
+  CHK(corner_chain(s, x.wt, x.qt, I.chi, I.D2, jobs));
+  x.corner_launches += 3 * ((jobs.size() + MAXG - 1) / MAXG);
+  ev_record(x, 1);
+  // projectors, all rows together
+  std::vector<SolveRow> rows;
+  for (int yp = 0; yp < ly; ++yp) {
+    SolveRow sr;
+    Row& R = x.rows[yp];
+    for (int q = 0; q < 4; ++q) sr.Q[q] = R.Q[q];
+    sr.R = &R;
+    int cut = ro.cut(xp, yp);
+    sr.Vkeep = I.Vkeep[k][cut];
+    sr.skeep = I.skeep[k][cut];
+    sr.warm = I.has_keep[k][cut];
+    rows.push_back(sr);
+  }
+  CHK(solve_projectors(x, I, rows));
+  for (int yp = 0; yp < ly; ++yp) I.has_keep[k][ro.cut(xp, yp)] = true;
+  if (x.wt != F64)
+    for (int yp = 0; yp < ly; ++yp) {
+      Row& R = x.rows[yp];
+      HIPCHK(convert(s, F64, R.P1, x.wt, R.P1w, (int64_t)I.n * I.chi));
+      HIPCHK(convert(s, F64, R.P2T, x.wt, R.P2Tw, (int64_t)I.n * I.chi));
+    }
+  ev_record(x, 2);
+  // absorption
+  for (int yp = 0; yp < ly; ++yp)
+    CHK(absorb_row(x, I, ro, xp, yp, x.rows[yp], x.rows[pmod(yp - 1, ly)]));
+  const int64_t c2 = (int64_t)I.chi * I.chi, t3 = c2 * I.D2;
+  for (int yp = 0; yp < ly; ++yp) {
+    Row& R = x.rows[yp];
+    HIPCHK(d2d(ro.C(0, xp + 1, yp), R.nC1, c2 * 8, s));
+    HIPCHK(d2d(ro.T(3, xp + 1, yp), R.nT4, t3 * 8, s));
+    HIPCHK(d2d(ro.C(3, xp + 1, yp), R.nC4, c2 * 8, s));
+  }
+  ev_record(x, 3);
+  if (x.timing) {
+    x.t_corner += ev_ms(x, 0, 1);
+    x.t_solver += ev_ms(x, 1, 2);
+    x.t_absorb += ev_ms(x, 2, 3);
+  }
+  return CTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// corner spectra and the convergence measure
+// ---------------------------------------------------------------------------
+__global__ void spectra_delta_kernel(const double* __restrict__ S, int chi, int ncorner,
+                                     double* __restrict__ spec_new, double* __restrict__ spec_old,
+                                     double* __restrict__ delta, int* flag, int first, int commit) {
+  // one block; S holds ncorner spectra (descending) of length chi
+  __shared__ double red[256];
+  double dmax = 0.0;
+  for (int c = 0; c < ncorner; ++c) {
+    double tot = 0.0;
+    for (int i = threadIdx.x; i < chi; i += blockDim.x) tot += S[c * chi + i];
+    red[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    tot = red[0];
+    __syncthreads();
+    double d = 0.0;
+    for (int i = threadIdx.x; i < chi; i += blockDim.x) {
+      double v = tot > 0 ? S[c * chi + i] / tot : S[c * chi + i];
+      if (!isfinite(v)) *flag = 1;
+      spec_new[c * chi + i] = v;
+      d += fabs(v - spec_old[c * chi + i]);
+    }
+    red[threadIdx.x] = d;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    dmax = fmax(dmax, red[0]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *delta = first ? INFINITY : dmax;
+  if (commit) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncorner * chi; i += blockDim.x) spec_old[i] = spec_new[i];
+  }
+}
+
+ctm_status corner_spectra(ctm_ctx_s& x, Inst& I, bool first, bool commit) {
+  hipStream_t s = x.stream;
+  const int npos = x.Lx * x.Ly, nc = 4 * npos, chi = I.chi;
+  for (int c0 = 0; c0 < nc; c0 += 8) {
+    int c1 = std::min(nc, c0 + 8);
+    CPtrSet M{};
+    PtrSet U{}, S{}, W{}, J{};
+    for (int c = c0; c < c1; ++c) {
+      int pos = c / 4, corner = c % 4;
+      M.p[c - c0] = I.C[corner][pos];
+      U.p[c - c0] = x.spec_tmp_U + (size_t)(c - c0) * chi * chi;
+      W.p[c - c0] = x.spec_tmp_W + (size_t)(c - c0) * chi * chi;
+      S.p[c - c0] = I.spec_new + (size_t)c * chi;
+      J.p[c - c0] = x.spec_tmp_J + (size_t)(c - c0) * 2 * chi * chi;
+    }
+    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, c1 - c0));
+  }
+  HIPCHK(spans({{I.spec_new, (size_t)nc * chi * 8}, {I.spec_old, (size_t)nc * chi * 8}, {I.delta, 8},
+                {I.flag, 4}}, "spectra"));
+  if (!dry_run())
+    hipLaunchKernelGGL(spectra_delta_kernel, dim3(1), dim3(256), 0, s, I.spec_new, chi, nc, I.spec_new,
+                       I.spec_old, I.delta, I.flag, first ? 1 : 0, commit ? 1 : 0);
+  HIPCHK(last_err());
+  return CTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// environment initialisation
+// ---------------------------------------------------------------------------
+__global__ void init_env_kernel(double* C, double* T, int chi, int Dk, int Db, int diag,
+                                const double* spec) {
+  const int D2 = Dk * Db;
+  const int64_t c2 = (int64_t)chi * chi, t3 = c2 * D2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < t3;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = e / ((int64_t)D2 * chi), rem = e % ((int64_t)D2 * chi);
+    int U = (int)(rem / chi), b = (int)(rem % chi);
+    int u = U / Db, uu = U % Db;
+    double v = 0.0;
+    if (u == uu) v = diag ? (a == b ? 1.0 : 0.0) : ((a == 0 && b == 0) ? 1.0 : 0.0);
+    T[e] = v;
+    if (e < c2) {
+      int i = (int)(e / chi), j = (int)(e % chi);
+      C[e] = diag ? (i == j ? spec[i] : 0.0) : ((i == 0 && j == 0) ? 1.0 : 0.0);
+    }
+  }
+}
+
+bool finite_host(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+ctm_status validate(const ctm_config* c) {
+  if (!c) return fail(CTM_E_INVALID, "null config");
+  if (c->n_inst < 1 || c->Lx < 1 || c->Ly < 1 || c->Lx > 4 || c->Ly > 4 || c->n_tensors < 1 ||
+      c->n_tensors > MAXT)
+    return fail(CTM_E_INVALID, "cell: need n_inst>=1, 1<=Lx,Ly<=4, 1<=n_tensors<=4");
+  if (!c->pattern || !c->d || !c->D || !c->chi) return fail(CTM_E_INVALID, "null pattern/d/D/chi");
+  for (int i = 0; i < c->Lx * c->Ly; ++i)
+    if (c->pattern[i] < 0 || c->pattern[i] >= c->n_tensors) return fail(CTM_E_INVALID, "pattern entry out of range");
+  if (c->prec < 0 || c->prec > 2) return fail(CTM_E_INVALID, "prec");
+  for (int i = 0; i < c->n_inst; ++i) {
+    int d = c->d[i], D = c->D[i], chi = c->chi[i];
+    if (d < 1 || D < 1 || chi < 1 || d > 64 || D > 16) return fail(CTM_E_INVALID, "d in 1..64, D in 1..16, chi >= 1");
+    int64_t n = (int64_t)chi * D * D;
+    if (n * n > (int64_t)INT32_MAX * 4) return fail(CTM_E_INVALID, "chi*D^2 too large");
+    int k = std::min<int64_t>(n, chi + std::max(0, c->svd_oversample));
+    if (k > 176) return fail(CTM_E_INVALID, "chi + oversample must be <= 176");
+    if (chi > 256) return fail(CTM_E_INVALID, "chi must be <= 256");
+  }
+  return CTM_OK;
+}
+
+ctm_status build_ctx(const ctm_config* cfg, ctm_ctx_s& x) {
+  CHK(validate(cfg));
+  x.cfg = *cfg;
+  x.Lx = cfg->Lx;
+  x.Ly = cfg->Ly;
+  x.ntens = cfg->n_tensors;
+  x.ninst = cfg->n_inst;
+  x.pattern.assign(cfg->pattern, cfg->pattern + x.Lx * x.Ly);
+  x.dv.assign(cfg->d, cfg->d + x.ninst);
+  x.Dv.assign(cfg->D, cfg->D + x.ninst);
+  x.chiv.assign(cfg->chi, cfg->chi + x.ninst);
+  x.cfg.pattern = x.pattern.data();
+  x.cfg.d = x.dv.data();
+  x.cfg.D = x.Dv.data();
+  x.cfg.chi = x.chiv.data();
+  x.prec = cfg->prec;
+  x.wt = wtype_of(cfg->prec);
+  x.qt = qtype_of(cfg->prec);
+  x.inst.assign(x.ninst, Inst());
+  for (int i = 0; i < x.ninst; ++i) {
+    Inst& I = x.inst[i];
+    I.d = x.dv[i];
+    I.D = x.Dv[i];
+    I.D2 = I.D * I.D;
+    I.chi = x.chiv[i];
+    I.n = I.chi * I.D2;
+    I.k = subspace_dim(x.cfg, I.chi, I.n);
+  }
+  Arena ar;
+  plan(x, ar);
+  x.ws_need = ar.off + 256;
+  return CTM_OK;
+}
+
+ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double* spec_host) {
+  hipStream_t s = x.stream;
+  const int npos = x.Lx * x.Ly;
+  int chimax = 0;
+  for (int v : x.chiv) chimax = std::max(chimax, v);
+  double* dspec = nullptr;
+  std::vector<double> hs;
+  if (init == CTM_INIT_DIAG) {
+    if (!spec_host) return fail(CTM_E_INVALID, "CTM_INIT_DIAG needs spectrum_host");
+    // stage the spectra in spec_old temporarily (npos*4*chi)
+    hs.resize((size_t)npos * 4 * I.chi);
+    for (int p = 0; p < npos; ++p)
+      for (int c = 0; c < 4; ++c)
+        for (int j = 0; j < I.chi; ++j)
+          hs[((size_t)p * 4 + c) * I.chi + j] =
+              spec_host[(((size_t)inst_idx * npos + p) * 4 + c) * chimax + j];
+    if (!finite_host(hs.data(), hs.size())) return fail(CTM_E_NONFINITE, "non-finite spectrum");
+    HIPCHK(h2d(I.spec_old, hs.data(), hs.size() * 8, s));
+    dspec = I.spec_old;
+  }
+  for (int p = 0; p < npos; ++p) {
+    for (int c = 0; c < 4; ++c) {
+      const double* sp = dspec ? dspec + ((size_t)p * 4 + c) * I.chi : nullptr;
+      HIPCHK(spans({{I.C[c][p], (size_t)I.chi * I.chi * 8}, {I.T[c][p], (size_t)I.chi * I.chi * I.D2 * 8},
+                    {sp, sp ? (size_t)I.chi * 8 : 0}}, "init env"));
+      if (!dry_run())
+        hipLaunchKernelGGL(init_env_kernel, dim3(256), dim3(256), 0, s, I.C[c][p], I.T[c][p], I.chi, I.D,
+                           I.D, init == CTM_INIT_DIAG ? 1 : 0, sp);
+      HIPCHK(last_err());
+    }
+  }
+  if (init == CTM_INIT_DIAG) {
+    Row& R = x.rows[0];
+    for (int p = 0; p < npos; ++p)
+      for (int c = 0; c < 4; ++c) {
+        CHK(frob_normalize(x, R, I.C[c][p], (int64_t)I.chi * I.chi));
+        CHK(frob_normalize(x, R, I.T[c][p], (int64_t)I.chi * I.chi * I.D2));
+      }
+  }
+  HIPCHK(dmemset(I.spec_old, 0, (size_t)npos * 4 * I.chi * 8, s));
+  HIPCHK(dmemset(I.flag, 0, sizeof(int) * 4, s));
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p) I.has_keep[c][p] = false;
+  for (int c = 0; c < 4; ++c) I.cursor[c] = 0;
+  CHK(corner_spectra(x, I, true, true));
+  return CTM_OK;
+}
+
+ctm_status do_move(ctm_ctx_s& x, Inst& I, int dir, int count) {
+  int lx, ly;
+  for (int i = 0; i < count; ++i) {
+    frame_dims(dir, x.Lx, x.Ly, lx, ly);
+    int xp = I.cursor[dir];
+    CHK(column_step(x, I, dir, xp));
+    I.cursor[dir] = (xp + 1) % lx;
+  }
+  return CTM_OK;
+}
+
+ctm_status do_sweep(ctm_ctx_s& x, Inst& I) {
+  const int order[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
+  for (int o = 0; o < 4; ++o) {
+    int lx, ly;
+    frame_dims(order[o], x.Lx, x.Ly, lx, ly);
+    CHK(do_move(x, I, order[o], lx));
+  }
+  return CTM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// observables
+// ===========================================================================
+namespace {
+
+__global__ void dot_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                           double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) acc += a[e] * b[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_parts_kernel(const double* __restrict__ part, int np, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+ctm_status dot_dev(ctm_ctx_s& x, const double* a, const double* b, int64_t n, double* out) {
+  int64_t blocks = std::min<int64_t>(256, std::max<int64_t>(1, (n + 255) / 256));
+  HIPCHK(spans({{a, (size_t)n * 8}, {b, (size_t)n * 8}, {x.obs.red, (size_t)blocks * 8}, {out, 8}}, "dot"));
+  if (dry_run()) return CTM_OK;
+  hipLaunchKernelGGL(dot_kernel, dim3((unsigned)blocks), dim3(256), 0, x.stream, a, b, n, x.obs.red);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, x.stream, x.obs.red, (int)blocks, out);
+  HIPCHK(last_err());
+  return CTM_OK;
+}
+
+// Strip along the top of the frame-k window anchored at (xp0, yp0) with lx
+// sites: out[a, U_0 .. U_{lx-1}, b] = C1 T1_0 .. T1_{lx-1} C2 (float64).
+ctm_status top_strip(ctm_ctx_s& x, Inst& I, int k, int xp0, int yp0, int lxw, double* out,
+                     double* w0, double* w1) {
+  hipStream_t s = x.stream;
+  Roles ro{&x, &I, k};
+  const int64_t c = I.chi, D2 = I.D2;
+  // cur [rows x chi] starting with C1 (rows = chi)
+  const double* cur = ro.C(0, xp0, yp0);
+  int64_t rows = c;
+  double* bufs[2] = {w0, w1};
+  int b = 0;
+  for (int i = 0; i < lxw; ++i) {
+    double* dst = bufs[b];
+    CHK(gemm1(s, F64, F64, rows, D2 * c, c, rowmajor(c), cur, rowmajor(D2 * c), ro.T(0, xp0 + i, yp0),
+              rowmajor(D2 * c), dst));
+    cur = dst;
+    rows *= D2;
+    b ^= 1;
+  }
+  CHK(gemm1(s, F64, F64, rows, c, c, rowmajor(c), cur, rowmajor(c), ro.C(1, xp0 + lxw - 1, yp0),
+            rowmajor(c), out));
+  return CTM_OK;
+}
+
+// Z10 of the frame-k window anchored at (xp0, yp0) of lxw x lyw sites: the top
+// strip joined directly to the bottom strip.  The bottom strip is the top strip
+// of the picture turned by two more quarter turns; joining reverses all legs.
+ctm_status z10(ctm_ctx_s& x, Inst& I, int k, int xp0, int yp0, int lxw, int lyw, double* out) {
+  Obs& O = x.obs;
+  const int64_t c = I.chi, D2 = I.D2;
+  CHK(top_strip(x, I, k, xp0, yp0, lxw, O.t0, O.t2, O.t3));
+  int lx, ly;
+  frame_dims(k, x.Lx, x.Ly, lx, ly);
+  // frame-(k+2) coordinates of the bottom-right site of the window
+  int bx = xp0 + lxw - 1, by = yp0 + lyw - 1;
+  int ax = pmod(-bx, lx), ay = pmod(-by, ly);
+  CHK(top_strip(x, I, (k + 2) % 4, ax, ay, lxw, O.t1, O.t2, O.t3));
+  int64_t dims[8];
+  int perm[8];
+  int nd = lxw + 2;
+  dims[0] = c;
+  for (int i = 0; i < lxw; ++i) dims[1 + i] = D2;
+  dims[nd - 1] = c;
+  for (int i = 0; i < nd; ++i) perm[i] = nd - 1 - i;
+  HIPCHK(permute(x.stream, F64, O.t1, F64, O.t2, nd, dims, perm));
+  int64_t tot = c * c;
+  for (int i = 0; i < lxw; ++i) tot *= D2;
+  return dot_dev(x, O.t0, O.t2, tot, out);
+}
+
+// Z00 = Tr(C1 C2 C3 C4) of the frame-0 window of the cell anchored at (0, 0).
+ctm_status z00(ctm_ctx_s& x, Inst& I, double* out) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  Roles ro{&x, &I, 0};
+  const int64_t c = I.chi;
+  const int lx = x.Lx, ly = x.Ly;
+  CHK(gemm1(s, F64, F64, c, c, c, rowmajor(c), ro.C(0, 0, 0), rowmajor(c), ro.C(1, lx - 1, 0), rowmajor(c), O.t0));
+  // (C3 C4)^T written through a transposed output view
+  CHK(gemm1(s, F64, F64, c, c, c, rowmajor(c), ro.C(2, lx - 1, ly - 1), rowmajor(c), ro.C(3, 0, ly - 1),
+            colmajor(c), O.t1));
+  return dot_dev(x, O.t0, O.t1, c * c, out);
+}
+
+// Left block of the frame-k site (xp, yp) with the double-layer matrix bq
+// [(L,U) x (Dn,R)]:  out[e, R, z] = sum C1 T1 T4 a C4 T3 (legs: e = T1's
+// C2-side, R = a's right leg, z = T3's C3-side).  G1/B1 are recomputed only
+// when `prep` is true.
+ctm_status left_block(ctm_ctx_s& x, Inst& I, int k, int xp, int yp, const double* bq, double* out,
+                      bool prep) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  Roles ro{&x, &I, k};
+  const int64_t c = I.chi, D2 = I.D2;
+  if (prep) {
+    // CT[p, (U, e)] = C1[p, n] T1[n, (U, e)]
+    CHK(gemm1(s, F64, F64, c, D2 * c, c, rowmajor(c), ro.C(0, xp, yp), rowmajor(D2 * c), ro.T(0, xp, yp),
+              rowmajor(D2 * c), O.CT));
+    // G1[(g,L), (U,e)] = T4[(g,L), p] CT[p, (U,e)]
+    CHK(gemm1(s, F64, F64, c * D2, D2 * c, c, rowmajor(c), ro.T(3, xp, yp), rowmajor(D2 * c), O.CT,
+              rowmajor(D2 * c), O.G1));
+    // B1[(z,Dn), g] = T3[(z,Dn), q] C4[q, g]
+    CHK(gemm1(s, F64, F64, c * D2, c, c, rowmajor(c), ro.T(2, xp, yp), rowmajor(c), ro.C(3, xp, yp),
+              rowmajor(c), O.B1));
+  }
+  // H[(g,e),(Dn,R)] = sum_(L,U) G1[g,L,U,e] bq[(L,U),(Dn,R)]
+  {
+    View va = view2(c, 1, D2 * D2 * c, BIG, c, 0);
+    CHK(gemm1(s, F64, F64, c * c, D2 * D2, D2 * D2, va, O.G1, rowmajor(D2 * D2), bq, rowmajor(D2 * D2), O.H));
+  }
+  // out[(e,R), z] = sum_(g,Dn) H[(g,e),(Dn,R)] B1[(z,Dn), g]
+  {
+    View va = view2(D2, 1, D2 * D2, D2, D2, c * D2 * D2);
+    View vb = view2(D2, c, 1, BIG, D2 * c, 0);
+    CHK(gemm1(s, F64, F64, c * D2, c, c * D2, va, O.H, vb, O.B1, rowmajor(c), out));
+  }
+  return CTM_OK;
+}
+
+// Z11 of a 1x1 cell: left block (C1 T1 / T4 a / C4 T3) joined to C2 T2 C3.
+ctm_status z11_1x1(ctm_ctx_s& x, Inst& I, double* out) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  Roles ro{&x, &I, 0};
+  const int64_t c = I.chi, D2 = I.D2;
+  CHK(left_block(x, I, 0, 0, 0, ro.b64(0, 0, 0), O.t0, true));
+  // right part [e, R, z] = C2[e, b] T2[b, (R, t)] C3[t, z]
+  CHK(gemm1(s, F64, F64, c, D2 * c, c, rowmajor(c), ro.C(1, 0, 0), rowmajor(D2 * c), ro.T(1, 0, 0),
+            rowmajor(D2 * c), O.t1));
+  CHK(gemm1(s, F64, F64, c * D2, c, c, rowmajor(c), O.t1, rowmajor(c), ro.C(2, 0, 0), rowmajor(c), O.t2));
+  return dot_dev(x, O.t0, O.t2, c * D2 * c, out);
+}
+
+// Z11 of a 2x2 cell: Tr(Q1 Q2 Q3 Q4) of the frame-0 plaquette at (0, 0), float64.
+ctm_status z11_2x2(ctm_ctx_s& x, Inst& I, double* out) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  Roles ro{&x, &I, 0};
+  const int64_t n = I.n;
+  std::vector<CornerJob> jobs;
+  const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
+  for (int q = 0; q < 4; ++q) {
+    CornerJob j;
+    j.C = ro.C(q, cx[q], cy[q]);
+    j.Tn = ro.T(q, cx[q], cy[q]);
+    j.Tp = ro.T((q + 3) % 4, cx[q], cy[q]);
+    j.b = ro.b64(cx[q], cy[q], q);
+    j.X = O.X;
+    j.Y = O.Y;
+    j.Q = O.Q[q];
+    std::vector<CornerJob> one{j};
+    CHK(corner_chain(s, F64, F64, I.chi, I.D2, one));
+  }
+  CHK(gemm1(s, F64, F64, n, n, n, rowmajor(n), O.Q[0], rowmajor(n), O.Q[1], rowmajor(n), O.Uh));
+  CHK(gemm1(s, F64, F64, n, n, n, rowmajor(n), O.Q[2], rowmajor(n), O.Q[3], colmajor(n), O.LhT));
+  return dot_dev(x, O.Uh, O.LhT, n * n, out);
+}
+
+ctm_status kappa(ctm_ctx_s& x, Inst& I, double* kap) {
+  Obs& O = x.obs;
+  double* v = O.vals;
+  if (x.Lx == 1 && x.Ly == 1) {
+    CHK(z11_1x1(x, I, v + 0));
+  } else if (x.Lx == 2 && x.Ly == 2) {
+    CHK(z11_2x2(x, I, v + 0));
+  } else {
+    return fail(CTM_E_INVALID, "norm per site is implemented for 1x1 and 2x2 cells");
+  }
+  CHK(z00(x, I, v + 1));
+  CHK(z10(x, I, 0, 0, 0, x.Lx, x.Ly, v + 2));
+  // Z01: the left strip is the top strip of the picture turned by three
+  // quarter turns, anchored at the frame coordinates of site (0, Ly-1)
+  int ax, ay;
+  to_frame(3, 0, x.Ly - 1, x.Lx, x.Ly, ax, ay);
+  CHK(z10(x, I, 3, ax, ay, x.Ly, x.Lx, v + 3));
+  double h[4];
+  HIPCHK(d2h(h, v, 4 * sizeof(double), x.stream));
+  HIPCHK(ssync(x.stream));
+  double kc = h[0] * h[1] / (h[2] * h[3]);
+  int ns = x.Lx * x.Ly;
+  if (ns > 1) kc = (kc < 0 ? -1.0 : 1.0) * std::pow(std::fabs(kc), 1.0 / ns);
+  *kap = kc;
+  return CTM_OK;
+}
+
+__global__ void rdm_finalize_kernel(const double* __restrict__ raw, int d1, int d2, double* __restrict__ rho,
+                                    const double* __restrict__ h, double* __restrict__ out3) {
+  // raw[(s1,s1'),(s2,s2')] -> rho[(s1,s2),(s1',s2')] / trace; out3 = {herm defect, tr(rho h), trace}
+  __shared__ double red[256];
+  __shared__ double s_tr;
+  const int m = d1 * d2;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    int s1 = i / d2, s2 = i % d2;
+    tr += raw[(s1 * d1 + s1) * (d2 * d2) + s2 * d2 + s2];
+  }
+  red[threadIdx.x] = tr;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s_tr = red[0];
+  __syncthreads();
+  const double t = s_tr;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    int r = e / m, cc = e % m;
+    int s1 = r / d2, s2 = r % d2, p1 = cc / d2, p2 = cc % d2;
+    rho[e] = raw[(s1 * d1 + p1) * (d2 * d2) + s2 * d2 + p2] / t;
+  }
+  __syncthreads();
+  double num = 0.0, den = 0.0, ev = 0.0;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    int r = e / m, cc = e % m;
+    double a = rho[e], b = rho[cc * m + r];
+    num += (a - b) * (a - b);
+    den += a * a;
+    if (h) ev += a * h[cc * m + r];
+  }
+  double vals[3] = {num, den, ev};
+  for (int q = 0; q < 3; ++q) {
+    __syncthreads();
+    red[threadIdx.x] = vals[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    vals[q] = red[0];
+  }
+  if (threadIdx.x == 0) {
+    out3[0] = sqrt(vals[0] / vals[1]);
+    out3[1] = vals[2];
+    out3[2] = t;
+  }
+}
+
+// Two-site density matrix of the bond from (x, y) to the right (vertical = 0)
+// or lower neighbour, left in O.rho (d^2 x d^2) with O.vals[4..6] = {herm
+// defect, tr(rho h), trace}.  Built from left blocks with open physical legs:
+// for every (s, s') the double layer A_s (x) B_s' replaces a.
+ctm_status rdm(ctm_ctx_s& x, Inst& I, int sx, int sy, int vertical, const double* hdev) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  const int k = vertical ? 1 : 0;
+  int xp, yp;
+  to_frame(k, sx, sy, x.Lx, x.Ly, xp, yp);
+  // right site in frame k is (xp+1, yp); its block is a left block two turns on
+  int rx, ry;
+  {
+    int ox, oy;
+    frame_site(k, xp + 1, yp, x.Lx, x.Ly, ox, oy);
+    to_frame((k + 2) % 4, ox, oy, x.Lx, x.Ly, rx, ry);
+  }
+  const int64_t c = I.chi, D2 = I.D2, a8 = D2 * D2 * D2 * D2;
+  const int D = I.D, d = I.d;
+  const int64_t t5s = (int64_t)D * D * D * D;  // one physical slice of A
+  const int64_t blk = c * D2 * c;
+  for (int side = 0; side < 2; ++side) {
+    int kk = side == 0 ? k : (k + 2) % 4;
+    int px = side == 0 ? xp : rx, py = side == 0 ? yp : ry;
+    Roles ro{&x, &I, kk};
+    int t = ro.tid(px, py);
+    double* dst = side == 0 ? O.Lall : O.Rall;
+    for (int s1 = 0; s1 < d; ++s1)
+      for (int s2 = 0; s2 < d; ++s2) {
+        double* outs[4] = {O.ab, O.ab + a8, O.ab + 2 * a8, O.ab + 3 * a8};
+        HIPCHK(double_layer(s, I.A[t] + s1 * t5s, I.B[t] + s2 * t5s, 1, D, outs, 0));
+        CHK(left_block(x, I, kk, px, py, O.ab + (kk % 4) * a8, dst + (int64_t)(s1 * d + s2) * blk,
+                       s1 == 0 && s2 == 0));
+      }
+  }
+  // Rp[(s2,s2')][e][R][z] = Rall[(s2,s2')][z][R][e]
+  {
+    int64_t dims[4] = {(int64_t)d * d, c, D2, c};
+    int perm[4] = {0, 3, 2, 1};
+    HIPCHK(permute(s, F64, O.Rall, F64, O.Rp, 4, dims, perm));
+  }
+  // raw[(s1,s1'),(s2,s2')] = Lall . Rp^T
+  CHK(gemm1(s, F64, F64, (int64_t)d * d, (int64_t)d * d, blk, rowmajor(blk), O.Lall, transposed(rowmajor(blk)),
+            O.Rp, rowmajor((int64_t)d * d), O.rho + (int64_t)d * d * d * d));
+  HIPCHK(spans({{O.rho, (size_t)2 * d * d * d * d * 8}, {hdev, hdev ? (size_t)d * d * d * d * 8 : 0},
+                {O.vals + 4, 3 * 8}}, "rdm finalize"));
+  if (!dry_run())
+    hipLaunchKernelGGL(rdm_finalize_kernel, dim3(1), dim3(256), 0, s, O.rho + (int64_t)d * d * d * d, d, d,
+                       O.rho, hdev, O.vals + 4);
+  HIPCHK(last_err());
+  return CTM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void ctm_config_default(ctm_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->n_inst = 1;
+  c->Lx = 1;
+  c->Ly = 1;
+  c->n_tensors = 1;
+  c->prec = CTM_FP64;
+  c->svd_oversample = 16;
+  c->svd_max_iters = 30;
+  c->svd_resid_tol = 1e-13;
+  c->svd_cutoff = 1e-12;
+  c->seed = 12345;
+}
+
+ctm_status ctm_workspace_size(const ctm_config* cfg, size_t* bytes) {
+  if (!bytes) return fail(CTM_E_INVALID, "null bytes");
+  ctm_ctx_s x;
+  CHK(build_ctx(cfg, x));
+  *bytes = x.ws_need;
+  return CTM_OK;
+}
+
+static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, const double* const* B_dev,
+                            void* ws_dev, size_t ws_bytes, void* stream, int32_t init,
+                            const double* spectrum_host, ctm_ctx* out) {
+  if (!out) return fail(CTM_E_INVALID, "null out");
+  *out = nullptr;
+  if (!A_dev) return fail(CTM_E_INVALID, "null tensors");
+  if (init != CTM_INIT_TRIVIAL && init != CTM_INIT_DIAG) return fail(CTM_E_INVALID, "init kind");
+  ctm_ctx_s* x = new ctm_ctx_s();
+  ctm_status st = build_ctx(cfg, *x);
+  if (st != CTM_OK) { delete x; return st; }
+  if (!ws_dev || ws_bytes < x->ws_need) {
+    size_t need = x->ws_need;
+    delete x;
+    return fail(CTM_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  if (((uintptr_t)ws_dev) & 255) { delete x; return fail(CTM_E_INVALID, "workspace must be 256-byte aligned"); }
+  x->stream = (hipStream_t)stream;
+  const char* dr = std::getenv("CTM_DRY_RUN");
+  x->reg.dry = dr && dr[0] == '1';
+  x->reg.lo = (uintptr_t)ws_dev;
+  x->reg.hi = (uintptr_t)ws_dev + x->ws_need;
+  Arena ar;
+  ar.base = (char*)ws_dev;
+  ar.reg = &x->reg;
+  plan(*x, ar);
+  std::sort(x->reg.allocs.begin(), x->reg.allocs.end());
+  RegGuard guard(&x->reg);
+  auto cleanup = [&](ctm_status s) { delete x; return s; };
+  // copy tensors and check them
+  for (int i = 0; i < x->ninst; ++i) {
+    Inst& I = x->inst[i];
+    const size_t t5 = (size_t)I.d * I.D2 * I.D2;
+    for (int t = 0; t < x->ntens; ++t) {
+      const double* a = A_dev[i * x->ntens + t];
+      const double* b = B_dev ? B_dev[i * x->ntens + t] : a;
+      if (!a || !b) return cleanup(fail(CTM_E_INVALID, "null tensor pointer"));
+      if (d2d(I.A[t], a, t5 * 8, x->stream) != hipSuccess ||
+          d2d(I.B[t], b, t5 * 8, x->stream) != hipSuccess)
+        return cleanup(fail(CTM_E_HIP, "tensor copy failed"));
+    }
+    if (dmemset(I.flag, 0, 16, x->stream) != hipSuccess) return cleanup(fail(CTM_E_HIP, "memset"));
+    for (int t = 0; t < x->ntens; ++t) {
+      if (nonfinite(x->stream, I.A[t], (int64_t)t5, I.flag) != hipSuccess ||
+          nonfinite(x->stream, I.B[t], (int64_t)t5, I.flag) != hipSuccess)
+        return cleanup(fail(CTM_E_HIP, "nonfinite check"));
+    }
+    int hflag = 0;
+    if (d2h(&hflag, I.flag, sizeof(int), x->stream) != hipSuccess ||
+        ssync(x->stream) != hipSuccess)
+      return cleanup(fail(CTM_E_HIP, "flag readback"));
+    if (hflag) return cleanup(fail(CTM_E_NONFINITE, "non-finite entry in a PEPS tensor"));
+    for (int t = 0; t < x->ntens; ++t) {
+      if (double_layer(x->stream, I.A[t], I.B[t], I.d, I.D, I.b64[t], 0) != hipSuccess)
+        return cleanup(fail(CTM_E_HIP, "double layer"));
+      if (x->wt != F64)
+        for (int r = 0; r < 4; ++r)
+          if (convert(x->stream, F64, I.b64[t][r], x->wt, I.bw[t][r], (int64_t)I.D2 * I.D2 * I.D2 * I.D2) !=
+              hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "convert"));
+    }
+    st = init_env(*x, I, i, init, spectrum_host);
+    if (st != CTM_OK) return cleanup(st);
+  }
+  if (!dry_run())
+    for (int e = 0; e < 4; ++e)
+      if (hipEventCreate(&x->ev[e]) != hipSuccess) return cleanup(fail(CTM_E_HIP, "event"));
+  *out = x;
+  return CTM_OK;
+}
+
+ctm_status ctm_init(const ctm_config* cfg, const double* const* A_dev, const double* const* B_dev,
+                    void* ws_dev, size_t ws_bytes, void* stream, int32_t init,
+                    const double* spectrum_host, ctm_ctx* out) {
+  return init_impl(cfg, A_dev, B_dev, ws_dev, ws_bytes, stream, init, spectrum_host, out);
+}
+
+ctm_status ctm_move(ctm_ctx x, int32_t dir, int32_t count) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  RegGuard guard(&x->reg);
+  if (count < 0 || dir < 0 || dir > CTM_SWEEP) return fail(CTM_E_INVALID, "dir/count");
+  for (Inst& I : x->inst) {
+    if (dir == CTM_SWEEP) {
+      for (int i = 0; i < count; ++i) CHK(do_sweep(*x, I));
+    } else {
+      CHK(do_move(*x, I, dir, count));
+    }
+  }
+  return CTM_OK;
+}
+
+ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check_every,
+                        int32_t* sweeps_out, double* delta_out) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  RegGuard guard(&x->reg);
+  if (max_sweeps < 0 || !(tol >= 0)) return fail(CTM_E_INVALID, "tol/max_sweeps");
+  if (check_every < 1) check_every = 1;
+  bool all_ok = true;
+  bool bad = false;
+  for (int i = 0; i < x->ninst; ++i) {
+    Inst& I = x->inst[i];
+    double dlt = INFINITY;
+    int done = 0;
+    bool conv = false;
+    while (done < max_sweeps) {
+      CHK(do_sweep(*x, I));
+      ++done;
+      bool check = (done % check_every == 0) || done == max_sweeps;
+      CHK(corner_spectra(*x, I, false, true));
+      if (check) {
+        int fl = 0;
+        HIPCHK(d2h(&dlt, I.delta, 8, x->stream));
+        HIPCHK(d2h(&fl, I.flag, sizeof(int), x->stream));
+        HIPCHK(ssync(x->stream));
+        if (fl || !std::isfinite(dlt)) { bad = true; break; }
+        if (dlt < tol) { conv = true; break; }
+      }
+    }
+    if (sweeps_out) sweeps_out[i] = done;
+    if (delta_out) delta_out[i] = dlt;
+    all_ok = all_ok && conv;
+  }
+  if (bad) return fail(CTM_E_NONFINITE, "non-finite corner spectrum");
+  if (!all_ok) return fail(CTM_E_NOCONV, "not converged within max_sweeps");
+  return CTM_OK;
+}
+
+ctm_status ctm_spectra(ctm_ctx x, int32_t inst, double* out) {
+  if (!x || !out || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  CHK(corner_spectra(*x, I, false, false));
+  HIPCHK(d2h(out, I.spec_new, (size_t)x->Lx * x->Ly * 4 * I.chi * 8, x->stream));
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_norm(ctm_ctx x, int32_t inst, double* kap) {
+  if (!x || !kap || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  return kappa(*x, x->inst[inst], kap);
+}
+
+ctm_status ctm_rdm(ctm_ctx x, int32_t inst, int32_t sx, int32_t sy, int32_t vertical, double* rho_host,
+                   double* herm) {
+  if (!x || !rho_host || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  CHK(rdm(*x, I, pmod(sx, x->Lx), pmod(sy, x->Ly), vertical ? 1 : 0, nullptr));
+  const int m = I.d * I.d;
+  double v3[3];
+  HIPCHK(d2h(rho_host, x->obs.rho, (size_t)m * m * 8, x->stream));
+  HIPCHK(d2h(v3, x->obs.vals + 4, 3 * 8, x->stream));
+  HIPCHK(ssync(x->stream));
+  if (herm) *herm = v3[0];
+  return CTM_OK;
+}
+
+ctm_status ctm_expect(ctm_ctx x, int32_t inst, int32_t sx, int32_t sy, int32_t vertical, const double* h_host,
+                      double* value) {
+  if (!x || !h_host || !value || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  const int m = I.d * I.d;
+  if (!finite_host(h_host, (size_t)m * m)) return fail(CTM_E_NONFINITE, "operator");
+  double* hdev = x->obs.t3;  // staging (m*m doubles fit in the scratch)
+  HIPCHK(h2d(hdev, h_host, (size_t)m * m * 8, x->stream));
+  CHK(rdm(*x, I, pmod(sx, x->Lx), pmod(sy, x->Ly), vertical ? 1 : 0, hdev));
+  double v3[3];
+  HIPCHK(d2h(v3, x->obs.vals + 4, 3 * 8, x->stream));
+  HIPCHK(ssync(x->stream));
+  *value = v3[1];
+  return CTM_OK;
+}
+
+size_t ctm_env_bytes(ctm_ctx x, int32_t inst) {
+  if (!x || inst < 0 || inst >= x->ninst) return 0;
+  Inst& I = x->inst[inst];
+  const size_t npos = (size_t)x->Lx * x->Ly, c2 = (size_t)I.chi * I.chi;
+  return npos * 4 * (c2 + c2 * I.D2) * 8;
+}
+
+ctm_status ctm_env_export(ctm_ctx x, int32_t inst, void* buf, size_t bytes) {
+  if (!x || !buf || bytes != ctm_env_bytes(x, inst)) return fail(CTM_E_INVALID, "args/bytes");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  const int npos = x->Lx * x->Ly;
+  const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+  char* p = (char*)buf;
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.C[c][q], c2 * 8, x->stream)); p += c2 * 8; }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.T[c][q], t3 * 8, x->stream)); p += t3 * 8; }
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes) {
+  if (!x || !buf || bytes != ctm_env_bytes(x, inst)) return fail(CTM_E_INVALID, "args/bytes");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  const int npos = x->Lx * x->Ly;
+  const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+  if (!finite_host((const double*)buf, bytes / 8)) return fail(CTM_E_NONFINITE, "non-finite environment");
+  const char* p = (const char*)buf;
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.C[c][q], p, c2 * 8, x->stream)); p += c2 * 8; }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.T[c][q], p, t3 * 8, x->stream)); p += t3 * 8; }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) I.has_keep[c][q] = false;
+  CHK(corner_spectra(*x, I, true, true));
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_set_timing(ctm_ctx x, int32_t enable) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  x->timing = enable != 0;
+  x->t_corner = x->t_solver = x->t_absorb = 0;
+  x->corner_launches = 0;
+  return CTM_OK;
+}
+
+ctm_status ctm_get_timing(ctm_ctx x, double* c, double* s, double* a, int64_t* nl) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  if (c) *c = x->t_corner;
+  if (s) *s = x->t_solver;
+  if (a) *a = x->t_absorb;
+  if (nl) *nl = x->corner_launches;
+  return CTM_OK;
+}
+
+void ctm_destroy(ctm_ctx x) {
+  if (!x) return;
+  for (int e = 0; e < 4; ++e)
+    if (x->ev[e]) (void)hipEventDestroy(x->ev[e]);
+  delete x;
+}
+
+const char* ctm_last_error(void) { return g_err.c_str(); }
+
+ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const double* const* B_dev,
+                        void* ws_dev, size_t ws_bytes, void* stream, double tol, int32_t max_sweeps,
+                        double* d_out, double* ln_d_out, int32_t* sweeps_out) {
+  if (!cfg || !A_dev || !B_dev || !d_out) return fail(CTM_E_INVALID, "args");
+  if (cfg->n_inst != 1) return fail(CTM_E_INVALID, "fidelity needs n_inst == 1");
+  double kap[3];
+  const double* const* kets[3] = {A_dev, B_dev, A_dev};
+  const double* const* bras[3] = {A_dev, B_dev, B_dev};
+  for (int r = 0; r < 3; ++r) {
+    ctm_ctx x = nullptr;
+    CHK(ctm_init(cfg, kets[r], bras[r], ws_dev, ws_bytes, stream, CTM_INIT_TRIVIAL, nullptr, &x));
+    int32_t sw = 0;
+    double dl = 0;
+    ctm_status s = ctm_converge(x, tol, max_sweeps, 1, &sw, &dl);
+    if (sweeps_out) sweeps_out[r] = sw;
+    if (s != CTM_OK && s != CTM_E_NOCONV) { ctm_destroy(x); return s; }
+    s = ctm_norm(x, 0, &kap[r]);
+    ctm_destroy(x);
+    if (s != CTM_OK) return s;
+  }
+  double dv = std::fabs(kap[2]) / std::sqrt(std::fabs(kap[0] * kap[1]));
+  *d_out = dv;
+  if (ln_d_out) *ln_d_out = std::log(dv);
+  return CTM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// unit-test entry points (include/ctm_debug.h)
+// ===========================================================================
+extern "C" {
+
+ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t K, const void* A,
+                          int32_t transA, const void* B, int32_t transB, void* C, void* stream) {
+  if (M <= 0 || N <= 0 || K <= 0 || ta < 0 || ta > 2 || tc < 0 || tc > 2)
+    return fail(CTM_E_INVALID, "sizes/types");
+  hipStream_t s = (hipStream_t)stream;
+  View va = transA ? transposed(rowmajor(M)) : rowmajor(K);
+  View vb = transB ? transposed(rowmajor(K)) : rowmajor(N);
+  GemmGroup g{};
+  g.A[0] = A;
+  g.B[0] = B;
+  g.C[0] = C;
+  hipError_t e = ctmk::gemm(s, ta, tc, M, N, K, 1.0, va, vb, 0.0, rowmajor(N), g, 1);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "unsupported type pair");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W, double* work,
+                         void* stream) {
+  if (k < 1 || k > 256) return fail(CTM_E_INVALID, "k");
+  hipStream_t s = (hipStream_t)stream;
+  CPtrSet m{};
+  PtrSet u{}, sv{}, w{}, j{};
+  m.p[0] = M; u.p[0] = U; sv.p[0] = S; w.p[0] = W; j.p[0] = work;
+  HIPCHK(jacobi_svd(s, k, m, u, sv, w, j, 1));
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+}  // extern "C"

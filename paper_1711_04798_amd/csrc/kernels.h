@@ -1,0 +1,93 @@
+// Internal launch interface of the gfx950 kernels (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+namespace ctmk {
+
+// ---------------------------------------------------------------------------
+// Host-side bounds registry.  Every launcher checks that each buffer span it
+// is about to touch lies inside a single workspace allocation and refuses the
+// launch otherwise (hipErrorInvalidValue), so an indexing mistake in the host
+// orchestration becomes an error instead of a device fault.  In dry-run mode
+// the launchers only check and never touch the device; this lets the whole
+// orchestration run on a machine without a GPU.
+// ---------------------------------------------------------------------------
+struct Registry {
+  uintptr_t lo = 0, hi = 0;                          // workspace range
+  std::vector<std::pair<uintptr_t, size_t>> allocs;  // sorted by start
+  bool dry = false;
+  int violations = 0;
+  const char* last = nullptr;
+};
+extern thread_local Registry* g_reg;
+// true if [p, p + bytes) lies inside one registered allocation, or entirely
+// outside the workspace (caller-owned buffers)
+bool span_ok(const void* p, size_t bytes, const char* what);
+inline bool dry_run() { return g_reg && g_reg->dry; }
+
+enum DType : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+inline size_t dtype_size(int t) { return t == F64 ? 8 : (t == F32 ? 4 : 2); }
+
+// A matrix view with two-level row and column indices:
+// element (r, c) lives at  base + (r / r_ext) * r_hs + (r % r_ext) * r_ls
+//                               + (c / c_ext) * c_hs + (c % c_ext) * c_ls
+// (in elements).  A plain row-major matrix has r_ext = c_ext = huge,
+// r_ls = ld, c_ls = 1.
+struct View {
+  int64_t r_ext, r_ls, r_hs;
+  int64_t c_ext, c_ls, c_hs;
+};
+
+inline View rowmajor(int64_t ld) { return View{INT64_MAX / 4, ld, 0, INT64_MAX / 4, 1, 0}; }
+inline View colmajor(int64_t ld) { return View{INT64_MAX / 4, 1, 0, INT64_MAX / 4, ld, 0}; }
+inline View transposed(const View& v) {
+  return View{v.c_ext, v.c_ls, v.c_hs, v.r_ext, v.r_ls, v.r_hs};
+}
+// largest element offset a view reaches over rows [0, R) and columns [0, C)
+int64_t view_max(const View& v, int64_t R, int64_t C);
+
+constexpr int MAXG = 16;  // problems per grouped launch
+
+struct GemmGroup {
+  const void* A[MAXG];
+  const void* B[MAXG];
+  void* C[MAXG];
+};
+
+// C = alpha * A(MxK) B(KxN) + beta * C for `groups` problems of identical
+// shape and views, with element types ta (= tb) and tc.  Inputs F64 or F32
+// run on the matching MFMA; BF16 inputs run on the bf16 MFMA with f32
+// accumulation.  beta != 0 reads C.
+hipError_t gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K,
+                double alpha, const View& va, const View& vb, double beta,
+                const View& vc, const GemmGroup& g, int groups);
+
+// out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
+// with type conversion.  out dims are in_dims[perm[i]].
+hipError_t permute(hipStream_t s, int tin, const void* in, int tout, void* out,
+                   int ndim, const int64_t* in_dims, const int* perm);
+
+// Type conversion / copy of n elements.
+hipError_t convert(hipStream_t s, int tin, const void* in, int tout, void* out, int64_t n);
+
+// a[(u,u'),(l,l'),(d,d'),(r,r')] = sum_s A[s,u,l,d,r] * B[s,u',l',d',r'], written in
+// four rotated layouts (see kernels.hip).
+hipError_t double_layer(hipStream_t s, const double* A, const double* B, int d,
+                        int D, double* out_rot[4], int64_t out_layout);
+
+// Sum of squares of n float64 into *out (deterministic two-pass).
+hipError_t sumsq(hipStream_t s, const double* x, int64_t n, double* partial, double* out);
+// x *= 1/sqrt(*nrm2) (if > 0) for n float64.
+hipError_t scale_by_rsqrt(hipStream_t s, double* x, int64_t n, const double* nrm2);
+// Sets *flag = 1 if any of n float64 is not finite (flag must be zeroed first).
+hipError_t nonfinite(hipStream_t s, const double* x, int64_t n, int* flag);
+
+// Fill out with n standard normals from the counter-based generator
+// (splitmix64 of seed + index, Box-Muller).
+hipError_t randn(hipStream_t s, double* out, int64_t n, uint64_t seed);
+
+}  // namespace ctmk

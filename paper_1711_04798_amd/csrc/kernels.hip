@@ -1,0 +1,539 @@
+// gfx950 kernels of the CTM library: generic MFMA GEMM with two-level
+// (layout-fusing) operand views, permutation, conversion, double layer,
+// reductions and the counter-based normal generator.
+#include "kernels.h"
+
+#include <hip/hip_bf16.h>
+#include <algorithm>
+#include <cmath>
+
+namespace ctmk {
+
+thread_local Registry* g_reg = nullptr;
+
+bool span_ok(const void* p, size_t bytes, const char* what) {
+  if (!g_reg || bytes == 0) return true;
+  uintptr_t a = (uintptr_t)p, b = a + bytes;
+  if (b <= g_reg->lo || a >= g_reg->hi) return true;  // not workspace memory
+  auto& v = g_reg->allocs;
+  size_t lo = 0, hi = v.size();
+  while (hi - lo > 1) {
+    size_t mid = (lo + hi) / 2;
+    if (v[mid].first <= a) lo = mid; else hi = mid;
+  }
+  if (!v.empty() && v[lo].first <= a && b <= v[lo].first + v[lo].second) return true;
+  g_reg->violations++;
+  g_reg->last = what;
+  return false;
+}
+
+static int64_t dim_max(int64_t ext, int64_t ls, int64_t hs, int64_t R) {
+  if (R <= 0) return 0;
+  if (ext >= R) return (R - 1) * ls;
+  int64_t q = R / ext, rem = R % ext;
+  int64_t m = (q - 1) * hs + (ext - 1) * ls;
+  if (rem > 0) m = std::max(m, q * hs + (rem - 1) * ls);
+  return m;
+}
+
+int64_t view_max(const View& v, int64_t R, int64_t C) {
+  return dim_max(v.r_ext, v.r_ls, v.r_hs, R) + dim_max(v.c_ext, v.c_ls, v.c_hs, C);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// element access through a two-level view
+// ---------------------------------------------------------------------------
+struct DevView {
+  int32_t r_ext, c_ext;
+  int64_t r_ls, r_hs, c_ls, c_hs;
+};
+
+static DevView dev_view(const View& v, int64_t rows, int64_t cols) {
+  DevView d;
+  d.r_ext = (int32_t)(v.r_ext > rows ? (rows > 0 ? rows : 1) : v.r_ext);
+  d.c_ext = (int32_t)(v.c_ext > cols ? (cols > 0 ? cols : 1) : v.c_ext);
+  d.r_ls = v.r_ls;
+  d.r_hs = v.r_hs;
+  d.c_ls = v.c_ls;
+  d.c_hs = v.c_hs;
+  // when the extent covers the whole dimension the high part is always 0
+  return d;
+}
+
+__device__ __forceinline__ int64_t row_off(const DevView& v, int32_t r) {
+  int32_t h = r / v.r_ext;
+  int32_t l = r - h * v.r_ext;
+  return (int64_t)h * v.r_hs + (int64_t)l * v.r_ls;
+}
+__device__ __forceinline__ int64_t col_off(const DevView& v, int32_t c) {
+  int32_t h = c / v.c_ext;
+  int32_t l = c - h * v.c_ext;
+  return (int64_t)h * v.c_hs + (int64_t)l * v.c_ls;
+}
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef double type; };
+template <> struct Acc<float> { typedef float type; };
+template <> struct Acc<__bf16> { typedef float type; };
+
+template <typename T> __device__ __forceinline__ T from_double(double x);
+template <> __device__ __forceinline__ double from_double<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_double<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ __bf16 from_double<__bf16>(double x) { return (__bf16)(float)x; }
+
+template <typename T> __device__ __forceinline__ double to_double(T x) { return (double)x; }
+template <> __device__ __forceinline__ double to_double<__bf16>(__bf16 x) { return (double)(float)x; }
+
+// ---------------------------------------------------------------------------
+// Generic GEMM.  256 threads = 4 waves in a 2x2 grid; each wave computes a
+// (BM/2) x (BN/2) block from 16x16 MFMA tiles.  Both operand tiles are staged
+// in LDS with k contiguous per row (A) / per column (B).
+//   f64: v_mfma_f64_16x16x4f64   lane l: A[l%16][k0 + l/16], B[k0 + l/16][l%16]
+//   f32: v_mfma_f32_16x16x4f32   same operand layout
+//   bf16: v_mfma_f32_16x16x32_bf16 lane l: A[l%16][8(l/16) .. +7], same for B
+// result: acc[j] = C[4 (l/16) + j][l % 16] (f32, bf16) or C[l/16 + 4 j][l % 16] (f64).
+// ---------------------------------------------------------------------------
+template <typename TI> struct MfmaCfg;
+template <> struct MfmaCfg<double> { static constexpr int KS = 4, BK = 16, PAD = 1; };
+template <> struct MfmaCfg<float> { static constexpr int KS = 4, BK = 16, PAD = 1; };
+template <> struct MfmaCfg<__bf16> { static constexpr int KS = 32, BK = 32, PAD = 8; };
+
+template <typename TI, typename TO, int BM, int BN, bool A_KFAST, bool B_KFAST>
+__global__ void __launch_bounds__(256)
+gemm_kernel(int32_t M, int32_t N, int32_t K, double alpha, double beta,
+            DevView va, DevView vb, DevView vc, GemmGroup g) {
+  typedef typename Acc<TI>::type TA;
+  constexpr int BK = MfmaCfg<TI>::BK;
+  constexpr int KS = MfmaCfg<TI>::KS;
+  constexpr int LDK = BK + MfmaCfg<TI>::PAD;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ TI As[BM * LDK];
+  __shared__ TI Bs[BN * LDK];
+
+  const int gi = blockIdx.z;
+  const TI* __restrict__ A = (const TI*)g.A[gi];
+  const TI* __restrict__ B = (const TI*)g.B[gi];
+  TO* __restrict__ C = (TO*)g.C[gi];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM;
+  const int wn0 = (wave & 1) * WN;
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+
+  // load slots: A tile BM x BK, B tile BN x BK (as B^T)
+  constexpr int AE = (BM * BK) / 256;
+  constexpr int BE = (BN * BK) / 256;
+  int a_r[AE], a_k[AE];
+  int64_t a_roff[AE];
+  bool a_rok[AE];
+#pragma unroll
+  for (int j = 0; j < AE; ++j) {
+    int e = tid + 256 * j;
+    if (A_KFAST) { a_r[j] = e / BK; a_k[j] = e % BK; }
+    else { a_r[j] = e % BM; a_k[j] = e / BM; }
+    int r = m0 + a_r[j];
+    a_rok[j] = r < M;
+    a_roff[j] = a_rok[j] ? row_off(va, r) : 0;
+  }
+  int b_c[BE], b_k[BE];
+  int64_t b_coff[BE];
+  bool b_cok[BE];
+#pragma unroll
+  for (int j = 0; j < BE; ++j) {
+    int e = tid + 256 * j;
+    if (B_KFAST) { b_c[j] = e / BK; b_k[j] = e % BK; }
+    else { b_c[j] = e % BN; b_k[j] = e / BN; }
+    int c = n0 + b_c[j];
+    b_cok[j] = c < N;
+    b_coff[j] = b_cok[j] ? col_off(vb, c) : 0;
+  }
+
+  typedef typename std::conditional<std::is_same<TA, double>::value, v4d, v4f>::type VACC;
+  VACC acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    TI ra[AE], rb[BE];
+#pragma unroll
+    for (int j = 0; j < AE; ++j) {
+      int k = k0 + a_k[j];
+      ra[j] = (a_rok[j] && k < K) ? A[a_roff[j] + col_off(va, k)] : from_double<TI>(0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < BE; ++j) {
+      int k = k0 + b_k[j];
+      rb[j] = (b_cok[j] && k < K) ? B[b_coff[j] + row_off(vb, k)] : from_double<TI>(0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < AE; ++j) As[a_r[j] * LDK + a_k[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < BE; ++j) Bs[b_c[j] * LDK + b_k[j]] = rb[j];
+    __syncthreads();
+
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    if constexpr (std::is_same<TI, __bf16>::value) {
+      v8bf av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const TI* p = &As[(wm0 + i * 16 + lr) * LDK + lk * 8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) av[i][q] = p[q];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const TI* p = &Bs[(wn0 + j * 16 + lr) * LDK + lk * 8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bv[j][q] = p[q];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += KS) {
+        TI av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) av[i] = As[(wm0 + i * 16 + lr) * LDK + ks + lk];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bv[j] = Bs[(wn0 + j * 16 + lr) * LDK + ks + lk];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (std::is_same<TI, double>::value)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+
+  // epilogue.  Result layout: f32/bf16 16x16 variants hold rows 4(l/16)+q,
+  // the f64 variant holds rows (l/16)+4q, column l%16 in both.
+  const int lc = lane & 15;
+  constexpr bool F64OUT = std::is_same<TI, double>::value;
+  const int rbase = F64OUT ? (lane >> 4) : (lane >> 4) * 4;
+  const int rstep = F64OUT ? 4 : 1;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    int c = n0 + wn0 + j * 16 + lc;
+    if (c >= N) continue;
+    int64_t coff = col_off(vc, c);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int r = m0 + wm0 + i * 16 + rbase + rstep * q;
+        if (r >= M) continue;
+        int64_t off = row_off(vc, r) + coff;
+        double v = alpha * (double)acc[i][j][q];
+        if (beta != 0.0) v += beta * to_double<TO>(C[off]);
+        C[off] = from_double<TO>(v);
+      }
+    }
+  }
+}
+
+template <typename TI, typename TO, bool AK, bool BK_>
+static hipError_t launch_gemm_t(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+                                const DevView& da, const DevView& db, double beta,
+                                const DevView& dc, const GemmGroup& g, int groups) {
+  constexpr int BM = 64, BN = 64;
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)groups);
+  hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, AK, BK_>), grid, dim3(256), 0, s,
+                     (int32_t)M, (int32_t)N, (int32_t)K, alpha, beta, da, db, dc, g);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+static hipError_t launch_gemm_ab(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+                                 const View& va, const View& vb, double beta, const View& vc,
+                                 const GemmGroup& g, int groups) {
+  DevView da = dev_view(va, M, K), db = dev_view(vb, K, N), dc = dev_view(vc, M, N);
+  // A is "k fast" when its column (k) stride is 1; B is "k fast" when its row (k) stride is 1
+  bool ak = (va.c_ls == 1);
+  bool bk = (vb.r_ls == 1);
+  if (ak && bk) return launch_gemm_t<TI, TO, true, true>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+  if (ak && !bk) return launch_gemm_t<TI, TO, true, false>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+  if (!ak && bk) return launch_gemm_t<TI, TO, false, true>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+  return launch_gemm_t<TI, TO, false, false>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+}
+
+hipError_t gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, double alpha,
+                const View& va, const View& vb, double beta, const View& vc,
+                const GemmGroup& g, int groups) {
+  if (M <= 0 || N <= 0 || groups <= 0) return hipSuccess;
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || groups > MAXG) return hipErrorInvalidValue;
+  {
+    const size_t ea = dtype_size(ta), ec = dtype_size(tc);
+    const size_t sa = (size_t)(view_max(va, M, K) + 1) * ea, sb = (size_t)(view_max(vb, K, N) + 1) * ea,
+                 sc = (size_t)(view_max(vc, M, N) + 1) * ec;
+    for (int i = 0; i < groups; ++i)
+      if (!span_ok(g.A[i], K > 0 ? sa : 0, "gemm A") || !span_ok(g.B[i], K > 0 ? sb : 0, "gemm B") ||
+          !span_ok(g.C[i], sc, "gemm C"))
+        return hipErrorInvalidValue;
+    if (dry_run()) return hipSuccess;
+  }
+  if (ta == F64 && tc == F64) return launch_gemm_ab<double, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == F32) return launch_gemm_ab<float, float>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == F64) return launch_gemm_ab<float, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == F32) return launch_gemm_ab<__bf16, float>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == F64) return launch_gemm_ab<__bf16, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == BF16) return launch_gemm_ab<__bf16, __bf16>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == BF16) return launch_gemm_ab<float, __bf16>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// permutation with conversion
+// ---------------------------------------------------------------------------
+struct PermArgs {
+  int ndim;
+  int64_t out_dims[8];
+  int64_t in_stride_of_out[8];
+};
+
+template <typename TI, typename TO>
+__global__ void permute_kernel(const TI* __restrict__ in, TO* __restrict__ out, int64_t n, PermArgs p) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e, off = 0;
+    for (int i = p.ndim - 1; i >= 0; --i) {
+      int64_t q = rem / p.out_dims[i];
+      int64_t idx = rem - q * p.out_dims[i];
+      rem = q;
+      off += idx * p.in_stride_of_out[i];
+    }
+    out[e] = from_double<TO>(to_double<TI>(in[off]));
+  }
+}
+
+template <typename TI, typename TO>
+static hipError_t launch_perm(hipStream_t s, const void* in, void* out, int64_t n, const PermArgs& p) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((permute_kernel<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const TI*)in, (TO*)out, n, p);
+  return hipGetLastError();
+}
+
+template <typename TI>
+static hipError_t perm_to(hipStream_t s, const void* in, int tout, void* out, int64_t n, const PermArgs& p) {
+  if (tout == F64) return launch_perm<TI, double>(s, in, out, n, p);
+  if (tout == F32) return launch_perm<TI, float>(s, in, out, n, p);
+  if (tout == BF16) return launch_perm<TI, __bf16>(s, in, out, n, p);
+  return hipErrorInvalidValue;
+}
+
+hipError_t permute(hipStream_t s, int tin, const void* in, int tout, void* out, int ndim,
+                   const int64_t* in_dims, const int* perm) {
+  if (ndim < 1 || ndim > 8) return hipErrorInvalidValue;
+  PermArgs p;
+  p.ndim = ndim;
+  int64_t stride[8];
+  int64_t acc = 1;
+  for (int i = ndim - 1; i >= 0; --i) { stride[i] = acc; acc *= in_dims[i]; }
+  for (int i = 0; i < ndim; ++i) {
+    p.out_dims[i] = in_dims[perm[i]];
+    p.in_stride_of_out[i] = stride[perm[i]];
+  }
+  int64_t n = acc;
+  if (!span_ok(in, n * dtype_size(tin), "permute in") || !span_ok(out, n * dtype_size(tout), "permute out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  if (tin == F64) return perm_to<double>(s, in, tout, out, n, p);
+  if (tin == F32) return perm_to<float>(s, in, tout, out, n, p);
+  if (tin == BF16) return perm_to<__bf16>(s, in, tout, out, n, p);
+  return hipErrorInvalidValue;
+}
+
+hipError_t convert(hipStream_t s, int tin, const void* in, int tout, void* out, int64_t n) {
+  int64_t dims[1] = {n};
+  int perm[1] = {0};
+  return permute(s, tin, in, tout, out, 1, dims, perm);
+}
+
+// ---------------------------------------------------------------------------
+// double layer: for rotation k, out_k[L'][U'][D'][R'] = rot_k(a)[U',L',D',R'],
+// a[U,L,Dn,R] = sum_s A[s,u,l,d,r] B[s,u',l',d',r'], U = u*D + u'.
+// Rotation k = 0..3 counter-clockwise quarter turns:
+//   k=1: U=L', L=D', Dn=R', R=U';  k=2: U=D', L=R', Dn=U', R=L';
+//   k=3: U=R', L=U', Dn=L', R=D'.
+// out_layout != 0 additionally writes the plain a[U][L][Dn][R] to out_rot[...]
+// (handled by the caller through rotation 0 with a transpose).
+// ---------------------------------------------------------------------------
+__global__ void double_layer_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                                    int d, int D, double* o0, double* o1, double* o2, double* o3) {
+  const int D2 = D * D;
+  const int64_t n = (int64_t)D2 * D2 * D2 * D2;
+  const int k = blockIdx.y;
+  double* out = k == 0 ? o0 : (k == 1 ? o1 : (k == 2 ? o2 : o3));
+  const int64_t sD = 1, sR = D, sDn = (int64_t)D * D, sL = (int64_t)D * D * D,
+                sU = (int64_t)D * D * D * D, sS = sU * D;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e;
+    int Rp = rem % D2; rem /= D2;
+    int Dp = rem % D2; rem /= D2;
+    int Up = rem % D2; rem /= D2;
+    int Lp = (int)rem;
+    int U, L, Dn, R;
+    if (k == 0) { U = Up; L = Lp; Dn = Dp; R = Rp; }
+    else if (k == 1) { U = Lp; L = Dp; Dn = Rp; R = Up; }
+    else if (k == 2) { U = Dp; L = Rp; Dn = Up; R = Lp; }
+    else { U = Rp; L = Up; Dn = Lp; R = Dp; }
+    int u = U / D, uu = U % D, l = L / D, ll = L % D, dd = Dn / D, ddd = Dn % D, r = R / D, rr = R % D;
+    int64_t oa = u * sU + l * sL + dd * sDn + r * sR;
+    int64_t ob = uu * sU + ll * sL + ddd * sDn + rr * sR;
+    double acc = 0.0;
+    for (int s = 0; s < d; ++s) acc += A[s * sS + oa] * B[s * sS + ob];
+    out[e] = acc;
+    (void)sD;
+  }
+}
+
+hipError_t double_layer(hipStream_t s, const double* A, const double* B, int d, int D,
+                        double* out_rot[4], int64_t) {
+  int64_t n = (int64_t)D * D * D * D * D * D * D * D;
+  const size_t t5 = (size_t)d * D * D * D * D * 8;
+  if (!span_ok(A, t5, "double layer A") || !span_ok(B, t5, "double layer B")) return hipErrorInvalidValue;
+  for (int r = 0; r < 4; ++r)
+    if (!span_ok(out_rot[r], n * 8, "double layer out")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(double_layer_kernel, dim3((unsigned)blocks, 4), dim3(256), 0, s, A, B, d, D,
+                     out_rot[0], out_rot[1], out_rot[2], out_rot[3]);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void sumsq_partial(const double* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) acc += x[e] * x[e];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void sum_final(const double* __restrict__ part, int np, double* __restrict__ out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+static const int kPartials = 256;
+
+hipError_t sumsq(hipStream_t s, const double* x, int64_t n, double* partial, double* out) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > kPartials) blocks = kPartials;
+  if (blocks < 1) blocks = 1;
+  if (!span_ok(x, n * 8, "sumsq x") || !span_ok(partial, blocks * 8, "sumsq partial") || !span_ok(out, 8, "sumsq out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(sumsq_partial, dim3((unsigned)blocks), dim3(256), 0, s, x, n, partial);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, s, partial, (int)blocks, out);
+  return hipGetLastError();
+}
+
+__global__ void scale_rsqrt_kernel(double* __restrict__ x, int64_t n, const double* __restrict__ nrm2) {
+  double v = *nrm2;
+  if (!(v > 0.0)) return;
+  double f = 1.0 / sqrt(v);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) x[e] *= f;
+}
+
+hipError_t scale_by_rsqrt(hipStream_t s, double* x, int64_t n, const double* nrm2) {
+  if (!span_ok(x, n * 8, "scale x") || !span_ok(nrm2, 8, "scale nrm2")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(scale_rsqrt_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, nrm2);
+  return hipGetLastError();
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) bad |= !isfinite(x[e]);
+  if (bad) *flag = 1;  // benign race: every writer stores the same value
+}
+
+hipError_t nonfinite(hipStream_t s, const double* x, int64_t n, int* flag) {
+  if (!span_ok(x, n * 8, "nonfinite x") || !span_ok(flag, 4, "nonfinite flag")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// counter-based normals: u = splitmix64(seed + 2i), splitmix64(seed + 2i + 1)
+// mapped to (0,1], Box-Muller.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void randn_kernel(double* __restrict__ out, int64_t n, uint64_t seed) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t a = splitmix64(seed + 2ull * (uint64_t)e);
+    uint64_t b = splitmix64(seed + 2ull * (uint64_t)e + 1ull);
+    double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    out[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+hipError_t randn(hipStream_t s, double* out, int64_t n, uint64_t seed) {
+  if (!span_ok(out, n * 8, "randn out")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(randn_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n, seed);
+  return hipGetLastError();
+}
+
+}  // namespace ctmk

@@ -1,0 +1,63 @@
+// Internal float64 solver kernels for the truncated SVD of the half-system
+// product (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ctmk {
+
+// Per-problem solver status, kept in device memory.
+struct SolveStatus {
+  int32_t chi_eff;     // kept singular values (sigma_i > cutoff * sigma_0, i < chi)
+  int32_t converged;   // every kept residual below tol * sigma_0
+  int32_t iters;       // iterations done
+  int32_t chol_fail;   // a Cholesky pivot was not positive
+  double sigma0;       // largest singular value
+  double max_resid;    // largest kept residual / sigma_0
+};
+
+constexpr int MAXP = 8;  // problems per small-kernel launch
+
+struct PtrSet {
+  double* p[MAXP];
+};
+struct CPtrSet {
+  const double* p[MAXP];
+};
+struct StatSet {
+  SolveStatus* p[MAXP];
+};
+
+// For each problem: R^T R = G + s I with s = shift_coef * trace(G) (G is k x k,
+// row-major), written back as R^{-1} (upper triangular, row-major k x k) into
+// Rinv.  G is left unchanged.
+hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
+                          const PtrSet& Rinv, const StatSet& st, int nprob);
+
+// One-sided Jacobi SVD of the k x k row-major matrix M: M W = U S with singular
+// values in descending order.  U, W row-major k x k; S length k.  Columns of U
+// with a zero singular value are zero.  `work` needs 2 k*k doubles per problem.
+hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U,
+                      const PtrSet& S, const PtrSet& W, const PtrSet& work, int nprob);
+
+// Residuals r_i = ||Z_i - S_i V_i|| of the columns of the n x k row-major
+// blocks; sets chi_eff (from S, chi, cutoff), converged (tol), sigma0,
+// max_resid and increments iters.
+hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cutoff, double tol,
+                           const CPtrSet& Z, const CPtrSet& V, const CPtrSet& S,
+                           const StatSet& st, int nprob);
+
+// Wp[j][c] = W[j][c] * (c < chi_eff ? S_c^{-1/2} : 0) for c < chi (k x chi out);
+// a null W stands for the identity.
+hipError_t scale_kept(hipStream_t s, int k, int chi, const CPtrSet& W, const CPtrSet& S,
+                      const PtrSet& Wp, const StatSet& st, int nprob);
+
+// V0 = random normals, then the first keep columns replaced by Vprev's, where
+// keep = prev->chi_eff (0 if prev is null or the context has no previous solve).
+hipError_t warm_start(hipStream_t s, int64_t n, int k, const PtrSet& V0, const CPtrSet& Vprev,
+                      const StatSet& prev, uint64_t seed, int nprob);
+
+// Resets the iteration counters of the statuses.
+hipError_t reset_status(hipStream_t s, const StatSet& st, int nprob);
+
+}  // namespace ctmk

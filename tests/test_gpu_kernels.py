@@ -1,0 +1,81 @@
+"""Kernel-level checks through the unit-test entry points of include/ctm_debug.h:
+the MFMA GEMM (float64, float32, bfloat16 operand layouts) against NumPy, and
+the one-sided Jacobi SVD against LAPACK."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1711_04798_amd import binding
+    lib = binding.load()
+    lib.ctm_debug_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ctm_debug_gemm.restype = ctypes.c_int
+    lib.ctm_debug_svd.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 6
+    lib.ctm_debug_svd.restype = ctypes.c_int
+    return lib
+
+
+TT = {0: "float64", 1: "float32", 2: "bfloat16"}
+
+
+@pytest.mark.parametrize("ta,tc", [(0, 0), (1, 1), (2, 1), (2, 0)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 4), (67, 45, 33), (130, 97, 200)])
+@pytest.mark.parametrize("transA,transB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    A = rng.standard_normal((K, M) if transA else (M, K))
+    B = rng.standard_normal((N, K) if transB else (K, N))
+    dt = getattr(torch, TT[ta])
+    At = torch.tensor(A, dtype=torch.float64).to(dt).cuda().contiguous()
+    Bt = torch.tensor(B, dtype=torch.float64).to(dt).cuda().contiguous()
+    Ct = torch.zeros((M, N), dtype=getattr(torch, TT[tc]), device="cuda")
+    print("gemm case", ta, tc, M, N, K, transA, transB, flush=True)
+    st = lib.ctm_debug_gemm(ta, tc, M, N, K, At.data_ptr(), transA, Bt.data_ptr(), transB, Ct.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    # reference from the operands as rounded to the input type, in float64
+    Ar = At.to(torch.float64).cpu().numpy()
+    Br = Bt.to(torch.float64).cpu().numpy()
+    ref = (Ar.T if transA else Ar) @ (Br.T if transB else Br)
+    got = Ct.to(torch.float64).cpu().numpy()
+    scale = np.abs(Ar).max() * np.abs(Br).max() * K
+    tol = {0: 1e-14, 1: 2e-6, 2: 2e-6}[ta] * scale
+    if tc == 2:
+        tol = max(tol, 1e-2 * np.abs(ref).max())
+    assert np.abs(got - ref).max() <= tol + 1e-300
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 33, 80, 144, 160])
+def test_jacobi_svd(gpu, k):
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(k)
+    # graded spectrum over ~12 decades, as in the projector problem
+    U0, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    V0, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    s0 = 10.0 ** (-12.0 * np.arange(k) / max(k - 1, 1))
+    M = (U0 * s0) @ V0.T
+    Mt = torch.tensor(M, device="cuda")
+    U = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+    W = torch.zeros_like(U)
+    S = torch.zeros(k, dtype=torch.float64, device="cuda")
+    work = torch.zeros(2 * k * k, dtype=torch.float64, device="cuda")
+    print("svd case", k, flush=True)
+    st = lib.ctm_debug_svd(k, Mt.data_ptr(), U.data_ptr(), S.data_ptr(), W.data_ptr(), work.data_ptr(),
+                           torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    S, U, W = S.cpu().numpy(), U.cpu().numpy(), W.cpu().numpy()
+    sref = np.linalg.svd(M, compute_uv=False)
+    # one-sided Jacobi has high relative accuracy on graded matrices
+    assert np.all(np.abs(S - sref) <= 1e-10 * sref + 1e-15 * sref[0])
+    # accumulated rotations: O(k * sweeps * u) loss of orthogonality
+    assert np.abs(W.T @ W - np.eye(k)).max() < 4e-15 * max(k, 8)
+    assert np.abs(M @ W - U * S).max() < 4e-15 * max(k, 8) * sref[0]
