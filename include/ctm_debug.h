@@ -35,6 +35,18 @@ ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t 
 ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W,
                          double* work, void* stream);
 
+/*
+ * Copies an internal buffer of the last column step of instance 0 to the host:
+ *   what = 0: enlarged corner Q_(q+1) of row r, float64 n x n row-major,
+ *             index = 4 r + q (float32 when the context's precision is not fp64);
+ *   what = 1: projector P1 of row r (float64 n x chi), index = r;
+ *   what = 2: projector P2^T of row r (float64 n x chi), index = r;
+ *   what = 3: solver status of row r {chi_eff, converged, iters, chol_fail as
+ *             int32, sigma0, max_resid as float64}, index = r.
+ * `bytes` must equal the buffer size.  Syncs.
+ */
+ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_buf, size_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1655,4 +1655,33 @@ ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, doubl
   return CTM_OK;
 }
 
+ctm_status ctm_debug_dump(ctm_ctx x, int32_t what, int32_t index, void* buf, size_t bytes) {
+  if (!x || !buf) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[0];
+  const int rows = std::max(x->Lx, x->Ly);
+  const size_t n = I.n, chi = I.chi;
+  const void* src = nullptr;
+  size_t need = 0;
+  if (what == 0) {
+    if (index < 0 || index >= 4 * rows) return fail(CTM_E_INVALID, "index");
+    src = x->rows[index / 4].Q[index % 4];
+    need = n * n * dtype_size(x->qt);
+  } else if (what == 1 || what == 2) {
+    if (index < 0 || index >= rows) return fail(CTM_E_INVALID, "index");
+    src = what == 1 ? x->rows[index].P1 : x->rows[index].P2T;
+    need = n * chi * 8;
+  } else if (what == 3) {
+    if (index < 0 || index >= rows) return fail(CTM_E_INVALID, "index");
+    src = x->rows[index].st;
+    need = sizeof(SolveStatus);
+  } else {
+    return fail(CTM_E_INVALID, "what");
+  }
+  if (bytes != need) return fail(CTM_E_INVALID, "bytes must be " + std::to_string(need));
+  HIPCHK(d2h(buf, src, bytes, x->stream));
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
 }  // extern "C"

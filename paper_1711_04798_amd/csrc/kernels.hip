@@ -387,8 +387,9 @@ __global__ void double_layer_kernel(const double* __restrict__ A, const double* 
   const int64_t n = (int64_t)D2 * D2 * D2 * D2;
   const int k = blockIdx.y;
   double* out = k == 0 ? o0 : (k == 1 ? o1 : (k == 2 ? o2 : o3));
-  const int64_t sD = 1, sR = D, sDn = (int64_t)D * D, sL = (int64_t)D * D * D,
-                sU = (int64_t)D * D * D * D, sS = sU * D;
+  // strides of A[s][u][l][d][r] (d x D x D x D x D, row-major)
+  const int64_t sR = 1, sDn = D, sL = (int64_t)D * D, sU = (int64_t)D * D * D,
+                sS = (int64_t)D * D * D * D;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t rem = e;
@@ -407,7 +408,6 @@ __global__ void double_layer_kernel(const double* __restrict__ A, const double* 
     double acc = 0.0;
     for (int s = 0; s < d; ++s) acc += A[s * sS + oa] * B[s * sS + ob];
     out[e] = acc;
-    (void)sD;
   }
 }
 

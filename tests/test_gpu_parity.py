@@ -4,6 +4,12 @@ and the nearest-neighbour density matrices.
 
 Environment tensors are defined only up to gauge, so the comparison is on
 gauge-invariant quantities: normalised corner spectra, kappa, rho.
+
+Tolerances: kappa and rho to 1e-10 relative.  Lock-step corner spectra to
+1e-8 absolute: when the smallest kept singular value of the half-system
+product is ~1e-8 of the largest (c0, seed 0), float64 fixes that singular
+direction only to ~u / (sigma_chi / sigma_1), in the oracle's dense SVD as in
+the GPU solver, and the corners inherit it.
 """
 import numpy as np
 import pytest
@@ -50,7 +56,7 @@ def test_c0_lockstep(gpu, seed):
     and both nearest-neighbour density matrices after 10 sweeps."""
     A, = synth.cell_tensors(seed, 2, 2, 1)
     print("case c0 seed", seed, flush=True)
-    g, cell, env, worst = _lockstep([A], 1, 1, [0], 16, 10, 1e-9)
+    g, cell, env, worst = _lockstep([A], 1, 1, [0], 16, 10, 1e-8)
     ko, kg = oobs.kappa(cell, env), g.norm()
     assert abs(kg - ko) <= 1e-10 * abs(ko)
     for vert in (False, True):
@@ -66,7 +72,7 @@ def test_checkerboard_small_lockstep(gpu):
     """2x2 checkerboard, d=2, D=2, chi=8 (several positions, both projector rows)."""
     A, B = synth.cell_tensors(3, 2, 2, 2)
     print("case 2x2 small", flush=True)
-    g, cell, env, worst = _lockstep([A, B], 2, 2, [0, 1, 1, 0], 8, 6, 1e-9)
+    g, cell, env, worst = _lockstep([A, B], 2, 2, [0, 1, 1, 0], 8, 6, 1e-8)
     ko, kg = oobs.kappa(cell, env), g.norm()
     assert abs(kg - ko) <= 1e-10 * abs(ko)
     for (x, y, v) in [(0, 0, False), (1, 0, False), (0, 1, True), (1, 1, True)]:
