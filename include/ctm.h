@@ -177,12 +177,20 @@ size_t ctm_env_bytes(ctm_ctx ctx, int32_t inst);
 ctm_status ctm_env_export(ctm_ctx ctx, int32_t inst, void* host_buf, size_t bytes);
 ctm_status ctm_env_import(ctm_ctx ctx, int32_t inst, const void* host_buf, size_t bytes);
 
-/* Kernel-time accounting of the last calls: seconds spent in enlarged-corner
- * contractions, projector solver, absorption (HIP events on the context's
- * stream; only filled when timing is enabled with ctm_set_timing). */
+/*
+ * Kernel-time accounting, enabled (and reset) by ctm_set_timing.  While
+ * enabled, HIP events on the context's stream bracket every column step's
+ * phases and every launch of the enlarged-corner double-layer contraction.
+ * ctm_get_timing fills v[8]:
+ *   v[0] seconds in enlarged corners, v[1] in the projector solver,
+ *   v[2] in absorption, v[3] seconds inside the double-layer contraction
+ *   launches of the enlarged corners, v[4] number of those launches, v[5]
+ *   their algorithmic flop (2 chi^2 D^8 per corner), v[6] corner-chain
+ *   launches, v[7] column steps timed.
+ * Timing synchronises the stream around each timed launch.
+ */
 ctm_status ctm_set_timing(ctm_ctx ctx, int32_t enable);
-ctm_status ctm_get_timing(ctm_ctx ctx, double* corner_s, double* solver_s,
-                          double* absorb_s, int64_t* corner_launches);
+ctm_status ctm_get_timing(ctm_ctx ctx, double* v);
 
 /* Releases the context (not the workspace). */
 void ctm_destroy(ctm_ctx ctx);

@@ -74,7 +74,7 @@ def load(path=LIB_PATH):
     lib.ctm_env_export.argtypes = [VP, I32, VP, SZ]
     lib.ctm_env_import.argtypes = [VP, I32, VP, SZ]
     lib.ctm_set_timing.argtypes = [VP, I32]
-    lib.ctm_get_timing.argtypes = [VP, P(F64), P(F64), P(F64), P(ctypes.c_int64)]
+    lib.ctm_get_timing.argtypes = [VP, P(F64)]
     lib.ctm_destroy.argtypes = [VP]
     lib.ctm_destroy.restype = None
     lib.ctm_last_error.argtypes = []
@@ -230,10 +230,11 @@ class CTM:
         _check(load().ctm_set_timing(self.ctx, int(on)))
 
     def timing(self):
-        c, s, a = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        nl = ctypes.c_int64()
-        _check(load().ctm_get_timing(self.ctx, ctypes.byref(c), ctypes.byref(s), ctypes.byref(a), ctypes.byref(nl)))
-        return {"corner_s": c.value, "solver_s": s.value, "absorb_s": a.value, "corner_launches": nl.value}
+        v = (ctypes.c_double * 8)()
+        _check(load().ctm_get_timing(self.ctx, v))
+        keys = ["corner_s", "solver_s", "absorb_s", "stage3_s", "stage3_launches", "stage3_flop",
+                "corner_launches", "moves"]
+        return dict(zip(keys, list(v)))
 
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:

@@ -183,9 +183,9 @@ struct ctm_ctx_s {
   double* spec_tmp_J = nullptr;
   size_t ws_need = 0;
   bool timing = false;
-  double t_corner = 0, t_solver = 0, t_absorb = 0;
-  int64_t corner_launches = 0;
-  hipEvent_t ev[4] = {};
+  double t_corner = 0, t_solver = 0, t_absorb = 0, t_stage3 = 0, stage3_flop = 0;
+  int64_t corner_launches = 0, stage3_launches = 0, moves = 0;
+  hipEvent_t ev[6] = {};
   Registry reg;
 };
 
@@ -409,7 +409,14 @@ struct CornerJob {
   void *X, *Y, *Q;
 };
 
-ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs) {
+struct Stage3Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  double* acc = nullptr;
+  int64_t* count = nullptr;
+};
+
+ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs,
+                        const Stage3Timer* tm = nullptr) {
   const int64_t c = chi, n = (int64_t)chi * D2;
   for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
     size_t j1 = std::min(jobs.size(), j0 + MAXG);
@@ -426,8 +433,18 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
     View va = view2(c, 1, (int64_t)D2 * D2 * c, BIG, c, 0);
     // C: rows m = (g, b) -> g*D2*n + b*D2; cols (dn, r) -> dn*n + r
     View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
+    const bool timed = tm && tm->a && !dry_run();
+    if (timed) HIPCHK(hipEventRecord(tm->a, s));
     CHK(gemm_run(s, tin, tq, c * c, (int64_t)D2 * D2, (int64_t)D2 * D2, va, rowmajor((int64_t)D2 * D2),
                  vc, g3));
+    if (timed) {
+      HIPCHK(hipEventRecord(tm->b, s));
+      HIPCHK(hipEventSynchronize(tm->b));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
+      *tm->acc += ms * 1e-3;
+      *tm->count += 1;
+    }
   }
   return CTM_OK;
 }
@@ -740,8 +757,19 @@ ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
       jobs.push_back(j);
     }
   }
-  CHK(corner_chain(s, x.wt, x.qt, I.chi, I.D2, jobs));
+  Stage3Timer tm;
+  if (x.timing) {
+    tm.a = x.ev[4];
+    tm.b = x.ev[5];
+    tm.acc = &x.t_stage3;
+    tm.count = &x.stage3_launches;
+    // algorithmic work of the (l,u)-contraction with the double layer:
+    // 2 chi^2 D^8 flop per corner
+    x.stage3_flop += 2.0 * (double)I.chi * I.chi * (double)I.D2 * I.D2 * I.D2 * I.D2 * (double)jobs.size();
+  }
+  CHK(corner_chain(s, x.wt, x.qt, I.chi, I.D2, jobs, x.timing ? &tm : nullptr));
   x.corner_launches += 3 * ((jobs.size() + MAXG - 1) / MAXG);
+  x.moves += 1;
   ev_record(x, 1);
   // projectors, all rows together
   std::vector<SolveRow> rows;
@@ -1415,7 +1443,7 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
     if (st != CTM_OK) return cleanup(st);
   }
   if (!dry_run())
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 6; ++e)
       if (hipEventCreate(&x->ev[e]) != hipSuccess) return cleanup(fail(CTM_E_HIP, "event"));
   *out = x;
   return CTM_OK;
@@ -1569,23 +1597,27 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
 ctm_status ctm_set_timing(ctm_ctx x, int32_t enable) {
   if (!x) return fail(CTM_E_INVALID, "null ctx");
   x->timing = enable != 0;
-  x->t_corner = x->t_solver = x->t_absorb = 0;
-  x->corner_launches = 0;
+  x->t_corner = x->t_solver = x->t_absorb = x->t_stage3 = x->stage3_flop = 0;
+  x->corner_launches = x->stage3_launches = x->moves = 0;
   return CTM_OK;
 }
 
-ctm_status ctm_get_timing(ctm_ctx x, double* c, double* s, double* a, int64_t* nl) {
-  if (!x) return fail(CTM_E_INVALID, "null ctx");
-  if (c) *c = x->t_corner;
-  if (s) *s = x->t_solver;
-  if (a) *a = x->t_absorb;
-  if (nl) *nl = x->corner_launches;
+ctm_status ctm_get_timing(ctm_ctx x, double* v) {
+  if (!x || !v) return fail(CTM_E_INVALID, "args");
+  v[0] = x->t_corner;
+  v[1] = x->t_solver;
+  v[2] = x->t_absorb;
+  v[3] = x->t_stage3;
+  v[4] = (double)x->stage3_launches;
+  v[5] = x->stage3_flop;
+  v[6] = (double)x->corner_launches;
+  v[7] = (double)x->moves;
   return CTM_OK;
 }
 
 void ctm_destroy(ctm_ctx x) {
   if (!x) return;
-  for (int e = 0; e < 4; ++e)
+  for (int e = 0; e < 6; ++e)
     if (x->ev[e]) (void)hipEventDestroy(x->ev[e]);
   delete x;
 }
