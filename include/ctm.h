@@ -74,8 +74,10 @@ typedef struct {
   int32_t prec;            /* ctm_prec of the bulk contractions                    */
   int32_t svd_oversample;  /* extra subspace columns p (default 16)                */
   int32_t svd_max_iters;   /* subspace iterations per projector (default 30)       */
-  double svd_resid_tol;    /* stop when every kept residual < tol*sigma_1; 0 = run
-                              exactly svd_max_iters iterations (default 1e-13)     */
+  double svd_resid_tol;    /* > 0: Rayleigh-Ritz every iteration, stop when every
+                              kept residual < tol*sigma_1 (default 1e-13);
+                              0: exactly svd_max_iters iterations, Rayleigh-Ritz
+                              only in the last                                    */
   double svd_cutoff;       /* keep sigma_i > cutoff*sigma_1 (default 1e-12)         */
   uint64_t seed;           /* seeds the random start of the subspace iteration     */
 } ctm_config;

@@ -28,9 +28,9 @@ ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t 
                           void* C, void* stream);
 
 /*
- * One-sided Jacobi SVD of the k x k float64 row-major matrix M (1 <= k <= 256):
+ * One-sided Jacobi SVD of the k x k float64 row-major matrix M (1 <= k <= 192):
  * M W = U diag(S), singular values descending.  U, W: k x k row-major; S: k.
- * work: 2 k^2 doubles.
+ * work: 3 k^2 doubles.
  */
 ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W,
                          double* work, void* stream);
@@ -42,7 +42,8 @@ ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, doubl
  *   what = 1: projector P1 of row r (float64 n x chi), index = r;
  *   what = 2: projector P2^T of row r (float64 n x chi), index = r;
  *   what = 3: solver status of row r {chi_eff, converged, iters, chol_fail as
- *             int32, sigma0, max_resid as float64}, index = r.
+ *             int32, sigma0, max_resid as float64, Jacobi sweeps of the last
+ *             Rayleigh-Ritz step, padding as int32} (40 bytes), index = r.
  * `bytes` must equal the buffer size.  Syncs.
  */
 ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_buf, size_t bytes);

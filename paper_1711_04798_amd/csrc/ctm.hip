@@ -177,6 +177,8 @@ struct ctm_ctx_s {
   std::vector<Inst> inst;
   Row rows[MAXROWS];
   Obs obs;
+  double* splitk = nullptr;      // split-K partial products of the solver
+  int64_t splitk_elems = 0;
   double* spec_tmp_U = nullptr;  // corner SVD scratch
   double* spec_tmp_W = nullptr;
   double* spec_tmp_S = nullptr;
@@ -263,7 +265,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     }
     R.G = ar.take<double>(k * k); R.Rinv = ar.take<double>(k * k); R.Rm = ar.take<double>(k * k);
     R.UR = ar.take<double>(k * k); R.WR = ar.take<double>(k * k); R.S = ar.take<double>(k);
-    R.Wp = ar.take<double>(k * chi); R.Up = ar.take<double>(k * chi); R.jw = ar.take<double>(2 * k * k);
+    R.Wp = ar.take<double>(k * chi); R.Up = ar.take<double>(k * chi); R.jw = ar.take<double>(3 * k * k);
     R.st = ar.take<SolveStatus>(1);
     R.P1 = ar.take<double>(n * chi); R.P2T = ar.take<double>(n * chi);
     R.P1w = (x.wt == F64) ? (void*)R.P1 : ar.take_bytes(n * chi * ws);
@@ -273,6 +275,9 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
     R.red = ar.take<double>(256); R.sums = ar.take<double>(8);
   }
+  // split-K partials of the k x n x k products (all rows in one launch)
+  x.splitk_elems = (int64_t)64 * k * k * rows;
+  x.splitk = ar.take<double>((size_t)x.splitk_elems);
   // corner-spectrum SVD scratch (8 corners per launch)
   x.spec_tmp_U = ar.take<double>(8 * c2);
   x.spec_tmp_W = ar.take<double>(8 * c2);
@@ -380,6 +385,12 @@ ctm_status gemm_run(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t
                     const View& vb, const View& vc, const G& g, double alpha = 1.0,
                     double beta = 0.0) {
   HIPCHK(ctmk::gemm(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g.g, g.n));
+  return CTM_OK;
+}
+
+ctm_status gemm_sk(ctm_ctx_s& x, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                   const View& vc, const G& g) {
+  HIPCHK(ctmk::gemm_splitk(x.stream, M, N, K, 1.0, va, vb, 0.0, vc, g.g, g.n, x.splitk, x.splitk_elems));
   return CTM_OK;
 }
 
@@ -528,7 +539,7 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
       Ri.p[r] = rows[r].R->Rinv;
       st.p[r] = rows[r].R->st;
     }
-    CHK(gemm_run(s, F64, F64, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
+    CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
     HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P));
     G gm;
     for (size_t r = 0; r < P; ++r) gm.add(Y[r], rows[r].R->Rinv, rows[r].R->tmp);
@@ -572,24 +583,37 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
   const int maxit = std::max(1, c.svd_max_iters);
   const bool adaptive = c.svd_resid_tol > 0;
   std::vector<SolveStatus> hst(P);
-  for (int it = 0; it < maxit; ++it) {
+  auto copy_blocks = [&](std::vector<double*>& dst, const std::vector<double*>& src) -> ctm_status {
+    for (size_t r = 0; r < P; ++r) HIPCHK(d2d(dst[r], src[r], (size_t)n * k * 8, s));
+    return CTM_OK;
+  };
+  // One Rayleigh-Ritz iteration: Y = N V = Q R, R = U_R S W_R^T, then the
+  // left vectors U = Q U_R, right vectors V' = V W_R, Z = N^T U and the
+  // residuals |Z_i - S_i V'_i|.
+  auto rr_iteration = [&]() -> ctm_status {
     CHK(napply(x, n, k, rows, V, Yb, LV, false));          // Y = N V, LV = Lh^T V
-    for (size_t r = 0; r < P; ++r)
-      HIPCHK(d2d(Qb[r], Yb[r], (size_t)n * k * 8, s));
+    CHK(copy_blocks(Qb, Yb));
     CHK(orthonormalize(x, n, k, rows, Qb));                // Q = orth(Y)
     {
       G g;
       for (size_t r = 0; r < P; ++r) g.add(Qb[r], Yb[r], rows[r].R->Rm);
-      CHK(gemm_run(s, F64, F64, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), g));
+      CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), g));
     }
     {
       CPtrSet M{};
       PtrSet U{}, S{}, W{}, J{};
+      // R is upper triangular with a graded diagonal: rotating its rows (the
+      // columns of R^T) converges in a few sweeps (preconditioned Jacobi,
+      // Drmac & Veselic 2008).  R^T W = X S gives R = W S X^T, so U_R = W
+      // and W_R = X.
+      StatSet stj{};
       for (size_t r = 0; r < P; ++r) {
         Row* R = rows[r].R;
-        M.p[r] = R->Rm; U.p[r] = R->UR; S.p[r] = R->S; W.p[r] = R->WR; J.p[r] = R->jw;
+        M.p[r] = R->Rm; U.p[r] = R->WR; S.p[r] = R->S; W.p[r] = R->UR; J.p[r] = R->jw;
+        stj.p[r] = R->st;
       }
-      HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P));     // R = U_R S W_R^T
+      // directions 100x below the cutoff can never be kept
+      HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P, true, true, &stj, 1e-2 * c.svd_cutoff));
     }
     {
       G gu, gv, gl;
@@ -602,8 +626,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gu));
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gv));
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gl));
-      for (size_t r = 0; r < P; ++r)
-        HIPCHK(d2d(LV[r], rows[r].R->tmp, (size_t)n * k * 8, s));
+      for (size_t r = 0; r < P; ++r) HIPCHK(d2d(LV[r], rows[r].R->tmp, (size_t)n * k * 8, s));
     }
     CHK(napply(x, n, k, rows, Ub, Z, UU, true));           // Z = N^T U, UU = Uh U
     {
@@ -615,19 +638,32 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
       HIPCHK(residual_status(s, n, k, chi, c.svd_cutoff, c.svd_resid_tol > 0 ? c.svd_resid_tol : 0.0,
                              Zs, Vs, Ss, st, (int)P));
     }
-    if (it + 1 >= maxit) break;
-    if (adaptive) {
+    return CTM_OK;
+  };
+  if (adaptive) {
+    // Rayleigh-Ritz every iteration; stop when all kept residuals are small
+    for (int it = 0; it < maxit; ++it) {
+      CHK(rr_iteration());
+      if (it + 1 >= maxit) break;
       bool all = true;
-      for (size_t r = 0; r < P; ++r) {
-        HIPCHK(d2h(&hst[r], rows[r].R->st, sizeof(SolveStatus), s));
-      }
+      for (size_t r = 0; r < P; ++r) HIPCHK(d2h(&hst[r], rows[r].R->st, sizeof(SolveStatus), s));
       HIPCHK(ssync(s));
       for (size_t r = 0; r < P; ++r) all = all && hst[r].converged;
       if (all) break;
+      CHK(copy_blocks(V, Z));
+      CHK(orthonormalize(x, n, k, rows, V));
     }
-    for (size_t r = 0; r < P; ++r)
-      HIPCHK(d2d(V[r], Z[r], (size_t)n * k * 8, s));
-    CHK(orthonormalize(x, n, k, rows, V));
+  } else {
+    // fixed count: plain subspace iterations V <- orth(N^T orth(N V)), then
+    // one Rayleigh-Ritz step
+    for (int it = 0; it + 1 < maxit; ++it) {
+      CHK(napply(x, n, k, rows, V, Yb, LV, false));
+      CHK(orthonormalize(x, n, k, rows, Yb));
+      CHK(napply(x, n, k, rows, Yb, Z, UU, true));
+      CHK(copy_blocks(V, Z));
+      CHK(orthonormalize(x, n, k, rows, V));
+    }
+    CHK(rr_iteration());
   }
   // projectors
   {
@@ -870,7 +906,8 @@ ctm_status corner_spectra(ctm_ctx_s& x, Inst& I, bool first, bool commit) {
       S.p[c - c0] = I.spec_new + (size_t)c * chi;
       J.p[c - c0] = x.spec_tmp_J + (size_t)(c - c0) * 2 * chi * chi;
     }
-    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, c1 - c0));
+    // corner singular values far below the solver cutoff carry no information
+    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, c1 - c0, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff));
   }
   HIPCHK(spans({{I.spec_new, (size_t)nc * chi * 8}, {I.spec_old, (size_t)nc * chi * 8}, {I.delta, 8},
                 {I.flag, 4}}, "spectra"));
@@ -925,7 +962,7 @@ ctm_status validate(const ctm_config* c) {
     if (n * n > (int64_t)INT32_MAX * 4) return fail(CTM_E_INVALID, "chi*D^2 too large");
     int k = std::min<int64_t>(n, chi + std::max(0, c->svd_oversample));
     if (k > 176) return fail(CTM_E_INVALID, "chi + oversample must be <= 176");
-    if (chi > 256) return fail(CTM_E_INVALID, "chi must be <= 256");
+    if (chi > 192) return fail(CTM_E_INVALID, "chi must be <= 192");
   }
   return CTM_OK;
 }
@@ -1677,7 +1714,7 @@ ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t 
 
 ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W, double* work,
                          void* stream) {
-  if (k < 1 || k > 256) return fail(CTM_E_INVALID, "k");
+  if (k < 1 || k > 192) return fail(CTM_E_INVALID, "k");
   hipStream_t s = (hipStream_t)stream;
   CPtrSet m{};
   PtrSet u{}, sv{}, w{}, j{};

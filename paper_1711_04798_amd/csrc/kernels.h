@@ -66,6 +66,14 @@ hipError_t gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K,
                 double alpha, const View& va, const View& vb, double beta,
                 const View& vc, const GemmGroup& g, int groups);
 
+// float64 C = alpha A B + beta C with K split over slices that write partial
+// products to `scratch` (needs slices * M * N * groups doubles; the slice
+// count is chosen to fill the GPU and shrunk to fit the scratch), summed in
+// a fixed order.  Falls back to gemm() when one slice suffices.
+hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const View& va,
+                       const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
+                       double* scratch, int64_t scratch_elems);
+
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].
 hipError_t permute(hipStream_t s, int tin, const void* in, int tout, void* out,

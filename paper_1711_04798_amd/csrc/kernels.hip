@@ -105,7 +105,7 @@ template <> struct MfmaCfg<__bf16> { static constexpr int KS = 32, BK = 32, PAD 
 template <typename TI, typename TO, int BM, int BN, bool A_KFAST, bool B_KFAST>
 __global__ void __launch_bounds__(256)
 gemm_kernel(int32_t M, int32_t N, int32_t K, double alpha, double beta,
-            DevView va, DevView vb, DevView vc, GemmGroup g) {
+            DevView va, DevView vb, DevView vc, GemmGroup g, int32_t ksplit) {
   typedef typename Acc<TI>::type TA;
   constexpr int BK = MfmaCfg<TI>::BK;
   constexpr int KS = MfmaCfg<TI>::KS;
@@ -115,10 +115,20 @@ gemm_kernel(int32_t M, int32_t N, int32_t K, double alpha, double beta,
   __shared__ TI As[BM * LDK];
   __shared__ TI Bs[BN * LDK];
 
-  const int gi = blockIdx.z;
+  // blockIdx.z = problem * ksplit + slice; with ksplit > 1 each slice sums a
+  // contiguous K range into its own row-major M x N partial behind g.C[problem]
+  const int gi = blockIdx.z / ksplit;
+  const int sp = blockIdx.z - gi * ksplit;
   const TI* __restrict__ A = (const TI*)g.A[gi];
   const TI* __restrict__ B = (const TI*)g.B[gi];
   TO* __restrict__ C = (TO*)g.C[gi];
+  int kbeg = 0, kend = K;
+  if (ksplit > 1) {
+    const int kc = (((K + ksplit - 1) / ksplit) + BK - 1) / BK * BK;
+    kbeg = sp * kc;
+    kend = min(K, kbeg + kc);
+    C += (int64_t)sp * M * N;
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -165,17 +175,17 @@ gemm_kernel(int32_t M, int32_t N, int32_t K, double alpha, double beta,
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[i][j][q] = 0;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     TI ra[AE], rb[BE];
 #pragma unroll
     for (int j = 0; j < AE; ++j) {
       int k = k0 + a_k[j];
-      ra[j] = (a_rok[j] && k < K) ? A[a_roff[j] + col_off(va, k)] : from_double<TI>(0.0);
+      ra[j] = (a_rok[j] && k < kend) ? A[a_roff[j] + col_off(va, k)] : from_double<TI>(0.0);
     }
 #pragma unroll
     for (int j = 0; j < BE; ++j) {
       int k = k0 + b_k[j];
-      rb[j] = (b_cok[j] && k < K) ? B[b_coff[j] + row_off(vb, k)] : from_double<TI>(0.0);
+      rb[j] = (b_cok[j] && k < kend) ? B[b_coff[j] + row_off(vb, k)] : from_double<TI>(0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -259,7 +269,71 @@ static hipError_t launch_gemm_t(hipStream_t s, int64_t M, int64_t N, int64_t K, 
   constexpr int BM = 64, BN = 64;
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)groups);
   hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, AK, BK_>), grid, dim3(256), 0, s,
-                     (int32_t)M, (int32_t)N, (int32_t)K, alpha, beta, da, db, dc, g);
+                     (int32_t)M, (int32_t)N, (int32_t)K, alpha, beta, da, db, dc, g, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// split-K float64 GEMM for short-and-wide products (k x n times n x k): every
+// K slice writes a partial product, then one kernel sums the slices in a
+// fixed order (deterministic) and applies alpha, beta and the output view.
+// ---------------------------------------------------------------------------
+__global__ void splitk_reduce_kernel(const double* __restrict__ part, int ksplit, int32_t M, int32_t N,
+                                     double alpha, double beta, DevView vc, GemmGroup g) {
+  const int gi = blockIdx.y;
+  const double* p = part + (int64_t)gi * ksplit * M * N;
+  double* C = (double*)g.C[gi];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)M * N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int sp = 0; sp < ksplit; ++sp) acc += p[(int64_t)sp * M * N + e];
+    int r = (int)(e / N), c = (int)(e % N);
+    int64_t off = row_off(vc, r) + col_off(vc, c);
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * C[off];
+    C[off] = v;
+  }
+}
+
+hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const View& va,
+                       const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
+                       double* scratch, int64_t scratch_elems) {
+  if (M <= 0 || N <= 0 || groups <= 0) return hipSuccess;
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * groups;
+  int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 64));
+  while (ksplit > 1 && ksplit * M * N * groups > scratch_elems) ksplit /= 2;
+  if (ksplit <= 1) return gemm(s, F64, F64, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || groups > MAXG) return hipErrorInvalidValue;
+  const size_t sa = (size_t)(view_max(va, M, K) + 1) * 8, sb = (size_t)(view_max(vb, K, N) + 1) * 8,
+               sc = (size_t)(view_max(vc, M, N) + 1) * 8;
+  for (int i = 0; i < groups; ++i)
+    if (!span_ok(g.A[i], sa, "splitk A") || !span_ok(g.B[i], sb, "splitk B") || !span_ok(g.C[i], sc, "splitk C"))
+      return hipErrorInvalidValue;
+  if (!span_ok(scratch, (size_t)ksplit * M * N * groups * 8, "splitk scratch")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  GemmGroup gp = g;
+  for (int i = 0; i < groups; ++i) gp.C[i] = scratch + (int64_t)i * ksplit * M * N;
+  DevView da = dev_view(va, M, K), db = dev_view(vb, K, N), dc = dev_view(rowmajor(N), M, N);
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)(groups * ksplit));
+  bool ak = (va.c_ls == 1), bk = (vb.r_ls == 1);
+  if (ak && bk)
+    hipLaunchKernelGGL((gemm_kernel<double, double, 64, 64, true, true>), grid, dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit);
+  else if (ak)
+    hipLaunchKernelGGL((gemm_kernel<double, double, 64, 64, true, false>), grid, dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit);
+  else if (bk)
+    hipLaunchKernelGGL((gemm_kernel<double, double, 64, 64, false, true>), grid, dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit);
+  else
+    hipLaunchKernelGGL((gemm_kernel<double, double, 64, 64, false, false>), grid, dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  DevView dvc = dev_view(vc, M, N);
+  int64_t blocks = std::min<int64_t>(1024, (M * N + 255) / 256);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks, groups), dim3(256), 0, s, scratch, (int)ksplit,
+                     (int32_t)M, (int32_t)N, alpha, beta, dvc, g);
   return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@ struct SolveStatus {
   int32_t chol_fail;   // a Cholesky pivot was not positive
   double sigma0;       // largest singular value
   double max_resid;    // largest kept residual / sigma_0
+  int32_t jsweeps;     // Jacobi sweeps of the last Rayleigh-Ritz step
+  int32_t pad;
 };
 
 constexpr int MAXP = 8;  // problems per small-kernel launch
@@ -34,11 +36,18 @@ struct StatSet {
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob);
 
-// One-sided Jacobi SVD of the k x k row-major matrix M: M W = U S with singular
+// One-sided Jacobi SVD of the k x k row-major matrix M (k <= 192): M W = U S with singular
 // values in descending order.  U, W row-major k x k; S length k.  Columns of U
-// with a zero singular value are zero.  `work` needs 2 k*k doubles per problem.
+// with a zero singular value are zero.  `work` needs 3 k*k doubles per problem
+// (2 k*k when only the singular values are wanted; U and W are then untouched).
+// With transpose_in the rotations act on the columns of M^T (the rows of M):
+// M^T W = U S, i.e. M = W S U^T.  Columns whose norm stays below noise_rel
+// (at least 4 u) times the largest are left unrotated; their singular values
+// and vectors are then only bounds.
 hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U,
-                      const PtrSet& S, const PtrSet& W, const PtrSet& work, int nprob);
+                      const PtrSet& S, const PtrSet& W, const PtrSet& work, int nprob,
+                      bool want_vectors = true, bool transpose_in = false,
+                      const StatSet* st = nullptr, double noise_rel = 0.0);
 
 // Residuals r_i = ||Z_i - S_i V_i|| of the columns of the n x k row-major
 // blocks; sets chi_eff (from S, chi, cutoff), converged (tol), sigma0,

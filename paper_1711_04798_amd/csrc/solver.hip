@@ -14,66 +14,90 @@ namespace ctmk {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int upk(int i, int l, int k) { return i * k - (i * (i - 1)) / 2 + (l - i); }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 chol_shift_inv_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st) {
   extern __shared__ double sm[];
   __shared__ double s_tr;
-  __shared__ double s_piv;
   const int pb = blockIdx.x;
   const double* g = G.p[pb];
   double* ri = Rinv.p[pb];
   const int tid = threadIdx.x, nt = blockDim.x;
 
+  __shared__ double s_red[16];
+  double tr = 0.0;
+  for (int i = tid; i < k; i += nt) tr += g[i * k + i];
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = tr;
+  __syncthreads();
   if (tid == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < k; ++i) tr += g[i * k + i];
-    s_tr = tr;
+    double t = 0.0;
+    for (int w = 0; w < (nt >> 6); ++w) t += s_red[w];
+    s_tr = t;
   }
   __syncthreads();
   const double shift = shift_coef * s_tr;
-  for (int i = 0; i < k; ++i)
-    for (int l = i + tid; l < k; l += nt) sm[upk(i, l, k)] = g[i * k + l] + (l == i ? shift : 0.0);
+  for (int e = tid; e < k * k; e += nt) {
+    int i = e / k, l = e - i * k;
+    if (l >= i) sm[upk(i, l, k)] = g[e] + (l == i ? shift : 0.0);
+  }
   __syncthreads();
 
+  // Right-looking Cholesky, two barriers per column.  Every thread forms the
+  // pivot itself; pivots and their reciprocals live in s_diag / s_rinv, so
+  // the diagonal entry read at the start of step j is never overwritten.
+  __shared__ double s_diag[256], s_rinv[256];
   int fail = 0;
+  const double floor_v = (s_tr > 0.0 ? s_tr : 1.0) * 1e-300;
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      double dj = sm[upk(j, j, k)];
-      double floor_v = (s_tr > 0.0 ? s_tr : 1.0) * 1e-300;
-      if (!(dj > floor_v)) { dj = floor_v; s_piv = -sqrt(dj); }
-      else s_piv = sqrt(dj);
-    }
+    double dj = sm[upk(j, j, k)];
+    if (!(dj > floor_v)) { dj = floor_v; fail = 1; }
+    const double r = sqrt(dj), rinv = 1.0 / r;
+    if (tid == 0) { s_diag[j] = r; s_rinv[j] = rinv; }
+    for (int l = j + 1 + tid; l < k; l += nt) sm[upk(j, l, k)] *= rinv;
     __syncthreads();
-    double r = s_piv;
-    if (r < 0) { fail = 1; r = -r; }
-    for (int l = j + tid; l < k; l += nt) sm[upk(j, l, k)] = (l == j) ? r : sm[upk(j, l, k)] / r;
-    __syncthreads();
-    // trailing update of rows i > j (upper part)
-    // 32 threads per row, nt/32 rows at a time
+    // trailing update of rows i > j (upper part), 32 threads per row
     for (int i = j + 1 + tid / 32; i < k; i += nt / 32) {
       const double rji = sm[upk(j, i, k)];
       for (int l = i + (tid & 31); l < k; l += 32) sm[upk(i, l, k)] -= rji * sm[upk(j, l, k)];
     }
     __syncthreads();
   }
-  // inverse of the upper-triangular R, one column per thread:
-  // column c: x_c = 1/R_cc; x_i = -(sum_{l=i+1..c} R_il x_l) / R_ii, i < c
-  for (int c = tid; c < k; c += nt) {
-    for (int i = c + 1; i < k; ++i) ri[i * k + c] = 0.0;
-    ri[c * k + c] = 1.0 / sm[upk(c, c, k)];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= c; ++l) acc += sm[upk(i, l, k)] * ri[l * k + c];
-      ri[i * k + c] = -acc / sm[upk(i, i, k)];
+  // inverse of the upper-triangular R by back substitution, column c:
+  //   x_c = 1 / R_cc,  x_i = -(sum_{l=i+1..c} R_il x_l) / R_ii  (i < c).
+  // 16 lanes per column, CH = 16 columns at a time; lane j owns the entries
+  // l = j (mod 16) of its column's x (kept in LDS, read back only by the
+  // same lane), partial sums are combined with width-16 shuffles.
+  double* xs = sm + (k * (k + 1)) / 2;  // [CH][k]
+  constexpr int CH = 16;
+  const int grp = tid >> 4, lj = tid & 15;   // threads beyond 16 groups idle here
+  for (int c0 = 0; c0 < k; c0 += CH) {
+    const int c = c0 + grp;
+    const bool active = (c < k) && (grp < CH);
+    double* x = xs + grp * k;
+    for (int i = (active ? c : -1); i >= 0; --i) {
+      double part = 0.0;
+      for (int l = i + 1 + ((lj - (i + 1)) & 15); l <= c; l += 16) part += sm[upk(i, l, k)] * x[l];
+      part += __shfl_xor(part, 8, 16);
+      part += __shfl_xor(part, 4, 16);
+      part += __shfl_xor(part, 2, 16);
+      part += __shfl_xor(part, 1, 16);
+      const double xi = (i == c) ? s_rinv[c] : -part * s_rinv[i];
+      if ((i & 15) == lj) x[i] = xi;
     }
+    if (active)
+      for (int i = lj; i < k; i += 16) ri[i * k + c] = (i <= c) ? x[i] : 0.0;
+    __syncthreads();
   }
   if (fail && tid == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
 }
 
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob) {
-  size_t lds = (size_t)k * (k + 1) / 2 * sizeof(double);
-  if (lds > 160 * 1024 - 64) return hipErrorInvalidValue;
+  // dynamic LDS: packed R plus 16 columns of the inverse; 8 KiB of the CU's
+  // 160 KiB stay for the kernel's static arrays
+  constexpr size_t kMaxDyn = 160 * 1024 - 8192;
+  size_t lds = ((size_t)k * (k + 1) / 2 + (size_t)16 * k) * sizeof(double);
+  if (lds > kMaxDyn) return hipErrorInvalidValue;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(G.p[i], (size_t)k * k * 8, "chol G") || !span_ok(Rinv.p[i], (size_t)k * k * 8, "chol Rinv") ||
         !span_ok(st.p[i], sizeof(SolveStatus), "chol status"))
@@ -82,11 +106,14 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)chol_shift_inv_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
-    if (e != hipSuccess) return e;
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxDyn);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // do not leave the error pending for later calls
+      return e;
+    }
     attr_set = true;
   }
-  hipLaunchKernelGGL(chol_shift_inv_kernel, dim3(nprob), dim3(256), lds, s, k, shift_coef, G, Rinv, st);
+  hipLaunchKernelGGL(chol_shift_inv_kernel, dim3(nprob), dim3(1024), lds, s, k, shift_coef, G, Rinv, st);
   return hipGetLastError();
 }
 
@@ -110,27 +137,79 @@ __device__ __forceinline__ int rr_player(int pos, int r, int kk) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (kk - 1));
 }
 
-__global__ void __launch_bounds__(512)
-jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work) {
+__global__ void __launch_bounds__(1024)
+jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work, int want_vectors,
+                  int transpose_in, StatSet st, double noise_rel) {
   const int pb = blockIdx.x;
-  double* A = work.p[pb];          // column-major k x k, column c at A + c*k
-  double* W = A + (size_t)k * k;   // column-major
+  double* A = work.p[pb];                 // column-major k x k, column c at A + c*k
+  double* Gm = A + (size_t)k * k;         // Gram of the columns at the start of a sweep
+  double* W = Gm + (size_t)k * k;         // column-major right rotations
   const double* M = Min.p[pb];
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   __shared__ int s_rot;
   __shared__ double s_norm[256];
   __shared__ int s_perm[256];
+  __shared__ int s_touched[256];
+  __shared__ unsigned s_sig[256 * 256 / 32];  // bit (p*k+q): pair significant at sweep start
+  __shared__ double s_amax;
 
+  // A holds M (or M^T when transpose_in) column-major
   for (int e = tid; e < k * k; e += nt) {
     int r = e / k, c = e % k;
-    A[c * k + r] = M[e];
-    W[c * k + r] = (r == c) ? 1.0 : 0.0;
+    A[c * k + r] = transpose_in ? M[c * k + r] : M[e];
+    if (want_vectors) W[c * k + r] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int kk = (k + 1) & ~1;  // even number of players; player k (if odd) is a dummy
   const double eps = 2.220446049250313e-16 * (double)k;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  int sweeps_done = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    sweeps_done = sweep + 1;
+    for (int e = tid; e < (k * k + 31) / 32; e += nt) s_sig[e] = 0u;
+    __syncthreads();
+    // Gram of all column pairs (upper triangle incl. diagonal): wave w holds
+    // column p = w, w + nw, ... in registers (lanes over rows, k <= 256) and
+    // forms its dot products with every later column, coalesced.
+    for (int p = wave; p < k; p += nw) {
+      double xp[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        int i = lane + 64 * t;
+        xp[t] = (i < k) ? A[(size_t)p * k + i] : 0.0;
+      }
+      for (int q = p; q < k; ++q) {
+        const double* xq = A + (size_t)q * k;
+        double g = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          int i = lane + 64 * t;
+          if (i < k) g += xp[t] * xq[i];
+        }
+        g = wsum(g);
+        if (lane == 0) Gm[(size_t)p * k + q] = g;
+      }
+    }
+    if (tid < k) s_touched[tid] = 0;
     if (tid == 0) s_rot = 0;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0;
+      for (int c = 0; c < k; ++c) m = fmax(m, Gm[(size_t)c * k + c]);
+      s_amax = m;
+    }
+    __syncthreads();
+    // columns whose norm is below noise_rel (at least 4 u) of the largest are
+    // noise for the caller and are not rotated: they cannot move anything
+    // above that level
+    const double nr = fmax(noise_rel, 4.0 * 1.1102230246251565e-16);
+    const double noise = s_amax * nr * nr;
+    // significance bits of all pairs from the sweep's Gram
+    for (int e = tid; e < k * k; e += nt) {
+      int p = e / k, q = e - p * k;
+      if (q <= p) continue;
+      double a0 = Gm[(size_t)p * k + p], b0 = Gm[(size_t)q * k + q], g0 = Gm[(size_t)p * k + q];
+      if (fmin(a0, b0) > noise && fabs(g0) > eps * sqrt(a0 * b0)) atomicOr(&s_sig[e >> 5], 1u << (e & 31));
+    }
     __syncthreads();
     int rotated = 0;
     for (int r = 0; r < kk - 1; ++r) {
@@ -138,6 +217,11 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
         int p = rr_player(j, r, kk), q = rr_player(kk - 1 - j, r, kk);
         if (p >= k || q >= k) continue;
         if (p > q) { int t = p; p = q; q = t; }
+        if (!s_touched[p] && !s_touched[q]) {
+          // both columns unchanged since the sweep's Gram: screen on it
+          const int e = p * k + q;
+          if (!((s_sig[e >> 5] >> (e & 31)) & 1u)) continue;
+        }
         double* xp = A + (size_t)p * k;
         double* xq = A + (size_t)q * k;
         double a = 0, b = 0, g = 0;
@@ -146,7 +230,7 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
           a += u * u; b += v * v; g += u * v;
         }
         a = wsum(a); b = wsum(b); g = wsum(g);
-        if (fabs(g) > eps * sqrt(a * b) && fabs(g) > 1e-300) {
+        if (fmin(a, b) > noise && fabs(g) > eps * sqrt(a * b)) {
           double zeta = (b - a) / (2.0 * g);
           double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
@@ -155,13 +239,16 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
             xp[i] = c * u - sn * v;
             xq[i] = sn * u + c * v;
           }
-          double* wp = W + (size_t)p * k;
-          double* wq = W + (size_t)q * k;
-          for (int i = lane; i < k; i += 64) {
-            double u = wp[i], v = wq[i];
-            wp[i] = c * u - sn * v;
-            wq[i] = sn * u + c * v;
+          if (want_vectors) {
+            double* wp = W + (size_t)p * k;
+            double* wq = W + (size_t)q * k;
+            for (int i = lane; i < k; i += 64) {
+              double u = wp[i], v = wq[i];
+              wp[i] = c * u - sn * v;
+              wq[i] = sn * u + c * v;
+            }
           }
+          if (lane == 0) { s_touched[p] = 1; s_touched[q] = 1; }
           rotated = 1;
         }
       }
@@ -191,8 +278,11 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
     s_perm[rank] = c;
   }
   __syncthreads();
-  double* U = Uout.p[pb];
   double* S = Sout.p[pb];
+  for (int j = tid; j < k; j += nt) S[j] = s_norm[s_perm[j]];
+  if (tid == 0 && st.p[pb]) st.p[pb]->jsweeps = sweeps_done;
+  if (!want_vectors) return;
+  double* U = Uout.p[pb];
   double* Wo = Wout.p[pb];
   for (int e = tid; e < k * k; e += nt) {
     int r = e / k, j = e % k;
@@ -201,42 +291,58 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
     U[e] = sv > 0 ? A[(size_t)c * k + r] / sv : 0.0;
     Wo[e] = W[(size_t)c * k + r];
   }
-  for (int j = tid; j < k; j += nt) S[j] = s_norm[s_perm[j]];
 }
 
 hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, const PtrSet& S,
-                      const PtrSet& W, const PtrSet& work, int nprob) {
-  if (k > 256) return hipErrorInvalidValue;
+                      const PtrSet& W, const PtrSet& work, int nprob, bool want_vectors, bool transpose_in,
+                      const StatSet* st, double noise_rel) {
+  if (k > 192) return hipErrorInvalidValue;  // 16 waves x 6 pairs, 3 rows per lane
   for (int i = 0; i < nprob; ++i)
-    if (!span_ok(M.p[i], (size_t)k * k * 8, "jacobi M") || !span_ok(U.p[i], (size_t)k * k * 8, "jacobi U") ||
-        !span_ok(S.p[i], (size_t)k * 8, "jacobi S") || !span_ok(W.p[i], (size_t)k * k * 8, "jacobi W") ||
-        !span_ok(work.p[i], (size_t)2 * k * k * 8, "jacobi work"))
+    if (!span_ok(M.p[i], (size_t)k * k * 8, "jacobi M") || !span_ok(S.p[i], (size_t)k * 8, "jacobi S") ||
+        !span_ok(work.p[i], (size_t)(want_vectors ? 3 : 2) * k * k * 8, "jacobi work") ||
+        (want_vectors && (!span_ok(U.p[i], (size_t)k * k * 8, "jacobi U") ||
+                          !span_ok(W.p[i], (size_t)k * k * 8, "jacobi W"))))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(512), 0, s, k, M, U, S, W, work);
+  StatSet none{};
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(1024), 0, s, k, M, U, S, W, work,
+                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // residuals and cutoff
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 residual_kernel(int64_t n, int k, int chi, double cutoff, double tol, CPtrSet Z, CPtrSet V,
                 CPtrSet S, StatSet st) {
+  // 16 waves; lane = column within a chunk of 64, wave = row phase
   const int pb = blockIdx.x;
   const double* z = Z.p[pb];
   const double* v = V.p[pb];
   const double* sv = S.p[pb];
+  __shared__ double s_part[16][64];
   __shared__ double s_res[256];
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double sc = sv[c], acc = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-      double d = z[i * k + c] - sc * v[i * k + c];
-      acc += d * d;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int c = c0 + lane;
+    double acc = 0.0;
+    if (c < k) {
+      const double sc = sv[c];
+      for (int64_t i = wave; i < n; i += 16) {
+        double d = z[i * k + c] - sc * v[i * k + c];
+        acc += d * d;
+      }
     }
-    s_res[c] = sqrt(acc);
+    s_part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && c < k) {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += s_part[w][lane];
+      s_res[c] = sqrt(t);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     SolveStatus* o = st.p[pb];
     double s0 = sv[0];
@@ -264,7 +370,7 @@ hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cuto
         !span_ok(S.p[i], (size_t)k * 8, "resid S") || !span_ok(st.p[i], sizeof(SolveStatus), "resid st"))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(residual_kernel, dim3(nprob), dim3(256), 0, s, n, k, chi, cutoff, tol, Z, V, S, st);
+  hipLaunchKernelGGL(residual_kernel, dim3(nprob), dim3(1024), 0, s, n, k, chi, cutoff, tol, Z, V, S, st);
   return hipGetLastError();
 }
 

@@ -109,7 +109,7 @@ def test_dry_run_orchestration(lib_path):
 def test_invalid_configs_rejected(lib_path):
     from paper_1711_04798_amd import binding as b
     b.load()
-    for bad in [dict(chi=[0]), dict(D=[0]), dict(chi=[300])]:
+    for bad in [dict(chi=[0]), dict(D=[0]), dict(chi=[200])]:
         kw = dict(d=[2], D=[2], chi=[4])
         kw.update(bad)
         cfg, keep = b.make_config(1, 1, [0], 1, kw["d"], kw["D"], kw["chi"])

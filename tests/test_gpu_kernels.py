@@ -67,7 +67,7 @@ def test_jacobi_svd(gpu, k):
     U = torch.zeros((k, k), dtype=torch.float64, device="cuda")
     W = torch.zeros_like(U)
     S = torch.zeros(k, dtype=torch.float64, device="cuda")
-    work = torch.zeros(2 * k * k, dtype=torch.float64, device="cuda")
+    work = torch.zeros(3 * k * k, dtype=torch.float64, device="cuda")
     print("svd case", k, flush=True)
     st = lib.ctm_debug_svd(k, Mt.data_ptr(), U.data_ptr(), S.data_ptr(), W.data_ptr(), work.data_ptr(),
                            torch.cuda.current_stream().cuda_stream)
