@@ -124,10 +124,12 @@ struct Inst {
   double* B[MAXT] = {};
   double* b64[MAXT][4] = {};
   void* bw[MAXT][4] = {};
+  void* bT[MAXT][4] = {};        // bf16 mode: double layer transposed, [(D',R') x (L',U')]
   double* C[4][MAXPOS] = {};
   double* T[4][MAXPOS] = {};
   void* Cw[4][MAXPOS] = {};
   void* Tw[4][MAXPOS] = {};
+  void* TwP[4][MAXPOS] = {};     // bf16 mode: edges as [prev][next][inner]
   double* spec_old = nullptr;  // [pos][4][chi]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
@@ -228,6 +230,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
       for (int r = 0; r < 4; ++r) {
         I.b64[t][r] = ar.take<double>(a8);
         I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : ar.take_bytes(a8 * ws);
+        if (x.wt == BF16) I.bT[t][r] = ar.take_bytes(a8 * ws);
       }
     }
     for (int c = 0; c < 4; ++c)
@@ -236,6 +239,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
         I.T[c][p] = ar.take<double>(t3);
         I.Cw[c][p] = (x.wt == F64) ? (void*)I.C[c][p] : ar.take_bytes(c2 * ws);
         I.Tw[c][p] = (x.wt == F64) ? (void*)I.T[c][p] : ar.take_bytes(t3 * ws);
+        if (x.wt == BF16) I.TwP[c][p] = ar.take_bytes(t3 * ws);
       }
     I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi);
     I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
@@ -364,6 +368,8 @@ struct Roles {
   double* T(int i, int xp, int yp) const { return I->T[(i + k) % 4][pos(xp, yp)]; }
   void* Cw(int i, int xp, int yp) const { return I->Cw[(i + k) % 4][pos(xp, yp)]; }
   void* Tw(int i, int xp, int yp) const { return I->Tw[(i + k) % 4][pos(xp, yp)]; }
+  void* TwP(int i, int xp, int yp) const { return I->TwP[(i + k) % 4][pos(xp, yp)]; }
+  void* bT(int xp, int yp, int r) const { return I->bT[tid(xp, yp)][(k + r) % 4]; }
   // double layer of the site in this frame, additionally turned by r
   double* b64(int xp, int yp, int r) const { return I->b64[tid(xp, yp)][(k + r) % 4]; }
   void* bw(int xp, int yp, int r) const { return I->bw[tid(xp, yp)][(k + r) % 4]; }
@@ -418,6 +424,7 @@ const int64_t BIG = INT64_MAX / 4;
 struct CornerJob {
   const void *C, *Tn, *Tp, *b;
   void *X, *Y, *Q;
+  const void *TnP = nullptr, *bT = nullptr;  // bf16 path: permuted edge, transposed double layer
 };
 
 struct Stage3Timer {
@@ -429,9 +436,38 @@ struct Stage3Timer {
 ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs,
                         const Stage3Timer* tm = nullptr) {
   const int64_t c = chi, n = (int64_t)chi * D2;
+  const int64_t K4 = (int64_t)D2 * D2;
+  const bool fast = tin == BF16 && tq == F32 && !jobs.empty() && jobs[0].TnP && jobs[0].bT &&
+                    corner_bf16_supported(c * c, K4, K4);
   for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
     size_t j1 = std::min(jobs.size(), j0 + MAXG);
     G g1, g2, g3;
+    if (fast) {
+      // stage 2 reads the edge as [n][(b,u)] and writes Y as [(g,b)][(l,u)], so
+      // that stage 3 has both operands contiguous in the contracted index
+      for (size_t j = j0; j < j1; ++j) {
+        g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
+        g2.add(jobs[j].X, jobs[j].TnP, jobs[j].Y);
+        g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
+      }
+      CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
+      // rows m = (g, l) -> g chi D^4 + l D^2; cols (b, u) -> b D^4 + u
+      View vy = view2(D2, D2, c * K4, D2, 1, K4);
+      CHK(gemm_run(s, tin, tin, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
+      View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
+      const bool timed = tm && tm->a && !dry_run();
+      if (timed) HIPCHK(hipEventRecord(tm->a, s));
+      HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.g, g3.n));
+      if (timed) {
+        HIPCHK(hipEventRecord(tm->b, s));
+        HIPCHK(hipEventSynchronize(tm->b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
+        *tm->acc += ms * 1e-3;
+        *tm->count += 1;
+      }
+      continue;
+    }
     for (size_t j = j0; j < j1; ++j) {
       g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
       g2.add(jobs[j].X, jobs[j].Tn, jobs[j].Y);
@@ -752,6 +788,11 @@ ctm_status refresh_working(ctm_ctx_s& x, Inst& I) {
     for (int p = 0; p < npos; ++p) {
       HIPCHK(convert(x.stream, F64, I.C[c][p], x.wt, I.Cw[c][p], c2));
       HIPCHK(convert(x.stream, F64, I.T[c][p], x.wt, I.Tw[c][p], t3));
+      if (I.TwP[c][p]) {
+        int64_t dims[3] = {I.chi, I.D2, I.chi};
+        int perm[3] = {0, 2, 1};
+        HIPCHK(permute(x.stream, F64, I.T[c][p], x.wt, I.TwP[c][p], 3, dims, perm));
+      }
     }
   return CTM_OK;
 }
@@ -790,6 +831,10 @@ ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
       j.X = R.X[q];
       j.Y = R.Y[q];
       j.Q = R.Q[q];
+      if (x.wt == BF16) {
+        j.TnP = ro.TwP(q, cx[q], cy[q]);
+        j.bT = ro.bT(cx[q], cy[q], q);
+      }
       jobs.push_back(j);
     }
   }
@@ -1475,6 +1520,13 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           if (convert(x->stream, F64, I.b64[t][r], x->wt, I.bw[t][r], (int64_t)I.D2 * I.D2 * I.D2 * I.D2) !=
               hipSuccess)
             return cleanup(fail(CTM_E_HIP, "convert"));
+      if (x->wt == BF16)
+        for (int r = 0; r < 4; ++r) {
+          int64_t dims[2] = {(int64_t)I.D2 * I.D2, (int64_t)I.D2 * I.D2};
+          int perm[2] = {1, 0};
+          if (permute(x->stream, F64, I.b64[t][r], BF16, I.bT[t][r], 2, dims, perm) != hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "transpose double layer"));
+        }
     }
     st = init_env(*x, I, i, init, spectrum_host);
     if (st != CTM_OK) return cleanup(st);

@@ -74,6 +74,13 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
                        const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
                        double* scratch, int64_t scratch_elems);
 
+// bf16 enlarged-corner contraction C(view) = A B with A = Y row-major M x K
+// and B given transposed (Bt row-major N x K), f32 output through a two-level
+// view; needs K % 8 == 0 and 16-byte aligned operands.
+bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
+hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
+                       int groups);
+
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].
 hipError_t permute(hipStream_t s, int tin, const void* in, int tout, void* out,

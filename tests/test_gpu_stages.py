@@ -96,3 +96,34 @@ def test_one_step_from_same_env(gpu, direction, case):
     print("kappa after step: oracle %.15f gpu-env %.15f" % (ko, kg))
     assert abs(ko - kg) < 1e-10 * abs(ko)
     g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-2), ("fp32", 1e-5)])
+@pytest.mark.parametrize("D,chi", [(2, 16), (4, 12)])
+def test_reduced_precision_corners(gpu, prec, tol, D, chi):
+    """Enlarged corners of the bf16 / fp32 paths against the float64 oracle
+    from the same environment.  The operands are rounded to the working type
+    (unit roundoff 2^-8 for bf16, 2^-24 for fp32) and accumulated in fp32, so
+    the relative Frobenius error is a few unit roundoffs."""
+    from paper_1711_04798_amd import CTM
+    tens = synth.cell_tensors(7, 2, D, 2)
+    Lx = Ly = 2
+    pat = [0, 1, 1, 0]
+    cell = octm.Cell(Lx, Ly, pat, tens)
+    env = octm.init_trivial(cell, chi)
+    for _ in range(3):
+        octm.sweep(cell, env)
+    print("case", prec, D, chi, flush=True)
+    g = CTM([tens], Lx=Lx, Ly=Ly, pattern=pat, chi=chi, prec=prec, max_iters=2, resid_tol=0.0, cutoff=1e-6)
+    g.import_env(env_to_flat(env, Lx, Ly))
+    g.move("L", 1)
+    n = chi * D * D
+    fr = octm._Frame(cell, env, 0)
+    for yp in range(2):
+        Qo = octm.plaquette_corners(fr, 0, yp)
+        for q in range(4):
+            Qg = _dump(g, 0, 4 * yp + q, (n, n), np.float32).astype(np.float64)
+            err = np.linalg.norm(Qg - Qo[q]) / np.linalg.norm(Qo[q])
+            print("%s Q%d row %d rel err %.2e" % (prec, q + 1, yp, err))
+            assert err < tol
+    g.close()
