@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -38,10 +40,10 @@ def log(*a):
 def solver_opts(prec):
     if prec == "fp64":
         return dict(oversample=16, max_iters=30, resid_tol=1e-13, cutoff=1e-12)
-    # float32 half-system products: singular values below ~1e-6 sigma_1 are
+    # float32 half-system products: singular values below ~1e-7 sigma_1 are
     # rounding noise; warm-started subspace iteration, one plain iteration
     # then one Rayleigh-Ritz step per projector
-    return dict(oversample=16, max_iters=2, resid_tol=0.0, cutoff=1e-6)
+    return dict(oversample=16, max_iters=2, resid_tol=0.0, cutoff=1e-7)
 
 
 def solver_status(g):
@@ -93,6 +95,105 @@ def cpu_baseline(tensors):
                       % dt}
 
 
+BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, tol=1e-4, max_sweeps=40,
+               plain_sample=16)
+
+
+def batched_leg():
+    """Batched form: 256 independent 1x1 instances, (D, chi) drawn per instance,
+    float32 contractions, one captured HIP graph per sweep, converged to tol;
+    against the same instances run one plain context at a time (a sample)."""
+    import torch
+    import synth
+    from paper_1711_04798_amd import CTM
+    b = BATCHED
+    inst = synth.batched_instances(b["seed"], b["n_inst"], d=b["d"], Ds=b["Ds"], chis=b["chis"])
+    kw = dict(prec="fp32", max_iters=2, resid_tol=0.0, cutoff=1e-6)
+    log("bench: batched leg, %d instances" % len(inst))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = CTM([[A] for _, _, A in inst], chi=[c for _, c, _ in inst], use_graph=True, **kw)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sw, dl, ok = g.converge(tol=b["tol"], max_sweeps=b["max_sweeps"])
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    n_conv = sum(1 for d in dl if d < b["tol"])
+    log("bench: batched converge %.2f s (init %.2f s), %d/%d converged, sweeps max %d"
+        % (t_b, t_init, n_conv, len(inst), max(sw)))
+    # plain: one context per instance, eager, the first plain_sample instances
+    t_p = 0.0
+    sw_p = []
+    for D, chi, A in inst[:b["plain_sample"]]:
+        p = CTM([[A]], chi=chi, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s1, d1, _ = p.converge(tol=b["tol"], max_sweeps=b["max_sweeps"])
+        torch.cuda.synchronize()
+        t_p += time.perf_counter() - t0
+        sw_p.append(s1[0])
+        p.close()
+    env_b = len(inst) / t_b
+    env_p = b["plain_sample"] / t_p
+    log("bench: plain %d instances %.2f s" % (b["plain_sample"], t_p))
+    return {"envs_per_s": env_b, "plain_envs_per_s": env_p, "speedup": env_b / env_p,
+            "unit": "converged environments/s", "n_inst": len(inst), "converged": n_conv,
+            "tol": b["tol"], "max_sweeps": b["max_sweeps"], "sweeps_mean": float(np.mean(sw)),
+            "sweeps_max": int(max(sw)), "plain_sample": b["plain_sample"],
+            "plain_sweeps_mean": float(np.mean(sw_p)), "dtype": "fp32",
+            "workload": "256 1x1 iPEPS, d=8, D in {3,4,5}, chi in {32,64,100} per instance (seed 0), "
+                        "fp32 contractions, one HIP graph per sweep; plain = one context per instance, "
+                        "eager, first %d instances" % b["plain_sample"]}
+
+
+WARM = dict(d=8, D=4, chi=64, family_seed=0, train_seed=1, test_seed=2, n_train=512, n_test=64, tol=1e-10,
+            max_sweeps=60, hidden=128, steps=4000, lr=2e-3)
+
+
+def warm_leg():
+    """Learned warm start: plain runs from the trivial start converge the
+    training members of the family A(theta) (their spectra are the targets);
+    the network trains on the device; held-out members then start from
+    diagonal corners with the predicted spectra (falling back to the trivial
+    start after a budget of twice the plain sweeps)."""
+    import torch
+    import synth
+    from paper_1711_04798_amd import warmstart as ws
+    w = WARM
+    base = synth.warm_family(w["family_seed"], d=w["d"], D=w["D"])
+    th_tr, th_te = synth.warm_thetas(w["train_seed"], w["n_train"]), synth.warm_thetas(w["test_seed"], w["n_test"])
+    T_tr = [synth.warm_member(base, t) for t in th_tr]
+    T_te = [synth.warm_member(base, t) for t in th_te]
+    log("bench: warm-start leg, %d training runs" % len(T_tr))
+    t0 = time.perf_counter()
+    s_tr, sw_tr, d_tr, _ = ws.converge_batch(T_tr, w["chi"], w["tol"], w["max_sweeps"])
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, hist = ws.train(th_tr, s_tr, hidden=w["hidden"], steps=w["steps"], lr=w["lr"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pred = ws.predict(net, th_te)
+    t0 = time.perf_counter()
+    s_tv, sw_tv, d_tv, k_tv = ws.converge_batch(T_te, w["chi"], w["tol"], w["max_sweeps"])
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s_w, sw_w, ok_w, k_w = ws.converge_with_fallback(T_te, w["chi"], w["tol"], w["max_sweeps"], pred,
+                                                      warm_budget=2 * int(sw_tv.max()))
+    t_warm = time.perf_counter() - t0
+    lg = lambda a: np.log10(np.maximum(a, 1e-16))
+    return {"plain_sweeps_mean": float(sw_tv.mean()), "warm_sweeps_mean": float(sw_w.mean()),
+            "warm_converged": int(ok_w.sum()), "n_test": len(T_te), "plain_envs_per_s": len(T_te) / t_plain,
+            "warm_envs_per_s": len(T_te) / t_warm, "n_train": len(T_tr), "train_data_s": t_data,
+            "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+            "pred_log10_err_top16": float(np.abs(lg(pred) - lg(s_tv))[:, :, :16].mean()),
+            "kappa_max_rel_diff": float(np.max(np.abs(k_w - k_tv) / np.abs(k_tv))), "tol": w["tol"],
+            "workload": "family A(theta) d=8 D=4 chi=64 1x1, float64 contractions, %d training runs, "
+                        "%d held-out" % (len(T_tr), len(T_te))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +201,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-warm", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the CTM hot path here is a single-GPU "
@@ -161,12 +264,17 @@ def main():
                    "Lx": 2, "Ly": 2, "d": 8, "D": 6, "chi": 144, "seed": 0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "enlarged-corner double-layer contraction (gemm_kernel, 8 corners "
-                               "per launch, 2 chi^2 D^8 flop each)",
+                     "kernel": "enlarged-corner double-layer contraction (%s, 8 corners "
+                               "per launch, 2 chi^2 D^8 flop each)"
+                               % ("corner_bf16_kernel" if args.prec == "bf16" else "gemm_kernel"),
                      "flop_per_launch": flop_per_launch, "avg_launch_s": avg,
                      "launches": int(launches)},
         "phase_s": {"corner": tm["corner_s"], "solver": tm["solver_s"], "absorb": tm["absorb_s"]},
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg()
+    if not args.no_warm:
+        out["warm_start"] = warm_leg()
     if not args.no_cpu:
         log("bench: cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(tensors)

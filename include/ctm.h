@@ -64,7 +64,10 @@ typedef enum { CTM_LEFT = 0, CTM_UP = 1, CTM_RIGHT = 2, CTM_DOWN = 3, CTM_SWEEP 
 typedef enum { CTM_INIT_TRIVIAL = 0, CTM_INIT_DIAG = 1 } ctm_init_kind;
 
 typedef struct {
-  int32_t n_inst;          /* independent instances (1 = plain CTM)                */
+  int32_t n_inst;          /* independent instances (1 = plain CTM).  Instances
+                              with equal (d, D, chi) form a class that is moved
+                              in lock-step, every stage one grouped launch over
+                              all of its rows (batched form)                      */
   int32_t Lx, Ly;          /* unit cell, 1..4 each                                 */
   int32_t n_tensors;       /* distinct tensors per instance                        */
   const int32_t* pattern;  /* host [Lx*Ly]: tensor id of site (x, y) at y*Lx+x     */
@@ -80,6 +83,12 @@ typedef struct {
                               only in the last                                    */
   double svd_cutoff;       /* keep sigma_i > cutoff*sigma_1 (default 1e-12)         */
   uint64_t seed;           /* seeds the random start of the subspace iteration     */
+  int32_t use_graph;       /* 1: ctm_converge replays one captured HIP graph per
+                              sweep (every instance, corner spectra included)
+                              after its first sweep; needs svd_resid_tol == 0,
+                              timing off and a non-NULL stream (default 0)         */
+  int32_t autotune;        /* 1: time the GEMM tile variants on first use of each
+                              shape and keep the fastest (default 1)               */
 } ctm_config;
 
 /* Fills *cfg with the defaults above for one instance (caller sets the rest). */
@@ -126,7 +135,10 @@ ctm_status ctm_move(ctm_ctx ctx, int32_t dir, int32_t count);
  * Sweeps until the largest l1 change of the normalised corner spectra
  * sigma(C)/sum sigma(C), over all corners and positions of an instance, is
  * below tol, or max_sweeps sweeps were done.  The change is read back to the
- * host every check_every sweeps.  sweeps_out, delta_out: host [n_inst] or NULL.
+ * host every check_every sweeps.  sweeps_out, delta_out: host [n_inst] or NULL;
+ * an instance reports the first checked sweep at which its change was below
+ * tol (the instances of a class keep sweeping together until all converged;
+ * with use_graph every instance sweeps until all converged).
  * Returns CTM_E_NOCONV (state valid) if some instance did not converge.
  */
 ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,

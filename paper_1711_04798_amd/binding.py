@@ -22,7 +22,8 @@ EXPORTS = [
     "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
     "ctm_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
-    "ctm_last_error",
+    "ctm_last_error", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
+    "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
 
 
@@ -35,7 +36,12 @@ class CtmConfig(ctypes.Structure):
         ("prec", ctypes.c_int32), ("svd_oversample", ctypes.c_int32),
         ("svd_max_iters", ctypes.c_int32), ("svd_resid_tol", ctypes.c_double),
         ("svd_cutoff", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
     ]
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32)]
 
 
 class CtmError(RuntimeError):
@@ -54,6 +60,10 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libctm.so not built (run __graft_entry__.build()): %s" % path)
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes the library bind to that runtime, so that torch's device pointers
+    # and streams are valid in library calls
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, F64, SZ, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
     cfgp = P(CtmConfig)
@@ -79,6 +89,19 @@ def load(path=LIB_PATH):
     lib.ctm_destroy.restype = None
     lib.ctm_last_error.argtypes = []
     lib.ctm_last_error.restype = ctypes.c_char_p
+    shp = P(MlpShape)
+    lib.ctm_mlp_param_count.argtypes = [shp]
+    lib.ctm_mlp_param_count.restype = ctypes.c_int64
+    lib.ctm_mlp_workspace_size.argtypes = [shp, I32, P(SZ)]
+    lib.ctm_mlp_features.argtypes = [VP, I32, VP, VP]
+    lib.ctm_mlp_targets.argtypes = [VP, ctypes.c_int64, VP, VP]
+    lib.ctm_mlp_forward.argtypes = [shp, VP, VP, I32, VP, I32, VP, SZ, VP]
+    lib.ctm_mlp_loss_grad.argtypes = [shp, VP, VP, VP, I32, VP, VP, VP, SZ, VP]
+    lib.ctm_mlp_adam.argtypes = [ctypes.c_int64, VP, VP, VP, VP, I32, F64, F64, F64, F64, VP]
+    lib.ctm_mlp_train.argtypes = [shp, VP, VP, VP, VP, I32, VP, VP, I32, I32, F64, VP, VP, SZ, VP]
+    for name in ("ctm_mlp_workspace_size", "ctm_mlp_features", "ctm_mlp_targets", "ctm_mlp_forward",
+                 "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge", "ctm_spectra",
                  "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_export",
                  "ctm_env_import", "ctm_set_timing", "ctm_get_timing"):
@@ -98,7 +121,8 @@ def _i32arr(v):
 
 
 def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=16,
-                max_iters=30, resid_tol=1e-13, cutoff=1e-12, seed=12345):
+                max_iters=30, resid_tol=1e-13, cutoff=1e-12, seed=12345, use_graph=False,
+                autotune=True):
     """ctm_config plus the ctypes arrays it points into (keep both alive)."""
     lib = load()
     cfg = CtmConfig()
@@ -114,6 +138,8 @@ def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=1
     cfg.svd_resid_tol = resid_tol
     cfg.svd_cutoff = cutoff
     cfg.seed = seed
+    cfg.use_graph = int(bool(use_graph))
+    cfg.autotune = int(bool(autotune))
     return cfg, keep
 
 
@@ -172,7 +198,14 @@ class CTM:
             sp = spectrum.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             self._spec = spectrum
         self.ctx = ctypes.c_void_p()
-        self.stream = _stream(torch, self.device)
+        if solver.get("use_graph"):
+            # graph capture needs a stream of its own (not the legacy default
+            # stream); the copies above ran on the current stream
+            self._side = torch.cuda.Stream(self.device)
+            torch.cuda.synchronize(self.device)
+            self.stream = ctypes.c_void_p(self._side.cuda_stream)
+        else:
+            self.stream = _stream(torch, self.device)
         _check(lib.ctm_init(ctypes.byref(self.cfg), ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p)),
                             ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)) if bp is not None else None,
                             ctypes.c_void_p(base + off), nbytes, self.stream, INIT[init], sp,
@@ -274,3 +307,84 @@ def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=
     torch.cuda.synchronize(dev)
     del at, bt, ws
     return dv.value, lv.value, list(sw)
+
+
+class MLP:
+    """Warm-start network on the device (include/ctm_mlp.h): float64 parameters,
+    Adam moments and workspace held as torch tensors; every computation is a
+    library call."""
+
+    def __init__(self, n_in, n_hidden, n_out, params, max_batch, device="cuda:0"):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.shape = MlpShape(n_in, n_hidden, n_out)
+        self.n_params = lib.ctm_mlp_param_count(ctypes.byref(self.shape))
+        if self.n_params < 0:
+            raise CtmError(CTM_E_INVALID, "bad network shape")
+        params = np.ascontiguousarray(params, dtype=np.float64)
+        if params.size != self.n_params:
+            raise CtmError(CTM_E_INVALID, "expected %d parameters" % self.n_params)
+        self.device = torch.device(device)
+        self.p = torch.as_tensor(params, device=self.device).clone()
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.g = torch.zeros_like(self.p)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.step = 0
+        self.max_batch = max_batch
+        nb = ctypes.c_size_t()
+        _check(lib.ctm_mlp_workspace_size(ctypes.byref(self.shape), max_batch, ctypes.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        self._off = (-self._ws.data_ptr()) % 256
+        self.ws_bytes = nb.value
+        self.stream = _stream(torch, self.device)
+
+    def _ws_ptr(self):
+        return ctypes.c_void_p(self._ws.data_ptr() + self._off)
+
+    def _dev(self, a):
+        return self._torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
+
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def features(self, theta):
+        th = self._dev(theta)
+        x = self._torch.empty((th.shape[0], 3), dtype=self._torch.float64, device=self.device)
+        _check(load().ctm_mlp_features(self._ptr(th), th.shape[0], self._ptr(x), self.stream))
+        return x
+
+    def targets(self, spectra):
+        s = self._dev(spectra)
+        t = self._torch.empty_like(s)
+        _check(load().ctm_mlp_targets(self._ptr(s), s.numel(), self._ptr(t), self.stream))
+        return t.reshape(s.shape[0], -1)
+
+    def forward(self, x, exp10=False):
+        B = x.shape[0]
+        y = self._torch.empty((B, self.shape.n_out), dtype=self._torch.float64, device=self.device)
+        _check(load().ctm_mlp_forward(ctypes.byref(self.shape), self._ptr(self.p), self._ptr(x), B, self._ptr(y),
+                                      int(exp10), self._ws_ptr(), self.ws_bytes, self.stream))
+        return y
+
+    def loss_grad(self, x, t):
+        _check(load().ctm_mlp_loss_grad(ctypes.byref(self.shape), self._ptr(self.p), self._ptr(x), self._ptr(t),
+                                        x.shape[0], self._ptr(self.loss_dev), self._ptr(self.g), self._ws_ptr(),
+                                        self.ws_bytes, self.stream))
+        return float(self.loss_dev.item()), self.g.clone()
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(load().ctm_mlp_adam(self.n_params, self._ptr(self.p), self._ptr(self.g), self._ptr(self.m),
+                                   self._ptr(self.v), self.step, lr, beta1, beta2, eps, self.stream))
+
+    def train(self, x, t, steps, lr):
+        hist = self._torch.zeros(max(steps, 1), dtype=self._torch.float64, device=self.device)
+        _check(load().ctm_mlp_train(ctypes.byref(self.shape), self._ptr(self.p), self._ptr(self.m),
+                                    self._ptr(self.v), self._ptr(self.g), self.step, self._ptr(x), self._ptr(t),
+                                    x.shape[0], steps, lr, self._ptr(hist), self._ws_ptr(), self.ws_bytes,
+                                    self.stream))
+        self.step += steps
+        return hist[:steps].cpu().numpy()

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <initializer_list>
 #include <string>
 #include <vector>
@@ -63,6 +64,11 @@ struct RegGuard {
   Registry* prev;
   explicit RegGuard(Registry* r) : prev(g_reg) { g_reg = r; }
   ~RegGuard() { g_reg = prev; }
+};
+
+struct TuneGuard {
+  explicit TuneGuard(bool on) { set_tuning(on); }
+  ~TuneGuard() { set_tuning(false); }
 };
 
 hipError_t d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -118,6 +124,23 @@ struct Arena {
   void* take_bytes(size_t bytes) { return take<char>(bytes); }
 };
 
+struct Row {  // scratch for one row of a column step
+  void* Q[4] = {};
+  void* X[4] = {};
+  void* Y[4] = {};
+  double *V = nullptr, *Yb = nullptr, *Qb = nullptr, *Z = nullptr, *LV = nullptr, *UU = nullptr,
+         *Ub = nullptr, *Vp = nullptr, *tmp = nullptr;
+  void *qin = nullptr, *q1 = nullptr, *q2 = nullptr;  // N-apply scratch in the Q type
+  double *G = nullptr, *Rinv = nullptr, *Rm = nullptr, *UR = nullptr, *WR = nullptr,
+         *S = nullptr, *Wp = nullptr, *Up = nullptr, *jw = nullptr;
+  SolveStatus* st = nullptr;
+  double *P1 = nullptr, *P2T = nullptr;
+  void *P1w = nullptr, *P2Tw = nullptr;
+  void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
+  double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
+  double *red = nullptr, *sums = nullptr;
+};
+
 struct Inst {
   int d = 0, D = 0, D2 = 0, chi = 0, n = 0, k = 0;
   double* A[MAXT] = {};
@@ -139,23 +162,7 @@ struct Inst {
   bool has_keep[4][MAXPOS] = {};
   int cursor[4] = {0, 0, 0, 0};
   uint64_t solves = 0;
-};
-
-struct Row {  // scratch for one row of a column step
-  void* Q[4] = {};
-  void* X[4] = {};
-  void* Y[4] = {};
-  double *V = nullptr, *Yb = nullptr, *Qb = nullptr, *Z = nullptr, *LV = nullptr, *UU = nullptr,
-         *Ub = nullptr, *Vp = nullptr, *tmp = nullptr;
-  void *qin = nullptr, *q1 = nullptr, *q2 = nullptr;  // N-apply scratch in the Q type
-  double *G = nullptr, *Rinv = nullptr, *Rm = nullptr, *UR = nullptr, *WR = nullptr,
-         *S = nullptr, *Wp = nullptr, *Up = nullptr, *jw = nullptr;
-  SolveStatus* st = nullptr;
-  double *P1 = nullptr, *P2T = nullptr;
-  void *P1w = nullptr, *P2Tw = nullptr;
-  void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
-  double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
-  double *red = nullptr, *sums = nullptr;
+  std::vector<Row> rows;        // scratch of the rows of one column step
 };
 
 struct Obs {  // float64 scratch of the observables
@@ -177,8 +184,13 @@ struct ctm_ctx_s {
   int wt = F64, qt = F64;  // contraction operand type, enlarged-corner type
   hipStream_t stream = nullptr;
   std::vector<Inst> inst;
-  Row rows[MAXROWS];
+  std::vector<std::vector<int>> classes;  // instances with equal (d, D, chi), moved in lock-step
   Obs obs;
+  double* norm_part = nullptr;   // grouped-normalisation partial sums
+  double* delta_all = nullptr;   // [n_inst] convergence measure of each instance
+  int* flag_all = nullptr;       // [n_inst][4] non-finite flags
+  int max_prob = 1;              // largest number of solver problems per launch
+  hipGraphExec_t gexec = nullptr;  // captured sweep of every class (graph mode)
   double* splitk = nullptr;      // split-K partial products of the solver
   int64_t splitk_elems = 0;
   double* spec_tmp_U = nullptr;  // corner SVD scratch
@@ -198,7 +210,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // sizes
 // ---------------------------------------------------------------------------
-int wtype_of(int prec) { return prec == CTM_FP64 ? F64 : (prec == CTM_FP32 ? F32 : BF16); }
+// working type of corners, edges, projectors and every contraction except
+// the double-layer stage of the enlarged corners, which is bf16 in CTM_BF16
+int wtype_of(int prec) { return prec == CTM_FP64 ? F64 : F32; }
 int qtype_of(int prec) { return prec == CTM_FP64 ? F64 : F32; }
 
 int subspace_dim(const ctm_config& c, int chi, int n) {
@@ -206,10 +220,37 @@ int subspace_dim(const ctm_config& c, int chi, int n) {
   return std::min(n, chi + p);
 }
 
+void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
+  const size_t ws = dtype_size(x.wt), qs = dtype_size(x.qt);
+  const size_t n = I.n, k = I.k, chi = I.chi, D2 = I.D2;
+  const size_t nk = n * k, c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
+  for (int q = 0; q < 4; ++q) {
+    R.Q[q] = ar.take_bytes(n * n * qs);
+    R.X[q] = ar.take_bytes(t3 * ws);
+    R.Y[q] = ar.take_bytes(y4 * ws);
+  }
+  R.V = ar.take<double>(nk); R.Yb = ar.take<double>(nk); R.Qb = ar.take<double>(nk);
+  R.Z = ar.take<double>(nk); R.LV = ar.take<double>(nk); R.UU = ar.take<double>(nk);
+  R.Ub = ar.take<double>(nk); R.Vp = ar.take<double>(nk); R.tmp = ar.take<double>(nk);
+  if (x.qt != F64) {
+    R.qin = ar.take_bytes(nk * qs); R.q1 = ar.take_bytes(nk * qs); R.q2 = ar.take_bytes(nk * qs);
+  }
+  R.G = ar.take<double>(k * k); R.Rinv = ar.take<double>(k * k); R.Rm = ar.take<double>(k * k);
+  R.UR = ar.take<double>(k * k); R.WR = ar.take<double>(k * k); R.S = ar.take<double>(k);
+  R.Wp = ar.take<double>(k * chi); R.Up = ar.take<double>(k * chi); R.jw = ar.take<double>(3 * k * k);
+  R.st = ar.take<SolveStatus>(1);
+  R.P1 = ar.take<double>(n * chi); R.P2T = ar.take<double>(n * chi);
+  R.P1w = (x.wt == F64) ? (void*)R.P1 : ar.take_bytes(n * chi * ws);
+  R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
+  R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
+  R.X6 = ar.take_bytes(t3 * ws);
+  R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
+}
+
 void plan(ctm_ctx_s& x, Arena& ar) {
   const int npos = x.Lx * x.Ly;
-  const size_t ws = dtype_size(x.wt), qs = dtype_size(x.qt);
-  int rows = std::max(x.Lx, x.Ly);
+  const size_t ws = dtype_size(x.wt);
+  const int rows = std::max(x.Lx, x.Ly);
   size_t mx_n = 0, mx_k = 0, mx_chi = 0, mx_D2 = 0, mx_d = 0;
   for (int i = 0; i < x.ninst; ++i) {
     Inst& I = x.inst[i];
@@ -219,6 +260,9 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     mx_D2 = std::max(mx_D2, (size_t)I.D2);
     mx_d = std::max(mx_d, (size_t)I.d);
   }
+  x.delta_all = ar.take<double>((size_t)x.ninst);
+  x.flag_all = ar.take<int>((size_t)4 * x.ninst);
+  x.norm_part = ar.take<double>((size_t)MAXJ * 64);
   for (int i = 0; i < x.ninst; ++i) {
     Inst& I = x.inst[i];
     const size_t t5 = (size_t)I.d * I.D2 * I.D2;
@@ -230,7 +274,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
       for (int r = 0; r < 4; ++r) {
         I.b64[t][r] = ar.take<double>(a8);
         I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : ar.take_bytes(a8 * ws);
-        if (x.wt == BF16) I.bT[t][r] = ar.take_bytes(a8 * ws);
+        if (x.prec == CTM_BF16) I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
       }
     }
     for (int c = 0; c < 4; ++c)
@@ -239,54 +283,33 @@ void plan(ctm_ctx_s& x, Arena& ar) {
         I.T[c][p] = ar.take<double>(t3);
         I.Cw[c][p] = (x.wt == F64) ? (void*)I.C[c][p] : ar.take_bytes(c2 * ws);
         I.Tw[c][p] = (x.wt == F64) ? (void*)I.T[c][p] : ar.take_bytes(t3 * ws);
-        if (x.wt == BF16) I.TwP[c][p] = ar.take_bytes(t3 * ws);
+        if (x.prec == CTM_BF16) I.TwP[c][p] = ar.take_bytes(t3 * ws);
       }
     I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi);
     I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
-    I.delta = ar.take<double>(4);
-    I.flag = ar.take<int>(4);
+    I.delta = x.delta_all ? x.delta_all + i : nullptr;
+    I.flag = x.flag_all ? x.flag_all + 4 * i : nullptr;
     for (int c = 0; c < 4; ++c)
       for (int p = 0; p < npos; ++p) {
         I.Vkeep[c][p] = ar.take<double>((size_t)I.n * I.k);
         I.skeep[c][p] = ar.take<SolveStatus>(1);
       }
+    // row scratch of this instance (all instances of a class step together)
+    I.rows.assign(rows, Row());
+    for (int r = 0; r < rows; ++r) plan_row(x, ar, I, I.rows[r]);
   }
-  // row scratch sized for the largest instance
+  // problems per solver launch: every row of every instance of a class, at most MAXP
+  x.max_prob = 1;
+  for (auto& cls : x.classes) x.max_prob = std::max(x.max_prob, std::min<int>(MAXP, (int)cls.size() * rows));
   const size_t n = mx_n, k = mx_k, chi = mx_chi, D2 = mx_D2;
-  const size_t nk = n * k, c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
-  for (int r = 0; r < rows; ++r) {
-    Row& R = x.rows[r];
-    for (int q = 0; q < 4; ++q) {
-      R.Q[q] = ar.take_bytes(n * n * qs);
-      R.X[q] = ar.take_bytes(t3 * ws);
-      R.Y[q] = ar.take_bytes(y4 * ws);
-    }
-    R.V = ar.take<double>(nk); R.Yb = ar.take<double>(nk); R.Qb = ar.take<double>(nk);
-    R.Z = ar.take<double>(nk); R.LV = ar.take<double>(nk); R.UU = ar.take<double>(nk);
-    R.Ub = ar.take<double>(nk); R.Vp = ar.take<double>(nk); R.tmp = ar.take<double>(nk);
-    if (x.qt != F64) {
-      R.qin = ar.take_bytes(nk * qs); R.q1 = ar.take_bytes(nk * qs); R.q2 = ar.take_bytes(nk * qs);
-    }
-    R.G = ar.take<double>(k * k); R.Rinv = ar.take<double>(k * k); R.Rm = ar.take<double>(k * k);
-    R.UR = ar.take<double>(k * k); R.WR = ar.take<double>(k * k); R.S = ar.take<double>(k);
-    R.Wp = ar.take<double>(k * chi); R.Up = ar.take<double>(k * chi); R.jw = ar.take<double>(3 * k * k);
-    R.st = ar.take<SolveStatus>(1);
-    R.P1 = ar.take<double>(n * chi); R.P2T = ar.take<double>(n * chi);
-    R.P1w = (x.wt == F64) ? (void*)R.P1 : ar.take_bytes(n * chi * ws);
-    R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
-    R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
-    R.X6 = ar.take_bytes(t3 * ws);
-    R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
-    R.red = ar.take<double>(256); R.sums = ar.take<double>(8);
-  }
-  // split-K partials of the k x n x k products (all rows in one launch)
-  x.splitk_elems = (int64_t)64 * k * k * rows;
+  const size_t c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
+  // split-K partials of the k x n x k products (all problems of a launch)
+  x.splitk_elems = (int64_t)64 * k * k * x.max_prob;
   x.splitk = ar.take<double>((size_t)x.splitk_elems);
-  // corner-spectrum SVD scratch (8 corners per launch)
-  x.spec_tmp_U = ar.take<double>(8 * c2);
-  x.spec_tmp_W = ar.take<double>(8 * c2);
-  x.spec_tmp_S = ar.take<double>(8 * chi);
-  x.spec_tmp_J = ar.take<double>(8 * 2 * c2);
+  // corner-spectrum SVD scratch (MAXP corners per launch)
+  x.spec_tmp_U = ar.take<double>(MAXP * c2);
+  x.spec_tmp_W = ar.take<double>(MAXP * c2);
+  x.spec_tmp_J = ar.take<double>(MAXP * 2 * c2);
   // observables (float64)
   const size_t d = mx_d, a8 = D2 * D2 * D2 * D2;
   Obs& O = x.obs;
@@ -380,23 +403,67 @@ struct Roles {
 // GEMM helpers
 // ---------------------------------------------------------------------------
 struct G {
-  GemmGroup g{};
-  int n = 0;
+  std::vector<const void*> A, B;
+  std::vector<void*> C;
   void add(const void* a, const void* b, void* c) {
-    g.A[n] = a; g.B[n] = b; g.C[n] = c; ++n;
+    A.push_back(a); B.push_back(b); C.push_back(c);
+  }
+  int size() const { return (int)A.size(); }
+  // problems j0 .. j0 + count - 1 as one launch group (count <= MAXG)
+  GemmGroup group(int j0, int count) const {
+    GemmGroup g{};
+    for (int j = 0; j < count; ++j) { g.A[j] = A[j0 + j]; g.B[j] = B[j0 + j]; g.C[j] = C[j0 + j]; }
+    return g;
   }
 };
 
+// every problem of `g` in launches of at most MAXG problems
 ctm_status gemm_run(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
                     const View& vb, const View& vc, const G& g, double alpha = 1.0,
                     double beta = 0.0) {
-  HIPCHK(ctmk::gemm(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g.g, g.n));
+  for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
+    int cnt = std::min(MAXG, g.size() - j0);
+    HIPCHK(ctmk::gemm(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g.group(j0, cnt), cnt));
+  }
   return CTM_OK;
 }
 
 ctm_status gemm_sk(ctm_ctx_s& x, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                    const View& vc, const G& g) {
-  HIPCHK(ctmk::gemm_splitk(x.stream, M, N, K, 1.0, va, vb, 0.0, vc, g.g, g.n, x.splitk, x.splitk_elems));
+  for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
+    int cnt = std::min(MAXG, g.size() - j0);
+    HIPCHK(ctmk::gemm_splitk(x.stream, M, N, K, 1.0, va, vb, 0.0, vc, g.group(j0, cnt), cnt, x.splitk,
+                             x.splitk_elems));
+  }
+  return CTM_OK;
+}
+
+// grouped copies / conversions, in launches of at most MAXJ tensors
+struct Xfer {
+  std::vector<const void*> src;
+  std::vector<void*> dst;
+  std::vector<int64_t> n;
+  void add(const void* a, void* b, int64_t cnt) { src.push_back(a); dst.push_back(b); n.push_back(cnt); }
+};
+
+ctm_status xfer_run(hipStream_t s, int tin, int tout, const Xfer& x) {
+  for (size_t j0 = 0; j0 < x.src.size(); j0 += MAXJ) {
+    int cnt = (int)std::min<size_t>(MAXJ, x.src.size() - j0);
+    XferSet xs{};
+    for (int j = 0; j < cnt; ++j) { xs.src[j] = x.src[j0 + j]; xs.dst[j] = x.dst[j0 + j]; xs.n[j] = x.n[j0 + j]; }
+    HIPCHK(convert_group(s, tin, tout, xs, cnt));
+  }
+  return CTM_OK;
+}
+
+// p /= ||p||_F for every listed float64 tensor
+ctm_status normalize_run(ctm_ctx_s& x, const std::vector<std::pair<double*, int64_t>>& t) {
+  for (size_t j0 = 0; j0 < t.size(); j0 += MAXJ) {
+    int cnt = (int)std::min<size_t>(MAXJ, t.size() - j0);
+    NormSet ns{};
+    for (int j = 0; j < cnt; ++j) { ns.p[j] = t[j0 + j].first; ns.n[j] = t[j0 + j].second; }
+    HIPCHK(normalize_group(x.stream, ns, cnt, x.norm_part));
+  }
   return CTM_OK;
 }
 
@@ -433,12 +500,31 @@ struct Stage3Timer {
   int64_t* count = nullptr;
 };
 
+ctm_status stage3_timed(hipStream_t s, const Stage3Timer* tm, const std::function<ctm_status()>& f) {
+  const bool timed = tm && tm->a && !dry_run();
+  if (timed) HIPCHK(hipEventRecord(tm->a, s));
+  CHK(f());
+  if (timed) {
+    HIPCHK(hipEventRecord(tm->b, s));
+    HIPCHK(hipEventSynchronize(tm->b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
+    *tm->acc += ms * 1e-3;
+    *tm->count += 1;
+  }
+  return CTM_OK;
+}
+
+// bf16: the double-layer stage (stage 3) takes bf16 operands (stage 2 writes
+// Y in bf16, the double layer is the transposed bf16 copy) with fp32
+// accumulation; stages 1 and 2 run in `tin`.
 ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs,
-                        const Stage3Timer* tm = nullptr) {
+                        const Stage3Timer* tm, bool bf16) {
   const int64_t c = chi, n = (int64_t)chi * D2;
   const int64_t K4 = (int64_t)D2 * D2;
-  const bool fast = tin == BF16 && tq == F32 && !jobs.empty() && jobs[0].TnP && jobs[0].bT &&
+  const bool fast = bf16 && tq == F32 && !jobs.empty() && jobs[0].TnP && jobs[0].bT &&
                     corner_bf16_supported(c * c, K4, K4);
+  const int ty = bf16 ? BF16 : tin;  // type of Y
   for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
     size_t j1 = std::min(jobs.size(), j0 + MAXG);
     G g1, g2, g3;
@@ -453,45 +539,29 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
       CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
       // rows m = (g, l) -> g chi D^4 + l D^2; cols (b, u) -> b D^4 + u
       View vy = view2(D2, D2, c * K4, D2, 1, K4);
-      CHK(gemm_run(s, tin, tin, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
+      CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
       View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
-      const bool timed = tm && tm->a && !dry_run();
-      if (timed) HIPCHK(hipEventRecord(tm->a, s));
-      HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.g, g3.n));
-      if (timed) {
-        HIPCHK(hipEventRecord(tm->b, s));
-        HIPCHK(hipEventSynchronize(tm->b));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
-        *tm->acc += ms * 1e-3;
-        *tm->count += 1;
-      }
+      CHK(stage3_timed(s, tm, [&]() -> ctm_status {
+        HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.group(0, g3.size()), g3.size()));
+        return CTM_OK;
+      }));
       continue;
     }
     for (size_t j = j0; j < j1; ++j) {
       g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
       g2.add(jobs[j].X, jobs[j].Tn, jobs[j].Y);
-      g3.add(jobs[j].Y, jobs[j].b, jobs[j].Q);
+      g3.add(jobs[j].Y, bf16 ? jobs[j].bT : jobs[j].b, jobs[j].Q);
     }
     CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
-    CHK(gemm_run(s, tin, tin, n, n, c, rowmajor(c), rowmajor(n), rowmajor(n), g2));
+    CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), rowmajor(n), g2));
     // A: rows m = (g, b): b low (extent chi, stride 1), g high (stride D2*D2*chi);
     //    cols k = (l, u): stride chi
     View va = view2(c, 1, (int64_t)D2 * D2 * c, BIG, c, 0);
+    // B: the double layer [(l,u)][(dn,r)], or its transposed bf16 copy
+    View vb = bf16 ? transposed(rowmajor(K4)) : rowmajor(K4);
     // C: rows m = (g, b) -> g*D2*n + b*D2; cols (dn, r) -> dn*n + r
     View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
-    const bool timed = tm && tm->a && !dry_run();
-    if (timed) HIPCHK(hipEventRecord(tm->a, s));
-    CHK(gemm_run(s, tin, tq, c * c, (int64_t)D2 * D2, (int64_t)D2 * D2, va, rowmajor((int64_t)D2 * D2),
-                 vc, g3));
-    if (timed) {
-      HIPCHK(hipEventRecord(tm->b, s));
-      HIPCHK(hipEventSynchronize(tm->b));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
-      *tm->acc += ms * 1e-3;
-      *tm->count += 1;
-    }
+    CHK(stage3_timed(s, tm, [&]() { return gemm_run(s, ty, tq, c * c, K4, K4, va, vb, vc, g3); }));
   }
   return CTM_OK;
 }
@@ -540,7 +610,11 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
     return CTM_OK;
   }
   // reduced precision: cast in, apply in the Q type, mid and out back to float64
-  for (size_t r = 0; r < P; ++r) HIPCHK(convert(s, F64, in[r], qt, rows[r].R->qin, (int64_t)n * k));
+  {
+    Xfer cv;
+    for (size_t r = 0; r < P; ++r) cv.add(in[r], rows[r].R->qin, (int64_t)n * k);
+    CHK(xfer_run(s, F64, qt, cv));
+  }
   for (int f = 0; f < 4; ++f) {
     G g;
     for (size_t r = 0; r < P; ++r) {
@@ -550,8 +624,11 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
       g.add(rows[r].Q[ord[f]], src, dst);
     }
     CHK(gemm_run(s, qt, f == 3 ? F64 : qt, n, k, n, vq, vb, vb, g));
-    if (f == 1)
-      for (size_t r = 0; r < P; ++r) HIPCHK(convert(s, qt, rows[r].R->q2, F64, mid[r], (int64_t)n * k));
+    if (f == 1) {
+      Xfer cv;
+      for (size_t r = 0; r < P; ++r) cv.add(rows[r].R->q2, mid[r], (int64_t)n * k);
+      CHK(xfer_run(s, qt, F64, cv));
+    }
   }
   return CTM_OK;
 }
@@ -580,8 +657,9 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
     G gm;
     for (size_t r = 0; r < P; ++r) gm.add(Y[r], rows[r].R->Rinv, rows[r].R->tmp);
     CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gm));
-    for (size_t r = 0; r < P; ++r)
-      HIPCHK(d2d(Y[r], rows[r].R->tmp, (size_t)n * k * 8, s));
+    Xfer cp;
+    for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, Y[r], (int64_t)n * k);
+    CHK(xfer_run(s, F64, F64, cp));
   }
   return CTM_OK;
 }
@@ -589,7 +667,7 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
 // Truncated SVD of N = (Lh Uh)^T by block subspace iteration with
 // Rayleigh-Ritz, then the projectors
 //   P1 = Lh^T V S^{-1/2},   P2^T = Uh U S^{-1/2}   (kept columns only).
-ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) {
+ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, uint64_t key) {
   hipStream_t s = x.stream;
   const int n = I.n, k = I.k, chi = I.chi;
   const size_t P = rows.size();
@@ -606,7 +684,10 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
       pr.p[r] = rows[r].warm ? rows[r].skeep : nullptr;
       st.p[r] = rows[r].R->st;
     }
-    HIPCHK(warm_start(s, n, k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (++I.solves), (int)P));
+    // the random columns of the start block depend only on the cut group
+    // (direction, column, launch), not on how often it was solved, so a
+    // captured sweep replays exactly what the eager sweep computes
+    HIPCHK(warm_start(s, n, k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (key + 1), (int)P));
     HIPCHK(reset_status(s, st, (int)P));
   }
   std::vector<double*> V(P), Yb(P), Qb(P), Z(P), LV(P), UU(P), Ub(P), Vpv(P);
@@ -620,8 +701,9 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
   const bool adaptive = c.svd_resid_tol > 0;
   std::vector<SolveStatus> hst(P);
   auto copy_blocks = [&](std::vector<double*>& dst, const std::vector<double*>& src) -> ctm_status {
-    for (size_t r = 0; r < P; ++r) HIPCHK(d2d(dst[r], src[r], (size_t)n * k * 8, s));
-    return CTM_OK;
+    Xfer cp;
+    for (size_t r = 0; r < P; ++r) cp.add(src[r], dst[r], (int64_t)n * k);
+    return xfer_run(s, F64, F64, cp);
   };
   // One Rayleigh-Ritz iteration: Y = N V = Q R, R = U_R S W_R^T, then the
   // left vectors U = Q U_R, right vectors V' = V W_R, Z = N^T U and the
@@ -662,7 +744,9 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gu));
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gv));
       CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gl));
-      for (size_t r = 0; r < P; ++r) HIPCHK(d2d(LV[r], rows[r].R->tmp, (size_t)n * k * 8, s));
+      Xfer cp;
+      for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
+      CHK(xfer_run(s, F64, F64, cp));
     }
     CHK(napply(x, n, k, rows, Ub, Z, UU, true));           // Z = N^T U, UU = Uh U
     {
@@ -722,79 +806,103 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows) 
     CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g1));
     CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g2));
     // keep the right vectors and status for the next solve on the same cut
+    static_assert(sizeof(SolveStatus) % 8 == 0, "status copied as 8-byte words");
+    Xfer cp;
     for (size_t r = 0; r < P; ++r) {
-      HIPCHK(d2d(rows[r].Vkeep, Vpv[r], (size_t)n * k * 8, s));
-      HIPCHK(d2d(rows[r].skeep, rows[r].R->st, sizeof(SolveStatus), s));
+      cp.add(Vpv[r], rows[r].Vkeep, (int64_t)n * k);
+      cp.add(rows[r].R->st, rows[r].skeep, (int64_t)(sizeof(SolveStatus) / 8));
     }
+    CHK(xfer_run(s, F64, F64, cp));
   }
   return CTM_OK;
 }
 
 // ---------------------------------------------------------------------------
-// absorption for one row (frame roles):
+// absorption, every row of every instance of a class together (frame roles):
 //   C1'  = P1[y-1]^T (C1 T1)
 //   T4'  = P1[y]^T-contracted ( (T4 P2[y-1]^T) b )
 //   C4'  = (T3 C4) P2[y]^T-contracted
+// then every new tensor divided by its Frobenius norm and stored.
 // ---------------------------------------------------------------------------
-ctm_status frob_normalize(ctm_ctx_s& x, Row& R, double* t, int64_t n) {
-  HIPCHK(sumsq(x.stream, t, n, R.red, R.sums));
-  HIPCHK(scale_by_rsqrt(x.stream, t, n, R.sums));
-  return CTM_OK;
-}
-
-ctm_status absorb_row(ctm_ctx_s& x, Inst& I, const Roles& ro, int xp, int yp, Row& R,
-                      Row& Rprev) {
+ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int xp) {
   hipStream_t s = x.stream;
   const int at = x.wt;
-  const int64_t c = I.chi, D2 = I.D2, n = I.n;
+  const Inst& I0 = *insts[0];
+  const int64_t c = I0.chi, D2 = I0.D2, n = I0.n;
+  int lx, ly;
+  frame_dims(k, x.Lx, x.Ly, lx, ly);
+  G g1, g2, g3, g4, g5, g6, g7;
+  for (Inst* I : insts) {
+    Roles ro{&x, I, k};
+    for (int yp = 0; yp < ly; ++yp) {
+      Row& R = I->rows[yp];
+      Row& Rp = I->rows[pmod(yp - 1, ly)];
+      g1.add(ro.Cw(0, xp, yp), ro.Tw(0, xp, yp), R.CT);
+      g2.add(Rp.P1w, R.CT, R.nC1);
+      g3.add(ro.Tw(3, xp, yp), Rp.P2Tw, R.W1);
+      g4.add(R.W1, ro.bw(xp, yp, 0), R.W2);
+      g5.add(R.P1w, R.W2, R.nT4);
+      g6.add(ro.Tw(2, xp, yp), ro.Cw(3, xp, yp), R.X6);
+      g7.add(R.X6, R.P2Tw, R.nC4);
+    }
+  }
   // C1' [b', r] = sum_(a,U) P1prev[(a,U), b'] CT[(a,U), r]
-  CHK(gemm1(s, at, at, c, D2 * c, c, rowmajor(c), ro.Cw(0, xp, yp), rowmajor(D2 * c), ro.Tw(0, xp, yp),
-            rowmajor(D2 * c), R.CT));
-  CHK(gemm1(s, at, F64, c, c, n, transposed(rowmajor(c)), Rprev.P1w, rowmajor(c), R.CT, rowmajor(c), R.nC1));
+  CHK(gemm_run(s, at, at, c, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g1));
+  CHK(gemm_run(s, at, F64, c, c, n, transposed(rowmajor(c)), rowmajor(c), rowmajor(c), g2));
   // W1[(g,l),(u,c2)] = sum_p T4[(g,l),p] P2T_prev[(p,u), c2]
-  CHK(gemm1(s, at, at, c * D2, D2 * c, c, rowmajor(c), ro.Tw(3, xp, yp), rowmajor(D2 * c), Rprev.P2Tw,
-            rowmajor(D2 * c), R.W1));
+  CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
   // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)]
-  {
-    View va = view2(c, 1, D2 * D2 * c, BIG, c, 0);
-    CHK(gemm1(s, at, at, c * c, D2 * D2, D2 * D2, va, R.W1, rowmajor(D2 * D2), ro.bw(xp, yp, 0),
-              rowmajor(D2 * D2), R.W2));
-  }
+  CHK(gemm_run(s, at, at, c * c, D2 * D2, D2 * D2, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(D2 * D2),
+               rowmajor(D2 * D2), g4));
   // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
-  {
-    // B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
-    // B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
-    View vb = view2(D2, D2, c * D2 * D2, c, D2 * D2, 1);
-    CHK(gemm1(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), R.P1w, vb, R.W2, rowmajor(D2 * c), R.nT4));
-  }
+  //   B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
+  //   B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
+  CHK(gemm_run(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), view2(D2, D2, c * D2 * D2, c, D2 * D2, 1),
+               rowmajor(D2 * c), g5));
   // X6[z, (g, dn)] = sum_q T3[(z,dn), q] C4[q, g]  written as [z][g][dn]
-  {
-    View vc = view2(D2, 1, c * D2, BIG, D2, 0);
-    CHK(gemm1(s, at, at, c * D2, c, c, rowmajor(c), ro.Tw(2, xp, yp), rowmajor(c), ro.Cw(3, xp, yp), vc, R.X6));
-  }
+  CHK(gemm_run(s, at, at, c * D2, c, c, rowmajor(c), rowmajor(c), view2(D2, 1, c * D2, BIG, D2, 0), g6));
   // C4'[z, c] = sum_(g,dn) X6[z,(g,dn)] P2T[(g,dn), c]
-  CHK(gemm1(s, at, F64, c, c, n, rowmajor(n), R.X6, rowmajor(c), R.P2Tw, rowmajor(c), R.nC4));
-  CHK(frob_normalize(x, R, R.nC1, c * c));
-  CHK(frob_normalize(x, R, R.nT4, c * c * D2));
-  CHK(frob_normalize(x, R, R.nC4, c * c));
+  CHK(gemm_run(s, at, F64, c, c, n, rowmajor(n), rowmajor(c), rowmajor(c), g7));
+  // normalise, then store into the environment (all projectors of the column
+  // step were computed before any tensor is replaced)
+  std::vector<std::pair<double*, int64_t>> nt;
+  Xfer st;
+  for (Inst* I : insts) {
+    Roles ro{&x, I, k};
+    for (int yp = 0; yp < ly; ++yp) {
+      Row& R = I->rows[yp];
+      nt.push_back({R.nC1, c * c});
+      nt.push_back({R.nT4, c * c * D2});
+      nt.push_back({R.nC4, c * c});
+      st.add(R.nC1, ro.C(0, xp + 1, yp), c * c);
+      st.add(R.nT4, ro.T(3, xp + 1, yp), c * c * D2);
+      st.add(R.nC4, ro.C(3, xp + 1, yp), c * c);
+    }
+  }
+  CHK(normalize_run(x, nt));
+  CHK(xfer_run(s, F64, F64, st));
   return CTM_OK;
 }
 
-ctm_status refresh_working(ctm_ctx_s& x, Inst& I) {
+// working-precision copies of every corner and edge of the instances
+ctm_status refresh_working(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
   if (x.wt == F64) return CTM_OK;
   const int npos = x.Lx * x.Ly;
-  const int64_t c2 = (int64_t)I.chi * I.chi, t3 = c2 * I.D2;
-  for (int c = 0; c < 4; ++c)
-    for (int p = 0; p < npos; ++p) {
-      HIPCHK(convert(x.stream, F64, I.C[c][p], x.wt, I.Cw[c][p], c2));
-      HIPCHK(convert(x.stream, F64, I.T[c][p], x.wt, I.Tw[c][p], t3));
-      if (I.TwP[c][p]) {
-        int64_t dims[3] = {I.chi, I.D2, I.chi};
-        int perm[3] = {0, 2, 1};
-        HIPCHK(permute(x.stream, F64, I.T[c][p], x.wt, I.TwP[c][p], 3, dims, perm));
+  Xfer cv;
+  for (Inst* I : insts) {
+    const int64_t c2 = (int64_t)I->chi * I->chi, t3 = c2 * I->D2;
+    for (int c = 0; c < 4; ++c)
+      for (int p = 0; p < npos; ++p) {
+        cv.add(I->C[c][p], I->Cw[c][p], c2);
+        cv.add(I->T[c][p], I->Tw[c][p], t3);
+        if (I->TwP[c][p]) {
+          int64_t dims[3] = {I->chi, I->D2, I->chi};
+          int perm[3] = {0, 2, 1};
+          HIPCHK(permute(x.stream, F64, I->T[c][p], x.wt, I->TwP[c][p], 3, dims, perm));
+        }
       }
-    }
-  return CTM_OK;
+  }
+  return xfer_run(x.stream, F64, x.wt, cv);
 }
 
 void ev_record(ctm_ctx_s& x, int i) {
@@ -808,34 +916,39 @@ double ev_ms(ctm_ctx_s& x, int a, int b) {
   return ms * 1e-3;
 }
 
-// One column step of the move in direction k at frame column xp.
-ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
+// One column step of the move in direction k at frame column xp, for every
+// instance of one class (equal d, D, chi) in lock-step: each stage is one
+// grouped launch over all rows of all of them.
+ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int xp) {
   hipStream_t s = x.stream;
-  Roles ro{&x, &I, k};
+  Inst& I0 = *insts[0];
   int lx, ly;
   frame_dims(k, x.Lx, x.Ly, lx, ly);
-  CHK(refresh_working(x, I));
+  CHK(refresh_working(x, insts));
   ev_record(x, 0);
   // enlarged corners of every plaquette (xp, yp)
   std::vector<CornerJob> jobs;
-  for (int yp = 0; yp < ly; ++yp) {
-    Row& R = x.rows[yp];
-    const int cx[4] = {xp, xp + 1, xp + 1, xp};
-    const int cy[4] = {yp, yp, yp + 1, yp + 1};
-    for (int q = 0; q < 4; ++q) {
-      CornerJob j;
-      j.C = ro.Cw(q, cx[q], cy[q]);
-      j.Tn = ro.Tw(q, cx[q], cy[q]);
-      j.Tp = ro.Tw((q + 3) % 4, cx[q], cy[q]);
-      j.b = ro.bw(cx[q], cy[q], q);
-      j.X = R.X[q];
-      j.Y = R.Y[q];
-      j.Q = R.Q[q];
-      if (x.wt == BF16) {
-        j.TnP = ro.TwP(q, cx[q], cy[q]);
-        j.bT = ro.bT(cx[q], cy[q], q);
+  for (Inst* I : insts) {
+    Roles ro{&x, I, k};
+    for (int yp = 0; yp < ly; ++yp) {
+      Row& R = I->rows[yp];
+      const int cx[4] = {xp, xp + 1, xp + 1, xp};
+      const int cy[4] = {yp, yp, yp + 1, yp + 1};
+      for (int q = 0; q < 4; ++q) {
+        CornerJob j;
+        j.C = ro.Cw(q, cx[q], cy[q]);
+        j.Tn = ro.Tw(q, cx[q], cy[q]);
+        j.Tp = ro.Tw((q + 3) % 4, cx[q], cy[q]);
+        j.b = ro.bw(cx[q], cy[q], q);
+        j.X = R.X[q];
+        j.Y = R.Y[q];
+        j.Q = R.Q[q];
+        if (x.prec == CTM_BF16) {
+          j.TnP = ro.TwP(q, cx[q], cy[q]);
+          j.bT = ro.bT(cx[q], cy[q], q);
+        }
+        jobs.push_back(j);
       }
-      jobs.push_back(j);
     }
   }
   Stage3Timer tm;
@@ -846,44 +959,48 @@ ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
     tm.count = &x.stage3_launches;
     // algorithmic work of the (l,u)-contraction with the double layer:
     // 2 chi^2 D^8 flop per corner
-    x.stage3_flop += 2.0 * (double)I.chi * I.chi * (double)I.D2 * I.D2 * I.D2 * I.D2 * (double)jobs.size();
+    x.stage3_flop += 2.0 * (double)I0.chi * I0.chi * (double)I0.D2 * I0.D2 * I0.D2 * I0.D2 * (double)jobs.size();
   }
-  CHK(corner_chain(s, x.wt, x.qt, I.chi, I.D2, jobs, x.timing ? &tm : nullptr));
+  CHK(corner_chain(s, x.wt, x.qt, I0.chi, I0.D2, jobs, x.timing ? &tm : nullptr, x.prec == CTM_BF16));
   x.corner_launches += 3 * ((jobs.size() + MAXG - 1) / MAXG);
   x.moves += 1;
   ev_record(x, 1);
-  // projectors, all rows together
+  // projectors, all rows together (at most MAXP problems per launch)
   std::vector<SolveRow> rows;
-  for (int yp = 0; yp < ly; ++yp) {
-    SolveRow sr;
-    Row& R = x.rows[yp];
-    for (int q = 0; q < 4; ++q) sr.Q[q] = R.Q[q];
-    sr.R = &R;
-    int cut = ro.cut(xp, yp);
-    sr.Vkeep = I.Vkeep[k][cut];
-    sr.skeep = I.skeep[k][cut];
-    sr.warm = I.has_keep[k][cut];
-    rows.push_back(sr);
-  }
-  CHK(solve_projectors(x, I, rows));
-  for (int yp = 0; yp < ly; ++yp) I.has_keep[k][ro.cut(xp, yp)] = true;
-  if (x.wt != F64)
+  for (Inst* I : insts) {
+    Roles ro{&x, I, k};
     for (int yp = 0; yp < ly; ++yp) {
-      Row& R = x.rows[yp];
-      HIPCHK(convert(s, F64, R.P1, x.wt, R.P1w, (int64_t)I.n * I.chi));
-      HIPCHK(convert(s, F64, R.P2T, x.wt, R.P2Tw, (int64_t)I.n * I.chi));
+      SolveRow sr;
+      Row& R = I->rows[yp];
+      for (int q = 0; q < 4; ++q) sr.Q[q] = R.Q[q];
+      sr.R = &R;
+      int cut = ro.cut(xp, yp);
+      sr.Vkeep = I->Vkeep[k][cut];
+      sr.skeep = I->skeep[k][cut];
+      sr.warm = I->has_keep[k][cut];
+      rows.push_back(sr);
     }
-  ev_record(x, 2);
-  // absorption
-  for (int yp = 0; yp < ly; ++yp)
-    CHK(absorb_row(x, I, ro, xp, yp, x.rows[yp], x.rows[pmod(yp - 1, ly)]));
-  const int64_t c2 = (int64_t)I.chi * I.chi, t3 = c2 * I.D2;
-  for (int yp = 0; yp < ly; ++yp) {
-    Row& R = x.rows[yp];
-    HIPCHK(d2d(ro.C(0, xp + 1, yp), R.nC1, c2 * 8, s));
-    HIPCHK(d2d(ro.T(3, xp + 1, yp), R.nT4, t3 * 8, s));
-    HIPCHK(d2d(ro.C(3, xp + 1, yp), R.nC4, c2 * 8, s));
   }
+  for (size_t r0 = 0; r0 < rows.size(); r0 += MAXP) {
+    std::vector<SolveRow> part(rows.begin() + r0, rows.begin() + std::min(rows.size(), r0 + MAXP));
+    CHK(solve_projectors(x, I0, part, ((uint64_t)k * MAXPOS + (uint64_t)xp) * 4096 + r0 / MAXP));
+  }
+  for (Inst* I : insts) {
+    Roles ro{&x, I, k};
+    for (int yp = 0; yp < ly; ++yp) I->has_keep[k][ro.cut(xp, yp)] = true;
+  }
+  if (x.wt != F64) {
+    Xfer cv;
+    for (Inst* I : insts)
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        cv.add(R.P1, R.P1w, (int64_t)I->n * I->chi);
+        cv.add(R.P2T, R.P2Tw, (int64_t)I->n * I->chi);
+      }
+    CHK(xfer_run(s, F64, x.wt, cv));
+  }
+  ev_record(x, 2);
+  CHK(absorb_rows(x, insts, k, xp));
   ev_record(x, 3);
   if (x.timing) {
     x.t_corner += ev_ms(x, 0, 1);
@@ -896,15 +1013,22 @@ ctm_status column_step(ctm_ctx_s& x, Inst& I, int k, int xp) {
 // ---------------------------------------------------------------------------
 // corner spectra and the convergence measure
 // ---------------------------------------------------------------------------
-__global__ void spectra_delta_kernel(const double* __restrict__ S, int chi, int ncorner,
-                                     double* __restrict__ spec_new, double* __restrict__ spec_old,
-                                     double* __restrict__ delta, int* flag, int first, int commit) {
-  // one block; S holds ncorner spectra (descending) of length chi
+struct SpecSet {
+  double* spec_new[MAXP];
+  double* spec_old[MAXP];
+  double* delta[MAXP];
+  int* flag[MAXP];
+};
+
+// one block per instance; spec_new holds its ncorner spectra (descending, length chi)
+__global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int first, int commit) {
   __shared__ double red[256];
+  double* __restrict__ spec_new = ss.spec_new[blockIdx.x];
+  double* __restrict__ spec_old = ss.spec_old[blockIdx.x];
   double dmax = 0.0;
   for (int c = 0; c < ncorner; ++c) {
     double tot = 0.0;
-    for (int i = threadIdx.x; i < chi; i += blockDim.x) tot += S[c * chi + i];
+    for (int i = threadIdx.x; i < chi; i += blockDim.x) tot += spec_new[c * chi + i];
     red[threadIdx.x] = tot;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -915,8 +1039,8 @@ __global__ void spectra_delta_kernel(const double* __restrict__ S, int chi, int 
     __syncthreads();
     double d = 0.0;
     for (int i = threadIdx.x; i < chi; i += blockDim.x) {
-      double v = tot > 0 ? S[c * chi + i] / tot : S[c * chi + i];
-      if (!isfinite(v)) *flag = 1;
+      double v = tot > 0 ? spec_new[c * chi + i] / tot : spec_new[c * chi + i];
+      if (!isfinite(v)) *ss.flag[blockIdx.x] = 1;
       spec_new[c * chi + i] = v;
       d += fabs(v - spec_old[c * chi + i]);
     }
@@ -929,37 +1053,53 @@ __global__ void spectra_delta_kernel(const double* __restrict__ S, int chi, int 
     dmax = fmax(dmax, red[0]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *delta = first ? INFINITY : dmax;
+  if (threadIdx.x == 0) *ss.delta[blockIdx.x] = first ? INFINITY : dmax;
   if (commit) {
     __syncthreads();
     for (int i = threadIdx.x; i < ncorner * chi; i += blockDim.x) spec_old[i] = spec_new[i];
   }
 }
 
-ctm_status corner_spectra(ctm_ctx_s& x, Inst& I, bool first, bool commit) {
+// singular values of every corner of the instances (one class), normalised
+// to unit sum; Delta = largest l1 change against the previous spectra
+ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool first, bool commit) {
   hipStream_t s = x.stream;
-  const int npos = x.Lx * x.Ly, nc = 4 * npos, chi = I.chi;
-  for (int c0 = 0; c0 < nc; c0 += 8) {
-    int c1 = std::min(nc, c0 + 8);
+  const int npos = x.Lx * x.Ly, nc = 4 * npos, chi = insts[0]->chi;
+  const size_t c2 = (size_t)chi * chi;
+  std::vector<std::pair<const double*, double*>> probs;  // (corner, output spectrum)
+  for (Inst* I : insts)
+    for (int c = 0; c < nc; ++c) probs.push_back({I->C[c % 4][c / 4], I->spec_new + (size_t)c * chi});
+  for (size_t c0 = 0; c0 < probs.size(); c0 += MAXP) {
+    int cnt = (int)std::min<size_t>(MAXP, probs.size() - c0);
     CPtrSet M{};
     PtrSet U{}, S{}, W{}, J{};
-    for (int c = c0; c < c1; ++c) {
-      int pos = c / 4, corner = c % 4;
-      M.p[c - c0] = I.C[corner][pos];
-      U.p[c - c0] = x.spec_tmp_U + (size_t)(c - c0) * chi * chi;
-      W.p[c - c0] = x.spec_tmp_W + (size_t)(c - c0) * chi * chi;
-      S.p[c - c0] = I.spec_new + (size_t)c * chi;
-      J.p[c - c0] = x.spec_tmp_J + (size_t)(c - c0) * 2 * chi * chi;
+    for (int j = 0; j < cnt; ++j) {
+      M.p[j] = probs[c0 + j].first;
+      S.p[j] = probs[c0 + j].second;
+      U.p[j] = x.spec_tmp_U + (size_t)j * c2;
+      W.p[j] = x.spec_tmp_W + (size_t)j * c2;
+      J.p[j] = x.spec_tmp_J + (size_t)j * 2 * c2;
     }
     // corner singular values far below the solver cutoff carry no information
-    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, c1 - c0, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff));
+    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, cnt, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff));
   }
-  HIPCHK(spans({{I.spec_new, (size_t)nc * chi * 8}, {I.spec_old, (size_t)nc * chi * 8}, {I.delta, 8},
-                {I.flag, 4}}, "spectra"));
-  if (!dry_run())
-    hipLaunchKernelGGL(spectra_delta_kernel, dim3(1), dim3(256), 0, s, I.spec_new, chi, nc, I.spec_new,
-                       I.spec_old, I.delta, I.flag, first ? 1 : 0, commit ? 1 : 0);
-  HIPCHK(last_err());
+  for (size_t i0 = 0; i0 < insts.size(); i0 += MAXP) {
+    int cnt = (int)std::min<size_t>(MAXP, insts.size() - i0);
+    SpecSet ss{};
+    for (int j = 0; j < cnt; ++j) {
+      Inst* I = insts[i0 + j];
+      HIPCHK(spans({{I->spec_new, (size_t)nc * chi * 8}, {I->spec_old, (size_t)nc * chi * 8}, {I->delta, 8},
+                    {I->flag, 4}}, "spectra"));
+      ss.spec_new[j] = I->spec_new;
+      ss.spec_old[j] = I->spec_old;
+      ss.delta[j] = I->delta;
+      ss.flag[j] = I->flag;
+    }
+    if (!dry_run())
+      hipLaunchKernelGGL(spectra_delta_kernel, dim3(cnt), dim3(256), 0, s, ss, chi, nc, first ? 1 : 0,
+                         commit ? 1 : 0);
+    HIPCHK(last_err());
+  }
   return CTM_OK;
 }
 
@@ -1040,6 +1180,20 @@ ctm_status build_ctx(const ctm_config* cfg, ctm_ctx_s& x) {
     I.n = I.chi * I.D2;
     I.k = subspace_dim(x.cfg, I.chi, I.n);
   }
+  // classes of instances with equal (d, D, chi), in order of first appearance
+  x.classes.clear();
+  for (int i = 0; i < x.ninst; ++i) {
+    bool placed = false;
+    for (auto& cls : x.classes) {
+      const Inst& J = x.inst[cls[0]];
+      if (J.d == x.inst[i].d && J.D == x.inst[i].D && J.chi == x.inst[i].chi) {
+        cls.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) x.classes.push_back({i});
+  }
   Arena ar;
   plan(x, ar);
   x.ws_need = ar.off + 256;
@@ -1078,41 +1232,84 @@ ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double*
     }
   }
   if (init == CTM_INIT_DIAG) {
-    Row& R = x.rows[0];
+    std::vector<std::pair<double*, int64_t>> nt;
     for (int p = 0; p < npos; ++p)
       for (int c = 0; c < 4; ++c) {
-        CHK(frob_normalize(x, R, I.C[c][p], (int64_t)I.chi * I.chi));
-        CHK(frob_normalize(x, R, I.T[c][p], (int64_t)I.chi * I.chi * I.D2));
+        nt.push_back({I.C[c][p], (int64_t)I.chi * I.chi});
+        nt.push_back({I.T[c][p], (int64_t)I.chi * I.chi * I.D2});
       }
+    CHK(normalize_run(x, nt));
   }
   HIPCHK(dmemset(I.spec_old, 0, (size_t)npos * 4 * I.chi * 8, s));
   HIPCHK(dmemset(I.flag, 0, sizeof(int) * 4, s));
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < npos; ++p) I.has_keep[c][p] = false;
   for (int c = 0; c < 4; ++c) I.cursor[c] = 0;
-  CHK(corner_spectra(x, I, true, true));
+  std::vector<Inst*> one{&I};
+  CHK(corner_spectra(x, one, true, true));
   return CTM_OK;
 }
 
-ctm_status do_move(ctm_ctx_s& x, Inst& I, int dir, int count) {
+std::vector<Inst*> class_insts(ctm_ctx_s& x, const std::vector<int>& cls) {
+  std::vector<Inst*> v;
+  for (int i : cls) v.push_back(&x.inst[i]);
+  return v;
+}
+
+ctm_status do_move(ctm_ctx_s& x, const std::vector<Inst*>& insts, int dir, int count) {
   int lx, ly;
+  frame_dims(dir, x.Lx, x.Ly, lx, ly);
   for (int i = 0; i < count; ++i) {
-    frame_dims(dir, x.Lx, x.Ly, lx, ly);
-    int xp = I.cursor[dir];
-    CHK(column_step(x, I, dir, xp));
-    I.cursor[dir] = (xp + 1) % lx;
+    int xp = insts[0]->cursor[dir];
+    CHK(column_step(x, insts, dir, xp));
+    for (Inst* I : insts) I->cursor[dir] = (xp + 1) % lx;
   }
   return CTM_OK;
 }
 
-ctm_status do_sweep(ctm_ctx_s& x, Inst& I) {
+ctm_status do_sweep(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
   const int order[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
   for (int o = 0; o < 4; ++o) {
     int lx, ly;
     frame_dims(order[o], x.Lx, x.Ly, lx, ly);
-    CHK(do_move(x, I, order[o], lx));
+    CHK(do_move(x, insts, order[o], lx));
   }
   return CTM_OK;
+}
+
+// One sweep of every class followed by the corner spectra and Delta of every
+// instance, captured once as a HIP graph and replayed (graph mode).  The
+// capture happens after an eager sweep, so that every cut has a kept subspace
+// (the solver's warm start) and every GEMM shape has been tuned.
+ctm_status capture_sweep(ctm_ctx_s& x) {
+  if (x.gexec) return CTM_OK;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal));
+  ctm_status st = CTM_OK;
+  const int64_t moves0 = x.moves;
+  for (auto& cls : x.classes) {
+    std::vector<Inst*> insts = class_insts(x, cls);
+    st = do_sweep(x, insts);
+    if (st != CTM_OK) break;
+    st = corner_spectra(x, insts, false, true);
+    if (st != CTM_OK) break;
+  }
+  x.moves = moves0;
+  hipError_t e = hipStreamEndCapture(x.stream, &g);
+  if (st != CTM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  HIPCHK(e);
+  e = hipGraphInstantiate(&x.gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) x.gexec = nullptr;
+  HIPCHK(e);
+  return CTM_OK;
+}
+
+bool graph_usable(const ctm_ctx_s& x) {
+  return x.cfg.use_graph && !(x.cfg.svd_resid_tol > 0) && !x.timing && !dry_run() && x.stream != nullptr;
 }
 
 }  // namespace
@@ -1292,7 +1489,7 @@ ctm_status z11_2x2(ctm_ctx_s& x, Inst& I, double* out) {
     j.Y = O.Y;
     j.Q = O.Q[q];
     std::vector<CornerJob> one{j};
-    CHK(corner_chain(s, F64, F64, I.chi, I.D2, one));
+    CHK(corner_chain(s, F64, F64, I.chi, I.D2, one, nullptr, false));
   }
   CHK(gemm1(s, F64, F64, n, n, n, rowmajor(n), O.Q[0], rowmajor(n), O.Q[1], rowmajor(n), O.Uh));
   CHK(gemm1(s, F64, F64, n, n, n, rowmajor(n), O.Q[2], rowmajor(n), O.Q[3], colmajor(n), O.LhT));
@@ -1451,6 +1648,8 @@ void ctm_config_default(ctm_config* c) {
   c->svd_resid_tol = 1e-13;
   c->svd_cutoff = 1e-12;
   c->seed = 12345;
+  c->use_graph = 0;
+  c->autotune = 1;
 }
 
 ctm_status ctm_workspace_size(const ctm_config* cfg, size_t* bytes) {
@@ -1520,7 +1719,7 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           if (convert(x->stream, F64, I.b64[t][r], x->wt, I.bw[t][r], (int64_t)I.D2 * I.D2 * I.D2 * I.D2) !=
               hipSuccess)
             return cleanup(fail(CTM_E_HIP, "convert"));
-      if (x->wt == BF16)
+      if (x->prec == CTM_BF16)
         for (int r = 0; r < 4; ++r) {
           int64_t dims[2] = {(int64_t)I.D2 * I.D2, (int64_t)I.D2 * I.D2};
           int perm[2] = {1, 0};
@@ -1547,12 +1746,14 @@ ctm_status ctm_init(const ctm_config* cfg, const double* const* A_dev, const dou
 ctm_status ctm_move(ctm_ctx x, int32_t dir, int32_t count) {
   if (!x) return fail(CTM_E_INVALID, "null ctx");
   RegGuard guard(&x->reg);
+  TuneGuard tg(x->cfg.autotune != 0);
   if (count < 0 || dir < 0 || dir > CTM_SWEEP) return fail(CTM_E_INVALID, "dir/count");
-  for (Inst& I : x->inst) {
+  for (auto& cls : x->classes) {
+    std::vector<Inst*> insts = class_insts(*x, cls);
     if (dir == CTM_SWEEP) {
-      for (int i = 0; i < count; ++i) CHK(do_sweep(*x, I));
+      for (int i = 0; i < count; ++i) CHK(do_sweep(*x, insts));
     } else {
-      CHK(do_move(*x, I, dir, count));
+      CHK(do_move(*x, insts, dir, count));
     }
   }
   return CTM_OK;
@@ -1562,32 +1763,65 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
                         int32_t* sweeps_out, double* delta_out) {
   if (!x) return fail(CTM_E_INVALID, "null ctx");
   RegGuard guard(&x->reg);
+  TuneGuard tg(x->cfg.autotune != 0);
   if (max_sweeps < 0 || !(tol >= 0)) return fail(CTM_E_INVALID, "tol/max_sweeps");
   if (check_every < 1) check_every = 1;
-  bool all_ok = true;
+  const int ni = x->ninst;
+  // instance i is reported at the first checked sweep with Delta < tol; the
+  // instances of a class keep sweeping together until all of them converged
+  std::vector<int> done(ni, 0), conv(ni, 0);
+  std::vector<double> dl(ni, INFINITY);
+  std::vector<double> hd(ni);
+  std::vector<int> hf(4 * ni);
+  std::vector<char> active(x->classes.size(), 1);
   bool bad = false;
-  for (int i = 0; i < x->ninst; ++i) {
-    Inst& I = x->inst[i];
-    double dlt = INFINITY;
-    int done = 0;
-    bool conv = false;
-    while (done < max_sweeps) {
-      CHK(do_sweep(*x, I));
-      ++done;
-      bool check = (done % check_every == 0) || done == max_sweeps;
-      CHK(corner_spectra(*x, I, false, true));
-      if (check) {
-        int fl = 0;
-        HIPCHK(d2h(&dlt, I.delta, 8, x->stream));
-        HIPCHK(d2h(&fl, I.flag, sizeof(int), x->stream));
-        HIPCHK(ssync(x->stream));
-        if (fl || !std::isfinite(dlt)) { bad = true; break; }
-        if (dlt < tol) { conv = true; break; }
+  bool cursors0 = true;
+  for (const Inst& I : x->inst)
+    for (int c = 0; c < 4; ++c) cursors0 = cursors0 && I.cursor[c] == 0;
+  const bool graph = graph_usable(*x) && cursors0;
+  int sweep = 0;
+  while (sweep < max_sweeps) {
+    const bool use_graph = graph && sweep >= 1;
+    if (use_graph) {
+      CHK(capture_sweep(*x));
+      HIPCHK(hipGraphLaunch(x->gexec, x->stream));
+      x->moves += (int64_t)(2 * x->Lx + 2 * x->Ly) * (int64_t)x->classes.size();
+    } else {
+      for (size_t c = 0; c < x->classes.size(); ++c) {
+        if (!active[c] && !graph) continue;
+        std::vector<Inst*> insts = class_insts(*x, x->classes[c]);
+        CHK(do_sweep(*x, insts));
+        CHK(corner_spectra(*x, insts, false, true));
       }
     }
-    if (sweeps_out) sweeps_out[i] = done;
-    if (delta_out) delta_out[i] = dlt;
-    all_ok = all_ok && conv;
+    ++sweep;
+    const bool check = (sweep % check_every == 0) || sweep == max_sweeps;
+    if (!check) continue;
+    HIPCHK(d2h(hd.data(), x->delta_all, (size_t)ni * 8, x->stream));
+    HIPCHK(d2h(hf.data(), x->flag_all, (size_t)ni * 16, x->stream));
+    HIPCHK(ssync(x->stream));
+    bool all = true;
+    for (size_t c = 0; c < x->classes.size(); ++c) {
+      if (!active[c]) continue;
+      bool cls_done = true;
+      for (int i : x->classes[c]) {
+        if (conv[i]) continue;
+        done[i] = sweep;
+        dl[i] = hd[i];
+        if (hf[4 * i] || !std::isfinite(hd[i])) bad = true;
+        else if (hd[i] < tol) conv[i] = 1;
+        cls_done = cls_done && conv[i];
+      }
+      if (cls_done) active[c] = 0;
+      all = all && cls_done;
+    }
+    if (bad || all) break;
+  }
+  bool all_ok = true;
+  for (int i = 0; i < ni; ++i) {
+    if (sweeps_out) sweeps_out[i] = done[i];
+    if (delta_out) delta_out[i] = dl[i];
+    all_ok = all_ok && conv[i];
   }
   if (bad) return fail(CTM_E_NONFINITE, "non-finite corner spectrum");
   if (!all_ok) return fail(CTM_E_NOCONV, "not converged within max_sweeps");
@@ -1598,7 +1832,7 @@ ctm_status ctm_spectra(ctm_ctx x, int32_t inst, double* out) {
   if (!x || !out || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
   RegGuard guard(&x->reg);
   Inst& I = x->inst[inst];
-  CHK(corner_spectra(*x, I, false, false));
+  CHK(corner_spectra(*x, std::vector<Inst*>{&I}, false, false));
   HIPCHK(d2h(out, I.spec_new, (size_t)x->Lx * x->Ly * 4 * I.chi * 8, x->stream));
   HIPCHK(ssync(x->stream));
   return CTM_OK;
@@ -1678,7 +1912,7 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
     for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.T[c][q], p, t3 * 8, x->stream)); p += t3 * 8; }
   for (int c = 0; c < 4; ++c)
     for (int q = 0; q < npos; ++q) I.has_keep[c][q] = false;
-  CHK(corner_spectra(*x, I, true, true));
+  CHK(corner_spectra(*x, std::vector<Inst*>{&I}, true, true));
   HIPCHK(ssync(x->stream));
   return CTM_OK;
 }
@@ -1706,6 +1940,7 @@ ctm_status ctm_get_timing(ctm_ctx x, double* v) {
 
 void ctm_destroy(ctm_ctx x) {
   if (!x) return;
+  if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
   for (int e = 0; e < 6; ++e)
     if (x->ev[e]) (void)hipEventDestroy(x->ev[e]);
   delete x;
@@ -1786,15 +2021,15 @@ ctm_status ctm_debug_dump(ctm_ctx x, int32_t what, int32_t index, void* buf, siz
   size_t need = 0;
   if (what == 0) {
     if (index < 0 || index >= 4 * rows) return fail(CTM_E_INVALID, "index");
-    src = x->rows[index / 4].Q[index % 4];
+    src = I.rows[index / 4].Q[index % 4];
     need = n * n * dtype_size(x->qt);
   } else if (what == 1 || what == 2) {
     if (index < 0 || index >= rows) return fail(CTM_E_INVALID, "index");
-    src = what == 1 ? x->rows[index].P1 : x->rows[index].P2T;
+    src = what == 1 ? I.rows[index].P1 : I.rows[index].P2T;
     need = n * chi * 8;
   } else if (what == 3) {
     if (index < 0 || index >= rows) return fail(CTM_E_INVALID, "index");
-    src = x->rows[index].st;
+    src = I.rows[index].st;
     need = sizeof(SolveStatus);
   } else {
     return fail(CTM_E_INVALID, "what");
@@ -1806,3 +2041,6 @@ ctm_status ctm_debug_dump(ctm_ctx x, int32_t what, int32_t index, void* buf, siz
 }
 
 }  // extern "C"
+
+// error reporting for the other C entry points of the library
+ctm_status ctm_internal_fail(ctm_status s, const char* msg) { return fail(s, msg); }

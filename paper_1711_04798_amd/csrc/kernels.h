@@ -50,7 +50,7 @@ inline View transposed(const View& v) {
 // largest element offset a view reaches over rows [0, R) and columns [0, C)
 int64_t view_max(const View& v, int64_t R, int64_t C);
 
-constexpr int MAXG = 16;  // problems per grouped launch
+constexpr int MAXG = 32;  // problems per grouped launch
 
 struct GemmGroup {
   const void* A[MAXG];
@@ -83,6 +83,33 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
 
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].
+// Tile-shape autotuning of the generic GEMM.  While enabled on the calling
+// thread, the first launch of each (types, M, N, K, operand order, groups)
+// outside stream capture times every tile variant on the real operands
+// (beta must be 0, so reruns are harmless; every variant sums K in the same
+// order, so results are bitwise identical) and caches the fastest for the
+// process.  Disabled, or while the stream is being captured, a cached choice
+// or the 64 x 64 default is used.
+void set_tuning(bool on);
+int tuned_entries();
+
+// Grouped element copy / conversion: dst[j][i] = (tout) src[j][i], i < n[j].
+constexpr int MAXJ = 32;
+struct XferSet {
+  const void* src[MAXJ];
+  void* dst[MAXJ];
+  int64_t n[MAXJ];
+};
+hipError_t convert_group(hipStream_t s, int tin, int tout, const XferSet& x, int njobs);
+
+// Grouped Frobenius normalisation p[j] /= ||p[j]||, float64; `partial` holds
+// MAXJ * 64 doubles of scratch.  Sums are taken in a fixed order.
+struct NormSet {
+  double* p[MAXJ];
+  int64_t n[MAXJ];
+};
+hipError_t normalize_group(hipStream_t s, const NormSet& x, int njobs, double* partial);
+
 hipError_t permute(hipStream_t s, int tin, const void* in, int tout, void* out,
                    int ndim, const int64_t* in_dims, const int* perm);
 

@@ -6,6 +6,9 @@
 #include <hip/hip_bf16.h>
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace ctmk {
 
@@ -262,15 +265,31 @@ gemm_kernel(int32_t M, int32_t N, int32_t K, double alpha, double beta,
   }
 }
 
-template <typename TI, typename TO, bool AK, bool BK_>
-static hipError_t launch_gemm_t(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
-                                const DevView& da, const DevView& db, double beta,
-                                const DevView& dc, const GemmGroup& g, int groups) {
-  constexpr int BM = 64, BN = 64;
+// Tile variants (BM x BN) of the generic GEMM; the autotuner picks one per shape.
+constexpr int NTILE = 4;
+constexpr int TILE_BM[NTILE] = {64, 32, 128, 128};
+constexpr int TILE_BN[NTILE] = {64, 32, 64, 128};
+
+template <typename TI, typename TO, bool AK, bool BK_, int BM, int BN>
+static hipError_t launch_gemm_tile(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+                                   const DevView& da, const DevView& db, double beta,
+                                   const DevView& dc, const GemmGroup& g, int groups) {
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)groups);
   hipLaunchKernelGGL((gemm_kernel<TI, TO, BM, BN, AK, BK_>), grid, dim3(256), 0, s,
                      (int32_t)M, (int32_t)N, (int32_t)K, alpha, beta, da, db, dc, g, 1);
   return hipGetLastError();
+}
+
+template <typename TI, typename TO, bool AK, bool BK_>
+static hipError_t launch_gemm_t(hipStream_t s, int tile, int64_t M, int64_t N, int64_t K, double alpha,
+                                const DevView& da, const DevView& db, double beta,
+                                const DevView& dc, const GemmGroup& g, int groups) {
+  switch (tile) {
+    case 1: return launch_gemm_tile<TI, TO, AK, BK_, 32, 32>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+    case 2: return launch_gemm_tile<TI, TO, AK, BK_, 128, 64>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+    case 3: return launch_gemm_tile<TI, TO, AK, BK_, 128, 128>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+    default: return launch_gemm_tile<TI, TO, AK, BK_, 64, 64>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -338,17 +357,92 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
 }
 
 template <typename TI, typename TO>
-static hipError_t launch_gemm_ab(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha,
+static hipError_t launch_gemm_ab(hipStream_t s, int tile, int64_t M, int64_t N, int64_t K, double alpha,
                                  const View& va, const View& vb, double beta, const View& vc,
                                  const GemmGroup& g, int groups) {
   DevView da = dev_view(va, M, K), db = dev_view(vb, K, N), dc = dev_view(vc, M, N);
   // A is "k fast" when its column (k) stride is 1; B is "k fast" when its row (k) stride is 1
   bool ak = (va.c_ls == 1);
   bool bk = (vb.r_ls == 1);
-  if (ak && bk) return launch_gemm_t<TI, TO, true, true>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
-  if (ak && !bk) return launch_gemm_t<TI, TO, true, false>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
-  if (!ak && bk) return launch_gemm_t<TI, TO, false, true>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
-  return launch_gemm_t<TI, TO, false, false>(s, M, N, K, alpha, da, db, beta, dc, g, groups);
+  if (ak && bk) return launch_gemm_t<TI, TO, true, true>(s, tile, M, N, K, alpha, da, db, beta, dc, g, groups);
+  if (ak && !bk) return launch_gemm_t<TI, TO, true, false>(s, tile, M, N, K, alpha, da, db, beta, dc, g, groups);
+  if (!ak && bk) return launch_gemm_t<TI, TO, false, true>(s, tile, M, N, K, alpha, da, db, beta, dc, g, groups);
+  return launch_gemm_t<TI, TO, false, false>(s, tile, M, N, K, alpha, da, db, beta, dc, g, groups);
+}
+
+static hipError_t launch_typed(hipStream_t s, int tile, int ta, int tc, int64_t M, int64_t N, int64_t K,
+                               double alpha, const View& va, const View& vb, double beta, const View& vc,
+                               const GemmGroup& g, int groups) {
+  if (ta == F64 && tc == F64) return launch_gemm_ab<double, double>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == F32) return launch_gemm_ab<float, float>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == F64) return launch_gemm_ab<float, double>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == F32) return launch_gemm_ab<__bf16, float>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == F64) return launch_gemm_ab<__bf16, double>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == BF16 && tc == BF16) return launch_gemm_ab<__bf16, __bf16>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  if (ta == F32 && tc == BF16) return launch_gemm_ab<float, __bf16>(s, tile, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: process-wide cache of the fastest tile per GEMM shape
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int dev, ta, tc, ak, bk, groups;
+  int64_t M, N, K;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, ta, tc, ak, bk, groups, M, N, K) <
+           std::tie(o.dev, o.ta, o.tc, o.ak, o.bk, o.groups, o.M, o.N, o.K);
+  }
+};
+std::map<TuneKey, int> g_tune;
+std::mutex g_tune_mu;
+thread_local bool g_tune_on = false;
+}  // namespace
+
+void set_tuning(bool on) { g_tune_on = on; }
+int tuned_entries() {
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+static int pick_tile(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, double alpha,
+                     const View& va, const View& vb, double beta, const View& vc, const GemmGroup& g,
+                     int groups) {
+  TuneKey key{0, ta, tc, va.c_ls == 1, vb.r_ls == 1, groups, M, N, K};
+  (void)hipGetDevice(&key.dev);
+  {
+    std::lock_guard<std::mutex> l(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  if (!g_tune_on || beta != 0.0) return 0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return 0;
+  }
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int t = 0; t < NTILE; ++t) {
+    float ms_min = 1e30f;
+    bool ok = true;
+    for (int rep = 0; rep < 2 && ok; ++rep) {
+      ok = hipEventRecord(e0, s) == hipSuccess &&
+           launch_typed(s, t, ta, tc, M, N, K, alpha, va, vb, beta, vc, g, groups) == hipSuccess &&
+           hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0;
+      if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+    }
+    if (ok && ms_min < best_ms) { best_ms = ms_min; best = t; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  g_tune[key] = best;
+  return best;
 }
 
 hipError_t gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, double alpha,
@@ -366,14 +460,8 @@ hipError_t gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, 
         return hipErrorInvalidValue;
     if (dry_run()) return hipSuccess;
   }
-  if (ta == F64 && tc == F64) return launch_gemm_ab<double, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == F32 && tc == F32) return launch_gemm_ab<float, float>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == F32 && tc == F64) return launch_gemm_ab<float, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == BF16 && tc == F32) return launch_gemm_ab<__bf16, float>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == BF16 && tc == F64) return launch_gemm_ab<__bf16, double>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == BF16 && tc == BF16) return launch_gemm_ab<__bf16, __bf16>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  if (ta == F32 && tc == BF16) return launch_gemm_ab<float, __bf16>(s, M, N, K, alpha, va, vb, beta, vc, g, groups);
-  return hipErrorInvalidValue;
+  const int tile = pick_tile(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g, groups);
+  return launch_typed(s, tile, ta, tc, M, N, K, alpha, va, vb, beta, vc, g, groups);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,6 +695,98 @@ hipError_t randn(hipStream_t s, double* out, int64_t n, uint64_t seed) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(randn_kernel, dim3((unsigned)blocks), dim3(256), 0, s, out, n, seed);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// grouped copy / conversion and grouped Frobenius normalisation
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ void convert_group_kernel(XferSet x) {
+  const int j = blockIdx.y;
+  const TI* __restrict__ in = (const TI*)x.src[j];
+  TO* __restrict__ out = (TO*)x.dst[j];
+  const int64_t n = x.n[j];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = from_double<TO>(to_double<TI>(in[e]));
+}
+
+template <typename TI>
+static hipError_t conv_to(hipStream_t s, int tout, dim3 grid, const XferSet& x) {
+  if (tout == F64) hipLaunchKernelGGL((convert_group_kernel<TI, double>), grid, dim3(256), 0, s, x);
+  else if (tout == F32) hipLaunchKernelGGL((convert_group_kernel<TI, float>), grid, dim3(256), 0, s, x);
+  else if (tout == BF16) hipLaunchKernelGGL((convert_group_kernel<TI, __bf16>), grid, dim3(256), 0, s, x);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t convert_group(hipStream_t s, int tin, int tout, const XferSet& x, int njobs) {
+  if (njobs <= 0) return hipSuccess;
+  if (njobs > MAXJ) return hipErrorInvalidValue;
+  int64_t nmax = 0;
+  for (int j = 0; j < njobs; ++j) {
+    if (x.n[j] < 0) return hipErrorInvalidValue;
+    if (!span_ok(x.src[j], x.n[j] * dtype_size(tin), "convert_group src") ||
+        !span_ok(x.dst[j], x.n[j] * dtype_size(tout), "convert_group dst"))
+      return hipErrorInvalidValue;
+    nmax = std::max(nmax, x.n[j]);
+  }
+  if (dry_run() || nmax == 0) return hipSuccess;
+  int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, (nmax + 255) / 256));
+  dim3 grid((unsigned)blocks, (unsigned)njobs);
+  if (tin == F64) return conv_to<double>(s, tout, grid, x);
+  if (tin == F32) return conv_to<float>(s, tout, grid, x);
+  if (tin == BF16) return conv_to<__bf16>(s, tout, grid, x);
+  return hipErrorInvalidValue;
+}
+
+constexpr int kNormParts = 64;
+
+__global__ void norm_partial_kernel(NormSet x, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int j = blockIdx.y;
+  const double* __restrict__ p = x.p[j];
+  const int64_t n = x.n[j];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) acc += p[e] * p[e];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[j * kNormParts + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void norm_scale_kernel(NormSet x, const double* __restrict__ part) {
+  __shared__ double f;
+  const int j = blockIdx.y;
+  if (threadIdx.x < 64) {
+    double v = part[j * kNormParts + threadIdx.x];  // kNormParts == one wave
+    v = wave_sum(v);
+    if (threadIdx.x == 0) f = v > 0.0 ? 1.0 / sqrt(v) : 1.0;
+  }
+  __syncthreads();
+  double* __restrict__ p = x.p[j];
+  const int64_t n = x.n[j];
+  const double g = f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) p[e] *= g;
+}
+
+hipError_t normalize_group(hipStream_t s, const NormSet& x, int njobs, double* partial) {
+  if (njobs <= 0) return hipSuccess;
+  if (njobs > MAXJ) return hipErrorInvalidValue;
+  int64_t nmax = 0;
+  for (int j = 0; j < njobs; ++j) {
+    if (x.n[j] < 0 || !span_ok(x.p[j], x.n[j] * 8, "normalize_group")) return hipErrorInvalidValue;
+    nmax = std::max(nmax, x.n[j]);
+  }
+  if (!span_ok(partial, (size_t)njobs * kNormParts * 8, "normalize_group partial")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  // every one of the kNormParts partial slots is written (zero for idle blocks)
+  hipLaunchKernelGGL(norm_partial_kernel, dim3(kNormParts, njobs), dim3(256), 0, s, x, partial);
+  int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, (nmax + 255) / 256));
+  hipLaunchKernelGGL(norm_scale_kernel, dim3((unsigned)blocks, njobs), dim3(256), 0, s, x, partial);
   return hipGetLastError();
 }
 

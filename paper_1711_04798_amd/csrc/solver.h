@@ -18,7 +18,7 @@ struct SolveStatus {
   int32_t pad;
 };
 
-constexpr int MAXP = 8;  // problems per small-kernel launch
+constexpr int MAXP = 32;  // problems per small-kernel launch
 
 struct PtrSet {
   double* p[MAXP];

@@ -93,6 +93,8 @@ chol_shift_inv_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet 
 
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   // dynamic LDS: packed R plus 16 columns of the inverse; 8 KiB of the CU's
   // 160 KiB stay for the kernel's static arrays
   constexpr size_t kMaxDyn = 160 * 1024 - 8192;
@@ -296,6 +298,8 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
 hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, const PtrSet& S,
                       const PtrSet& W, const PtrSet& work, int nprob, bool want_vectors, bool transpose_in,
                       const StatSet* st, double noise_rel) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   if (k > 192) return hipErrorInvalidValue;  // 16 waves x 6 pairs, 3 rows per lane
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(M.p[i], (size_t)k * k * 8, "jacobi M") || !span_ok(S.p[i], (size_t)k * 8, "jacobi S") ||
@@ -364,6 +368,8 @@ residual_kernel(int64_t n, int k, int chi, double cutoff, double tol, CPtrSet Z,
 hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cutoff, double tol,
                            const CPtrSet& Z, const CPtrSet& V, const CPtrSet& S,
                            const StatSet& st, int nprob) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   if (k > 256) return hipErrorInvalidValue;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(Z.p[i], (size_t)n * k * 8, "resid Z") || !span_ok(V.p[i], (size_t)n * k * 8, "resid V") ||
@@ -389,6 +395,8 @@ __global__ void scale_kept_kernel(int k, int chi, CPtrSet W, CPtrSet S, PtrSet W
 
 hipError_t scale_kept(hipStream_t s, int k, int chi, const CPtrSet& W, const CPtrSet& S,
                       const PtrSet& Wp, const StatSet& st, int nprob) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if ((W.p[i] && !span_ok(W.p[i], (size_t)k * k * 8, "scale W")) || !span_ok(S.p[i], (size_t)k * 8, "scale S") ||
         !span_ok(Wp.p[i], (size_t)k * chi * 8, "scale Wp") || !span_ok(st.p[i], sizeof(SolveStatus), "scale st"))
@@ -426,6 +434,8 @@ __global__ void warm_start_kernel(int64_t n, int k, PtrSet V0, CPtrSet Vprev, St
 
 hipError_t warm_start(hipStream_t s, int64_t n, int k, const PtrSet& V0, const CPtrSet& Vprev,
                       const StatSet& prev, uint64_t seed, int nprob) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(V0.p[i], (size_t)n * k * 8, "warm V0") ||
         (Vprev.p[i] && !span_ok(Vprev.p[i], (size_t)n * k * 8, "warm Vprev")) ||
@@ -446,6 +456,8 @@ __global__ void reset_status_kernel(StatSet st) {
 }
 
 hipError_t reset_status(hipStream_t s, const StatSet& st, int nprob) {
+  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(st.p[i], sizeof(SolveStatus), "reset st")) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;

@@ -90,6 +90,8 @@ CASES = [
     ("mixed_1x1", 1, 1, [0], 1, [8, 8, 8], [3, 5, 4], [32, 100, 64], "fp32"),
     ("tiny_chi", 1, 1, [0], 1, [2], [3], [1], "fp64"),
     ("rect_2x1", 2, 1, [0, 1], 2, [2], [2], [8], "fp64"),
+    # batched form: classes of equal (d, D, chi) moved in lock-step
+    ("batched", 1, 1, [0], 1, [8] * 40, [3, 4, 5, 3] * 10, [32, 64, 100, 32] * 10, "fp32"),
 ]
 
 
