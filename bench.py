@@ -183,12 +183,14 @@ def warm_leg():
     s_w, sw_w, ok_w, k_w = ws.converge_with_fallback(T_te, w["chi"], w["tol"], w["max_sweeps"], pred,
                                                       warm_budget=2 * int(sw_tv.max()))
     t_warm = time.perf_counter() - t0
-    lg = lambda a: np.log10(np.maximum(a, 1e-16))
+    lg = lambda a: np.log10(np.maximum(a, ws.TARGET_FLOOR))
+    mean_pred = lg(s_tr).mean(axis=0)[None]
     return {"plain_sweeps_mean": float(sw_tv.mean()), "warm_sweeps_mean": float(sw_w.mean()),
             "warm_converged": int(ok_w.sum()), "n_test": len(T_te), "plain_envs_per_s": len(T_te) / t_plain,
             "warm_envs_per_s": len(T_te) / t_warm, "n_train": len(T_tr), "train_data_s": t_data,
             "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
-            "pred_log10_err_top16": float(np.abs(lg(pred) - lg(s_tv))[:, :, :16].mean()),
+            "pred_log10_err_top8": float(np.abs(lg(pred) - lg(s_tv))[:, :, :8].mean()),
+            "mean_predictor_log10_err_top8": float(np.abs(mean_pred - lg(s_tv))[:, :, :8].mean()),
             "kappa_max_rel_diff": float(np.max(np.abs(k_w - k_tv) / np.abs(k_tv))), "tol": w["tol"],
             "workload": "family A(theta) d=8 D=4 chi=64 1x1, float64 contractions, %d training runs, "
                         "%d held-out" % (len(T_tr), len(T_te))}
@@ -197,8 +199,8 @@ def warm_leg():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -235,7 +237,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tm = g.timing()
-    log("bench: solver status of the last column step: %s" % solver_status(g))
+    status = solver_status(g)
+    log("bench: solver status of the last column step: %s" % status)
     g.close()
 
     moves = moves_per_sweep * args.steps
@@ -261,7 +264,9 @@ def main():
         "config": {"workload": "2x2 checkerboard iPEPS d=8 D=6 chi=144, %s contractions, "
                                "float64 projector SVD; step = 1 sweep (8 moves) + convergence check"
                                % args.prec,
-                   "Lx": 2, "Ly": 2, "d": 8, "D": 6, "chi": 144, "seed": 0},
+                   "Lx": 2, "Ly": 2, "d": 8, "D": 6, "chi": 144, "seed": 0,
+                   "chi_eff": max([r["chi_eff"] for r in status] or [0]),
+                   "cutoff": solver_opts(args.prec)["cutoff"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "enlarged-corner double-layer contraction (%s, 8 corners "

@@ -135,10 +135,9 @@ ctm_status ctm_move(ctm_ctx ctx, int32_t dir, int32_t count);
  * Sweeps until the largest l1 change of the normalised corner spectra
  * sigma(C)/sum sigma(C), over all corners and positions of an instance, is
  * below tol, or max_sweeps sweeps were done.  The change is read back to the
- * host every check_every sweeps.  sweeps_out, delta_out: host [n_inst] or NULL;
- * an instance reports the first checked sweep at which its change was below
- * tol (the instances of a class keep sweeping together until all converged;
- * with use_graph every instance sweeps until all converged).
+ * host every check_every sweeps; an instance stops sweeping at the first check
+ * at which its change is below tol (the instances of a class that are still
+ * sweeping move together).  sweeps_out, delta_out: host [n_inst] or NULL.
  * Returns CTM_E_NOCONV (state valid) if some instance did not converge.
  */
 ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,

@@ -13,7 +13,7 @@
  *   layers     h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3
  *   parameters one flat vector W1[n_in][n_hidden], b1[n_hidden],
  *              W2[n_hidden][n_hidden], b2, W3[n_hidden][n_out], b3[n_out]
- *   targets    t = log10(max(s, 1e-16)) of each normalised corner spectrum s
+ *   targets    t = log10(max(s, floor)) of each normalised corner spectrum s
  *   loss       mean over batch and outputs of (y - t)^2
  *   optimiser  Adam (Kingma & Ba 2015) with bias correction, full batch
  *
@@ -46,8 +46,8 @@ ctm_status ctm_mlp_workspace_size(const ctm_mlp_shape* shape, int32_t batch, siz
 /* theta [batch][2] -> x [batch][3] = (cos t1, sin t1, t2). */
 ctm_status ctm_mlp_features(const double* theta, int32_t batch, double* x, void* stream);
 
-/* spectra [count] -> targets [count], t = log10(max(s, 1e-16)). */
-ctm_status ctm_mlp_targets(const double* spectra, int64_t count, double* t, void* stream);
+/* spectra [count] -> targets [count], t = log10(max(s, floor)), floor > 0. */
+ctm_status ctm_mlp_targets(const double* spectra, int64_t count, double floor, double* t, void* stream);
 
 /* y [batch][n_out] = network(x); with exp10 != 0 the outputs are 10^y, the
  * predicted spectra in the layout of ctm_init's spectrum_host. */

@@ -18,8 +18,10 @@ Definitions used here (the GPU kernels implement the same ones):
 * optimiser: Adam (Kingma & Ba, "Adam: a method for stochastic optimization",
   ICLR 2015, Algorithm 1) with bias-corrected moment estimates, on the full
   training set each step;
-* targets: t = log10(max(s, 1e-16)) for the normalised spectrum s of each
-  corner, chi values per corner, corners C1..C4 in order (4 chi outputs).
+* targets: t = log10(max(s, floor)) for the normalised spectrum s of each
+  corner, chi values per corner, corners C1..C4 in order (4 chi outputs);
+  the floor (1e-16 by default) hides values below the resolution of the
+  environment.
 """
 import numpy as np
 
@@ -93,10 +95,10 @@ def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p, m, v
 
 
-def spectra_to_targets(spec):
+def spectra_to_targets(spec, floor=FLOOR):
     """Normalised spectra [..., 4, chi] -> log10 targets [..., 4 chi]."""
     spec = np.asarray(spec, dtype=np.float64)
-    t = np.log10(np.maximum(spec, FLOOR))
+    t = np.log10(np.maximum(spec, floor))
     return t.reshape(t.shape[:-2] + (-1,))
 
 

@@ -94,7 +94,7 @@ def load(path=LIB_PATH):
     lib.ctm_mlp_param_count.restype = ctypes.c_int64
     lib.ctm_mlp_workspace_size.argtypes = [shp, I32, P(SZ)]
     lib.ctm_mlp_features.argtypes = [VP, I32, VP, VP]
-    lib.ctm_mlp_targets.argtypes = [VP, ctypes.c_int64, VP, VP]
+    lib.ctm_mlp_targets.argtypes = [VP, ctypes.c_int64, F64, VP, VP]
     lib.ctm_mlp_forward.argtypes = [shp, VP, VP, I32, VP, I32, VP, SZ, VP]
     lib.ctm_mlp_loss_grad.argtypes = [shp, VP, VP, VP, I32, VP, VP, VP, SZ, VP]
     lib.ctm_mlp_adam.argtypes = [ctypes.c_int64, VP, VP, VP, VP, I32, F64, F64, F64, F64, VP]
@@ -356,10 +356,10 @@ class MLP:
         _check(load().ctm_mlp_features(self._ptr(th), th.shape[0], self._ptr(x), self.stream))
         return x
 
-    def targets(self, spectra):
+    def targets(self, spectra, floor=1e-16):
         s = self._dev(spectra)
         t = self._torch.empty_like(s)
-        _check(load().ctm_mlp_targets(self._ptr(s), s.numel(), self._ptr(t), self.stream))
+        _check(load().ctm_mlp_targets(self._ptr(s), s.numel(), floor, self._ptr(t), self.stream))
         return t.reshape(s.shape[0], -1)
 
     def forward(self, x, exp10=False):

@@ -143,6 +143,7 @@ struct Row {  // scratch for one row of a column step
 
 struct Inst {
   int d = 0, D = 0, D2 = 0, chi = 0, n = 0, k = 0;
+  int k_act = 0;                 // subspace columns in use (<= k, follows chi_eff)
   double* A[MAXT] = {};
   double* B[MAXT] = {};
   double* b64[MAXT][4] = {};
@@ -159,6 +160,7 @@ struct Inst {
   int* flag = nullptr;         // device: non-finite flag
   double* Vkeep[4][MAXPOS] = {};
   SolveStatus* skeep[4][MAXPOS] = {};
+  SolveStatus* skeep_all = nullptr;  // the statuses above, contiguous [4][npos]
   bool has_keep[4][MAXPOS] = {};
   int cursor[4] = {0, 0, 0, 0};
   uint64_t solves = 0;
@@ -289,10 +291,11 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
     I.delta = x.delta_all ? x.delta_all + i : nullptr;
     I.flag = x.flag_all ? x.flag_all + 4 * i : nullptr;
+    I.skeep_all = ar.take<SolveStatus>((size_t)4 * npos);
     for (int c = 0; c < 4; ++c)
       for (int p = 0; p < npos; ++p) {
         I.Vkeep[c][p] = ar.take<double>((size_t)I.n * I.k);
-        I.skeep[c][p] = ar.take<SolveStatus>(1);
+        I.skeep[c][p] = I.skeep_all ? I.skeep_all + c * npos + p : nullptr;
       }
     // row scratch of this instance (all instances of a class step together)
     I.rows.assign(rows, Row());
@@ -669,7 +672,7 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
 //   P1 = Lh^T V S^{-1/2},   P2^T = Uh U S^{-1/2}   (kept columns only).
 ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, uint64_t key) {
   hipStream_t s = x.stream;
-  const int n = I.n, k = I.k, chi = I.chi;
+  const int n = I.n, k = I.k_act, chi = I.chi;
   const size_t P = rows.size();
   const ctm_config& c = x.cfg;
   // start block: kept columns of the previous solve on this cut, then normals
@@ -687,7 +690,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     // the random columns of the start block depend only on the cut group
     // (direction, column, launch), not on how often it was solved, so a
     // captured sweep replays exactly what the eager sweep computes
-    HIPCHK(warm_start(s, n, k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (key + 1), (int)P));
+    HIPCHK(warm_start(s, n, k, I.k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (key + 1), (int)P));
     HIPCHK(reset_status(s, st, (int)P));
   }
   std::vector<double*> V(P), Yb(P), Qb(P), Z(P), LV(P), UU(P), Ub(P), Vpv(P);
@@ -1017,11 +1020,12 @@ struct SpecSet {
   double* spec_new[MAXP];
   double* spec_old[MAXP];
   double* delta[MAXP];
-  int* flag[MAXP];
+  int* flag[MAXP];             // [0] non-finite, [1] largest chi_eff of the last solves
+  const SolveStatus* st[MAXP];  // the instance's kept-solve statuses, contiguous
 };
 
 // one block per instance; spec_new holds its ncorner spectra (descending, length chi)
-__global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int first, int commit) {
+__global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int nstat, int first, int commit) {
   __shared__ double red[256];
   double* __restrict__ spec_new = ss.spec_new[blockIdx.x];
   double* __restrict__ spec_old = ss.spec_old[blockIdx.x];
@@ -1053,7 +1057,12 @@ __global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int first
     dmax = fmax(dmax, red[0]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *ss.delta[blockIdx.x] = first ? INFINITY : dmax;
+  if (threadIdx.x == 0) {
+    *ss.delta[blockIdx.x] = first ? INFINITY : dmax;
+    int ce = 0;
+    for (int i = 0; i < nstat; ++i) ce = max(ce, ss.st[blockIdx.x][i].chi_eff);
+    ss.flag[blockIdx.x][1] = ce;
+  }
   if (commit) {
     __syncthreads();
     for (int i = threadIdx.x; i < ncorner * chi; i += blockDim.x) spec_old[i] = spec_new[i];
@@ -1089,14 +1098,15 @@ ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool fi
     for (int j = 0; j < cnt; ++j) {
       Inst* I = insts[i0 + j];
       HIPCHK(spans({{I->spec_new, (size_t)nc * chi * 8}, {I->spec_old, (size_t)nc * chi * 8}, {I->delta, 8},
-                    {I->flag, 4}}, "spectra"));
+                    {I->flag, 8}, {I->skeep_all, (size_t)nc * sizeof(SolveStatus)}}, "spectra"));
       ss.spec_new[j] = I->spec_new;
       ss.spec_old[j] = I->spec_old;
       ss.delta[j] = I->delta;
       ss.flag[j] = I->flag;
+      ss.st[j] = I->skeep_all;
     }
     if (!dry_run())
-      hipLaunchKernelGGL(spectra_delta_kernel, dim3(cnt), dim3(256), 0, s, ss, chi, nc, first ? 1 : 0,
+      hipLaunchKernelGGL(spectra_delta_kernel, dim3(cnt), dim3(256), 0, s, ss, chi, nc, nc, first ? 1 : 0,
                          commit ? 1 : 0);
     HIPCHK(last_err());
   }
@@ -1179,6 +1189,7 @@ ctm_status build_ctx(const ctm_config* cfg, ctm_ctx_s& x) {
     I.chi = x.chiv[i];
     I.n = I.chi * I.D2;
     I.k = subspace_dim(x.cfg, I.chi, I.n);
+    I.k_act = I.k;
   }
   // classes of instances with equal (d, D, chi), in order of first appearance
   x.classes.clear();
@@ -1242,6 +1253,8 @@ ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double*
   }
   HIPCHK(dmemset(I.spec_old, 0, (size_t)npos * 4 * I.chi * 8, s));
   HIPCHK(dmemset(I.flag, 0, sizeof(int) * 4, s));
+  HIPCHK(dmemset(I.skeep_all, 0, sizeof(SolveStatus) * 4 * npos, s));
+  I.k_act = I.k;
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < npos; ++p) I.has_keep[c][p] = false;
   for (int c = 0; c < 4; ++c) I.cursor[c] = 0;
@@ -1277,18 +1290,28 @@ ctm_status do_sweep(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
   return CTM_OK;
 }
 
-// One sweep of every class followed by the corner spectra and Delta of every
-// instance, captured once as a HIP graph and replayed (graph mode).  The
-// capture happens after an eager sweep, so that every cut has a kept subspace
-// (the solver's warm start) and every GEMM shape has been tuned.
-ctm_status capture_sweep(ctm_ctx_s& x) {
+// The instances of each class that are still sweeping (live[i] != 0).
+std::vector<Inst*> live_insts(ctm_ctx_s& x, const std::vector<int>& cls, const std::vector<char>& live) {
+  std::vector<Inst*> v;
+  for (int i : cls)
+    if (live[i]) v.push_back(&x.inst[i]);
+  return v;
+}
+
+// One sweep of every live instance followed by its corner spectra and Delta,
+// captured once as a HIP graph and replayed (graph mode) until the live set or
+// the subspace width changes.  The first capture follows an eager sweep, so
+// that every cut has a kept subspace (the solver's warm start) and every GEMM
+// shape has been tuned.
+ctm_status capture_sweep(ctm_ctx_s& x, const std::vector<char>& live) {
   if (x.gexec) return CTM_OK;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal));
   ctm_status st = CTM_OK;
   const int64_t moves0 = x.moves;
   for (auto& cls : x.classes) {
-    std::vector<Inst*> insts = class_insts(x, cls);
+    std::vector<Inst*> insts = live_insts(x, cls, live);
+    if (insts.empty()) continue;
     st = do_sweep(x, insts);
     if (st != CTM_OK) break;
     st = corner_spectra(x, insts, false, true);
@@ -1306,6 +1329,13 @@ ctm_status capture_sweep(ctm_ctx_s& x) {
   if (e != hipSuccess) x.gexec = nullptr;
   HIPCHK(e);
   return CTM_OK;
+}
+
+void drop_graph(ctm_ctx_s& x) {
+  if (x.gexec) {
+    (void)hipGraphExecDestroy(x.gexec);
+    x.gexec = nullptr;
+  }
 }
 
 bool graph_usable(const ctm_ctx_s& x) {
@@ -1767,29 +1797,34 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
   if (max_sweeps < 0 || !(tol >= 0)) return fail(CTM_E_INVALID, "tol/max_sweeps");
   if (check_every < 1) check_every = 1;
   const int ni = x->ninst;
-  // instance i is reported at the first checked sweep with Delta < tol; the
-  // instances of a class keep sweeping together until all of them converged
+  // every instance sweeps until its own change is below tol; instances of a
+  // class that are still sweeping move together
   std::vector<int> done(ni, 0), conv(ni, 0);
+  std::vector<char> live(ni, 1);
   std::vector<double> dl(ni, INFINITY);
   std::vector<double> hd(ni);
   std::vector<int> hf(4 * ni);
-  std::vector<char> active(x->classes.size(), 1);
   bool bad = false;
   bool cursors0 = true;
   for (const Inst& I : x->inst)
     for (int c = 0; c < 4; ++c) cursors0 = cursors0 && I.cursor[c] == 0;
   const bool graph = graph_usable(*x) && cursors0;
+  drop_graph(*x);
   int sweep = 0;
+  bool eager_next = true;  // an eager sweep tunes new GEMM shapes before a capture
   while (sweep < max_sweeps) {
-    const bool use_graph = graph && sweep >= 1;
+    const bool use_graph = graph && !eager_next;
+    eager_next = false;
     if (use_graph) {
-      CHK(capture_sweep(*x));
+      CHK(capture_sweep(*x, live));
       HIPCHK(hipGraphLaunch(x->gexec, x->stream));
-      x->moves += (int64_t)(2 * x->Lx + 2 * x->Ly) * (int64_t)x->classes.size();
+      int nl = 0;
+      for (int i = 0; i < ni; ++i) nl += live[i];
+      x->moves += (int64_t)(2 * x->Lx + 2 * x->Ly) * nl;
     } else {
-      for (size_t c = 0; c < x->classes.size(); ++c) {
-        if (!active[c] && !graph) continue;
-        std::vector<Inst*> insts = class_insts(*x, x->classes[c]);
+      for (auto& cls : x->classes) {
+        std::vector<Inst*> insts = live_insts(*x, cls, live);
+        if (insts.empty()) continue;
         CHK(do_sweep(*x, insts));
         CHK(corner_spectra(*x, insts, false, true));
       }
@@ -1800,23 +1835,37 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
     HIPCHK(d2h(hd.data(), x->delta_all, (size_t)ni * 8, x->stream));
     HIPCHK(d2h(hf.data(), x->flag_all, (size_t)ni * 16, x->stream));
     HIPCHK(ssync(x->stream));
-    bool all = true;
-    for (size_t c = 0; c < x->classes.size(); ++c) {
-      if (!active[c]) continue;
-      bool cls_done = true;
-      for (int i : x->classes[c]) {
-        if (conv[i]) continue;
-        done[i] = sweep;
-        dl[i] = hd[i];
-        if (hf[4 * i] || !std::isfinite(hd[i])) bad = true;
-        else if (hd[i] < tol) conv[i] = 1;
-        cls_done = cls_done && conv[i];
+    // the subspace follows the number of kept singular values: chi_eff + p
+    // columns suffice, and chi_eff can grow by p per column step
+    for (auto& cls : x->classes) {
+      int ce = 0;
+      for (int i : cls)
+        if (live[i]) ce = std::max(ce, hf[4 * i + 1]);
+      Inst& J = x->inst[cls[0]];
+      const int p = std::max(0, x->cfg.svd_oversample);
+      const int kn = std::max(1, std::min(J.k, ce + p));
+      if (ce > 0 && kn != J.k_act) {
+        for (int i : cls) x->inst[i].k_act = kn;
+        eager_next = true;
+        drop_graph(*x);
       }
-      if (cls_done) active[c] = 0;
-      all = all && cls_done;
+    }
+    bool all = true;
+    for (int i = 0; i < ni; ++i) {
+      if (!live[i]) continue;
+      done[i] = sweep;
+      dl[i] = hd[i];
+      if (hf[4 * i] || !std::isfinite(hd[i])) bad = true;
+      else if (hd[i] < tol) {
+        conv[i] = 1;
+        live[i] = 0;
+        drop_graph(*x);  // the live set changed
+      }
+      all = all && conv[i];
     }
     if (bad || all) break;
   }
+  drop_graph(*x);
   bool all_ok = true;
   for (int i = 0; i < ni; ++i) {
     if (sweeps_out) sweeps_out[i] = done[i];

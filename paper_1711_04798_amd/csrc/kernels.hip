@@ -409,7 +409,8 @@ int tuned_entries() {
 static int pick_tile(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, double alpha,
                      const View& va, const View& vb, double beta, const View& vc, const GemmGroup& g,
                      int groups) {
-  TuneKey key{0, ta, tc, va.c_ls == 1, vb.r_ls == 1, groups, M, N, K};
+  // one choice per shape, whatever the number of problems in the launch
+  TuneKey key{0, ta, tc, va.c_ls == 1, vb.r_ls == 1, 0, M, N, K};
   (void)hipGetDevice(&key.dev);
   {
     std::lock_guard<std::mutex> l(g_tune_mu);

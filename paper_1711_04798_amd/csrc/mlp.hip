@@ -168,9 +168,9 @@ __global__ void features_kernel(const double* __restrict__ theta, int64_t B, dou
   }
 }
 
-__global__ void targets_kernel(const double* __restrict__ s, int64_t n, double* __restrict__ t) {
+__global__ void targets_kernel(const double* __restrict__ s, int64_t n, double floor, double* __restrict__ t) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    t[e] = log10(fmax(s[e], 1e-16));
+    t[e] = log10(fmax(s[e], floor));
 }
 
 // forward into w.h1, w.h2 and y
@@ -252,9 +252,10 @@ ctm_status ctm_mlp_features(const double* theta, int32_t batch, double* x, void*
   return CTM_OK;
 }
 
-ctm_status ctm_mlp_targets(const double* spectra, int64_t count, double* t, void* stream) {
-  if (!spectra || !t || count < 1) return ctm_internal_fail(CTM_E_INVALID, "targets args");
-  hipLaunchKernelGGL(targets_kernel, dim3(blocks_for(count)), dim3(256), 0, (hipStream_t)stream, spectra, count, t);
+ctm_status ctm_mlp_targets(const double* spectra, int64_t count, double floor, double* t, void* stream) {
+  if (!spectra || !t || count < 1 || !(floor > 0)) return ctm_internal_fail(CTM_E_INVALID, "targets args");
+  hipLaunchKernelGGL(targets_kernel, dim3(blocks_for(count)), dim3(256), 0, (hipStream_t)stream, spectra, count,
+                     floor, t);
   MLP_HIP(hipGetLastError());
   return CTM_OK;
 }

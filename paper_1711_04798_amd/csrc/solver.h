@@ -15,7 +15,7 @@ struct SolveStatus {
   double sigma0;       // largest singular value
   double max_resid;    // largest kept residual / sigma_0
   int32_t jsweeps;     // Jacobi sweeps of the last Rayleigh-Ritz step
-  int32_t pad;
+  int32_t kcols;       // columns of the subspace this status belongs to
 };
 
 constexpr int MAXP = 32;  // problems per small-kernel launch
@@ -63,7 +63,9 @@ hipError_t scale_kept(hipStream_t s, int k, int chi, const CPtrSet& W, const CPt
 
 // V0 = random normals, then the first keep columns replaced by Vprev's, where
 // keep = prev->chi_eff (0 if prev is null or the context has no previous solve).
-hipError_t warm_start(hipStream_t s, int64_t n, int k, const PtrSet& V0, const CPtrSet& Vprev,
+// V0 (n x k) = the chi_eff kept columns of Vprev (stored n x prev->kcols,
+// buffer n x kmax), then counter-based normals
+hipError_t warm_start(hipStream_t s, int64_t n, int k, int kmax, const PtrSet& V0, const CPtrSet& Vprev,
                       const StatSet& prev, uint64_t seed, int nprob);
 
 // Resets the iteration counters of the statuses.

@@ -362,6 +362,7 @@ residual_kernel(int64_t n, int k, int chi, double cutoff, double tol, CPtrSet Z,
     o->max_resid = mr;
     o->converged = (mr <= tol) ? 1 : 0;
     o->iters += 1;
+    o->kcols = k;
   }
 }
 
@@ -413,18 +414,22 @@ __device__ __forceinline__ uint64_t sm64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ void warm_start_kernel(int64_t n, int k, PtrSet V0, CPtrSet Vprev, StatSet prev, uint64_t seed) {
+__global__ void warm_start_kernel(int64_t n, int k, int kmax, PtrSet V0, CPtrSet Vprev, StatSet prev, uint64_t seed) {
   const int pb = blockIdx.y;
   double* v0 = V0.p[pb];
   const double* vp = Vprev.p[pb];
-  int keep = (prev.p[pb] && vp) ? prev.p[pb]->chi_eff : 0;
+  // the kept block was stored with its own column count (leading dimension)
+  int kp = (prev.p[pb] && vp) ? prev.p[pb]->kcols : 0;
+  if (kp < 0 || kp > kmax) kp = 0;  // never read past the kept buffer (n x kmax)
+  int keep = (prev.p[pb] && vp && kp > 0) ? prev.p[pb]->chi_eff : 0;
   if (keep > k) keep = k;
+  if (keep > kp) keep = kp;
   const uint64_t sd = seed + 0x1000193ull * (uint64_t)pb * (uint64_t)n * (uint64_t)k * 2ull;
   const int64_t tot = n * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     int c = (int)(e % k);
-    if (c < keep) { v0[e] = vp[e]; continue; }
+    if (c < keep) { v0[e] = vp[(e / k) * kp + c]; continue; }
     uint64_t a = sm64(sd + 2ull * (uint64_t)e), b = sm64(sd + 2ull * (uint64_t)e + 1ull);
     double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);
     double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
@@ -432,19 +437,21 @@ __global__ void warm_start_kernel(int64_t n, int k, PtrSet V0, CPtrSet Vprev, St
   }
 }
 
-hipError_t warm_start(hipStream_t s, int64_t n, int k, const PtrSet& V0, const CPtrSet& Vprev,
+hipError_t warm_start(hipStream_t s, int64_t n, int k, int kmax, const PtrSet& V0, const CPtrSet& Vprev,
                       const StatSet& prev, uint64_t seed, int nprob) {
+  if (k > kmax) return hipErrorInvalidValue;
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(V0.p[i], (size_t)n * k * 8, "warm V0") ||
-        (Vprev.p[i] && !span_ok(Vprev.p[i], (size_t)n * k * 8, "warm Vprev")) ||
+        (Vprev.p[i] && !span_ok(Vprev.p[i], (size_t)n * kmax * 8, "warm Vprev")) ||
         (prev.p[i] && !span_ok(prev.p[i], sizeof(SolveStatus), "warm prev")))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   int64_t blocks = (n * k + 255) / 256;
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(warm_start_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, n, k, V0, Vprev, prev, seed);
+  hipLaunchKernelGGL(warm_start_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, n, k, kmax, V0, Vprev, prev,
+                     seed);
   return hipGetLastError();
 }
 

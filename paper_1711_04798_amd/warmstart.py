@@ -58,13 +58,18 @@ def init_params(seed, n_in, n_hidden, n_out):
     return np.concatenate(parts)
 
 
-def train(theta, spectra, hidden=128, steps=4000, lr=2e-3, seed=0, device="cuda:0"):
+# corner-spectrum values below this fraction of the total are at the noise
+# level of a float64 environment with relative cutoff 1e-8 and are not fitted
+TARGET_FLOOR = 1e-10
+
+
+def train(theta, spectra, hidden=128, steps=4000, lr=2e-3, seed=0, floor=TARGET_FLOOR, device="cuda:0"):
     """Full-batch Adam on the device; returns (network, loss history)."""
     theta = np.asarray(theta, dtype=np.float64)
     N, _, chi = spectra.shape
     net = MLP(3, hidden, 4 * chi, init_params(seed, 3, hidden, 4 * chi), max_batch=N, device=device)
     x = net.features(theta)
-    t = net.targets(spectra)
+    t = net.targets(spectra, floor)
     hist = net.train(x, t, steps, lr)
     return net, hist
 

@@ -40,6 +40,8 @@ def test_features_and_targets(gpu):
     spec[:, :, 50:] = 0.0
     t = net.targets(spec).cpu().numpy()
     assert np.allclose(t, omlp.spectra_to_targets(spec), rtol=0, atol=1e-14)
+    t = net.targets(spec, 1e-10).cpu().numpy()
+    assert np.allclose(t, omlp.spectra_to_targets(spec, 1e-10), rtol=0, atol=1e-14)
 
 
 def test_forward(gpu):
