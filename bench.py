@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the CTM hot path here is a single-GPU "
@@ -216,6 +218,15 @@ def main():
     import torch
     import synth
     from paper_1711_04798_amd import CTM
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 8, "launches": 5}))
+        return
 
     w = WORKLOAD
     tensors = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)

@@ -1,7 +1,7 @@
 /*
  * ctm_debug.h -- unit-test entry points of the gfx950 CTM library.
  *
- * These expose two internal building blocks so that their numerics can be
+ * These expose internal building blocks so that their numerics can be
  * checked in isolation against a CPU reference.  They are not needed to use
  * the library.  All pointers are device pointers; all calls are enqueued on
  * `stream` and synchronise it before returning.
@@ -28,6 +28,24 @@ ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t 
                           void* C, void* stream);
 
 /*
+ * C = op(A) B on the split-K kernel for few columns (1 <= N <= 192): A is
+ * M x K (K x M if transA), B is K x N, C is M x N, row-major and dense.
+ * (ta, tc) in {(1,1), (1,0), (0,0)}; scratch: device buffer of scratch_bytes
+ * for the partial products.
+ */
+ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t K,
+                            const void* A, int32_t transA, const void* B, void* C,
+                            void* scratch, int64_t scratch_bytes, void* stream);
+
+/*
+ * C = A Bt^T on the bf16 enlarged-corner kernel: A bf16 M x K row-major, Bt
+ * bf16 N x K row-major (both 16-byte aligned, K a multiple of 8), C float32
+ * M x N row-major.
+ */
+ctm_status ctm_debug_corner_bf16(int64_t M, int64_t N, int64_t K, const void* A, const void* Bt,
+                                 void* C, void* stream);
+
+/*
  * One-sided Jacobi SVD of the k x k float64 row-major matrix M (1 <= k <= 192):
  * M W = U diag(S), singular values descending.  U, W: k x k row-major; S: k.
  * work: 3 k^2 doubles.
@@ -43,7 +61,7 @@ ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, doubl
  *   what = 2: projector P2^T of row r (float64 n x chi), index = r;
  *   what = 3: solver status of row r {chi_eff, converged, iters, chol_fail as
  *             int32, sigma0, max_resid as float64, Jacobi sweeps of the last
- *             Rayleigh-Ritz step, padding as int32} (40 bytes), index = r.
+ *             Rayleigh-Ritz step, subspace columns as int32} (40 bytes), index = r.
  * `bytes` must equal the buffer size.  Syncs.
  */
 ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_buf, size_t bytes);

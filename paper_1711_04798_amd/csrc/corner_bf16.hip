@@ -4,14 +4,17 @@
 //
 // with Y (bf16, row-major M x K, M = chi^2, K = D^4) and the double layer
 // stored transposed, bT = b^T (bf16, row-major N x K, N = D^4).  Both operands
-// are K-contiguous, so 16-byte global loads land in LDS tiles [row][k] that
-// feed v_mfma_f32_16x16x32_bf16 directly (lane l reads row l%16, k 8(l/16) ..
-// +7).  Workgroup tile 256 x 144, four waves of 64 x 144 (4 x 9 MFMA tiles),
+// are K-contiguous, so 16-byte global loads land in LDS tiles [row][k]
+// (chunk-swizzled, see lds_off) that feed v_mfma_f32_16x16x32_bf16 directly
+// (lane l reads row l%16, k 8(l/16) .. +7).  Workgroup tile 256 x 144, four waves of 64 x 144 (4 x 9 MFMA tiles),
 // K step 32, register-staged double buffering.  The f32 result is written
 // through the two-level output view of the enlarged-corner matrix.
 #include "kernels.h"
 
 #include <hip/hip_bf16.h>
+
+#include <cstdlib>
+#include <cstring>
 
 namespace ctmk {
 
@@ -21,7 +24,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 256, BN = 144, BK = 32, LDK = BK + 8;  // LDS row: 40 bf16 = 80 B
+constexpr int BM = 256, BN = 144, BK = 32, LDK = BK;      // LDS row: 32 bf16 = 64 B, no padding
 constexpr int TM = 4, TN = 9;                              // 16x16 tiles per wave
 constexpr int A_CHUNKS = BM * BK / 8 / 256;                // 16-byte chunks per thread: 4
 constexpr int B_CHUNKS = (BN * BK / 8 + 255) / 256;        // 3 (576 chunks)
@@ -31,22 +34,41 @@ struct OutView {
   int64_t r_ls, r_hs, c_ls, c_hs;
 };
 
+// LDS rows hold four 16-byte chunks (8 bf16 of k each); chunk c of row r is
+// stored in slot c ^ swz(r).  A fragment read takes 16 consecutive rows at one
+// chunk and a tile store takes 4 consecutive rows at all chunks; with the
+// swizzle both touch distinct banks in every group of 8 (32 banks) or 16
+// (64 banks) lanes.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+__device__ __forceinline__ int lds_off(int r, int chunk) { return r * LDK + ((chunk ^ swz(r)) << 3); }
+
 __device__ __forceinline__ u32x4 load16(const __bf16* p, bool ok) {
   if (ok) return *reinterpret_cast<const u32x4*>(p);
   u32x4 z = {0u, 0u, 0u, 0u};
   return z;
 }
 
+// Work-groups are dealt to the 8 XCDs round-robin in launch order, and each
+// XCD has its own L2.  Launch index L runs on XCD L % 8; it takes tile
+// t = (L % 8) * per_xcd + L / 8 of the (problem, M tile, N tile) sequence
+// with N fastest, so each XCD works through a contiguous run of tiles: the
+// N tiles that share an A row block run side by side on one XCD (A is read
+// from HBM once), and the few B tiles of a problem stay in that XCD's L2.
 __global__ void __launch_bounds__(256, 2)
-corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g) {
+corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
+                   int32_t tiles, int32_t per_xcd) {
   __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * LDK];
-  const int gi = blockIdx.z;
+  const int L = blockIdx.x;
+  const int t = (L & 7) * per_xcd + (L >> 3);
+  if (t >= tiles) return;  // padding of the last XCD's run (whole work-group)
+  const int gi = t / (mt * nt);
+  const int rem = t - gi * (mt * nt);
+  const int m0 = (rem / nt) * BM, n0 = (rem % nt) * BN;
   const __bf16* __restrict__ A = (const __bf16*)g.A[gi];
   const __bf16* __restrict__ Bt = (const __bf16*)g.B[gi];
   float* __restrict__ C = (float*)g.C[gi];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
 
   // load slots: chunk e covers row e / 4, k 8 (e % 4) .. +7 of the tile
   u32x4 ra[A_CHUNKS], rb[B_CHUNKS];
@@ -67,13 +89,13 @@ corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g) {
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < A_CHUNKS; ++j) {
-      const int e = tid + 256 * j, row = e >> 2, kc = (e & 3) * 8;
-      *reinterpret_cast<u32x4*>(&As[buf][row * LDK + kc]) = ra[j];
+      const int e = tid + 256 * j, row = e >> 2;
+      *reinterpret_cast<u32x4*>(&As[buf][lds_off(row, e & 3)]) = ra[j];
     }
 #pragma unroll
     for (int j = 0; j < B_CHUNKS; ++j) {
-      const int e = tid + 256 * j, row = e >> 2, kc = (e & 3) * 8;
-      if (e < BN * 4) *reinterpret_cast<u32x4*>(&Bs[buf][row * LDK + kc]) = rb[j];
+      const int e = tid + 256 * j, row = e >> 2;
+      if (e < BN * 4) *reinterpret_cast<u32x4*>(&Bs[buf][lds_off(row, e & 3)]) = rb[j];
     }
   };
 
@@ -87,17 +109,17 @@ corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g) {
   gload(0);
   lstore(0);
   __syncthreads();
-  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  const int lr = lane & 15, lc = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * BK);
     v8bf av[TM], bv[TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
-      av[i] = *reinterpret_cast<const v8bf*>(&As[cur][(wave * 64 + i * 16 + lr) * LDK + lk]);
+      av[i] = *reinterpret_cast<const v8bf*>(&As[cur][lds_off(wave * 64 + i * 16 + lr, lc)]);
 #pragma unroll
     for (int j = 0; j < TN; ++j)
-      bv[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][(j * 16 + lr) * LDK + lk]);
+      bv[j] = *reinterpret_cast<const v8bf*>(&Bs[cur][lds_off(j * 16 + lr, lc)]);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -108,12 +130,140 @@ corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g) {
   }
 
   // epilogue: acc[i][j][q] = C[4 (lane/16) + q][lane % 16] of tile (i, j)
-  const int lc = lane & 15, lr4 = (lane >> 4) * 4;
+  const int lcol = lane & 15, lr4 = (lane >> 4) * 4;
   int64_t coff[TN];
   bool cok[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
-    const int n = n0 + j * 16 + lc;
+    const int n = n0 + j * 16 + lcol;
+    cok[j] = n < N;
+    const int h = n / vc.c_ext, l = n - h * vc.c_ext;
+    coff[j] = (int64_t)h * vc.c_hs + (int64_t)l * vc.c_ls;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + wave * 64 + i * 16 + lr4 + q;
+      if (m >= M) continue;
+      const int h = m / vc.r_ext, l = m - h * vc.r_ext;
+      const int64_t roff = (int64_t)h * vc.r_hs + (int64_t)l * vc.r_ls;
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (cok[j]) C[roff + coff[j]] = acc[i][j][q];
+    }
+}
+
+
+// Second form of the same contraction: the tiles go from HBM to LDS by 16-byte
+// direct-to-LDS loads (lane t of a wave fills bytes 16 t .. 16 t + 15 after the
+// wave-uniform base) into three LDS stages, issued two K steps ahead, with no
+// register staging.  The chunk a lane loads is chosen so that its LDS slot
+// follows the lds_off swizzle.  Rows past the matrix edge load a clamped
+// (valid) row whose results are never stored; in a partial last K step the
+// chunks past K load a clamped chunk and the B side of those chunks is zeroed
+// in LDS before use.
+constexpr int STAGES = 3;
+constexpr int STAGE_ELEMS = (BM + BN) * BK;
+
+__device__ __forceinline__ void wait_vm(int n) {
+  // s_waitcnt vmcnt(n), other counters unconstrained (gfx9 encoding)
+  if (n >= 7) __builtin_amdgcn_s_waitcnt(0xF77);
+  else if (n == 6) __builtin_amdgcn_s_waitcnt(0xF76);
+  else __builtin_amdgcn_s_waitcnt(0xF70);
+}
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
+
+__global__ void __launch_bounds__(256, 2)
+corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
+                       int32_t tiles, int32_t per_xcd) {
+  __shared__ __attribute__((aligned(16))) __bf16 smem[STAGES * STAGE_ELEMS];
+  const int L = blockIdx.x;
+  const int t = (L & 7) * per_xcd + (L >> 3);
+  if (t >= tiles) return;
+  const int gi = t / (mt * nt);
+  const int rem = t - gi * (mt * nt);
+  const int m0 = (rem / nt) * BM, n0 = (rem % nt) * BN;
+  const __bf16* __restrict__ A = (const __bf16*)g.A[gi];
+  const __bf16* __restrict__ Bt = (const __bf16*)g.B[gi];
+  float* __restrict__ C = (float*)g.C[gi];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nk = (K + BK - 1) / BK;
+  const bool partial = (K % BK) != 0;
+  const int n_issue = wave == 0 ? 7 : 6;  // loads per wave per K step
+
+  // loads of K step kt into stage kt % 3.  A: 16 blocks of 64 chunks (4 per
+  // wave); B: 9 blocks (waves take blocks w, w + 4, w + 8 < 9)
+  auto issue = [&](int kt) {
+    __bf16* As = smem + (kt % STAGES) * STAGE_ELEMS;
+    __bf16* Bs = As + BM * BK;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int blk = j * 4 + wave, e = blk * 64 + lane, row = e >> 2;
+      const int chunk = (e & 3) ^ swz(row);
+      const int m = min(m0 + row, M - 1), k = min(k0 + chunk * 8, K - 8);
+      __builtin_amdgcn_global_load_lds(A + (int64_t)m * K + k, As + blk * 512, 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int blk = j * 4 + wave;
+      if (blk < 9) {
+        const int e = blk * 64 + lane, row = e >> 2;
+        const int chunk = (e & 3) ^ swz(row);
+        const int n = min(n0 + row, N - 1), k = min(k0 + chunk * 8, K - 8);
+        __builtin_amdgcn_global_load_lds(Bt + (int64_t)n * K + k, Bs + blk * 512, 16, 0, 0);
+      }
+    }
+  };
+
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int lr = lane & 15, lc = lane >> 4;
+  issue(0);
+  if (nk > 1) issue(1);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of step kt are done once at most those of step kt + 1
+    // are outstanding; the barrier then covers every wave's loads, and every
+    // wave's reads of the stage that step kt + 2 refills
+    wait_vm(kt + 1 < nk ? n_issue : 0);
+    __bf16* As = smem + (kt % STAGES) * STAGE_ELEMS;
+    __bf16* Bs = As + BM * BK;
+    if (partial && kt == nk - 1) {
+      const int k0 = kt * BK;
+      for (int e = tid; e < BN * 4; e += 256) {
+        const int row = e >> 2, c = e & 3;
+        if (k0 + c * 8 >= K) *reinterpret_cast<u32x4*>(&Bs[lds_off(row, c)]) = u32x4{0u, 0u, 0u, 0u};
+      }
+      wait_lgkm0();
+    }
+    // a bare barrier: __syncthreads() would also wait for the loads of the
+    // next step (its fence drains every outstanding memory operation)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + 2 < nk) issue(kt + 2);
+    v8bf av[TM], bv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bv[j] = *reinterpret_cast<const v8bf*>(&Bs[lds_off(j * 16 + lr, lc)]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) av[i] = *reinterpret_cast<const v8bf*>(&As[lds_off(wave * 64 + i * 16 + lr, lc)]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+
+  const int lcol = lane & 15, lr4 = (lane >> 4) * 4;
+  int64_t coff[TN];
+  bool cok[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + j * 16 + lcol;
     cok[j] = n < N;
     const int h = n / vc.c_ext, l = n - h * vc.c_ext;
     coff[j] = (int64_t)h * vc.c_hs + (int64_t)l * vc.c_ls;
@@ -151,8 +301,19 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   ov.r_ext = (int32_t)(vc.r_ext > M ? M : vc.r_ext);
   ov.c_ext = (int32_t)(vc.c_ext > N ? N : vc.c_ext);
   ov.r_ls = vc.r_ls; ov.r_hs = vc.r_hs; ov.c_ls = vc.c_ls; ov.c_hs = vc.c_hs;
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)groups);
-  hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g);
+  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
+  if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
+  const int64_t per_xcd = (tiles + 7) / 8;
+  static const bool use_dma = [] {
+    const char* e = std::getenv("CTM_CORNER_STAGING");  // "registers" selects the first form
+    return !(e && std::strcmp(e, "registers") == 0);
+  }();
+  if (use_dma)
+    hipLaunchKernelGGL(corner_bf16_dma_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+  else
+    hipLaunchKernelGGL(corner_bf16_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, (int32_t)M,
+                       (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
   return hipGetLastError();
 }
 

@@ -195,6 +195,8 @@ struct ctm_ctx_s {
   hipGraphExec_t gexec = nullptr;  // captured sweep of every class (graph mode)
   double* splitk = nullptr;      // split-K partial products of the solver
   int64_t splitk_elems = 0;
+  void* ts_scratch = nullptr;    // K-chunk partials of the tall-skinny products
+  int64_t ts_bytes = 0;
   double* spec_tmp_U = nullptr;  // corner SVD scratch
   double* spec_tmp_W = nullptr;
   double* spec_tmp_S = nullptr;
@@ -309,6 +311,13 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   // split-K partials of the k x n x k products (all problems of a launch)
   x.splitk_elems = (int64_t)64 * k * k * x.max_prob;
   x.splitk = ar.take<double>((size_t)x.splitk_elems);
+  // K-chunk partials of the tall-skinny products (n x k and chi x chi outputs)
+  {
+    const int64_t cols = (int64_t)std::max(k, chi);
+    const int64_t want = (int64_t)16 * (int64_t)std::max(n, chi) * cols * std::min(MAXG, x.max_prob) * 8;
+    x.ts_bytes = std::min<int64_t>(want, (int64_t)256 << 20);
+    x.ts_scratch = ar.take_bytes((size_t)x.ts_bytes);
+  }
   // corner-spectrum SVD scratch (MAXP corners per launch)
   x.spec_tmp_U = ar.take<double>(MAXP * c2);
   x.spec_tmp_W = ar.take<double>(MAXP * c2);
@@ -427,6 +436,18 @@ ctm_status gemm_run(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t
   for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
     int cnt = std::min(MAXG, g.size() - j0);
     HIPCHK(ctmk::gemm(s, ta, tc, M, N, K, alpha, va, vb, beta, vc, g.group(j0, cnt), cnt));
+  }
+  return CTM_OK;
+}
+
+// long contractions with few output columns go to the split-K kernel
+ctm_status gemm_long(ctm_ctx_s& x, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
+                     const View& vb, const View& vc, const G& g) {
+  if (K < 1024 || !ts_gemm_supported(ta, tc, M, N, K, va, vb, vc))
+    return gemm_run(x.stream, ta, tc, M, N, K, va, vb, vc, g);
+  for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
+    int cnt = std::min(MAXG, g.size() - j0);
+    HIPCHK(ts_gemm(x.stream, ta, tc, M, N, K, va, vb, vc, g.group(j0, cnt), cnt, x.ts_scratch, x.ts_bytes));
   }
   return CTM_OK;
 }
@@ -608,7 +629,7 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
         double* dst = f == 0 ? R->tmp : (f == 1 ? mid[r] : (f == 2 ? R->tmp : out[r]));
         g.add(rows[r].Q[ord[f]], src, dst);
       }
-      CHK(gemm_run(s, F64, F64, n, k, n, vq, vb, vb, g));
+      CHK(gemm_long(x, F64, F64, n, k, n, vq, vb, vb, g));
     }
     return CTM_OK;
   }
@@ -626,7 +647,7 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
       void* dst = f == 0 ? R->q1 : (f == 1 ? R->q2 : (f == 2 ? R->q1 : (void*)out[r]));
       g.add(rows[r].Q[ord[f]], src, dst);
     }
-    CHK(gemm_run(s, qt, f == 3 ? F64 : qt, n, k, n, vq, vb, vb, g));
+    CHK(gemm_long(x, qt, f == 3 ? F64 : qt, n, k, n, vq, vb, vb, g));
     if (f == 1) {
       Xfer cv;
       for (size_t r = 0; r < P; ++r) cv.add(rows[r].R->q2, mid[r], (int64_t)n * k);
@@ -851,10 +872,13 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   }
   // C1' [b', r] = sum_(a,U) P1prev[(a,U), b'] CT[(a,U), r]
   CHK(gemm_run(s, at, at, c, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g1));
-  CHK(gemm_run(s, at, F64, c, c, n, transposed(rowmajor(c)), rowmajor(c), rowmajor(c), g2));
+  CHK(gemm_long(x, at, F64, c, c, n, transposed(rowmajor(c)), rowmajor(c), rowmajor(c), g2));
   // W1[(g,l),(u,c2)] = sum_p T4[(g,l),p] P2T_prev[(p,u), c2]
   CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
-  // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)]
+  // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)]: the new
+  // edge itself, so in the working type even in bf16 mode (rounding the
+  // double layer here perturbs the fixed point directly: ~10x the energy
+  // error of bf16 enlarged corners, which only steer the truncation)
   CHK(gemm_run(s, at, at, c * c, D2 * D2, D2 * D2, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(D2 * D2),
                rowmajor(D2 * D2), g4));
   // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
@@ -865,7 +889,7 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // X6[z, (g, dn)] = sum_q T3[(z,dn), q] C4[q, g]  written as [z][g][dn]
   CHK(gemm_run(s, at, at, c * D2, c, c, rowmajor(c), rowmajor(c), view2(D2, 1, c * D2, BIG, D2, 0), g6));
   // C4'[z, c] = sum_(g,dn) X6[z,(g,dn)] P2T[(g,dn), c]
-  CHK(gemm_run(s, at, F64, c, c, n, rowmajor(n), rowmajor(c), rowmajor(c), g7));
+  CHK(gemm_long(x, at, F64, c, c, n, rowmajor(n), rowmajor(c), rowmajor(c), g7));
   // normalise, then store into the environment (all projectors of the column
   // step were computed before any tensor is replaced)
   std::vector<std::pair<double*, int64_t>> nt;
@@ -2043,6 +2067,39 @@ ctm_status ctm_debug_gemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t 
   g.C[0] = C;
   hipError_t e = ctmk::gemm(s, ta, tc, M, N, K, 1.0, va, vb, 0.0, rowmajor(N), g, 1);
   if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "unsupported type pair");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_t K, const void* A,
+                            int32_t transA, const void* B, void* C, void* scratch, int64_t scratch_bytes,
+                            void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  View va = transA ? transposed(rowmajor(M)) : rowmajor(K);
+  if (!ts_gemm_supported(ta, tc, M, N, K, va, rowmajor(N), rowmajor(N)) || !A || !B || !C || !scratch)
+    return fail(CTM_E_INVALID, "sizes/types");
+  GemmGroup g{};
+  g.A[0] = A;
+  g.B[0] = B;
+  g.C[0] = C;
+  hipError_t e = ts_gemm(s, ta, tc, M, N, K, va, rowmajor(N), rowmajor(N), g, 1, scratch, scratch_bytes);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "scratch too small");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_corner_bf16(int64_t M, int64_t N, int64_t K, const void* A, const void* Bt, void* C,
+                                 void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!corner_bf16_supported(M, N, K) || !A || !Bt || !C) return fail(CTM_E_INVALID, "sizes");
+  GemmGroup g{};
+  g.A[0] = A;
+  g.B[0] = Bt;
+  g.C[0] = C;
+  hipError_t e = corner_bf16(s, M, N, K, rowmajor(N), g, 1);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "alignment");
   HIPCHK(e);
   HIPCHK(ssync(s));
   return CTM_OK;

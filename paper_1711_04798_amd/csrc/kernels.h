@@ -77,6 +77,13 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
 // bf16 enlarged-corner contraction C(view) = A B with A = Y row-major M x K
 // and B given transposed (Bt row-major N x K), f32 output through a two-level
 // view; needs K % 8 == 0 and 16-byte aligned operands.
+// Split-K GEMM for few columns (N <= 192) and plain strided operands:
+// f32 -> f32/f64 and f64 -> f64.  `scratch` holds the K-chunk partials.
+bool ts_gemm_supported(int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                       const View& vc);
+hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
+
 bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
                        int groups);

@@ -1,0 +1,239 @@
+// Tall-skinny GEMM split over K, for products C (M x N) = op(A) (M x K) B (K x N)
+// with few columns (N <= 192) and a long contraction: the half-system
+// applications of the projector solver (n x n enlarged corner times an
+// n x k block) and the n-long contractions of the absorption.  The plain
+// tiled kernel gives these shapes too few work-groups and re-reads the block
+// B per row tile; here each work-group takes 64 rows of A and one K chunk,
+// holds all N columns, and writes a partial product; a second kernel sums the
+// K chunks in a fixed order (deterministic) into C.
+//   f32: v_mfma_f32_16x16x4f32, f64: v_mfma_f64_16x16x4f64; lane l feeds
+//   A[l%16][k0 + l/16] and B[k0 + l/16][l%16].
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace ctmk {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T> struct TsCfg;
+template <> struct TsCfg<float> { static constexpr int BK = 32; typedef v4f V; };
+template <> struct TsCfg<double> { static constexpr int BK = 16; typedef v4d V; };
+
+constexpr int BM = 64;        // rows per work-group (16 per wave)
+constexpr int NMAX = 192;     // columns held by one work-group
+
+template <typename T>
+__device__ __forceinline__ typename TsCfg<T>::V mfma(T a, T b, typename TsCfg<T>::V c);
+template <>
+__device__ __forceinline__ v4f mfma<float>(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v4d mfma<double>(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// A element (m, k) at m * lda + k (A_KFAST) or k * lda + m; B (k, n) at k * ldb + n.
+// part[(gi * nsplit + s)][m][n], row-major M x N.
+template <typename T, bool A_KFAST, int NT>
+__global__ void __launch_bounds__(256, 2)
+ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
+                  int32_t mtiles, GemmGroup g, T* __restrict__ part) {
+  constexpr int BK = TsCfg<T>::BK, LDK = BK + 1, NP = NT * 16;
+  __shared__ T As[2][BM * LDK];
+  __shared__ T Bs[2][NP * LDK];
+  // launch order: row tile fastest, then K chunk, then problem
+  const int bid = blockIdx.x;
+  const int mt = bid % mtiles;
+  const int sk = (bid / mtiles) % nsplit;
+  const int gi = bid / (mtiles * nsplit);
+  const T* __restrict__ A = (const T*)g.A[gi];
+  const T* __restrict__ B = (const T*)g.B[gi];
+  const int m0 = mt * BM;
+  const int kbeg = sk * kchunk, kend = min(K, kbeg + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  constexpr int AE = BM * BK / 256;                 // A elements per thread
+  constexpr int BE = (NP * BK + 255) / 256;         // B elements per thread
+  T ra[AE], rb[BE];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < AE; ++j) {
+      const int e = tid + 256 * j;
+      const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
+      const int m = m0 + r, k = k0 + kk;
+      ra[j] = (m < M && k < kend) ? A[A_KFAST ? (int64_t)m * lda + k : (int64_t)k * lda + m] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < BE; ++j) {
+      const int e = tid + 256 * j;
+      const int n = e % NP, kk = e / NP;
+      const int k = k0 + kk;
+      rb[j] = (kk < BK && n < N && k < kend) ? B[(int64_t)k * ldb + n] : T(0);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < AE; ++j) {
+      const int e = tid + 256 * j;
+      const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
+      As[buf][r * LDK + kk] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < BE; ++j) {
+      const int e = tid + 256 * j;
+      const int n = e % NP, kk = e / NP;
+      if (kk < BK) Bs[buf][n * LDK + kk] = rb[j];
+    }
+  };
+
+  typedef typename TsCfg<T>::V V;
+  V acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[j][q] = 0;
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    lstore(0);
+  }
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const T av = As[cur][(wave * 16 + lr) * LDK + ks + lk];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[j] = mfma<T>(av, Bs[cur][(j * 16 + lr) * LDK + ks + lk], acc[j]);
+    }
+    if (kt + 1 < nk) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // partial product rows: f32 4 (l/16) + q, f64 (l/16) + 4 q; column l % 16
+  T* __restrict__ P = part + ((int64_t)gi * nsplit + sk) * M * N;
+  constexpr bool F64 = sizeof(T) == 8;
+  const int rb0 = F64 ? lk : lk * 4, rst = F64 ? 4 : 1;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int n = j * 16 + lr;
+    if (n >= N) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + wave * 16 + rb0 + rst * q;
+      if (m < M) P[(int64_t)m * N + n] = acc[j][q];
+    }
+  }
+}
+
+template <typename T, typename TO>
+__global__ void ts_reduce_kernel(const T* __restrict__ part, int32_t M, int32_t N, int32_t nsplit, int64_t ldc,
+                                 GemmGroup g) {
+  const int gi = blockIdx.y;
+  const T* __restrict__ p = part + (int64_t)gi * nsplit * M * N;
+  TO* __restrict__ C = (TO*)g.C[gi];
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
+    T acc = 0;
+    for (int s = 0; s < nsplit; ++s) acc += p[(int64_t)s * MN + e];
+    const int64_t m = e / N, n = e - m * N;
+    C[m * ldc + n] = (TO)acc;
+  }
+}
+
+template <typename T, bool AK>
+hipError_t launch_partial(hipStream_t s, int nt, dim3 grid, int32_t M, int32_t N, int32_t K, int64_t lda,
+                          int64_t ldb, int32_t kchunk, int32_t nsplit, int32_t mtiles, const GemmGroup& g,
+                          T* part) {
+#define TS_CASE(NTV)                                                                                  \
+  case NTV:                                                                                           \
+    hipLaunchKernelGGL((ts_partial_kernel<T, AK, NTV>), grid, dim3(256), 0, s, M, N, K, lda, ldb,      \
+                       kchunk, nsplit, mtiles, g, part);                                              \
+    break;
+  switch (nt) {
+    TS_CASE(1) TS_CASE(2) TS_CASE(3) TS_CASE(4) TS_CASE(5) TS_CASE(6)
+    TS_CASE(7) TS_CASE(8) TS_CASE(9) TS_CASE(10) TS_CASE(11) TS_CASE(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef TS_CASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool ts_gemm_supported(int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                       const View& vc) {
+  if (!((ta == F32 && (tc == F32 || tc == F64)) || (ta == F64 && tc == F64))) return false;
+  if (N < 1 || N > NMAX || M < 1 || K < 1 || M > INT32_MAX || K > INT32_MAX) return false;
+  // plain strided operands only
+  const bool a_plain = (va.r_hs == 0 && va.c_hs == 0) && (va.c_ls == 1 || va.r_ls == 1);
+  const bool b_plain = vb.r_hs == 0 && vb.c_hs == 0 && vb.c_ls == 1;
+  const bool c_plain = vc.r_hs == 0 && vc.c_hs == 0 && vc.c_ls == 1;
+  return a_plain && b_plain && c_plain;
+}
+
+int64_t ts_gemm_scratch_elems(int64_t M, int64_t N, int groups, int nsplit) {
+  return (int64_t)nsplit * M * N * groups;
+}
+
+hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes) {
+  if (groups < 1 || groups > MAXG || !ts_gemm_supported(ta, tc, M, N, K, va, vb, vc)) return hipErrorInvalidValue;
+  const bool ak = va.c_ls == 1;
+  const int64_t lda = ak ? va.r_ls : va.c_ls, ldb = vb.r_ls, ldc = vc.r_ls;
+  const size_t ea = dtype_size(ta), ec = dtype_size(tc);
+  const size_t sa = (size_t)(view_max(va, M, K) + 1) * ea, sb = (size_t)(view_max(vb, K, N) + 1) * ea,
+               sc = (size_t)(view_max(vc, M, N) + 1) * ec;
+  for (int i = 0; i < groups; ++i)
+    if (!span_ok(g.A[i], sa, "ts A") || !span_ok(g.B[i], sb, "ts B") || !span_ok(g.C[i], sc, "ts C"))
+      return hipErrorInvalidValue;
+  // enough work-groups to fill the chip several times over, K chunks of at
+  // least 8 steps, and partials that fit the scratch
+  const int BK = ta == F32 ? 32 : 16;
+  const int64_t mtiles = (M + BM - 1) / BM;
+  int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>((2048 + mtiles * groups - 1) / (mtiles * groups),
+                                                          K / (8 * BK)));
+  while (nsplit > 1 && ts_gemm_scratch_elems(M, N, groups, (int)nsplit) * (int64_t)ea > scratch_bytes) nsplit /= 2;
+  if (ts_gemm_scratch_elems(M, N, groups, (int)nsplit) * (int64_t)ea > scratch_bytes) return hipErrorInvalidValue;
+  const int64_t kchunk = ((K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
+  nsplit = (K + kchunk - 1) / kchunk;
+  if (!span_ok(scratch, (size_t)ts_gemm_scratch_elems(M, N, groups, (int)nsplit) * ea, "ts scratch"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const int nt = (int)((N + 15) / 16);
+  dim3 grid((unsigned)(mtiles * nsplit * groups));
+  hipError_t e;
+  if (ta == F32)
+    e = ak ? launch_partial<float, true>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb, (int32_t)kchunk,
+                                         (int32_t)nsplit, (int32_t)mtiles, g, (float*)scratch)
+           : launch_partial<float, false>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
+                                          (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (float*)scratch);
+  else
+    e = ak ? launch_partial<double, true>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
+                                          (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (double*)scratch)
+           : launch_partial<double, false>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
+                                           (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (double*)scratch);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (M * N + 255) / 256));
+  dim3 rg((unsigned)blocks, (unsigned)groups);
+  if (ta == F32 && tc == F32)
+    hipLaunchKernelGGL((ts_reduce_kernel<float, float>), rg, dim3(256), 0, s, (const float*)scratch, (int32_t)M,
+                       (int32_t)N, (int32_t)nsplit, ldc, g);
+  else if (ta == F32)
+    hipLaunchKernelGGL((ts_reduce_kernel<float, double>), rg, dim3(256), 0, s, (const float*)scratch, (int32_t)M,
+                       (int32_t)N, (int32_t)nsplit, ldc, g);
+  else
+    hipLaunchKernelGGL((ts_reduce_kernel<double, double>), rg, dim3(256), 0, s, (const double*)scratch, (int32_t)M,
+                       (int32_t)N, (int32_t)nsplit, ldc, g);
+  return hipGetLastError();
+}
+
+}  // namespace ctmk

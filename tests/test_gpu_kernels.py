@@ -1,6 +1,7 @@
 """Kernel-level checks through the unit-test entry points of include/ctm_debug.h:
-the MFMA GEMM (float64, float32, bfloat16 operand layouts) against NumPy, and
-the one-sided Jacobi SVD against LAPACK."""
+the MFMA GEMM (float64, float32, bfloat16 operand layouts) and the split-K
+GEMM for few columns against NumPy, and the one-sided Jacobi SVD against
+LAPACK."""
 import ctypes
 
 import numpy as np
@@ -16,6 +17,12 @@ def _lib():
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     lib.ctm_debug_gemm.restype = ctypes.c_int
+    lib.ctm_debug_tsgemm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.ctm_debug_tsgemm.restype = ctypes.c_int
+    lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
+    lib.ctm_debug_corner_bf16.restype = ctypes.c_int
     lib.ctm_debug_svd.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 6
     lib.ctm_debug_svd.restype = ctypes.c_int
     return lib
@@ -51,6 +58,60 @@ def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
     if tc == 2:
         tol = max(tol, 1e-2 * np.abs(ref).max())
     assert np.abs(got - ref).max() <= tol + 1e-300
+
+
+@pytest.mark.parametrize("ta,tc", [(0, 0), (1, 1), (1, 0)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 16, 32), (67, 45, 1030), (5184, 50, 5184), (700, 192, 2500),
+                                   (144, 144, 5184), (130, 1, 4097)])
+@pytest.mark.parametrize("transA", [0, 1])
+def test_tsgemm(gpu, ta, tc, M, N, K, transA):
+    """Split-K product for few columns: several K chunks, ragged row tiles
+    (M not a multiple of 64), N from 1 to 192, both layouts of A."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(M + 7 * N + 13 * K)
+    A = rng.standard_normal((K, M) if transA else (M, K))
+    B = rng.standard_normal((K, N))
+    dt = getattr(torch, TT[ta])
+    At = torch.tensor(A, dtype=dt, device="cuda")
+    Bt = torch.tensor(B, dtype=dt, device="cuda")
+    Ct = torch.full((M, N), 7.0, dtype=getattr(torch, TT[tc]), device="cuda")
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    print("tsgemm case", ta, tc, M, N, K, transA, flush=True)
+    st = lib.ctm_debug_tsgemm(ta, tc, M, N, K, At.data_ptr(), transA, Bt.data_ptr(), Ct.data_ptr(),
+                              scratch.data_ptr(), scratch.numel(), torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    Ar = At.to(torch.float64).cpu().numpy()
+    Br = Bt.to(torch.float64).cpu().numpy()
+    ref = (Ar.T if transA else Ar) @ Br
+    got = Ct.to(torch.float64).cpu().numpy()
+    scale = np.abs(Ar).max() * np.abs(Br).max() * K
+    tol = {0: 1e-14, 1: 2e-6}[ta] * scale
+    assert np.abs(got - ref).max() <= tol
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 8), (256, 144, 32), (300, 150, 1296), (20736, 1296, 1296),
+                                   (1000, 81, 264), (513, 290, 64)])
+def test_corner_bf16(gpu, M, N, K):
+    """The bf16 double-layer kernel: full tiles, ragged M and N, K with and
+    without a partial last step (K = D^4 = 1296 for D = 6)."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(M + N + K)
+    A = torch.tensor(rng.standard_normal((M, K)), dtype=torch.bfloat16, device="cuda")
+    Bt = torch.tensor(rng.standard_normal((N, K)), dtype=torch.bfloat16, device="cuda")
+    C = torch.full((M, N), 3.0, dtype=torch.float32, device="cuda")
+    print("corner_bf16 case", M, N, K, flush=True)
+    st = lib.ctm_debug_corner_bf16(M, N, K, A.data_ptr(), Bt.data_ptr(), C.data_ptr(),
+                                   torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    rows = np.unique(np.concatenate([np.arange(min(M, 64)), rng.integers(0, M, 64), [M - 1]]))
+    Ar = A.to(torch.float64).cpu().numpy()[rows]
+    Br = Bt.to(torch.float64).cpu().numpy()
+    ref = Ar @ Br.T
+    got = C.to(torch.float64).cpu().numpy()[rows]
+    # fp32 accumulation of exact bf16 products
+    assert np.abs(got - ref).max() <= 1e-5 * np.sqrt(K) * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("k", [1, 2, 7, 16, 33, 80, 144, 160])
