@@ -33,6 +33,25 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 WORKLOAD = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], d=8, D=6, chi=144, seed=0)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "corner_bf16_2x2_d8_D6_chi144_hbm_counters.md")
+CORNER_SRC = os.path.join(ROOT, "paper_1711_04798_amd", "csrc", "corner_bf16.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the bf16 corner kernel from the committed
+    counter summary, or None when the kernel source changed since."""
+    import hashlib
+    try:
+        sha = hashlib.sha1(open(CORNER_SRC, "rb").read()).hexdigest()
+        fields = dict(l.split(":", 1) for l in open(COUNTERS).read().splitlines()
+                      if l.startswith(("source_sha1:", "hbm_bytes_per_launch:")))
+        if fields.get("source_sha1", "").strip() != sha:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -279,7 +298,9 @@ def main():
                    "chi_eff": max([r["chi_eff"] for r in status] or [0]),
                    "cutoff": solver_opts(args.prec)["cutoff"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic() if args.prec == "bf16" else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "enlarged-corner double-layer contraction (%s, 8 corners "
                                "per launch, 2 chi^2 D^8 flop each)"
                                % ("corner_bf16_kernel" if args.prec == "bf16" else "gemm_kernel"),
