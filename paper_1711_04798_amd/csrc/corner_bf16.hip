@@ -174,6 +174,7 @@ __device__ __forceinline__ void wait_vm(int n) {
 }
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
 
+template <typename TO>
 __global__ void __launch_bounds__(256, 2)
 corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
                        int32_t tiles, int32_t per_xcd) {
@@ -186,7 +187,7 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
   const int m0 = (rem / nt) * BM, n0 = (rem % nt) * BN;
   const __bf16* __restrict__ A = (const __bf16*)g.A[gi];
   const __bf16* __restrict__ Bt = (const __bf16*)g.B[gi];
-  float* __restrict__ C = (float*)g.C[gi];
+  TO* __restrict__ C = (TO*)g.C[gi];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nk = (K + BK - 1) / BK;
   const bool partial = (K % BK) != 0;
@@ -278,7 +279,7 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
       const int64_t roff = (int64_t)h * vc.r_hs + (int64_t)l * vc.r_ls;
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        if (cok[j]) C[roff + coff[j]] = acc[i][j][q];
+        if (cok[j]) C[roff + coff[j]] = (TO)acc[i][j][q];
     }
 }
 
@@ -289,9 +290,10 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K) {
 }
 
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups) {
-  if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG) return hipErrorInvalidValue;
-  const size_t sc = (size_t)(view_max(vc, M, N) + 1) * 4;
+                       int groups, int tout) {
+  if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || (tout != F32 && tout != BF16))
+    return hipErrorInvalidValue;
+  const size_t sc = (size_t)(view_max(vc, M, N) + 1) * dtype_size(tout);
   for (int i = 0; i < groups; ++i)
     if (!span_ok(g.A[i], (size_t)M * K * 2, "corner A") || !span_ok(g.B[i], (size_t)N * K * 2, "corner Bt") ||
         !span_ok(g.C[i], sc, "corner C") || ((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15))
@@ -305,15 +307,19 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
   const int64_t per_xcd = (tiles + 7) / 8;
   static const bool use_dma = [] {
-    const char* e = std::getenv("CTM_CORNER_STAGING");  // "registers" selects the first form
+    const char* e = std::getenv("CTM_CORNER_STAGING");  // "registers" selects the first form (fp32 output)
     return !(e && std::strcmp(e, "registers") == 0);
   }();
-  if (use_dma)
-    hipLaunchKernelGGL(corner_bf16_dma_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, (int32_t)M,
-                       (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+  const dim3 grid((unsigned)(8 * per_xcd));
+  if (tout == BF16)
+    hipLaunchKernelGGL(corner_bf16_dma_kernel<__bf16>, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K,
+                       ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+  else if (use_dma)
+    hipLaunchKernelGGL(corner_bf16_dma_kernel<float>, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K,
+                       ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
   else
-    hipLaunchKernelGGL(corner_bf16_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, (int32_t)M,
-                       (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+    hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g,
+                       (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
   return hipGetLastError();
 }
 

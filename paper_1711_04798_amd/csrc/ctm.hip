@@ -137,6 +137,7 @@ struct Row {  // scratch for one row of a column step
   double *P1 = nullptr, *P2T = nullptr;
   void *P1w = nullptr, *P2Tw = nullptr;
   void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
+  void* A3 = nullptr;  // bf16 mode: [hi | hi | lo] split of W1 for the three-term product
   double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
   double *red = nullptr, *sums = nullptr;
 };
@@ -154,6 +155,8 @@ struct Inst {
   void* Cw[4][MAXPOS] = {};
   void* Tw[4][MAXPOS] = {};
   void* TwP[4][MAXPOS] = {};     // bf16 mode: edges as [prev][next][inner]
+  void* TwR[4][MAXPOS] = {};     // bf16 mode: bf16 edges as [next][inner][prev]
+  void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
   double* spec_old = nullptr;  // [pos][4][chi]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
@@ -248,6 +251,7 @@ void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
   R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
   R.X6 = ar.take_bytes(t3 * ws);
+  if (x.prec == CTM_BF16) R.A3 = ar.take_bytes(3 * y4 * dtype_size(BF16));
   R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
 }
 
@@ -278,7 +282,10 @@ void plan(ctm_ctx_s& x, Arena& ar) {
       for (int r = 0; r < 4; ++r) {
         I.b64[t][r] = ar.take<double>(a8);
         I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : ar.take_bytes(a8 * ws);
-        if (x.prec == CTM_BF16) I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
+        if (x.prec == CTM_BF16) {
+          I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
+          I.bT3[t][r] = ar.take_bytes(3 * a8 * dtype_size(BF16));
+        }
       }
     }
     for (int c = 0; c < 4; ++c)
@@ -287,7 +294,10 @@ void plan(ctm_ctx_s& x, Arena& ar) {
         I.T[c][p] = ar.take<double>(t3);
         I.Cw[c][p] = (x.wt == F64) ? (void*)I.C[c][p] : ar.take_bytes(c2 * ws);
         I.Tw[c][p] = (x.wt == F64) ? (void*)I.T[c][p] : ar.take_bytes(t3 * ws);
-        if (x.prec == CTM_BF16) I.TwP[c][p] = ar.take_bytes(t3 * ws);
+        if (x.prec == CTM_BF16) {
+          I.TwP[c][p] = ar.take_bytes(t3 * ws);
+          I.TwR[c][p] = ar.take_bytes(t3 * dtype_size(BF16));
+        }
       }
     I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi);
     I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
@@ -404,6 +414,7 @@ struct Roles {
   void* Cw(int i, int xp, int yp) const { return I->Cw[(i + k) % 4][pos(xp, yp)]; }
   void* Tw(int i, int xp, int yp) const { return I->Tw[(i + k) % 4][pos(xp, yp)]; }
   void* TwP(int i, int xp, int yp) const { return I->TwP[(i + k) % 4][pos(xp, yp)]; }
+  void* TwR(int i, int xp, int yp) const { return I->TwR[(i + k) % 4][pos(xp, yp)]; }
   void* bT(int xp, int yp, int r) const { return I->bT[tid(xp, yp)][(k + r) % 4]; }
   // double layer of the site in this frame, additionally turned by r
   double* b64(int xp, int yp, int r) const { return I->b64[tid(xp, yp)][(k + r) % 4]; }
@@ -516,6 +527,7 @@ struct CornerJob {
   const void *C, *Tn, *Tp, *b;
   void *X, *Y, *Q;
   const void *TnP = nullptr, *bT = nullptr;  // bf16 path: permuted edge, transposed double layer
+  const void* TnR = nullptr;                 // bf16 path: bf16 edge as [next][inner][prev]
 };
 
 struct Stage3Timer {
@@ -549,21 +561,35 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
   const bool fast = bf16 && tq == F32 && !jobs.empty() && jobs[0].TnP && jobs[0].bT &&
                     corner_bf16_supported(c * c, K4, K4);
   const int ty = bf16 ? BF16 : tin;  // type of Y
+  const bool fast2 = fast && jobs[0].TnR && corner_bf16_supported(n, n, c);
   for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
     size_t j1 = std::min(jobs.size(), j0 + MAXG);
     G g1, g2, g3;
     if (fast) {
-      // stage 2 reads the edge as [n][(b,u)] and writes Y as [(g,b)][(l,u)], so
-      // that stage 3 has both operands contiguous in the contracted index
-      for (size_t j = j0; j < j1; ++j) {
-        g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
-        g2.add(jobs[j].X, jobs[j].TnP, jobs[j].Y);
-        g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
-      }
-      CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
-      // rows m = (g, l) -> g chi D^4 + l D^2; cols (b, u) -> b D^4 + u
+      // stage 2 writes Y as [(g,b)][(l,u)], so that stage 3 has both operands
+      // contiguous in the contracted index; rows m = (g, l) -> g chi D^4 + l D^2,
+      // cols (b, u) -> b D^4 + u
       View vy = view2(D2, D2, c * K4, D2, 1, K4);
-      CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
+      if (fast2) {
+        // stage 2 on the bf16 kernel too: X in bf16 from stage 1, the edge as
+        // [(b,u)][n] (its bf16 copy ordered [next][inner][prev])
+        for (size_t j = j0; j < j1; ++j) {
+          g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
+          g2.add(jobs[j].X, jobs[j].TnR, jobs[j].Y);
+          g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
+        }
+        CHK(gemm_run(s, tin, BF16, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
+        HIPCHK(corner_bf16(s, n, n, c, vy, g2.group(0, g2.size()), g2.size(), BF16));
+      } else {
+        // stage 2 reads the edge as [n][(b,u)]
+        for (size_t j = j0; j < j1; ++j) {
+          g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
+          g2.add(jobs[j].X, jobs[j].TnP, jobs[j].Y);
+          g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
+        }
+        CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
+        CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
+      }
       View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
       CHK(stage3_timed(s, tm, [&]() -> ctm_status {
         HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.group(0, g3.size()), g3.size()));
@@ -875,12 +901,31 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   CHK(gemm_long(x, at, F64, c, c, n, transposed(rowmajor(c)), rowmajor(c), rowmajor(c), g2));
   // W1[(g,l),(u,c2)] = sum_p T4[(g,l),p] P2T_prev[(p,u), c2]
   CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
-  // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)]: the new
-  // edge itself, so in the working type even in bf16 mode (rounding the
-  // double layer here perturbs the fixed point directly: ~10x the energy
-  // error of bf16 enlarged corners, which only steer the truncation)
-  CHK(gemm_run(s, at, at, c * c, D2 * D2, D2 * D2, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(D2 * D2),
-               rowmajor(D2 * D2), g4));
+  // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)] is the new
+  // edge itself: rounding its operands to bf16 perturbs the fixed point
+  // directly (~10x the energy error of bf16 enlarged corners, which only steer
+  // the truncation).  In bf16 mode it is the three-term product
+  // hi.hi + hi.lo + lo.hi of bf16 splits (operand error ~2^-16) on the bf16
+  // kernel; otherwise in the working type.
+  const View vw1 = view2(c, 1, D2 * D2 * c, BIG, c, 0);
+  const int64_t K4 = D2 * D2;
+  if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
+    G g3x;
+    for (Inst* I : insts) {
+      Roles ro{&x, I, k};
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        HIPCHK(split3_bf16(s, at, R.W1, vw1, c * c, K4, true, R.A3));
+        g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], R.W2);
+      }
+    }
+    for (int j0 = 0; j0 < g3x.size(); j0 += MAXG) {
+      int cnt = std::min(MAXG, g3x.size() - j0);
+      HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, rowmajor(K4), g3x.group(j0, cnt), cnt, F32));
+    }
+  } else {
+    CHK(gemm_run(s, at, at, c * c, K4, K4, vw1, rowmajor(K4), rowmajor(K4), g4));
+  }
   // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
   //   B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
   //   B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
@@ -927,6 +972,11 @@ ctm_status refresh_working(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
           int perm[3] = {0, 2, 1};
           HIPCHK(permute(x.stream, F64, I->T[c][p], x.wt, I->TwP[c][p], 3, dims, perm));
         }
+        if (I->TwR[c][p]) {
+          int64_t dims[3] = {I->chi, I->D2, I->chi};
+          int perm[3] = {2, 1, 0};
+          HIPCHK(permute(x.stream, F64, I->T[c][p], BF16, I->TwR[c][p], 3, dims, perm));
+        }
       }
   }
   return xfer_run(x.stream, F64, x.wt, cv);
@@ -971,6 +1021,7 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
         j.Y = R.Y[q];
         j.Q = R.Q[q];
         if (x.prec == CTM_BF16) {
+          j.TnR = ro.TwR(q, cx[q], cy[q]);
           j.TnP = ro.TwP(q, cx[q], cy[q]);
           j.bT = ro.bT(cx[q], cy[q], q);
         }
@@ -1779,6 +1830,11 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           int perm[2] = {1, 0};
           if (permute(x->stream, F64, I.b64[t][r], BF16, I.bT[t][r], 2, dims, perm) != hipSuccess)
             return cleanup(fail(CTM_E_HIP, "transpose double layer"));
+          // B side of the three-term product: rows (dn,R), columns (l,u)
+          const int64_t K4 = (int64_t)I.D2 * I.D2;
+          if (split3_bf16(x->stream, F64, I.b64[t][r], transposed(rowmajor(K4)), K4, K4, false, I.bT3[t][r]) !=
+              hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "split double layer"));
         }
     }
     st = init_env(*x, I, i, init, spectrum_host);

@@ -85,8 +85,18 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
                    const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
 
 bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
+
+// Three-term bf16 split of float data for products with fp32-like accuracy:
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); A-side rows [hi | hi | lo],
+// B-side rows [hi | lo | hi], so that one bf16 product over 3K gives
+// hi.hi + hi.lo + lo.hi.  `in` is read through the view (rows x K), out is
+// row-major rows x 3K.  tin = F32 or F64.
+hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, int64_t rows, int64_t K, bool a_side,
+                       void* out);
+// C (tout = F32 or BF16, through the view vc) = A Bt^T, A bf16 M x K and
+// Bt bf16 N x K row-major (16-byte aligned, K % 8 == 0), fp32 accumulation
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups);
+                       int groups, int tout = F32);
 
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].

@@ -791,4 +791,42 @@ hipError_t normalize_group(hipStream_t s, const NormSet& x, int njobs, double* p
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// three-term bf16 split (see kernels.h)
+// ---------------------------------------------------------------------------
+template <typename TI>
+__global__ void split3_kernel(const TI* __restrict__ in, DevView v, int64_t rows, int64_t K, int a_side,
+                              __bf16* __restrict__ out) {
+  const int64_t n = rows * K;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / K, k = e - r * K;
+    const double x = (double)in[row_off(v, (int32_t)r) + col_off(v, (int32_t)k)];
+    const __bf16 hi = (__bf16)(float)x;
+    const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+    __bf16* o = out + r * 3 * K + k;
+    o[0] = hi;
+    o[K] = a_side ? hi : lo;
+    o[2 * K] = a_side ? lo : hi;
+  }
+}
+
+hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, int64_t rows, int64_t K, bool a_side,
+                       void* out) {
+  if (rows <= 0 || K <= 0 || rows > INT32_MAX || K > INT32_MAX || (tin != F32 && tin != F64))
+    return hipErrorInvalidValue;
+  if (!span_ok(in, (size_t)(view_max(vin, rows, K) + 1) * dtype_size(tin), "split3 in") ||
+      !span_ok(out, (size_t)rows * 3 * K * 2, "split3 out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const DevView dv = dev_view(vin, rows, K);
+  const int64_t blocks = std::min<int64_t>(8192, (rows * K + 255) / 256);
+  if (tin == F32)
+    hipLaunchKernelGGL((split3_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, s, (const float*)in, dv, rows, K,
+                       a_side ? 1 : 0, (__bf16*)out);
+  else
+    hipLaunchKernelGGL((split3_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double*)in, dv, rows,
+                       K, a_side ? 1 : 0, (__bf16*)out);
+  return hipGetLastError();
+}
+
 }  // namespace ctmk

@@ -16,7 +16,8 @@ float64 GPU path with the same cutoff (itself checked against the oracle by
 the parity tests).
 
 Bounds: energy per spin 1e-4 relative (fp32 and bf16); kappa 1e-7 relative;
-spectrum ratios 1e-3 absolute.
+spectrum ratios 1e-3 absolute in fp32, 5e-3 in bf16 (where the normalised
+spectra fluctuate by ~2e-3 from one sweep to the next).
 """
 import json
 import os
@@ -31,7 +32,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BONDS = [(x, y, v) for v in (False, True) for y in range(2) for x in range(2)]
-BOUNDS = {"fp32": (1e-4, 1e-7, 1e-3), "bf16": (1e-4, 1e-7, 1e-3)}
+BOUNDS = {"fp32": (1e-4, 1e-7, 1e-3), "bf16": (1e-4, 1e-7, 5e-3)}
 
 
 def _energy(g):
