@@ -138,6 +138,7 @@ struct Row {  // scratch for one row of a column step
   void *P1w = nullptr, *P2Tw = nullptr;
   void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
   void* A3 = nullptr;  // bf16 mode: [hi | hi | lo] split of W1 for the three-term product
+  void* W2t = nullptr; // fp32 working type: W2 as [(g,dn)][(R,c2)]
   double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
   double *red = nullptr, *sums = nullptr;
 };
@@ -252,6 +253,7 @@ void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
   R.X6 = ar.take_bytes(t3 * ws);
   if (x.prec == CTM_BF16) R.A3 = ar.take_bytes(3 * y4 * dtype_size(BF16));
+  if (x.wt == F32) R.W2t = ar.take_bytes(y4 * ws);
   R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
 }
 
@@ -899,23 +901,24 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // C1' [b', r] = sum_(a,U) P1prev[(a,U), b'] CT[(a,U), r]
   CHK(gemm_run(s, at, at, c, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g1));
   CHK(gemm_long(x, at, F64, c, c, n, transposed(rowmajor(c)), rowmajor(c), rowmajor(c), g2));
-  // W1[(g,l),(u,c2)] = sum_p T4[(g,l),p] P2T_prev[(p,u), c2]
-  CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+  // W1 = sum_p T4[(g,l),p] P2T_prev[(p,u), c2];  then
   // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)] is the new
   // edge itself: rounding its operands to bf16 perturbs the fixed point
   // directly (~10x the energy error of bf16 enlarged corners, which only steer
   // the truncation).  In bf16 mode it is the three-term product
   // hi.hi + hi.lo + lo.hi of bf16 splits (operand error ~2^-16) on the bf16
-  // kernel; otherwise in the working type.
-  const View vw1 = view2(c, 1, D2 * D2 * c, BIG, c, 0);
+  // kernel (the split also transposes W1 to [(g,c2)][(l,u)], through LDS);
+  // otherwise in the working type.
   const int64_t K4 = D2 * D2;
   if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
+    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
     G g3x;
     for (Inst* I : insts) {
       Roles ro{&x, I, k};
       for (int yp = 0; yp < ly; ++yp) {
         Row& R = I->rows[yp];
-        HIPCHK(split3_bf16(s, at, R.W1, vw1, c * c, K4, true, R.A3));
+        // W1 as c matrices [(l,u)][c2] -> A3[(g,c2)][hi | hi | lo over (l,u)]
+        HIPCHK(split3_transpose_bf16(s, (const float*)R.W1, c, K4, c, true, R.A3));
         g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], R.W2);
       }
     }
@@ -924,13 +927,33 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, rowmajor(K4), g3x.group(j0, cnt), cnt, F32));
     }
   } else {
-    CHK(gemm_run(s, at, at, c * c, K4, K4, vw1, rowmajor(K4), rowmajor(K4), g4));
+    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+    CHK(gemm_run(s, at, at, c * c, K4, K4, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(K4), rowmajor(K4), g4));
   }
   // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
   //   B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
   //   B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
-  CHK(gemm_run(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), view2(D2, D2, c * D2 * D2, c, D2 * D2, 1),
-               rowmajor(D2 * c), g5));
+  if (at == F32) {
+    // W2 read through that view touches one element per cache line: transpose
+    // it first (per g: [c2][(dn,R)] -> [(dn,R)][c2], i.e. W2t[(g,dn)][(R,c2)]),
+    // then a plain product with few rows (chi) and a long contraction (n),
+    // split over K
+    G g5t;
+    for (Inst* I : insts)
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        HIPCHK(transpose_batched(s, (const float*)R.W2, c, c, K4, (float*)R.W2t));
+        g5t.add(R.P1w, R.W2t, R.nT4);
+      }
+    for (int j0 = 0; j0 < g5t.size(); j0 += MAXG) {
+      int cnt = std::min(MAXG, g5t.size() - j0);
+      HIPCHK(gemm_splitk_f32(s, F64, c, D2 * c, n, transposed(rowmajor(c)), rowmajor(D2 * c), rowmajor(D2 * c),
+                             g5t.group(j0, cnt), cnt, x.ts_scratch, x.ts_bytes));
+    }
+  } else {
+    CHK(gemm_run(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), view2(D2, D2, c * D2 * D2, c, D2 * D2, 1),
+                 rowmajor(D2 * c), g5));
+  }
   // X6[z, (g, dn)] = sum_q T3[(z,dn), q] C4[q, g]  written as [z][g][dn]
   CHK(gemm_run(s, at, at, c * D2, c, c, rowmajor(c), rowmajor(c), view2(D2, 1, c * D2, BIG, D2, 0), g6));
   // C4'[z, c] = sum_(g,dn) X6[z,(g,dn)] P2T[(g,dn), c]

@@ -84,6 +84,14 @@ bool ts_gemm_supported(int ta, int tc, int64_t M, int64_t N, int64_t K, const Vi
 hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                    const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
 
+// out[b][c][r] = in[b][r][c], float32, nb matrices R x C.
+hipError_t transpose_batched(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, float* out);
+
+// Split-K product with float32 operands and float32 or float64 output through
+// any views (float partials in `scratch`, summed in a fixed order).
+hipError_t gemm_splitk_f32(hipStream_t s, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                           const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
+
 bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
 
 // Three-term bf16 split of float data for products with fp32-like accuracy:
@@ -93,6 +101,10 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
 // row-major rows x 3K.  tin = F32 or F64.
 hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, int64_t rows, int64_t K, bool a_side,
                        void* out);
+// The same for float32 `in` = nb matrices [R][C] (row-major, batch-major),
+// transposed on the way: out row (b, c) = split of in[b][.][c], length 3R.
+hipError_t split3_transpose_bf16(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, bool a_side,
+                                 void* out);
 // C (tout = F32 or BF16, through the view vc) = A Bt^T, A bf16 M x K and
 // Bt bf16 N x K row-major (16-byte aligned, K % 8 == 0), fp32 accumulation
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,

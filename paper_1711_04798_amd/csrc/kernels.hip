@@ -356,6 +356,66 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
   return hipGetLastError();
 }
 
+// split-K for float32 operands: float partials, summed in a fixed order and
+// written through the output view in float32 or float64
+template <typename TO>
+__global__ void splitk_reduce_f32_kernel(const float* __restrict__ part, int ksplit, int32_t M, int32_t N,
+                                         DevView vc, GemmGroup g) {
+  const int gi = blockIdx.y;
+  const float* p = part + (int64_t)gi * ksplit * M * N;
+  TO* C = (TO*)g.C[gi];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)M * N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.0f;
+    for (int sp = 0; sp < ksplit; ++sp) acc += p[(int64_t)sp * M * N + e];
+    int r = (int)(e / N), c = (int)(e % N);
+    C[row_off(vc, r) + col_off(vc, c)] = (TO)acc;
+  }
+}
+
+hipError_t gemm_splitk_f32(hipStream_t s, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
+                           const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes) {
+  if (M <= 0 || N <= 0 || groups <= 0) return hipSuccess;
+  if (tc != F32 && tc != F64) return hipErrorInvalidValue;
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * groups;
+  int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / std::max<int64_t>(tiles, 1),
+                                                          K / 256));
+  while (ksplit > 1 && ksplit * M * N * groups * 4 > scratch_bytes) ksplit /= 2;
+  if (ksplit <= 1) return gemm(s, F32, tc, M, N, K, 1.0, va, vb, 0.0, vc, g, groups);
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || groups > MAXG) return hipErrorInvalidValue;
+  const size_t sa = (size_t)(view_max(va, M, K) + 1) * 4, sb = (size_t)(view_max(vb, K, N) + 1) * 4,
+               sc = (size_t)(view_max(vc, M, N) + 1) * dtype_size(tc);
+  for (int i = 0; i < groups; ++i)
+    if (!span_ok(g.A[i], sa, "splitk32 A") || !span_ok(g.B[i], sb, "splitk32 B") || !span_ok(g.C[i], sc, "splitk32 C"))
+      return hipErrorInvalidValue;
+  if (!span_ok(scratch, (size_t)ksplit * M * N * groups * 4, "splitk32 scratch")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  GemmGroup gp = g;
+  for (int i = 0; i < groups; ++i) gp.C[i] = (float*)scratch + (int64_t)i * ksplit * M * N;
+  DevView da = dev_view(va, M, K), db = dev_view(vb, K, N), dc = dev_view(rowmajor(N), M, N);
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)(groups * ksplit));
+  const bool ak = (va.c_ls == 1), bk = (vb.r_ls == 1);
+#define SK32(AKV, BKV)                                                                                          \
+  hipLaunchKernelGGL((gemm_kernel<float, float, 64, 64, AKV, BKV>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, \
+                     (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit)
+  if (ak && bk) SK32(true, true);
+  else if (ak) SK32(true, false);
+  else if (bk) SK32(false, true);
+  else SK32(false, false);
+#undef SK32
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  DevView dvc = dev_view(vc, M, N);
+  const int64_t blocks = std::min<int64_t>(2048, (M * N + 255) / 256);
+  if (tc == F64)
+    hipLaunchKernelGGL(splitk_reduce_f32_kernel<double>, dim3((unsigned)blocks, groups), dim3(256), 0, s,
+                       (const float*)scratch, (int)ksplit, (int32_t)M, (int32_t)N, dvc, g);
+  else
+    hipLaunchKernelGGL(splitk_reduce_f32_kernel<float>, dim3((unsigned)blocks, groups), dim3(256), 0, s,
+                       (const float*)scratch, (int)ksplit, (int32_t)M, (int32_t)N, dvc, g);
+  return hipGetLastError();
+}
+
 template <typename TI, typename TO>
 static hipError_t launch_gemm_ab(hipStream_t s, int tile, int64_t M, int64_t N, int64_t K, double alpha,
                                  const View& va, const View& vb, double beta, const View& vc,
@@ -826,6 +886,73 @@ hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, 
   else
     hipLaunchKernelGGL((split3_kernel<double>), dim3((unsigned)blocks), dim3(256), 0, s, (const double*)in, dv, rows,
                        K, a_side ? 1 : 0, (__bf16*)out);
+  return hipGetLastError();
+}
+
+// 32 x 32 tiles through LDS: coalesced reads along c, coalesced writes along r
+__global__ void split3_transpose_kernel(const float* __restrict__ in, int64_t R, int64_t C, int a_side,
+                                        __bf16* __restrict__ out) {
+  __shared__ float t[32][33];
+  const int64_t b = blockIdx.z;
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows of 32
+  const float* src = in + b * R * C;
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < R && c < C) ? src[r * C + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < C && r < R) {
+      const float x = t[tx][i];
+      const __bf16 hi = (__bf16)x;
+      const __bf16 lo = (__bf16)(x - (float)hi);
+      __bf16* o = out + (b * C + c) * 3 * R + r;
+      o[0] = hi;
+      o[R] = a_side ? hi : lo;
+      o[2 * R] = a_side ? lo : hi;
+    }
+  }
+}
+
+hipError_t split3_transpose_bf16(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, bool a_side,
+                                 void* out) {
+  if (nb <= 0 || R <= 0 || C <= 0 || nb > 65535) return hipErrorInvalidValue;
+  if (!span_ok(in, (size_t)nb * R * C * 4, "split3t in") || !span_ok(out, (size_t)nb * C * 3 * R * 2, "split3t out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32), (unsigned)nb);
+  hipLaunchKernelGGL(split3_transpose_kernel, grid, dim3(256), 0, s, in, R, C, a_side ? 1 : 0, (__bf16*)out);
+  return hipGetLastError();
+}
+
+// batched transpose out[b][c][r] = in[b][r][c] (float), 32 x 32 LDS tiles
+__global__ void transpose_batched_kernel(const float* __restrict__ in, int64_t R, int64_t C, float* __restrict__ out) {
+  __shared__ float t[32][33];
+  const int64_t b = blockIdx.z;
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const float* src = in + b * R * C;
+  float* dst = out + b * R * C;
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < R && c < C) t[i][tx] = src[r * C + c];
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < C && r < R) dst[c * R + r] = t[tx][i];
+  }
+}
+
+hipError_t transpose_batched(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, float* out) {
+  if (nb <= 0 || R <= 0 || C <= 0 || nb > 65535) return hipErrorInvalidValue;
+  if (!span_ok(in, (size_t)nb * R * C * 4, "transpose in") || !span_ok(out, (size_t)nb * R * C * 4, "transpose out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32), (unsigned)nb);
+  hipLaunchKernelGGL(transpose_batched_kernel, grid, dim3(256), 0, s, in, R, C, out);
   return hipGetLastError();
 }
 

@@ -141,9 +141,10 @@ __device__ __forceinline__ int rr_player(int pos, int r, int kk) {
 
 __global__ void __launch_bounds__(1024)
 jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work, int want_vectors,
-                  int transpose_in, StatSet st, double noise_rel) {
+                  int transpose_in, StatSet st, double noise_rel, int in_lds) {
+  extern __shared__ double jsm[];         // A, Gram and W when they fit in LDS
   const int pb = blockIdx.x;
-  double* A = work.p[pb];                 // column-major k x k, column c at A + c*k
+  double* A = in_lds ? jsm : work.p[pb];  // column-major k x k, column c at A + c*k
   double* Gm = A + (size_t)k * k;         // Gram of the columns at the start of a sweep
   double* W = Gm + (size_t)k * k;         // column-major right rotations
   const double* M = Min.p[pb];
@@ -309,8 +310,23 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, c
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   StatSet none{};
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(1024), 0, s, k, M, U, S, W, work,
-                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel);
+  // the columns, their Gram matrix and the rotations live in LDS when they fit
+  // next to the kernel's static arrays (about 12 KiB)
+  constexpr size_t kJMaxDyn = 160 * 1024 - 16384;
+  const size_t lds = (size_t)(want_vectors ? 3 : 2) * k * k * sizeof(double);
+  const bool in_lds = lds <= kJMaxDyn;
+  static bool attr_set = false;
+  if (in_lds && !attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)jacobi_svd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kJMaxDyn);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(1024), in_lds ? lds : 0, s, k, M, U, S, W, work,
+                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel, in_lds ? 1 : 0);
   return hipGetLastError();
 }
 

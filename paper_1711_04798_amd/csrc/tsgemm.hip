@@ -39,7 +39,9 @@ __device__ __forceinline__ v4d mfma<double>(double a, double b, v4d c) {
 
 // A element (m, k) at m * lda + k (A_KFAST) or k * lda + m; B (k, n) at k * ldb + n.
 // part[(gi * nsplit + s)][m][n], row-major M x N.
-template <typename T, bool A_KFAST, int NT>
+// VEC (float only): A is read in 16-byte chunks along its contiguous index
+// (needs lda, K and M multiples of 4 and a 16-byte aligned base)
+template <typename T, bool A_KFAST, int NT, bool VEC>
 __global__ void __launch_bounds__(256, 2)
 ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
                   int32_t mtiles, GemmGroup g, T* __restrict__ part) {
@@ -60,13 +62,32 @@ ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int
   constexpr int AE = BM * BK / 256;                 // A elements per thread
   constexpr int BE = (NP * BK + 255) / 256;         // B elements per thread
   T ra[AE], rb[BE];
+  // vector form: chunk e of 4 consecutive elements along the contiguous index
+  //   k-fast: row e / (BK / 4), k 4 (e % (BK / 4)); m-fast: k e / (BM / 4), m 4 (e % (BM / 4))
+  auto chunk_rk = [&](int e, int& r, int& kk) {
+    if (A_KFAST) { r = e / (BK / 4); kk = (e % (BK / 4)) * 4; }
+    else { kk = e / (BM / 4); r = (e % (BM / 4)) * 4; }
+  };
   auto gload = [&](int k0) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int j = 0; j < AE; ++j) {
-      const int e = tid + 256 * j;
-      const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
-      const int m = m0 + r, k = k0 + kk;
-      ra[j] = (m < M && k < kend) ? A[A_KFAST ? (int64_t)m * lda + k : (int64_t)k * lda + m] : T(0);
+      for (int j = 0; j < AE / 4; ++j) {
+        int r, kk;
+        chunk_rk(tid + 256 * j, r, kk);
+        const int m = m0 + r, k = k0 + kk;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (A_KFAST ? (m < M && k < kend) : (m < M && k < kend))
+          v = *reinterpret_cast<const float4*>(A_KFAST ? A + (int64_t)m * lda + k : A + (int64_t)k * lda + m);
+        ra[4 * j] = v.x; ra[4 * j + 1] = v.y; ra[4 * j + 2] = v.z; ra[4 * j + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < AE; ++j) {
+        const int e = tid + 256 * j;
+        const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
+        const int m = m0 + r, k = k0 + kk;
+        ra[j] = (m < M && k < kend) ? A[A_KFAST ? (int64_t)m * lda + k : (int64_t)k * lda + m] : T(0);
+      }
     }
 #pragma unroll
     for (int j = 0; j < BE; ++j) {
@@ -77,11 +98,24 @@ ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int
     }
   };
   auto lstore = [&](int buf) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int j = 0; j < AE; ++j) {
-      const int e = tid + 256 * j;
-      const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
-      As[buf][r * LDK + kk] = ra[j];
+      for (int j = 0; j < AE / 4; ++j) {
+        int r, kk;
+        chunk_rk(tid + 256 * j, r, kk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (A_KFAST) As[buf][r * LDK + kk + i] = ra[4 * j + i];
+          else As[buf][(r + i) * LDK + kk] = ra[4 * j + i];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < AE; ++j) {
+        const int e = tid + 256 * j;
+        const int r = A_KFAST ? e / BK : e % BM, kk = A_KFAST ? e % BK : e / BM;
+        As[buf][r * LDK + kk] = ra[j];
+      }
     }
 #pragma unroll
     for (int j = 0; j < BE; ++j) {
@@ -149,13 +183,13 @@ __global__ void ts_reduce_kernel(const T* __restrict__ part, int32_t M, int32_t 
   }
 }
 
-template <typename T, bool AK>
+template <typename T, bool AK, bool VEC>
 hipError_t launch_partial(hipStream_t s, int nt, dim3 grid, int32_t M, int32_t N, int32_t K, int64_t lda,
                           int64_t ldb, int32_t kchunk, int32_t nsplit, int32_t mtiles, const GemmGroup& g,
                           T* part) {
 #define TS_CASE(NTV)                                                                                  \
   case NTV:                                                                                           \
-    hipLaunchKernelGGL((ts_partial_kernel<T, AK, NTV>), grid, dim3(256), 0, s, M, N, K, lda, ldb,      \
+    hipLaunchKernelGGL((ts_partial_kernel<T, AK, NTV, VEC>), grid, dim3(256), 0, s, M, N, K, lda, ldb, \
                        kchunk, nsplit, mtiles, g, part);                                              \
     break;
   switch (nt) {
@@ -211,16 +245,25 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
   const int nt = (int)((N + 15) / 16);
   dim3 grid((unsigned)(mtiles * nsplit * groups));
   hipError_t e;
-  if (ta == F32)
-    e = ak ? launch_partial<float, true>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb, (int32_t)kchunk,
-                                         (int32_t)nsplit, (int32_t)mtiles, g, (float*)scratch)
-           : launch_partial<float, false>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
-                                          (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (float*)scratch);
-  else
-    e = ak ? launch_partial<double, true>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
-                                          (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (double*)scratch)
-           : launch_partial<double, false>(s, nt, grid, (int32_t)M, (int32_t)N, (int32_t)K, lda, ldb,
-                                           (int32_t)kchunk, (int32_t)nsplit, (int32_t)mtiles, g, (double*)scratch);
+  // 16-byte A loads when every chunk start is 16-byte aligned and chunks never
+  // straddle the M or K edge
+  bool vec = ta == F32 && lda % 4 == 0 && K % 4 == 0 && M % 4 == 0;
+  for (int i = 0; i < groups && vec; ++i) vec = ((uintptr_t)g.A[i] & 15) == 0;
+  const int32_t M32 = (int32_t)M, N32 = (int32_t)N, K32 = (int32_t)K, kc32 = (int32_t)kchunk,
+                ns32 = (int32_t)nsplit, mt32 = (int32_t)mtiles;
+  if (ta == F32) {
+    float* ps = (float*)scratch;
+    if (vec)
+      e = ak ? launch_partial<float, true, true>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps)
+             : launch_partial<float, false, true>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps);
+    else
+      e = ak ? launch_partial<float, true, false>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps)
+             : launch_partial<float, false, false>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps);
+  } else {
+    double* ps = (double*)scratch;
+    e = ak ? launch_partial<double, true, false>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps)
+           : launch_partial<double, false, false>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps);
+  }
   if (e != hipSuccess) return e;
   const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (M * N + 255) / 256));
   dim3 rg((unsigned)blocks, (unsigned)groups);
