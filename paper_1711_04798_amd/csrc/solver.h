@@ -38,8 +38,11 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
 
 // One-sided Jacobi SVD of the k x k row-major matrix M (k <= 192): M W = U S with singular
 // values in descending order.  U, W row-major k x k; S length k.  Columns of U
-// with a zero singular value are zero.  `work` needs 3 k*k doubles per problem
-// (2 k*k when only the singular values are wanted; U and W are then untouched).
+// with a zero singular value are zero.  The working columns live in LDS when
+// they fit; otherwise `work` holds them: 2 k*k16 doubles per problem (k*k16
+// when only the singular values are wanted), k16 = k rounded up to a multiple
+// of 16.  When only the singular values are wanted, U and W are untouched and
+// rows and columns that are exactly zero are dropped before the sweeps.
 // With transpose_in the rotations act on the columns of M^T (the rows of M):
 // M^T W = U S, i.e. M = W S U^T.  Columns whose norm stays below noise_rel
 // (at least 4 u) times the largest are left unrotated; their singular values

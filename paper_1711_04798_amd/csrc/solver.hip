@@ -91,9 +91,151 @@ chol_shift_inv_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet 
   if (fail && tid == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
 }
 
+// ---------------------------------------------------------------------------
+// The same factorisation and inverse for k <= 64 with one wave per problem.
+// Left-looking (Cholesky-Crout) order in blocks of four columns: lane i owns
+// row i of L = R^T.  For a block j0..j0+3 each lane first subtracts the
+// finished columns l < j0 from its four entries (one read of its own row
+// serves four dot products; rows j0..j0+3 are LDS broadcasts), then the 4 x 4
+// diagonal block is finished in registers, the entries of rows j0..j0+3
+// coming from their owner lanes by readlane.  Then lane c forms column c of
+// L^{-1} by forward substitution in the same blocking, with reciprocal
+// pivots; that column is row c of R^{-1} = (L^{-1})^T.
+// ---------------------------------------------------------------------------
+constexpr int CW = 64;       // largest k of the one-wave form
+constexpr int CWL = CW + 4;  // LDS row stride (a block may read 3 entries past column k-1)
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// s[b] -= sum_{l < n} x[l] * y[b * CWL + l], b = 0..3, n a multiple of 4;
+// eight columns of loads are issued before their products
+__device__ __forceinline__ void dot4_lds(const double* x, const double* y, int n, double s[4]) {
+  int l = 0;
+  for (; l + 8 <= n; l += 8) {
+    double xv[8], yv[4][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[l + u];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) yv[b][u] = y[b * CWL + l + u];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[b] -= xv[u] * yv[b][u];
+  }
+  if (l < n) {  // n - l == 4
+    double xv[4], yv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = x[l + u];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) yv[b][u] = y[b * CWL + l + u];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[b] -= xv[u] * yv[b][u];
+  }
+}
+
+__global__ void __launch_bounds__(64)
+chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st) {
+  __shared__ double L[CW * CWL];  // row i at L + i*CWL; G + sI (lower part) in, L out, zero elsewhere
+  __shared__ double X[CW * CWL];  // row c at X + c*CWL: column c of L^{-1}
+  __shared__ double rpiv[CW];     // 1 / L_jj
+  const int pb = blockIdx.x, lane = threadIdx.x;
+  const double* g = G.p[pb];
+  double* ri = Rinv.p[pb];
+  // lane c reads column c of G (coalesced rows, every load in flight at
+  // once; indices clamped so that no load leaves the k x k block)
+  const int cc = lane < k ? lane : k - 1;
+  double col[CW];
+#pragma unroll
+  for (int r = 0; r < CW; ++r) col[r] = g[(r < k ? r : k - 1) * k + cc];
+  double tr = 0.0;
+#pragma unroll
+  for (int r = 0; r < CW; ++r)
+    if (r == lane && r < k) tr = col[r];
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  const double shift = shift_coef * tr;
+  // the upper triangle of G is the input (as in the wide form): row c of the
+  // lower factor's input is L_cr = G_rc (r <= c), zero elsewhere
+  double* li = L + lane * CWL;
+#pragma unroll
+  for (int r = 0; r < CW; ++r) li[r] = (r <= lane && lane < k) ? col[r] + (r == lane ? shift : 0.0) : 0.0;
+#pragma unroll
+  for (int r = CW; r < CWL; ++r) li[r] = 0.0;
+  __syncthreads();
+  const double floor_v = (tr > 0.0 ? tr : 1.0) * 1e-300;
+  int fail = 0;
+  for (int j0 = 0; j0 < k; j0 += 4) {
+    double sv[4] = {li[j0], li[j0 + 1], li[j0 + 2], li[j0 + 3]};
+    dot4_lds(li, L + j0 * CWL, j0, sv);
+    double lb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + b;
+      lb[b] = 0.0;
+      if (j < k) {
+        double sb = sv[b];
+#pragma unroll
+        for (int m = 0; m < b; ++m) sb -= lb[m] * readlane_f64(lb[m], j);
+        double d = readlane_f64(sb, j);
+        if (!(d > floor_v)) { d = floor_v; fail = 1; }
+        const double r = sqrt(d), rinv = 1.0 / r;
+        lb[b] = lane == j ? r : (lane > j ? sb * rinv : 0.0);
+        if (lane == 0) rpiv[j] = rinv;
+      }
+    }
+    if (lane < k) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (j0 + b < k) li[j0 + b] = lb[b];
+    }
+    __syncthreads();
+  }
+  // forward substitution, rows in blocks of four:
+  //   x_i = (delta_ic - sum_{l<i} L_il x_l) / L_ii
+  double* xc = X + lane * CWL;
+  for (int i0 = 0; i0 < k; i0 += 4) {
+    double sv[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sv[b] = lane == i0 + b ? 1.0 : 0.0;
+    dot4_lds(xc, L + i0 * CWL, i0, sv);
+    double xb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      xb[b] = 0.0;
+      if (i0 + b < k) {
+        double sb = sv[b];
+#pragma unroll
+        for (int m = 0; m < b; ++m) sb -= L[(i0 + b) * CWL + i0 + m] * xb[m];
+        xb[b] = sb * rpiv[i0 + b];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (i0 + b < k) xc[i0 + b] = xb[b];
+  }
+  __syncthreads();
+  // lane c writes column c of R^{-1} (row r of R^{-1} is X's row r)
+  if (lane < k) {
+#pragma unroll
+    for (int r = 0; r < CW; ++r)
+      if (r < k) ri[r * k + lane] = X[r * CWL + lane];
+  }
+  if (fail && lane == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
+}
+
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob) {
-  if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
+  if (nprob < 0 || nprob > MAXP || k < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   // dynamic LDS: packed R plus 16 columns of the inverse; 8 KiB of the CU's
   // 160 KiB stay for the kernel's static arrays
@@ -105,6 +247,10 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
         !span_ok(st.p[i], sizeof(SolveStatus), "chol status"))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
+  if (k <= CW) {
+    hipLaunchKernelGGL(chol_wave_kernel, dim3(nprob), dim3(64), 0, s, k, shift_coef, G, Rinv, st);
+    return hipGetLastError();
+  }
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)chol_shift_inv_kernel,
@@ -121,14 +267,39 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
 
 // ---------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of a k x k matrix, one workgroup per
-// problem.  Columns are kept column-major in `work` (A then W); each round
-// rotates k/2 disjoint column pairs of the round-robin schedule, one pair per
-// wave at a time.  A pair (p, q) with Gram entries a = |x_p|^2, b = |x_q|^2,
-// g = x_p . x_q is rotated when |g| > eps sqrt(a b); the rotation makes the
-// two columns orthogonal (Golub & Van Loan, Sec. 8.6.3 / Hestenes 1958).
+// problem (Golub & Van Loan, Sec. 8.6.3; Hestenes 1958).  Columns are kept
+// column-major (in LDS when they fit) and rotated in pairs of the round-robin
+// schedule: k/2 disjoint pairs per round, every pair once per sweep.  A pair
+// (p, q) with a = |x_p|^2, b = |x_q|^2, g = x_p . x_q is rotated when
+// |g| > eps sqrt(a b); the rotation makes the two columns orthogonal.
+//
+// A pair is handled by 16 lanes (one DPP row): lane l holds rows l, l+16, ...
+// of both columns in registers and the three dot products are butterfly sums
+// within the row (DPP moves, no LDS round trip), so a work-group of nt
+// threads rotates nt/16 pairs at a time with one barrier per round.
+//
+// When only singular values are wanted, rows and columns of the input that
+// are exactly zero are dropped first (they contribute only zero singular
+// values); a corner of rank chi_eff < chi is then a chi_eff-sized problem.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wsum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+constexpr int JMAX = 192;      // largest k
+constexpr int JR = JMAX / 16;  // rows per lane
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over the 16 lanes of a DPP row; every lane gets the same bits (each
+// step adds a value to its mirror image, and fp addition commutes)
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -136,146 +307,229 @@ __device__ __forceinline__ double wsum(double v) {
 // rotate.  pair j of round r: (pos j, pos kk-1-j) with pos 0 = player 0 and
 // pos t>0 = 1 + ((t - 1 + r) mod (kk - 1)).
 __device__ __forceinline__ int rr_player(int pos, int r, int kk) {
-  return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (kk - 1));
+  int v = pos - 1 + r;            // < 2 (kk - 1) for pos, r < kk - 1
+  if (v >= kk - 1) v -= kk - 1;
+  return pos == 0 ? 0 : 1 + v;
 }
 
-__global__ void __launch_bounds__(1024)
-jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work, int want_vectors,
-                  int transpose_in, StatSet st, double noise_rel, int in_lds) {
-  extern __shared__ double jsm[];         // A, Gram and W when they fit in LDS
-  const int pb = blockIdx.x;
-  double* A = in_lds ? jsm : work.p[pb];  // column-major k x k, column c at A + c*k
-  double* Gm = A + (size_t)k * k;         // Gram of the columns at the start of a sweep
-  double* W = Gm + (size_t)k * k;         // column-major right rotations
-  const double* M = Min.p[pb];
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  __shared__ int s_rot;
-  __shared__ double s_norm[256];
-  __shared__ int s_perm[256];
-  __shared__ int s_touched[256];
-  __shared__ unsigned s_sig[256 * 256 / 32];  // bit (p*k+q): pair significant at sweep start
-  __shared__ double s_amax;
-
-  // A holds M (or M^T when transpose_in) column-major
-  for (int e = tid; e < k * k; e += nt) {
-    int r = e / k, c = e % k;
-    A[c * k + r] = transpose_in ? M[c * k + r] : M[e];
-    if (want_vectors) W[c * k + r] = (r == c) ? 1.0 : 0.0;
+// compacted index list of the set flags fl[0..k) into map, count into *cnt
+// (one wave, in order)
+__device__ __forceinline__ void compact_flags(const int* fl, int k, int* map, int* cnt, int lane) {
+  int base = 0;
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int c = c0 + lane;
+    const bool f = c < k && fl[c];
+    const unsigned long long m = __ballot(f);
+    if (f) map[base + __popcll(m & ((1ull << lane) - 1ull))] = c;
+    base += __popcll(m);
   }
-  __syncthreads();
-  const int kk = (k + 1) & ~1;  // even number of players; player k (if odd) is a dummy
+  if (lane == 0) *cnt = base;
+}
+
+extern __shared__ double jsm[];  // dynamic LDS of the Jacobi kernel
+
+// The sweeps on the kr x kc working matrix A (column-major, leading dimension
+// 16 NRL, rows kr.. zero) and the kc x kc rotations W right after it (same
+// leading dimension): at the start of the dynamic LDS (IN_LDS) or at gA.
+// NRL and the memory kind are compile-time constants so that the loads of a
+// pair's columns are plain LDS (or global) loads issued together.  Returns the
+// number of sweeps.
+template <int NRL, bool IN_LDS>
+__device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, double nr,
+                             double* s_cn, double* s_amax, int* s_rot) {
+  constexpr int ld = 16 * NRL;
+  double* A = IN_LDS ? jsm : gA;
+  double* W = A + (size_t)ld * kc;
+  const int tid = threadIdx.x, ql = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
+  const int kk = (kc + 1) & ~1;  // even number of players; player kc (if odd) is a dummy
+  const int half = kk / 2;
   const double eps = 2.220446049250313e-16 * (double)k;
+  const double eps2 = eps * eps;
   int sweeps_done = 0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  for (int sweep = 0; sweep < 60 && kc > 1; ++sweep) {
     sweeps_done = sweep + 1;
-    for (int e = tid; e < (k * k + 31) / 32; e += nt) s_sig[e] = 0u;
-    __syncthreads();
-    // Gram of all column pairs (upper triangle incl. diagonal): wave w holds
-    // column p = w, w + nw, ... in registers (lanes over rows, k <= 256) and
-    // forms its dot products with every later column, coalesced.
-    for (int p = wave; p < k; p += nw) {
-      double xp[4];
+    for (int c = grp; c < kc; c += ngrp) {
+      const double* x = A + (size_t)c * ld;
+      double xv[NRL];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        int i = lane + 64 * t;
-        xp[t] = (i < k) ? A[(size_t)p * k + i] : 0.0;
-      }
-      for (int q = p; q < k; ++q) {
-        const double* xq = A + (size_t)q * k;
-        double g = 0;
+      for (int t = 0; t < NRL; ++t) xv[t] = x[ql + 16 * t];
+      double a = 0.0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          int i = lane + 64 * t;
-          if (i < k) g += xp[t] * xq[i];
-        }
-        g = wsum(g);
-        if (lane == 0) Gm[(size_t)p * k + q] = g;
-      }
-    }
-    if (tid < k) s_touched[tid] = 0;
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    if (tid == 0) {
-      double m = 0;
-      for (int c = 0; c < k; ++c) m = fmax(m, Gm[(size_t)c * k + c]);
-      s_amax = m;
+      for (int t = 0; t < NRL; ++t) a += xv[t] * xv[t];
+      a = sum16(a);
+      if (ql == 0) s_cn[c] = a;
     }
     __syncthreads();
-    // columns whose norm is below noise_rel (at least 4 u) of the largest are
-    // noise for the caller and are not rotated: they cannot move anything
-    // above that level
-    const double nr = fmax(noise_rel, 4.0 * 1.1102230246251565e-16);
-    const double noise = s_amax * nr * nr;
-    // significance bits of all pairs from the sweep's Gram
-    for (int e = tid; e < k * k; e += nt) {
-      int p = e / k, q = e - p * k;
-      if (q <= p) continue;
-      double a0 = Gm[(size_t)p * k + p], b0 = Gm[(size_t)q * k + q], g0 = Gm[(size_t)p * k + q];
-      if (fmin(a0, b0) > noise && fabs(g0) > eps * sqrt(a0 * b0)) atomicOr(&s_sig[e >> 5], 1u << (e & 31));
+    if (tid < 64) {
+      double m = 0.0;
+      for (int c = tid; c < kc; c += 64) m = fmax(m, s_cn[c]);
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      if (tid == 0) { *s_amax = m; *s_rot = 0; }
     }
     __syncthreads();
+    // columns whose norm is below nr of the largest are noise for the caller
+    // and are not rotated: they cannot move anything above that level
+    const double noise = *s_amax * nr * nr;
     int rotated = 0;
     for (int r = 0; r < kk - 1; ++r) {
-      for (int j = wave; j < kk / 2; j += nw) {
+      for (int j = grp; j < half; j += ngrp) {
         int p = rr_player(j, r, kk), q = rr_player(kk - 1 - j, r, kk);
-        if (p >= k || q >= k) continue;
-        if (p > q) { int t = p; p = q; q = t; }
-        if (!s_touched[p] && !s_touched[q]) {
-          // both columns unchanged since the sweep's Gram: screen on it
-          const int e = p * k + q;
-          if (!((s_sig[e >> 5] >> (e & 31)) & 1u)) continue;
+        if (p >= kc || q >= kc) continue;
+        if (p > q) { const int t = p; p = q; q = t; }
+        double* cp = A + (size_t)p * ld;
+        double* cq = A + (size_t)q * ld;
+        double* wp = W + (size_t)p * ld;
+        double* wq = W + (size_t)q * ld;
+        // for short columns the rotations' columns are loaded with the
+        // pair's, so that their latency hides behind the rotation arithmetic
+        constexpr bool early = NRL <= 6;
+        double xp[NRL], xq[NRL], u[NRL], v[NRL];
+#pragma unroll
+        for (int t = 0; t < NRL; ++t) {
+          xp[t] = cp[ql + 16 * t];
+          xq[t] = cq[ql + 16 * t];
+          if (early && want_vectors) {
+            u[t] = wp[ql + 16 * t];
+            v[t] = wq[ql + 16 * t];
+          }
         }
-        double* xp = A + (size_t)p * k;
-        double* xq = A + (size_t)q * k;
-        double a = 0, b = 0, g = 0;
-        for (int i = lane; i < k; i += 64) {
-          double u = xp[i], v = xq[i];
-          a += u * u; b += v * v; g += u * v;
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int t = 0; t < NRL; ++t) {
+          a += xp[t] * xp[t];
+          b += xq[t] * xq[t];
+          g += xp[t] * xq[t];
         }
-        a = wsum(a); b = wsum(b); g = wsum(g);
-        if (fmin(a, b) > noise && fabs(g) > eps * sqrt(a * b)) {
-          double zeta = (b - a) / (2.0 * g);
-          double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          for (int i = lane; i < k; i += 64) {
-            double u = xp[i], v = xq[i];
-            xp[i] = c * u - sn * v;
-            xq[i] = sn * u + c * v;
+        a = sum16(a);
+        b = sum16(b);
+        g = sum16(g);
+        if (fmin(a, b) > noise && g * g > eps2 * (a * b)) {
+          // tangent of the smaller angle that zeroes g (Rutishauser's form of
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g)
+          const double d = b - a;
+          const double tn = (d >= 0 ? 2.0 * g : -2.0 * g) / (fabs(d) + sqrt(d * d + 4.0 * g * g));
+          const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+#pragma unroll
+          for (int t = 0; t < NRL; ++t) {
+            cp[ql + 16 * t] = c * xp[t] - sn * xq[t];
+            cq[ql + 16 * t] = sn * xp[t] + c * xq[t];
           }
           if (want_vectors) {
-            double* wp = W + (size_t)p * k;
-            double* wq = W + (size_t)q * k;
-            for (int i = lane; i < k; i += 64) {
-              double u = wp[i], v = wq[i];
-              wp[i] = c * u - sn * v;
-              wq[i] = sn * u + c * v;
+            if (!early) {
+#pragma unroll
+              for (int t = 0; t < NRL; ++t) {
+                u[t] = wp[ql + 16 * t];
+                v[t] = wq[ql + 16 * t];
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < NRL; ++t) {
+              wp[ql + 16 * t] = c * u[t] - sn * v[t];
+              wq[ql + 16 * t] = sn * u[t] + c * v[t];
             }
           }
-          if (lane == 0) { s_touched[p] = 1; s_touched[q] = 1; }
           rotated = 1;
         }
       }
       __syncthreads();
     }
-    if (rotated && lane == 0) s_rot = 1;
+    if (rotated) *s_rot = 1;
     __syncthreads();
-    if (!s_rot) break;
+    if (!*s_rot) break;
+  }
+  return sweeps_done;
+}
+
+__global__ void __launch_bounds__(1024)
+jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work, int want_vectors,
+                  int transpose_in, StatSet st, double noise_rel, size_t lds_cap) {
+  const int pb = blockIdx.x;
+  const double* M = Min.p[pb];
+  const int tid = threadIdx.x, nt = blockDim.x, ql = tid & 15, grp = tid >> 4, ngrp = nt >> 4;
+  __shared__ int s_rnz[JMAX], s_cnz[JMAX], s_rmap[JMAX], s_cmap[JMAX];
+  __shared__ int s_kr, s_kc, s_rot;
+  __shared__ double s_cn[JMAX], s_norm[JMAX], s_amax;
+  __shared__ int s_perm[JMAX];
+  // X = M (or M^T).  Rows / columns kept: all, or the non-zero ones.
+  auto X = [&](int r, int c) { return transpose_in ? M[(size_t)c * k + r] : M[(size_t)r * k + c]; };
+  if (want_vectors) {
+    for (int c = tid; c < k; c += nt) { s_rmap[c] = c; s_cmap[c] = c; }
+    if (tid == 0) { s_kr = k; s_kc = k; }
+  } else {
+    for (int c = tid; c < k; c += nt) { s_rnz[c] = 0; s_cnz[c] = 0; }
     __syncthreads();
+    for (int e = tid; e < k * k; e += nt) {
+      const int r = e / k, c = e - r * k;
+      if (X(r, c) != 0.0) { s_rnz[r] = 1; s_cnz[c] = 1; }
+    }
+    __syncthreads();
+    if (tid < 64) compact_flags(s_rnz, k, s_rmap, &s_kr, tid);
+    else if (tid < 128) compact_flags(s_cnz, k, s_cmap, &s_kc, tid - 64);
   }
-  // singular values = column norms, sorted descending (stable)
-  for (int c = wave; c < k; c += nw) {
-    double a = 0;
-    for (int i = lane; i < k; i += 64) a += A[(size_t)c * k + i] * A[(size_t)c * k + i];
-    a = wsum(a);
-    if (lane == 0) s_norm[c] = sqrt(a);
+  __syncthreads();
+  // the working matrix A: kr rows (padded with zeros to ld = 16 nrl) x kc
+  // columns, column-major, with the shorter side as columns when vectors are
+  // not wanted
+  const bool flip = !want_vectors && s_kc > s_kr;
+  const int kr = flip ? s_kc : s_kr, kc = flip ? s_kr : s_kc;
+  const int nrl = (kr + 15) >> 4, ld = 16 * nrl;
+  const size_t need = (size_t)(want_vectors ? 2 : 1) * ld * kc * sizeof(double);
+  const bool in_lds = need <= lds_cap;
+  double* A = in_lds ? jsm : work.p[pb];
+  double* W = A + (size_t)ld * kc;  // column-major kc x kc right rotations (leading dimension ld)
+  for (int e = tid; e < ld * kc; e += nt) {
+    const int j = e / ld, i = e - j * ld;
+    A[e] = i >= kr ? 0.0 : (flip ? X(s_rmap[j], s_cmap[i]) : X(s_rmap[i], s_cmap[j]));
+    if (want_vectors) W[e] = (i == j) ? 1.0 : 0.0;
   }
+  __syncthreads();
+  const double nr = fmax(noise_rel, 4.0 * 1.1102230246251565e-16);  // at least 4 u
+  const bool wv = want_vectors != 0;
+  int sweeps_done = 0;
+  switch (in_lds ? nrl : nrl + 16) {
+    case 1: sweeps_done = jacobi_sweeps<1, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 2: sweeps_done = jacobi_sweeps<2, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 3: sweeps_done = jacobi_sweeps<3, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 4: sweeps_done = jacobi_sweeps<4, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 5: sweeps_done = jacobi_sweeps<5, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 6: sweeps_done = jacobi_sweeps<6, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 7: sweeps_done = jacobi_sweeps<7, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 8: sweeps_done = jacobi_sweeps<8, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 9: sweeps_done = jacobi_sweeps<9, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 10: sweeps_done = jacobi_sweeps<10, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 11: sweeps_done = jacobi_sweeps<11, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 12: sweeps_done = jacobi_sweeps<12, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 17: sweeps_done = jacobi_sweeps<1, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 18: sweeps_done = jacobi_sweeps<2, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 19: sweeps_done = jacobi_sweeps<3, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 20: sweeps_done = jacobi_sweeps<4, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 21: sweeps_done = jacobi_sweeps<5, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 22: sweeps_done = jacobi_sweeps<6, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 23: sweeps_done = jacobi_sweeps<7, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 24: sweeps_done = jacobi_sweeps<8, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 25: sweeps_done = jacobi_sweeps<9, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 26: sweeps_done = jacobi_sweeps<10, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 27: sweeps_done = jacobi_sweeps<11, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 28: sweeps_done = jacobi_sweeps<12, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    default: break;  // kr == 0: an all-zero input
+  }
+  // singular values = column norms (zero for the dropped part), sorted
+  // descending (stable)
+  for (int c = grp; c < kc; c += ngrp) {
+    const double* x = A + (size_t)c * ld;
+    double a = 0.0;
+    for (int t = 0; t < nrl; ++t) a += x[ql + 16 * t] * x[ql + 16 * t];
+    a = sum16(a);
+    if (ql == 0) s_norm[c] = sqrt(a);
+  }
+  for (int c = kc + tid; c < k; c += nt) s_norm[c] = 0.0;
   __syncthreads();
   // non-finite norms sort last (key -1), so the ranks form a permutation
   for (int c = tid; c < k; c += nt) {
-    double v = isfinite(s_norm[c]) ? s_norm[c] : -1.0;
+    const double v = isfinite(s_norm[c]) ? s_norm[c] : -1.0;
     int rank = 0;
     for (int o = 0; o < k; ++o) {
-      double w = isfinite(s_norm[o]) ? s_norm[o] : -1.0;
+      const double w = isfinite(s_norm[o]) ? s_norm[o] : -1.0;
       rank += (w > v) || (w == v && o < c);
     }
     s_perm[rank] = c;
@@ -285,14 +539,15 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
   for (int j = tid; j < k; j += nt) S[j] = s_norm[s_perm[j]];
   if (tid == 0 && st.p[pb]) st.p[pb]->jsweeps = sweeps_done;
   if (!want_vectors) return;
+  // vectors: no rows or columns were dropped (kr = kc = k)
   double* U = Uout.p[pb];
   double* Wo = Wout.p[pb];
   for (int e = tid; e < k * k; e += nt) {
-    int r = e / k, j = e % k;
-    int c = s_perm[j];
-    double sv = s_norm[c];
-    U[e] = sv > 0 ? A[(size_t)c * k + r] / sv : 0.0;
-    Wo[e] = W[(size_t)c * k + r];
+    const int r = e / k, j = e - r * k;
+    const int c = s_perm[j];
+    const double sv = s_norm[c];
+    U[e] = sv > 0 ? A[(size_t)c * ld + r] / sv : 0.0;
+    Wo[e] = W[(size_t)c * ld + r];
   }
 }
 
@@ -301,22 +556,23 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, c
                       const StatSet* st, double noise_rel) {
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
-  if (k > 192) return hipErrorInvalidValue;  // 16 waves x 6 pairs, 3 rows per lane
+  if (k < 1 || k > JMAX) return hipErrorInvalidValue;
+  // the columns (and rotations) live in LDS when they fit next to the
+  // kernel's static arrays (about 7 KiB); the kernel decides after dropping
+  // zero rows and columns.  Otherwise `work` holds them: rows padded to a
+  // multiple of 16.
+  constexpr size_t kJMaxDyn = 160 * 1024 - 16384;
+  const size_t full = (size_t)(want_vectors ? 2 : 1) * (size_t)((k + 15) / 16 * 16) * k * sizeof(double);
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(M.p[i], (size_t)k * k * 8, "jacobi M") || !span_ok(S.p[i], (size_t)k * 8, "jacobi S") ||
-        !span_ok(work.p[i], (size_t)(want_vectors ? 3 : 2) * k * k * 8, "jacobi work") ||
+        (full > kJMaxDyn && !span_ok(work.p[i], full, "jacobi work")) ||
         (want_vectors && (!span_ok(U.p[i], (size_t)k * k * 8, "jacobi U") ||
                           !span_ok(W.p[i], (size_t)k * k * 8, "jacobi W"))))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   StatSet none{};
-  // the columns, their Gram matrix and the rotations live in LDS when they fit
-  // next to the kernel's static arrays (about 12 KiB)
-  constexpr size_t kJMaxDyn = 160 * 1024 - 16384;
-  const size_t lds = (size_t)(want_vectors ? 3 : 2) * k * k * sizeof(double);
-  const bool in_lds = lds <= kJMaxDyn;
   static bool attr_set = false;
-  if (in_lds && !attr_set) {
+  if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)jacobi_svd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kJMaxDyn);
     if (e != hipSuccess) {
@@ -325,8 +581,12 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, c
     }
     attr_set = true;
   }
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(1024), in_lds ? lds : 0, s, k, M, U, S, W, work,
-                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel, in_lds ? 1 : 0);
+  // 16 lanes per pair: enough waves for every pair of a round (at most 16)
+  const int half = ((k + 1) & ~1) / 2;
+  int waves = (half + 3) / 4;
+  waves = waves < 2 ? 2 : (waves > 16 ? 16 : waves);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(64 * waves), kJMaxDyn, s, k, M, U, S, W, work,
+                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel, kJMaxDyn);
   return hipGetLastError();
 }
 
