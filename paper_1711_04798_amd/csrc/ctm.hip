@@ -685,14 +685,14 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
   return CTM_OK;
 }
 
-// Y <- Y R^{-1} three times with R from the shifted Cholesky factor of Y^T Y
+// Y <- Y R^{-1} `passes` times with R from the shifted Cholesky factor of Y^T Y
 // (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020).
 ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
-                          const std::vector<double*>& Y) {
+                          const std::vector<double*>& Y, int passes = 3) {
   hipStream_t s = x.stream;
   const size_t P = rows.size();
   const double u = 1.1102230246251565e-16;
-  for (int pass = 0; pass < 3; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     double coef = pass == 0 ? 11.0 * ((double)n * k + (double)k * (k + 1)) * u : 4.0 * u;
     G gg;
     CPtrSet Gs{};
@@ -748,7 +748,9 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     V[r] = R->V; Yb[r] = R->Yb; Qb[r] = R->Qb; Z[r] = R->Z; LV[r] = R->LV; UU[r] = R->UU;
     Ub[r] = R->Ub; Vpv[r] = R->Vp;
   }
-  CHK(orthonormalize(x, n, k, rows, V));
+  // the start block (kept orthonormal columns and independent normals) is
+  // well conditioned: Cholesky-QR twice orthonormalises it to rounding level
+  CHK(orthonormalize(x, n, k, rows, V, 2));
   const int maxit = std::max(1, c.svd_max_iters);
   const bool adaptive = c.svd_resid_tol > 0;
   std::vector<SolveStatus> hst(P);
@@ -933,23 +935,36 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // T4'[c1, (R, c2)] = sum_(g,dn) P1[(g,dn), c1] W2[(g,dn), (R, c2)]
   //   B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
   //   B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
-  if (at == F32) {
+  if (at == F32 && D2 >= 2) {
     // W2 read through that view touches one element per cache line: transpose
-    // it first (per g: [c2][(dn,R)] -> [(dn,R)][c2], i.e. W2t[(g,dn)][(R,c2)]),
-    // then a plain product with few rows (chi) and a long contraction (n),
-    // split over K
+    // it first (per g: [c2][(dn,R)] -> [(dn,R)][c2], i.e. W2t[(g,dn)][(R,c2)]).
+    // The product is then tall and skinny in transposed form,
+    //   T4'^T[(R,c2), c1] = sum_(g,dn) W2t[(g,dn),(R,c2)] P1[(g,dn), c1],
+    // with chi output columns and a contraction of length n (the freed W2,
+    // chi^2 D2^2 floats >= chi^2 D2 doubles, holds it), transposed back into T4'.
     G g5t;
     for (Inst* I : insts)
       for (int yp = 0; yp < ly; ++yp) {
         Row& R = I->rows[yp];
         HIPCHK(transpose_batched(s, (const float*)R.W2, c, c, K4, (float*)R.W2t));
-        g5t.add(R.P1w, R.W2t, R.nT4);
+        g5t.add(R.W2t, R.P1w, R.W2);
       }
-    for (int j0 = 0; j0 < g5t.size(); j0 += MAXG) {
-      int cnt = std::min(MAXG, g5t.size() - j0);
-      HIPCHK(gemm_splitk_f32(s, F64, c, D2 * c, n, transposed(rowmajor(c)), rowmajor(D2 * c), rowmajor(D2 * c),
-                             g5t.group(j0, cnt), cnt, x.ts_scratch, x.ts_bytes));
+    if (ts_gemm_supported(F32, F64, D2 * c, c, n, transposed(rowmajor(D2 * c)), rowmajor(c), rowmajor(c))) {
+      for (int j0 = 0; j0 < g5t.size(); j0 += MAXG) {
+        int cnt = std::min(MAXG, g5t.size() - j0);
+        HIPCHK(ts_gemm(s, F32, F64, D2 * c, c, n, transposed(rowmajor(D2 * c)), rowmajor(c), rowmajor(c),
+                       g5t.group(j0, cnt), cnt, x.ts_scratch, x.ts_bytes));
+      }
+    } else {
+      CHK(gemm_run(s, F32, F64, D2 * c, c, n, transposed(rowmajor(D2 * c)), rowmajor(c), rowmajor(c), g5t));
     }
+    const int64_t dims[2] = {D2 * c, c};
+    const int perm[2] = {1, 0};
+    for (Inst* I : insts)
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        HIPCHK(permute(s, F64, R.W2, F64, R.nT4, 2, dims, perm));
+      }
   } else {
     CHK(gemm_run(s, at, F64, c, D2 * c, n, transposed(rowmajor(c)), view2(D2, D2, c * D2 * D2, c, D2 * D2, 1),
                  rowmajor(D2 * c), g5));

@@ -87,11 +87,6 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
 // out[b][c][r] = in[b][r][c], float32, nb matrices R x C.
 hipError_t transpose_batched(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, float* out);
 
-// Split-K product with float32 operands and float32 or float64 output through
-// any views (float partials in `scratch`, summed in a fixed order).
-hipError_t gemm_splitk_f32(hipStream_t s, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
-                           const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
-
 bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
 
 // Three-term bf16 split of float data for products with fp32-like accuracy:

@@ -297,20 +297,32 @@ static hipError_t launch_gemm_t(hipStream_t s, int tile, int64_t M, int64_t N, i
 // K slice writes a partial product, then one kernel sums the slices in a
 // fixed order (deterministic) and applies alpha, beta and the output view.
 // ---------------------------------------------------------------------------
+// Sum of the ksplit partials of every output element: 8 lanes per element,
+// lane t adding partials t, t+8, ... in order, then a fixed xor tree over the
+// 8 lanes (deterministic, and 8x fewer dependent loads per lane).
 __global__ void splitk_reduce_kernel(const double* __restrict__ part, int ksplit, int32_t M, int32_t N,
                                      double alpha, double beta, DevView vc, GemmGroup g) {
   const int gi = blockIdx.y;
   const double* p = part + (int64_t)gi * ksplit * M * N;
   double* C = (double*)g.C[gi];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)M * N;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  const int t = threadIdx.x & 7;
+  const int64_t MN = (int64_t)M * N;
+  const int64_t per = (int64_t)gridDim.x * (blockDim.x >> 3);
+  for (int64_t e0 = (int64_t)blockIdx.x * (blockDim.x >> 3); e0 < MN; e0 += per) {
+    const int64_t e = e0 + (threadIdx.x >> 3);  // uniform trip count over the block: all lanes shuffle
     double acc = 0.0;
-    for (int sp = 0; sp < ksplit; ++sp) acc += p[(int64_t)sp * M * N + e];
-    int r = (int)(e / N), c = (int)(e % N);
-    int64_t off = row_off(vc, r) + col_off(vc, c);
-    double v = alpha * acc;
-    if (beta != 0.0) v += beta * C[off];
-    C[off] = v;
+    if (e < MN)
+      for (int sp = t; sp < ksplit; sp += 8) acc += p[(int64_t)sp * MN + e];
+    acc += __shfl_xor(acc, 1, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 4, 8);
+    if (e < MN && t == 0) {
+      int r = (int)(e / N), c = (int)(e % N);
+      int64_t off = row_off(vc, r) + col_off(vc, c);
+      double v = alpha * acc;
+      if (beta != 0.0) v += beta * C[off];
+      C[off] = v;
+    }
   }
 }
 
@@ -350,69 +362,10 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   DevView dvc = dev_view(vc, M, N);
-  int64_t blocks = std::min<int64_t>(1024, (M * N + 255) / 256);
+  // 32 elements per block of 256 (8 lanes each)
+  int64_t blocks = std::min<int64_t>(2048, (M * N + 31) / 32);
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks, groups), dim3(256), 0, s, scratch, (int)ksplit,
                      (int32_t)M, (int32_t)N, alpha, beta, dvc, g);
-  return hipGetLastError();
-}
-
-// split-K for float32 operands: float partials, summed in a fixed order and
-// written through the output view in float32 or float64
-template <typename TO>
-__global__ void splitk_reduce_f32_kernel(const float* __restrict__ part, int ksplit, int32_t M, int32_t N,
-                                         DevView vc, GemmGroup g) {
-  const int gi = blockIdx.y;
-  const float* p = part + (int64_t)gi * ksplit * M * N;
-  TO* C = (TO*)g.C[gi];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)M * N;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    float acc = 0.0f;
-    for (int sp = 0; sp < ksplit; ++sp) acc += p[(int64_t)sp * M * N + e];
-    int r = (int)(e / N), c = (int)(e % N);
-    C[row_off(vc, r) + col_off(vc, c)] = (TO)acc;
-  }
-}
-
-hipError_t gemm_splitk_f32(hipStream_t s, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
-                           const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes) {
-  if (M <= 0 || N <= 0 || groups <= 0) return hipSuccess;
-  if (tc != F32 && tc != F64) return hipErrorInvalidValue;
-  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * groups;
-  int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / std::max<int64_t>(tiles, 1),
-                                                          K / 256));
-  while (ksplit > 1 && ksplit * M * N * groups * 4 > scratch_bytes) ksplit /= 2;
-  if (ksplit <= 1) return gemm(s, F32, tc, M, N, K, 1.0, va, vb, 0.0, vc, g, groups);
-  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || groups > MAXG) return hipErrorInvalidValue;
-  const size_t sa = (size_t)(view_max(va, M, K) + 1) * 4, sb = (size_t)(view_max(vb, K, N) + 1) * 4,
-               sc = (size_t)(view_max(vc, M, N) + 1) * dtype_size(tc);
-  for (int i = 0; i < groups; ++i)
-    if (!span_ok(g.A[i], sa, "splitk32 A") || !span_ok(g.B[i], sb, "splitk32 B") || !span_ok(g.C[i], sc, "splitk32 C"))
-      return hipErrorInvalidValue;
-  if (!span_ok(scratch, (size_t)ksplit * M * N * groups * 4, "splitk32 scratch")) return hipErrorInvalidValue;
-  if (dry_run()) return hipSuccess;
-  GemmGroup gp = g;
-  for (int i = 0; i < groups; ++i) gp.C[i] = (float*)scratch + (int64_t)i * ksplit * M * N;
-  DevView da = dev_view(va, M, K), db = dev_view(vb, K, N), dc = dev_view(rowmajor(N), M, N);
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)(groups * ksplit));
-  const bool ak = (va.c_ls == 1), bk = (vb.r_ls == 1);
-#define SK32(AKV, BKV)                                                                                          \
-  hipLaunchKernelGGL((gemm_kernel<float, float, 64, 64, AKV, BKV>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, \
-                     (int32_t)K, 1.0, 0.0, da, db, dc, gp, (int32_t)ksplit)
-  if (ak && bk) SK32(true, true);
-  else if (ak) SK32(true, false);
-  else if (bk) SK32(false, true);
-  else SK32(false, false);
-#undef SK32
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  DevView dvc = dev_view(vc, M, N);
-  const int64_t blocks = std::min<int64_t>(2048, (M * N + 255) / 256);
-  if (tc == F64)
-    hipLaunchKernelGGL(splitk_reduce_f32_kernel<double>, dim3((unsigned)blocks, groups), dim3(256), 0, s,
-                       (const float*)scratch, (int)ksplit, (int32_t)M, (int32_t)N, dvc, g);
-  else
-    hipLaunchKernelGGL(splitk_reduce_f32_kernel<float>, dim3((unsigned)blocks, groups), dim3(256), 0, s,
-                       (const float*)scratch, (int)ksplit, (int32_t)M, (int32_t)N, dvc, g);
   return hipGetLastError();
 }
 
