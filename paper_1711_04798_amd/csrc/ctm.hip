@@ -157,6 +157,9 @@ struct Inst {
   void* Tw[4][MAXPOS] = {};
   void* TwP[4][MAXPOS] = {};     // bf16 mode: edges as [prev][next][inner]
   void* TwR[4][MAXPOS] = {};     // bf16 mode: bf16 edges as [next][inner][prev]
+  // working copies (Cw, Tw, TwP, TwR) that no longer match their float64 master
+  bool staleC[4][MAXPOS] = {};
+  bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
   double* spec_old = nullptr;  // [pos][4][chi]
   double* spec_new = nullptr;
@@ -294,6 +297,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
       for (int p = 0; p < npos; ++p) {
         I.C[c][p] = ar.take<double>(c2);
         I.T[c][p] = ar.take<double>(t3);
+        I.staleC[c][p] = I.staleT[c][p] = true;
         I.Cw[c][p] = (x.wt == F64) ? (void*)I.C[c][p] : ar.take_bytes(c2 * ws);
         I.Tw[c][p] = (x.wt == F64) ? (void*)I.T[c][p] : ar.take_bytes(t3 * ws);
         if (x.prec == CTM_BF16) {
@@ -413,6 +417,8 @@ struct Roles {
   int tid(int xp, int yp) const { return x->pattern[pos(xp, yp)]; }
   double* C(int i, int xp, int yp) const { return I->C[(i + k) % 4][pos(xp, yp)]; }
   double* T(int i, int xp, int yp) const { return I->T[(i + k) % 4][pos(xp, yp)]; }
+  void stale_C(int i, int xp, int yp) const { I->staleC[(i + k) % 4][pos(xp, yp)] = true; }
+  void stale_T(int i, int xp, int yp) const { I->staleT[(i + k) % 4][pos(xp, yp)] = true; }
   void* Cw(int i, int xp, int yp) const { return I->Cw[(i + k) % 4][pos(xp, yp)]; }
   void* Tw(int i, int xp, int yp) const { return I->Tw[(i + k) % 4][pos(xp, yp)]; }
   void* TwP(int i, int xp, int yp) const { return I->TwP[(i + k) % 4][pos(xp, yp)]; }
@@ -686,7 +692,8 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
 }
 
 // Y <- Y R^{-1} `passes` times with R from the shifted Cholesky factor of Y^T Y
-// (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020).
+// (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020); up to
+// 64 columns by substitution with R, otherwise through R^{-1} and a product.
 ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
                           const std::vector<double*>& Y, int passes = 3) {
   hipStream_t s = x.stream;
@@ -705,6 +712,15 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
       st.p[r] = rows[r].R->st;
     }
     CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
+    if (k <= CHOL_WAVE_MAX) {
+      // R itself, then Y <- Y R^{-1} by substitution in place
+      HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P, false));
+      PtrSet Ys{};
+      CPtrSet Rs{};
+      for (size_t r = 0; r < P; ++r) { Ys.p[r] = Y[r]; Rs.p[r] = rows[r].R->Rinv; }
+      HIPCHK(trsm_rows(s, n, k, Ys, Rs, (int)P));
+      continue;
+    }
     HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P));
     G gm;
     for (size_t r = 0; r < P; ++r) gm.add(Y[r], rows[r].R->Rinv, rows[r].R->tmp);
@@ -810,7 +826,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
         Zs.p[r] = Z[r]; Vs.p[r] = Vpv[r]; Ss.p[r] = rows[r].R->S; st.p[r] = rows[r].R->st;
       }
       HIPCHK(residual_status(s, n, k, chi, c.svd_cutoff, c.svd_resid_tol > 0 ? c.svd_resid_tol : 0.0,
-                             Zs, Vs, Ss, st, (int)P));
+                             Zs, Vs, Ss, st, (int)P, x.splitk, x.splitk_elems));
     }
     return CTM_OK;
   };
@@ -987,6 +1003,9 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       st.add(R.nC1, ro.C(0, xp + 1, yp), c * c);
       st.add(R.nT4, ro.T(3, xp + 1, yp), c * c * D2);
       st.add(R.nC4, ro.C(3, xp + 1, yp), c * c);
+      ro.stale_C(0, xp + 1, yp);
+      ro.stale_T(3, xp + 1, yp);
+      ro.stale_C(3, xp + 1, yp);
     }
   }
   CHK(normalize_run(x, nt));
@@ -1003,7 +1022,8 @@ ctm_status refresh_working(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
     const int64_t c2 = (int64_t)I->chi * I->chi, t3 = c2 * I->D2;
     for (int c = 0; c < 4; ++c)
       for (int p = 0; p < npos; ++p) {
-        cv.add(I->C[c][p], I->Cw[c][p], c2);
+        if (I->staleC[c][p]) cv.add(I->C[c][p], I->Cw[c][p], c2);
+        if (!I->staleT[c][p]) continue;
         cv.add(I->T[c][p], I->Tw[c][p], t3);
         if (I->TwP[c][p]) {
           int64_t dims[3] = {I->chi, I->D2, I->chi};
@@ -1017,7 +1037,12 @@ ctm_status refresh_working(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
         }
       }
   }
-  return xfer_run(x.stream, F64, x.wt, cv);
+  CHK(xfer_run(x.stream, F64, x.wt, cv));
+  // only once the copies are enqueued (a failure above leaves them stale)
+  for (Inst* I : insts)
+    for (int c = 0; c < 4; ++c)
+      for (int p = 0; p < npos; ++p) I->staleC[c][p] = I->staleT[c][p] = false;
+  return CTM_OK;
 }
 
 void ev_record(ctm_ctx_s& x, int i) {
@@ -1367,6 +1392,8 @@ ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double*
   HIPCHK(dmemset(I.spec_old, 0, (size_t)npos * 4 * I.chi * 8, s));
   HIPCHK(dmemset(I.flag, 0, sizeof(int) * 4, s));
   HIPCHK(dmemset(I.skeep_all, 0, sizeof(SolveStatus) * 4 * npos, s));
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p) I.staleC[c][p] = I.staleT[c][p] = true;
   I.k_act = I.k;
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < npos; ++p) I.has_keep[c][p] = false;
@@ -2078,7 +2105,10 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
   for (int c = 0; c < 4; ++c)
     for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.T[c][q], p, t3 * 8, x->stream)); p += t3 * 8; }
   for (int c = 0; c < 4; ++c)
-    for (int q = 0; q < npos; ++q) I.has_keep[c][q] = false;
+    for (int q = 0; q < npos; ++q) {
+      I.has_keep[c][q] = false;
+      I.staleC[c][q] = I.staleT[c][q] = true;
+    }
   CHK(corner_spectra(*x, std::vector<Inst*>{&I}, true, true));
   HIPCHK(ssync(x->stream));
   return CTM_OK;

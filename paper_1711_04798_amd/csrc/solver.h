@@ -33,8 +33,16 @@ struct StatSet {
 // For each problem: R^T R = G + s I with s = shift_coef * trace(G) (G is k x k,
 // row-major), written back as R^{-1} (upper triangular, row-major k x k) into
 // Rinv.  G is left unchanged.
+// With want_inverse false (k <= 64 only) R itself is written instead.
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
-                          const PtrSet& Rinv, const StatSet& st, int nprob);
+                          const PtrSet& Rinv, const StatSet& st, int nprob, bool want_inverse = true);
+
+// Largest k of the one-wave Cholesky and of trsm_rows.
+constexpr int CHOL_WAVE_MAX = 64;
+
+// Y <- Y R^{-1} in place, Y n x k row-major, R k x k upper triangular
+// row-major (k <= 64), for each problem.
+hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob);
 
 // One-sided Jacobi SVD of the k x k row-major matrix M (k <= 192): M W = U S with singular
 // values in descending order.  U, W row-major k x k; S length k.  Columns of U
@@ -54,10 +62,11 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U,
 
 // Residuals r_i = ||Z_i - S_i V_i|| of the columns of the n x k row-major
 // blocks; sets chi_eff (from S, chi, cutoff), converged (tol), sigma0,
-// max_resid and increments iters.
+// max_resid and increments iters.  scratch: at least 64 k nprob doubles for
+// full parallelism (fewer row chunks otherwise).
 hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cutoff, double tol,
                            const CPtrSet& Z, const CPtrSet& V, const CPtrSet& S,
-                           const StatSet& st, int nprob);
+                           const StatSet& st, int nprob, double* scratch, int64_t scratch_elems);
 
 // Wp[j][c] = W[j][c] * (c < chi_eff ? S_c^{-1/2} : 0) for c < chi (k x chi out);
 // a null W stands for the identity.

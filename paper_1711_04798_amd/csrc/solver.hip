@@ -4,6 +4,7 @@
 #include "solver.h"
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace ctmk {
@@ -102,7 +103,7 @@ chol_shift_inv_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet 
 // L^{-1} by forward substitution in the same blocking, with reciprocal
 // pivots; that column is row c of R^{-1} = (L^{-1})^T.
 // ---------------------------------------------------------------------------
-constexpr int CW = 64;       // largest k of the one-wave form
+constexpr int CW = CHOL_WAVE_MAX;  // largest k of the one-wave form
 constexpr int CWL = CW + 4;  // LDS row stride (a block may read 3 entries past column k-1)
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -145,7 +146,7 @@ __device__ __forceinline__ void dot4_lds(const double* x, const double* y, int n
 }
 
 __global__ void __launch_bounds__(64)
-chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st) {
+chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st, int want_inverse) {
   __shared__ double L[CW * CWL];  // row i at L + i*CWL; G + sI (lower part) in, L out, zero elsewhere
   __shared__ double X[CW * CWL];  // row c at X + c*CWL: column c of L^{-1}
   __shared__ double rpiv[CW];     // 1 / L_jj
@@ -200,6 +201,16 @@ chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st) {
     }
     __syncthreads();
   }
+  if (!want_inverse) {
+    // R itself (upper triangular, row-major): R_rc = L_cr
+    if (lane < k) {
+#pragma unroll
+      for (int r = 0; r < CW; ++r)
+        if (r < k) ri[r * k + lane] = r <= lane ? li[r] : 0.0;
+    }
+    if (fail && lane == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
+    return;
+  }
   // forward substitution, rows in blocks of four:
   //   x_i = (delta_ic - sum_{l<i} L_il x_l) / L_ii
   double* xc = X + lane * CWL;
@@ -234,7 +245,8 @@ chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st) {
 }
 
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
-                          const PtrSet& Rinv, const StatSet& st, int nprob) {
+                          const PtrSet& Rinv, const StatSet& st, int nprob, bool want_inverse) {
+  if (!want_inverse && k > CW) return hipErrorInvalidValue;
   if (nprob < 0 || nprob > MAXP || k < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   // dynamic LDS: packed R plus 16 columns of the inverse; 8 KiB of the CU's
@@ -248,7 +260,8 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   if (k <= CW) {
-    hipLaunchKernelGGL(chol_wave_kernel, dim3(nprob), dim3(64), 0, s, k, shift_coef, G, Rinv, st);
+    hipLaunchKernelGGL(chol_wave_kernel, dim3(nprob), dim3(64), 0, s, k, shift_coef, G, Rinv, st,
+                       want_inverse ? 1 : 0);
     return hipGetLastError();
   }
   static bool attr_set = false;
@@ -262,6 +275,69 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
     attr_set = true;
   }
   hipLaunchKernelGGL(chol_shift_inv_kernel, dim3(nprob), dim3(1024), lds, s, k, shift_coef, G, Rinv, st);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Y <- Y R^{-1} in place for n x k row-major Y and upper-triangular R (k <= 64):
+// one thread per row, right-looking substitution
+//   x_j = v_j / R_jj,  then v_l -= x_j R_jl for every l > j,
+// so that the updates after each x_j are independent of one another (the
+// dependent chain is one multiply and one FMA per column).  The row lives in
+// registers (loops unrolled to compile-time indices), R in LDS (every lane
+// reads the same entry: broadcasts).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+trsm_rows_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
+  __shared__ double Rs[CW * CW];  // row-major, zero outside the upper triangle of the k x k block
+  __shared__ double rd[CW];       // 1 / R_jj
+  const int pb = blockIdx.y;
+  const double* r = R.p[pb];
+  // every load in flight at once (indices clamped into the k x k block)
+  constexpr int PER = CW * CW / 256;
+  double rv[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int e = threadIdx.x + 256 * t, i = e / CW, j = e - i * CW;
+    rv[t] = r[min(i, k - 1) * k + min(j, k - 1)];
+  }
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int e = threadIdx.x + 256 * t, i = e / CW, j = e - i * CW;
+    Rs[e] = (i < k && j < k && i <= j) ? rv[t] : 0.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < CW; j += blockDim.x) rd[j] = j < k ? 1.0 / Rs[j * CW + j] : 0.0;
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double* y = Y.p[pb] + row * k;
+  double v[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) v[j] = y[j < k ? j : k - 1];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) {
+    if (j < k) {
+      const double xj = v[j] * rd[j];
+      v[j] = xj;
+#pragma unroll
+      for (int l = j + 1; l < CW; ++l) v[l] -= xj * Rs[j * CW + l];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CW; ++j)
+    if (j < k) y[j] = v[j];
+}
+
+hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob) {
+  if (nprob < 0 || nprob > MAXP || k < 1 || k > CW || n < 1) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
+  for (int i = 0; i < nprob; ++i)
+    if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R"))
+      return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nprob);
+  hipLaunchKernelGGL(trsm_rows_kernel, grid, dim3(256), 0, s, n, k, Y, R);
   return hipGetLastError();
 }
 
@@ -458,9 +534,21 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
   } else {
     for (int c = tid; c < k; c += nt) { s_rnz[c] = 0; s_cnz[c] = 0; }
     __syncthreads();
-    for (int e = tid; e < k * k; e += nt) {
-      const int r = e / k, c = e - r * k;
-      if (X(r, c) != 0.0) { s_rnz[r] = 1; s_cnz[c] = 1; }
+    // scan M in order, eight loads in flight per thread (indices clamped);
+    // M(a, b) is X(a, b), or X(b, a) with transpose_in
+    const int kk2 = k * k;
+    for (int e0 = tid; e0 < kk2; e0 += 8 * nt) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = M[min(e0 + u * nt, kk2 - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * nt, a = e / k, b = e - a * k;
+        if (e < kk2 && v[u] != 0.0) {
+          s_rnz[transpose_in ? b : a] = 1;
+          s_cnz[transpose_in ? a : b] = 1;
+        }
+      }
     }
     __syncthreads();
     if (tid < 64) compact_flags(s_rnz, k, s_rmap, &s_kr, tid);
@@ -477,10 +565,24 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
   const bool in_lds = need <= lds_cap;
   double* A = in_lds ? jsm : work.p[pb];
   double* W = A + (size_t)ld * kc;  // column-major kc x kc right rotations (leading dimension ld)
-  for (int e = tid; e < ld * kc; e += nt) {
-    const int j = e / ld, i = e - j * ld;
-    A[e] = i >= kr ? 0.0 : (flip ? X(s_rmap[j], s_cmap[i]) : X(s_rmap[i], s_cmap[j]));
-    if (want_vectors) W[e] = (i == j) ? 1.0 : 0.0;
+  // gather, four loads in flight per thread (rows past kr read a valid
+  // element that is then replaced by zero)
+  for (int e0 = tid; e0 < ld * kc; e0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + u * nt, ld * kc - 1), j = e / ld, i = min(e - j * ld, kr - 1);
+      v[u] = flip ? X(s_rmap[j], s_cmap[i]) : X(s_rmap[i], s_cmap[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * nt;
+      if (e < ld * kc) {
+        const int j = e / ld, i = e - j * ld;
+        A[e] = i >= kr ? 0.0 : v[u];
+        if (want_vectors) W[e] = (i == j) ? 1.0 : 0.0;
+      }
+    }
   }
   __syncthreads();
   const double nr = fmax(noise_rel, 4.0 * 1.1102230246251565e-16);  // at least 4 u
@@ -593,36 +695,50 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, c
 // ---------------------------------------------------------------------------
 // residuals and cutoff
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-residual_kernel(int64_t n, int k, int chi, double cutoff, double tol, CPtrSet Z, CPtrSet V,
-                CPtrSet S, StatSet st) {
-  // 16 waves; lane = column within a chunk of 64, wave = row phase
-  const int pb = blockIdx.x;
+// Residual norms in two deterministic stages: work-group (b, problem) adds
+// the squared residuals of rows b, b + NB, b + 2 NB, ... per column (lanes over
+// columns, waves over rows, all loads of a thread independent), then one
+// work-group per problem sums the NB partials of each column in order and
+// sets the status.
+__global__ void __launch_bounds__(256)
+residual_partial_kernel(int64_t n, int k, CPtrSet Z, CPtrSet V, CPtrSet S, double* part) {
+  const int b = blockIdx.x, nb = gridDim.x, pb = blockIdx.y;
   const double* z = Z.p[pb];
   const double* v = V.p[pb];
   const double* sv = S.p[pb];
-  __shared__ double s_part[16][64];
-  __shared__ double s_res[256];
+  __shared__ double s_part[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* out = part + ((size_t)pb * nb + b) * k;
   for (int c0 = 0; c0 < k; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
     if (c < k) {
       const double sc = sv[c];
-      for (int64_t i = wave; i < n; i += 16) {
-        double d = z[i * k + c] - sc * v[i * k + c];
+      for (int64_t i = b + (int64_t)nb * wave; i < n; i += (int64_t)nb * 4) {
+        const double d = z[i * k + c] - sc * v[i * k + c];
         acc += d * d;
       }
     }
     s_part[wave][lane] = acc;
     __syncthreads();
-    if (wave == 0 && c < k) {
-      double t = 0.0;
-      for (int w = 0; w < 16; ++w) t += s_part[w][lane];
-      s_res[c] = sqrt(t);
-    }
+    if (wave == 0 && c < k) out[c] = ((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) + s_part[3][lane];
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256)
+residual_final_kernel(int k, int nb, int chi, double cutoff, double tol, CPtrSet S, const double* part,
+                      StatSet st) {
+  const int pb = blockIdx.x;
+  const double* sv = S.p[pb];
+  __shared__ double s_res[256];
+  const double* p = part + (size_t)pb * nb * k;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += p[(size_t)b * k + c];
+    s_res[c] = sqrt(t);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     SolveStatus* o = st.p[pb];
     double s0 = sv[0];
@@ -644,16 +760,21 @@ residual_kernel(int64_t n, int k, int chi, double cutoff, double tol, CPtrSet Z,
 
 hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cutoff, double tol,
                            const CPtrSet& Z, const CPtrSet& V, const CPtrSet& S,
-                           const StatSet& st, int nprob) {
+                           const StatSet& st, int nprob, double* scratch, int64_t scratch_elems) {
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
-  if (k > 256) return hipErrorInvalidValue;
+  if (k > 256 || k < 1 || n < 1) return hipErrorInvalidValue;
+  int nb = (int)std::min<int64_t>(64, (n + 63) / 64);
+  while (nb > 1 && (int64_t)nb * k * nprob > scratch_elems) nb /= 2;
+  if ((int64_t)nb * k * nprob > scratch_elems) return hipErrorInvalidValue;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(Z.p[i], (size_t)n * k * 8, "resid Z") || !span_ok(V.p[i], (size_t)n * k * 8, "resid V") ||
         !span_ok(S.p[i], (size_t)k * 8, "resid S") || !span_ok(st.p[i], sizeof(SolveStatus), "resid st"))
       return hipErrorInvalidValue;
+  if (!span_ok(scratch, (size_t)nb * k * nprob * 8, "resid scratch")) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(residual_kernel, dim3(nprob), dim3(1024), 0, s, n, k, chi, cutoff, tol, Z, V, S, st);
+  hipLaunchKernelGGL(residual_partial_kernel, dim3(nb, nprob), dim3(256), 0, s, n, k, Z, V, S, scratch);
+  hipLaunchKernelGGL(residual_final_kernel, dim3(nprob), dim3(256), 0, s, k, nb, chi, cutoff, tol, S, scratch, st);
   return hipGetLastError();
 }
 
