@@ -11,6 +11,8 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 namespace ctmk {
 
@@ -168,6 +170,103 @@ ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-streaming form for float32 with N <= 64 and k-fast A (A[m][k]):
+// one wave computes 64 rows x NT*16 columns over a K chunk with no LDS and no
+// barrier.  A is read in 16-byte pieces straight into registers (three
+// 16-wide K blocks in flight), B (small, L2-resident) element by element.
+// Lane l (row r = l % 16, group g = l / 16) reads A[m0 + 16 rb + r][k + 4 g ..
+// 4 g + 3]; value i feeds MFMA step i of the block, so step i contracts
+// k + 4 g + i over the groups g, and B is read with the same order:
+// B[k + 4 g + i][16 cb + r].  (For m-fast A the LDS-tiled form is faster.)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256, 2)
+ts_stream_ak_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
+                    int32_t mtiles, int32_t ntasks, GemmGroup g, float* __restrict__ part) {
+  constexpr int R = 4;
+  const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (task >= ntasks) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int mt = task % mtiles;
+  const int sk = (task / mtiles) % nsplit;
+  const int gi = task / (mtiles * nsplit);
+  const float* __restrict__ A = (const float*)g.A[gi];
+  const float* __restrict__ B = (const float*)g.B[gi];
+  const int m0 = mt * 16 * R;
+  const int kbeg = sk * kchunk, kend = min(K, kbeg + kchunk);
+  const int nblk = (kend - kbeg + 15) / 16;
+  const float* arow[R];
+#pragma unroll
+  for (int rb = 0; rb < R; ++rb) arow[rb] = A + (int64_t)min(m0 + rb * 16 + lr, M - 1) * lda;
+  int ncol[NT];
+#pragma unroll
+  for (int cb = 0; cb < NT; ++cb) ncol[cb] = min(cb * 16 + lr, N - 1);
+  v4f acc[R][NT];
+#pragma unroll
+  for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+  float4 a[3][R];
+  float b[3][NT][4];
+  // K block t of the chunk into ring slot st (blocks past the chunk read
+  // clamped addresses and become zeros)
+  auto load = [&](int st, int t) {
+    const int k = kbeg + t * 16 + 4 * lg;  // kend and k are multiples of 4
+    const bool kin = k < kend;
+    const int kc = kin ? k : kend - 4;
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+      const float4 v = *reinterpret_cast<const float4*>(arow[rb] + kc);
+      a[st][rb] = kin ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = B[(int64_t)(kc + i) * ldb + ncol[cb]];
+        b[st][cb][i] = kin ? v : 0.f;
+      }
+  };
+  auto compute = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int rb = 0; rb < R; ++rb) {
+        const float av = i == 0 ? a[st][rb].x : (i == 1 ? a[st][rb].y : (i == 2 ? a[st][rb].z : a[st][rb].w));
+#pragma unroll
+        for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = mfma4(av, b[st][cb][i], acc[rb][cb]);
+      }
+  };
+  load(0, 0);
+  load(1, 1);
+  load(2, 2);
+  for (int t = 0; t < nblk; t += 3) {
+    compute(0);
+    load(0, t + 3);
+    compute(1);
+    load(1, t + 4);
+    compute(2);
+    load(2, t + 5);
+  }
+  float* __restrict__ P = part + ((int64_t)gi * nsplit + sk) * M * N;
+#pragma unroll
+  for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb) {
+      const int n = cb * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + rb * 16 + 4 * lg + q;
+        if (m < M && n < N) P[(int64_t)m * N + n] = acc[rb][cb][q];
+      }
+    }
+}
+
 template <typename T, typename TO>
 __global__ void ts_reduce_kernel(const T* __restrict__ part, int32_t M, int32_t N, int32_t nsplit, int64_t ldc,
                                  GemmGroup g) {
@@ -202,6 +301,16 @@ hipError_t launch_partial(hipStream_t s, int nt, dim3 grid, int32_t M, int32_t N
 }
 
 }  // namespace
+
+// the register-streaming form is the default; CTM_TS_FORM=lds selects the
+// LDS-tiled form for every shape (both compute the same sums in other orders)
+static bool stream_form() {
+  static const bool v = [] {
+    const char* e = std::getenv("CTM_TS_FORM");
+    return !(e && std::strcmp(e, "lds") == 0);
+  }();
+  return v;
+}
 
 bool ts_gemm_supported(int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                        const View& vc) {
@@ -251,6 +360,35 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
   for (int i = 0; i < groups && vec; ++i) vec = ((uintptr_t)g.A[i] & 15) == 0;
   const int32_t M32 = (int32_t)M, N32 = (int32_t)N, K32 = (int32_t)K, kc32 = (int32_t)kchunk,
                 ns32 = (int32_t)nsplit, mt32 = (int32_t)mtiles;
+  if (ta == F32 && vec && N <= 64 && ak && stream_form()) {
+    // register-streaming form: 64 rows per wave, K chunks of whole
+    // three-block groups, about 2048 waves
+    const int64_t mt64 = (M + 63) / 64;
+    int64_t ns2 = std::max<int64_t>(1, std::min<int64_t>((2048 + mt64 * groups - 1) / (mt64 * groups), K / 48));
+    while (ns2 > 1 && ts_gemm_scratch_elems(M, N, groups, (int)ns2) * 4 > scratch_bytes) ns2 /= 2;
+    int64_t kc2 = ((K + ns2 - 1) / ns2 + 47) / 48 * 48;
+    ns2 = (K + kc2 - 1) / kc2;
+    if (ts_gemm_scratch_elems(M, N, groups, (int)ns2) * 4 <= scratch_bytes &&
+        span_ok(scratch, (size_t)ts_gemm_scratch_elems(M, N, groups, (int)ns2) * 4, "ts scratch")) {
+      const int64_t ntasks = mt64 * ns2 * groups;
+      dim3 g2((unsigned)((ntasks + 3) / 4));
+      const int nt2 = (int)((N + 15) / 16);
+#define TS2_CASE(NTV)                                                                                        \
+  case NTV:                                                                                                  \
+    hipLaunchKernelGGL((ts_stream_ak_kernel<NTV>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb, (int32_t)kc2,   \
+                       (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);                       \
+    break;
+      switch (nt2) {
+        TS2_CASE(1) TS2_CASE(2) TS2_CASE(3) TS2_CASE(4)
+        default: return hipErrorInvalidValue;
+      }
+#undef TS2_CASE
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      nsplit = ns2;
+      goto reduce;
+    }
+  }
   if (ta == F32) {
     float* ps = (float*)scratch;
     if (vec)
@@ -265,6 +403,7 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
            : launch_partial<double, false, false>(s, nt, grid, M32, N32, K32, lda, ldb, kc32, ns32, mt32, g, ps);
   }
   if (e != hipSuccess) return e;
+reduce:
   const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (M * N + 255) / 256));
   dim3 rg((unsigned)blocks, (unsigned)groups);
   if (ta == F32 && tc == F32)

@@ -62,11 +62,14 @@ def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
 
 @pytest.mark.parametrize("ta,tc", [(0, 0), (1, 1), (1, 0)])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 16, 32), (67, 45, 1030), (5184, 50, 5184), (700, 192, 2500),
-                                   (144, 144, 5184), (130, 1, 4097)])
+                                   (144, 144, 5184), (130, 1, 4097), (68, 45, 1036), (1000, 64, 772), (4, 3, 8)])
 @pytest.mark.parametrize("transA", [0, 1])
 def test_tsgemm(gpu, ta, tc, M, N, K, transA):
     """Split-K product for few columns: several K chunks, ragged row tiles
-    (M not a multiple of 64), N from 1 to 192, both layouts of A."""
+    (M not a multiple of 64), N from 1 to 192, both layouts of A.  float32
+    with k-fast A, M, K and the leading dimension multiples of 4 and N <= 64
+    takes the register-streaming form (ragged 16-wide K blocks: K = 1036, 772,
+    8)."""
     import torch
     lib = _lib()
     rng = np.random.default_rng(M + 7 * N + 13 * K)
