@@ -138,6 +138,8 @@ struct Row {  // scratch for one row of a column step
   void *P1w = nullptr, *P2Tw = nullptr;
   void *CT = nullptr, *W1 = nullptr, *W2 = nullptr, *X6 = nullptr;
   void* A3 = nullptr;  // bf16 mode: [hi | hi | lo] split of W1 for the three-term product
+  void* T3s = nullptr; // bf16 mode: three-term splits of T4 (A side) and P2T (B side) for W1
+  void* P3s = nullptr;
   void* W2t = nullptr; // fp32 working type: W2 as [(g,dn)][(R,c2)]
   double *nC1 = nullptr, *nT4 = nullptr, *nC4 = nullptr;
   double *red = nullptr, *sums = nullptr;
@@ -255,7 +257,11 @@ void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
   R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
   R.X6 = ar.take_bytes(t3 * ws);
-  if (x.prec == CTM_BF16) R.A3 = ar.take_bytes(3 * y4 * dtype_size(BF16));
+  if (x.prec == CTM_BF16) {
+    R.A3 = ar.take_bytes(3 * y4 * dtype_size(BF16));
+    R.T3s = ar.take_bytes(3 * t3 * dtype_size(BF16));
+    R.P3s = ar.take_bytes(3 * t3 * dtype_size(BF16));
+  }
   if (x.wt == F32) R.W2t = ar.take_bytes(y4 * ws);
   R.nC1 = ar.take<double>(c2); R.nT4 = ar.take<double>(t3); R.nC4 = ar.take<double>(c2);
 }
@@ -923,13 +929,33 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // W2[(g,c2),(dn,R)] = sum_(l,u) W1[(g,c2),(l,u)] b[(l,u),(dn,R)] is the new
   // edge itself: rounding its operands to bf16 perturbs the fixed point
   // directly (~10x the energy error of bf16 enlarged corners, which only steer
-  // the truncation).  In bf16 mode it is the three-term product
+  // the truncation).  In bf16 mode both are three-term products
   // hi.hi + hi.lo + lo.hi of bf16 splits (operand error ~2^-16) on the bf16
-  // kernel (the split also transposes W1 to [(g,c2)][(l,u)], through LDS);
-  // otherwise in the working type.
+  // kernel (the split of W1 also transposes it to [(g,c2)][(l,u)], through
+  // LDS); otherwise in the working type.
   const int64_t K4 = D2 * D2;
   if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
-    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+    if (I0.rows[0].T3s && corner_bf16_supported(c * D2, D2 * c, 3 * c)) {
+      // W1 as a three-term bf16 product too, split from the float64 masters:
+      //   A side T4[(g,l), p], B side (P2T as [p][(u,c2)])^T
+      G g3b;
+      for (Inst* I : insts) {
+        Roles ro{&x, I, k};
+        for (int yp = 0; yp < ly; ++yp) {
+          Row& R = I->rows[yp];
+          Row& Rp = I->rows[pmod(yp - 1, ly)];
+          HIPCHK(split3_bf16(s, F64, ro.T(3, xp, yp), rowmajor(c), c * D2, c, true, R.T3s));
+          HIPCHK(split3_bf16(s, F64, Rp.P2T, transposed(rowmajor(D2 * c)), D2 * c, c, false, R.P3s));
+          g3b.add(R.T3s, R.P3s, R.W1);
+        }
+      }
+      for (int j0 = 0; j0 < g3b.size(); j0 += MAXG) {
+        int cnt = std::min(MAXG, g3b.size() - j0);
+        HIPCHK(corner_bf16(s, c * D2, D2 * c, 3 * c, rowmajor(D2 * c), g3b.group(j0, cnt), cnt, F32));
+      }
+    } else {
+      CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+    }
     G g3x;
     for (Inst* I : insts) {
       Roles ro{&x, I, k};

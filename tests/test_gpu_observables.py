@@ -97,6 +97,35 @@ def test_c1_converged(gpu):
     assert np.abs(sg - so).max() < 1e-8
 
 
+def test_c2_converged(gpu):
+    """The benchmark workload (2x2, d=8, D=6, chi=144) in float64 on the GPU,
+    converged from the trivial start, against the oracle's converged
+    environment (tests/golden/make_golden.py, cutoff 1e-8, Delta < 1e-8):
+    kappa, the energy per spin and the corner spectra.  The bounds allow for
+    the 1e-8 convergence threshold of both runs."""
+    import time
+    from paper_1711_04798_amd import CTM
+    gold = _golden("c2")
+    w = gold["workload"]
+    A, B = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)
+    print("case c2 converged", flush=True)
+    t0 = time.time()
+    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=w["chi"], cutoff=w["cutoff"])
+    sw, dl, ok = g.converge(tol=w["tol"], max_sweeps=w["max_sweeps"])
+    assert ok == gold["converged"], (sw, dl)
+    kg = g.norm()
+    eg, _ = _gpu_energy(g, models.ruby_bond_h())
+    sg = g.spectra()
+    g.close()
+    so = np.array(gold["spectra"])
+    print("c2: gpu sweeps %d delta %.2e (oracle %d) in %.1f s; kappa rel %.2e; E/spin %.15f vs %.15f; spectra %.2e"
+          % (sw[0], dl[0], gold["sweeps"], time.time() - t0, abs(kg - gold["kappa"]) / gold["kappa"], eg / 12,
+             gold["energy_per_spin"], np.abs(sg - so).max()))
+    assert abs(kg - gold["kappa"]) <= 1e-9 * abs(gold["kappa"])
+    assert abs(eg / 12 - gold["energy_per_spin"]) <= 1e-9 * max(abs(gold["energy_per_spin"]), 1e-3)
+    assert np.abs(sg - so).max() < 1e-7
+
+
 def test_fidelity_gpu(gpu):
     """Fidelity per site of two nearby 1x1 states (d=2, D=2, chi=16) against
     the oracle's three converged runs; d(A, A) = 1."""
