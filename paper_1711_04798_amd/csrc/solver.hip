@@ -280,53 +280,95 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
 
 // ---------------------------------------------------------------------------
 // Y <- Y R^{-1} in place for n x k row-major Y and upper-triangular R (k <= 64):
-// one thread per row, right-looking substitution
+// one wave per 64 rows, one row per lane, right-looking substitution
 //   x_j = v_j / R_jj,  then v_l -= x_j R_jl for every l > j,
-// so that the updates after each x_j are independent of one another (the
-// dependent chain is one multiply and one FMA per column).  The row lives in
-// registers (loops unrolled to compile-time indices), R in LDS (every lane
-// reads the same entry: broadcasts).
+// in blocks of 8 columns: a block is solved in registers, then each later
+// block of the row is loaded from LDS, updated (8 x 8 products with R read
+// as LDS broadcasts) and stored back.  The unrolled code is one block's worth,
+// the block loops run at run time (a fully unrolled 64-column form spends most
+// of its time fetching instructions).  Rows move between HBM and LDS
+// coalesced.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+constexpr int TSB = 8;           // columns per block
+constexpr int TSL = CW + 1;      // LDS row stride of Y (odd: conflict-free row access by lane)
+
+__global__ void __launch_bounds__(64)
 trsm_rows_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
-  __shared__ double Rs[CW * CW];  // row-major, zero outside the upper triangle of the k x k block
-  __shared__ double rd[CW];       // 1 / R_jj
-  const int pb = blockIdx.y;
+  __shared__ double Rs[CW * CW];   // row-major, zero outside the upper triangle of the k x k block
+  __shared__ double rd[CW];        // 1 / R_jj (zero past k)
+  __shared__ double Vs[64 * TSL];  // the 64 rows of this wave
+  const int pb = blockIdx.y, lane = threadIdx.x;
   const double* r = R.p[pb];
-  // every load in flight at once (indices clamped into the k x k block)
-  constexpr int PER = CW * CW / 256;
-  double rv[PER];
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int nrows = (int)min<int64_t>(64, n - row0);
+  double* y = Y.p[pb] + row0 * k;
+  // R and the rows: every load in flight before any store (indices clamped)
+  constexpr int PER = CW * CW / 64;
+  for (int t0 = 0; t0 < PER; t0 += 16) {
+    double rv[16];
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int e = threadIdx.x + 256 * t, i = e / CW, j = e - i * CW;
-    rv[t] = r[min(i, k - 1) * k + min(j, k - 1)];
-  }
+    for (int t = 0; t < 16; ++t) {
+      const int e = lane + 64 * (t0 + t), i = e / CW, j = e - i * CW;
+      rv[t] = r[min(i, k - 1) * k + min(j, k - 1)];
+    }
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int e = threadIdx.x + 256 * t, i = e / CW, j = e - i * CW;
-    Rs[e] = (i < k && j < k && i <= j) ? rv[t] : 0.0;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < CW; j += blockDim.x) rd[j] = j < k ? 1.0 / Rs[j * CW + j] : 0.0;
-  __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  double* y = Y.p[pb] + row * k;
-  double v[CW];
-#pragma unroll
-  for (int j = 0; j < CW; ++j) v[j] = y[j < k ? j : k - 1];
-#pragma unroll
-  for (int j = 0; j < CW; ++j) {
-    if (j < k) {
-      const double xj = v[j] * rd[j];
-      v[j] = xj;
-#pragma unroll
-      for (int l = j + 1; l < CW; ++l) v[l] -= xj * Rs[j * CW + l];
+    for (int t = 0; t < 16; ++t) {
+      const int e = lane + 64 * (t0 + t), i = e / CW, j = e - i * CW;
+      Rs[e] = (i < k && j < k && i <= j) ? rv[t] : 0.0;
     }
   }
+  const int tot = nrows * k;
+  for (int e0 = lane; e0 < 64 * CW; e0 += 64 * 16) {
+    double yv[16];
 #pragma unroll
-  for (int j = 0; j < CW; ++j)
-    if (j < k) y[j] = v[j];
+    for (int t = 0; t < 16; ++t) yv[t] = y[min(e0 + 64 * t, tot - 1)];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = e0 + 64 * t, i = e / k, j = e - i * k;
+      if (e < tot) Vs[i * TSL + j] = yv[t];
+    }
+  }
+  __syncthreads();
+  if (lane < CW) rd[lane] = lane < k ? 1.0 / Rs[lane * CW + lane] : 0.0;
+  // columns k .. CW of the rows are never read into a result, but keep them finite
+  for (int e = lane; e < 64 * TSL; e += 64) {
+    const int j = e % TSL;
+    if (j >= k) Vs[e] = 0.0;
+  }
+  __syncthreads();
+  double* vr = Vs + lane * TSL;
+  const int nb = (k + TSB - 1) / TSB;
+  for (int b = 0; b < nb; ++b) {
+    const int c0 = b * TSB;
+    double x[TSB];
+#pragma unroll
+    for (int u = 0; u < TSB; ++u) x[u] = vr[c0 + u];
+#pragma unroll
+    for (int u = 0; u < TSB; ++u) {
+      x[u] *= rd[c0 + u];
+#pragma unroll
+      for (int w = u + 1; w < TSB; ++w) x[w] -= x[u] * Rs[(c0 + u) * CW + c0 + w];
+    }
+#pragma unroll
+    for (int u = 0; u < TSB; ++u) vr[c0 + u] = x[u];
+    for (int b2 = b + 1; b2 < nb; ++b2) {
+      const int c2 = b2 * TSB;
+      double w[TSB];
+#pragma unroll
+      for (int t = 0; t < TSB; ++t) w[t] = vr[c2 + t];
+#pragma unroll
+      for (int u = 0; u < TSB; ++u)
+#pragma unroll
+        for (int t = 0; t < TSB; ++t) w[t] -= x[u] * Rs[(c0 + u) * CW + c2 + t];
+#pragma unroll
+      for (int t = 0; t < TSB; ++t) vr[c2 + t] = w[t];
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < tot; e += 64) {
+    const int i = e / k, j = e - i * k;
+    y[e] = Vs[i * TSL + j];
+  }
 }
 
 hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob) {
@@ -336,8 +378,8 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
     if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R"))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nprob);
-  hipLaunchKernelGGL(trsm_rows_kernel, grid, dim3(256), 0, s, n, k, Y, R);
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)nprob);
+  hipLaunchKernelGGL(trsm_rows_kernel, grid, dim3(64), 0, s, n, k, Y, R);
   return hipGetLastError();
 }
 
