@@ -191,16 +191,18 @@ ctm_status ctm_env_export(ctm_ctx ctx, int32_t inst, void* host_buf, size_t byte
 ctm_status ctm_env_import(ctm_ctx ctx, int32_t inst, const void* host_buf, size_t bytes);
 
 /*
- * Kernel-time accounting, enabled (and reset) by ctm_set_timing.  While
- * enabled, HIP events on the context's stream bracket every column step's
- * phases and every launch of the enlarged-corner double-layer contraction.
+ * Kernel-time accounting, enabled (and reset) by ctm_set_timing: enable = 1
+ * brackets every column step's phases and every launch of the enlarged-corner
+ * double-layer contraction with HIP events on the context's stream; enable = 2
+ * only the latter (fewer events in the stream); 0 switches it off.  The events
+ * are read, and pending ones dropped, by ctm_get_timing / ctm_set_timing, which
+ * then wait for them; nothing waits in between.
  * ctm_get_timing fills v[8]:
  *   v[0] seconds in enlarged corners, v[1] in the projector solver,
- *   v[2] in absorption, v[3] seconds inside the double-layer contraction
- *   launches of the enlarged corners, v[4] number of those launches, v[5]
- *   their algorithmic flop (2 chi^2 D^8 per corner), v[6] corner-chain
- *   launches, v[7] column steps timed.
- * Timing synchronises the stream around each timed launch.
+ *   v[2] in absorption (zero with enable = 2), v[3] seconds inside the
+ *   double-layer contraction launches of the enlarged corners, v[4] number of
+ *   those launches, v[5] their algorithmic flop (2 chi^2 D^8 per corner),
+ *   v[6] corner-chain launches, v[7] column steps timed.
  */
 ctm_status ctm_set_timing(ctm_ctx ctx, int32_t enable);
 ctm_status ctm_get_timing(ctm_ctx ctx, double* v);

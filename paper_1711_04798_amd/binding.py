@@ -259,8 +259,10 @@ class CTM:
         buf = np.ascontiguousarray(buf, dtype=np.float64)
         _check(load().ctm_env_import(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
 
-    def set_timing(self, on=True):
-        _check(load().ctm_set_timing(self.ctx, int(on)))
+    def set_timing(self, mode=1):
+        """1: phases and corner-kernel launches, 2: corner-kernel launches
+        only, 0 / False: off (see ctm_set_timing)."""
+        _check(load().ctm_set_timing(self.ctx, int(mode)))
 
     def timing(self):
         v = (ctypes.c_double * 8)()

@@ -26,6 +26,7 @@
 #include <functional>
 #include <initializer_list>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "kernels.h"
@@ -214,7 +215,14 @@ struct ctm_ctx_s {
   bool timing = false;
   double t_corner = 0, t_solver = 0, t_absorb = 0, t_stage3 = 0, stage3_flop = 0;
   int64_t corner_launches = 0, stage3_launches = 0, moves = 0;
-  hipEvent_t ev[6] = {};
+  // timing (ctm_set_timing): one record of four phase events per timed column
+  // step and one event pair per timed stage-3 launch, recorded without waiting
+  // and read when timing is queried (a wait per column step would drain the
+  // stream between column steps)
+  bool phase_timing = false;
+  std::vector<std::array<hipEvent_t, 4>> tpool;
+  std::vector<std::array<hipEvent_t, 2>> spool;
+  size_t tused = 0, sused = 0;
   Registry reg;
 };
 
@@ -545,23 +553,23 @@ struct CornerJob {
 };
 
 struct Stage3Timer {
-  hipEvent_t a = nullptr, b = nullptr;
-  double* acc = nullptr;
-  int64_t* count = nullptr;
+  std::vector<std::array<hipEvent_t, 2>>* pool = nullptr;
+  size_t* used = nullptr;
 };
 
 ctm_status stage3_timed(hipStream_t s, const Stage3Timer* tm, const std::function<ctm_status()>& f) {
-  const bool timed = tm && tm->a && !dry_run();
-  if (timed) HIPCHK(hipEventRecord(tm->a, s));
-  CHK(f());
-  if (timed) {
-    HIPCHK(hipEventRecord(tm->b, s));
-    HIPCHK(hipEventSynchronize(tm->b));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, tm->a, tm->b));
-    *tm->acc += ms * 1e-3;
-    *tm->count += 1;
+  const bool timed = tm && tm->pool && !dry_run();
+  if (!timed) return f();
+  if (*tm->used == tm->pool->size()) {
+    std::array<hipEvent_t, 2> e{};
+    for (auto& v : e) HIPCHK(hipEventCreate(&v));
+    tm->pool->push_back(e);
   }
+  const std::array<hipEvent_t, 2>& e = (*tm->pool)[*tm->used];
+  HIPCHK(hipEventRecord(e[0], s));
+  CHK(f());
+  HIPCHK(hipEventRecord(e[1], s));
+  *tm->used += 1;
   return CTM_OK;
 }
 
@@ -1071,15 +1079,36 @@ ctm_status refresh_working(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
   return CTM_OK;
 }
 
-void ev_record(ctm_ctx_s& x, int i) {
-  if (x.timing && !dry_run()) (void)hipEventRecord(x.ev[i], x.stream);
+// the record of the current column step (created on first use)
+ctm_status timing_begin(ctm_ctx_s& x) {
+  if (!x.timing || !x.phase_timing || dry_run() || x.tused < x.tpool.size()) return CTM_OK;
+  std::array<hipEvent_t, 4> e{};
+  for (auto& v : e) HIPCHK(hipEventCreate(&v));
+  x.tpool.push_back(e);
+  return CTM_OK;
 }
-double ev_ms(ctm_ctx_s& x, int a, int b) {
+void ev_record(ctm_ctx_s& x, int i) {
+  if (x.timing && x.phase_timing && !dry_run()) (void)hipEventRecord(x.tpool[x.tused][i], x.stream);
+}
+double ev_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0;
-  if (dry_run()) return 0.0;
-  (void)hipEventSynchronize(x.ev[b]);
-  (void)hipEventElapsedTime(&ms, x.ev[a], x.ev[b]);
+  (void)hipEventSynchronize(b);
+  (void)hipEventElapsedTime(&ms, a, b);
   return ms * 1e-3;
+}
+// adds every pending record to the totals
+void timing_flush(ctm_ctx_s& x) {
+  for (size_t i = 0; i < x.tused; ++i) {
+    const auto& e = x.tpool[i];
+    x.t_corner += ev_ms(e[0], e[1]);
+    x.t_solver += ev_ms(e[1], e[2]);
+    x.t_absorb += ev_ms(e[2], e[3]);
+  }
+  for (size_t i = 0; i < x.sused; ++i) {
+    x.t_stage3 += ev_ms(x.spool[i][0], x.spool[i][1]);
+    x.stage3_launches += 1;
+  }
+  x.tused = x.sused = 0;
 }
 
 // One column step of the move in direction k at frame column xp, for every
@@ -1091,6 +1120,7 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   int lx, ly;
   frame_dims(k, x.Lx, x.Ly, lx, ly);
   CHK(refresh_working(x, insts));
+  CHK(timing_begin(x));
   ev_record(x, 0);
   // enlarged corners of every plaquette (xp, yp)
   std::vector<CornerJob> jobs;
@@ -1120,10 +1150,8 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   }
   Stage3Timer tm;
   if (x.timing) {
-    tm.a = x.ev[4];
-    tm.b = x.ev[5];
-    tm.acc = &x.t_stage3;
-    tm.count = &x.stage3_launches;
+    tm.pool = &x.spool;
+    tm.used = &x.sused;
     // algorithmic work of the (l,u)-contraction with the double layer:
     // 2 chi^2 D^8 flop per corner
     x.stage3_flop += 2.0 * (double)I0.chi * I0.chi * (double)I0.D2 * I0.D2 * I0.D2 * I0.D2 * (double)jobs.size();
@@ -1169,10 +1197,9 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   ev_record(x, 2);
   CHK(absorb_rows(x, insts, k, xp));
   ev_record(x, 3);
-  if (x.timing) {
-    x.t_corner += ev_ms(x, 0, 1);
-    x.t_solver += ev_ms(x, 1, 2);
-    x.t_absorb += ev_ms(x, 2, 3);
+  if (x.timing && !dry_run()) {
+    if (x.phase_timing) x.tused += 1;
+    if (x.tused >= 1024 || x.sused >= 1024) timing_flush(x);  // bounded event pools
   }
   return CTM_OK;
 }
@@ -1931,9 +1958,6 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
     st = init_env(*x, I, i, init, spectrum_host);
     if (st != CTM_OK) return cleanup(st);
   }
-  if (!dry_run())
-    for (int e = 0; e < 6; ++e)
-      if (hipEventCreate(&x->ev[e]) != hipSuccess) return cleanup(fail(CTM_E_HIP, "event"));
   *out = x;
   return CTM_OK;
 }
@@ -2142,7 +2166,11 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
 
 ctm_status ctm_set_timing(ctm_ctx x, int32_t enable) {
   if (!x) return fail(CTM_E_INVALID, "null ctx");
+  if (x->tused || x->sused) (void)hipStreamSynchronize(x->stream);  // pending records are dropped
+  if (enable < 0 || enable > 2) return fail(CTM_E_INVALID, "enable must be 0, 1 or 2");
+  x->tused = x->sused = 0;
   x->timing = enable != 0;
+  x->phase_timing = enable == 1;
   x->t_corner = x->t_solver = x->t_absorb = x->t_stage3 = x->stage3_flop = 0;
   x->corner_launches = x->stage3_launches = x->moves = 0;
   return CTM_OK;
@@ -2150,6 +2178,7 @@ ctm_status ctm_set_timing(ctm_ctx x, int32_t enable) {
 
 ctm_status ctm_get_timing(ctm_ctx x, double* v) {
   if (!x || !v) return fail(CTM_E_INVALID, "args");
+  timing_flush(*x);
   v[0] = x->t_corner;
   v[1] = x->t_solver;
   v[2] = x->t_absorb;
@@ -2164,8 +2193,11 @@ ctm_status ctm_get_timing(ctm_ctx x, double* v) {
 void ctm_destroy(ctm_ctx x) {
   if (!x) return;
   if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
-  for (int e = 0; e < 6; ++e)
-    if (x->ev[e]) (void)hipEventDestroy(x->ev[e]);
+  if (x->tused || x->sused) (void)hipStreamSynchronize(x->stream);
+  for (auto& r : x->tpool)
+    for (hipEvent_t e : r) (void)hipEventDestroy(e);
+  for (auto& r : x->spool)
+    for (hipEvent_t e : r) (void)hipEventDestroy(e);
   delete x;
 }
 
