@@ -220,6 +220,7 @@ struct ctm_ctx_s {
   // and read when timing is queried (a wait per column step would drain the
   // stream between column steps)
   bool phase_timing = false;
+  bool resid_step = true;  // fixed-count solver: form the residuals in this column step
   std::vector<std::array<hipEvent_t, 4>> tpool;
   std::vector<std::array<hipEvent_t, 2>> spool;
   size_t tused = 0, sused = 0;
@@ -655,10 +656,11 @@ struct SolveRow {
 
 // out = op(N) in for all problems, with N = Q2^T Q1^T Q4^T Q3^T (transposeN =
 // false) or N^T = Q3 Q4 Q1 Q2 (true).  `mid` receives the product after the
-// first two factors (Lh^T in, or Uh in).  in/out/mid float64 n x k.
+// first two factors (Lh^T in, or Uh in).  in/out/mid float64 n x k.  With
+// nfac = 2 only mid is formed.
 ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
                   const std::vector<double*>& in, const std::vector<double*>& out,
-                  const std::vector<double*>& mid, bool transposeN) {
+                  const std::vector<double*>& mid, bool transposeN, int nfac = 4) {
   hipStream_t s = x.stream;
   const int qt = x.qt;
   const View vq = transposeN ? rowmajor(n) : transposed(rowmajor(n));
@@ -669,7 +671,7 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
   const int* ord = transposeN ? ord_t : ord_n;
   const size_t P = rows.size();
   if (qt == F64) {
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < nfac; ++f) {
       G g;
       for (size_t r = 0; r < P; ++r) {
         Row* R = rows[r].R;
@@ -687,7 +689,7 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
     for (size_t r = 0; r < P; ++r) cv.add(in[r], rows[r].R->qin, (int64_t)n * k);
     CHK(xfer_run(s, F64, qt, cv));
   }
-  for (int f = 0; f < 4; ++f) {
+  for (int f = 0; f < nfac; ++f) {
     G g;
     for (size_t r = 0; r < P; ++r) {
       Row* R = rows[r].R;
@@ -792,7 +794,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   // One Rayleigh-Ritz iteration: Y = N V = Q R, R = U_R S W_R^T, then the
   // left vectors U = Q U_R, right vectors V' = V W_R, Z = N^T U and the
   // residuals |Z_i - S_i V'_i|.
-  auto rr_iteration = [&]() -> ctm_status {
+  auto rr_iteration = [&](bool want_resid) -> ctm_status {
     CHK(napply(x, n, k, rows, V, Yb, LV, false));          // Y = N V, LV = Lh^T V
     CHK(copy_blocks(Qb, Yb));
     CHK(orthonormalize(x, n, k, rows, Qb));                // Q = orth(Y)
@@ -832,12 +834,13 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
       CHK(xfer_run(s, F64, F64, cp));
     }
-    CHK(napply(x, n, k, rows, Ub, Z, UU, true));           // Z = N^T U, UU = Uh U
+    // UU = Uh U (the projector's factor), and Z = N^T U for the residuals
+    CHK(napply(x, n, k, rows, Ub, Z, UU, true, want_resid ? 4 : 2));
     {
       CPtrSet Zs{}, Vs{}, Ss{};
       StatSet st{};
       for (size_t r = 0; r < P; ++r) {
-        Zs.p[r] = Z[r]; Vs.p[r] = Vpv[r]; Ss.p[r] = rows[r].R->S; st.p[r] = rows[r].R->st;
+        Zs.p[r] = want_resid ? Z[r] : nullptr; Vs.p[r] = Vpv[r]; Ss.p[r] = rows[r].R->S; st.p[r] = rows[r].R->st;
       }
       HIPCHK(residual_status(s, n, k, chi, c.svd_cutoff, c.svd_resid_tol > 0 ? c.svd_resid_tol : 0.0,
                              Zs, Vs, Ss, st, (int)P, x.splitk, x.splitk_elems));
@@ -847,7 +850,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   if (adaptive) {
     // Rayleigh-Ritz every iteration; stop when all kept residuals are small
     for (int it = 0; it < maxit; ++it) {
-      CHK(rr_iteration());
+      CHK(rr_iteration(true));
       if (it + 1 >= maxit) break;
       bool all = true;
       for (size_t r = 0; r < P; ++r) HIPCHK(d2h(&hst[r], rows[r].R->st, sizeof(SolveStatus), s));
@@ -859,15 +862,19 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     }
   } else {
     // fixed count: plain subspace iterations V <- orth(N^T orth(N V)), then
-    // one Rayleigh-Ritz step
+    // one Rayleigh-Ritz step.  The inner basis only carries the span to
+    // N^T: two Cholesky-QR passes (the shifted one and one more) leave it well
+    // conditioned, which is all that step needs.  The residuals steer nothing
+    // here; they are formed on the last column step of a sweep (and of every
+    // single move) as the accuracy record of the solver.
     for (int it = 0; it + 1 < maxit; ++it) {
       CHK(napply(x, n, k, rows, V, Yb, LV, false));
-      CHK(orthonormalize(x, n, k, rows, Yb));
+      CHK(orthonormalize(x, n, k, rows, Yb, 2));
       CHK(napply(x, n, k, rows, Yb, Z, UU, true));
       CHK(copy_blocks(V, Z));
       CHK(orthonormalize(x, n, k, rows, V));
     }
-    CHK(rr_iteration());
+    CHK(rr_iteration(x.resid_step));
   }
   // projectors
   {
@@ -1478,8 +1485,17 @@ ctm_status do_sweep(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
   for (int o = 0; o < 4; ++o) {
     int lx, ly;
     frame_dims(order[o], x.Lx, x.Ly, lx, ly);
-    CHK(do_move(x, insts, order[o], lx));
+    if (o < 3) {
+      x.resid_step = false;
+      CHK(do_move(x, insts, order[o], lx));
+    } else {
+      x.resid_step = false;
+      CHK(do_move(x, insts, order[o], lx - 1));
+      x.resid_step = true;  // the sweep's last column step
+      CHK(do_move(x, insts, order[o], 1));
+    }
   }
+  x.resid_step = true;
   return CTM_OK;
 }
 
@@ -1978,6 +1994,7 @@ ctm_status ctm_move(ctm_ctx x, int32_t dir, int32_t count) {
     if (dir == CTM_SWEEP) {
       for (int i = 0; i < count; ++i) CHK(do_sweep(*x, insts));
     } else {
+      x->resid_step = true;
       CHK(do_move(*x, insts, dir, count));
     }
   }

@@ -63,7 +63,8 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U,
 // Residuals r_i = ||Z_i - S_i V_i|| of the columns of the n x k row-major
 // blocks; sets chi_eff (from S, chi, cutoff), converged (tol), sigma0,
 // max_resid and increments iters.  scratch: at least 64 k nprob doubles for
-// full parallelism (fewer row chunks otherwise).
+// full parallelism (fewer row chunks otherwise).  With Z.p[0] null the
+// residuals are not formed: max_resid = -1, converged = 0, the rest as above.
 hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cutoff, double tol,
                            const CPtrSet& Z, const CPtrSet& V, const CPtrSet& S,
                            const StatSet& st, int nprob, double* scratch, int64_t scratch_elems);

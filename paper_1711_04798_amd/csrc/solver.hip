@@ -774,7 +774,7 @@ residual_final_kernel(int k, int nb, int chi, double cutoff, double tol, CPtrSet
   const int pb = blockIdx.x;
   const double* sv = S.p[pb];
   __shared__ double s_res[256];
-  const double* p = part + (size_t)pb * nb * k;
+  const double* p = nb > 0 ? part + (size_t)pb * nb * k : nullptr;
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double t = 0.0;
     for (int b = 0; b < nb; ++b) t += p[(size_t)b * k + c];
@@ -791,10 +791,11 @@ residual_final_kernel(int k, int nb, int chi, double cutoff, double tol, CPtrSet
     double mr = 0.0;
     for (int c = 0; c < keep; ++c) mr = fmax(mr, s_res[c]);
     mr = s0 > 0 ? mr / s0 : 0.0;
+    if (nb == 0) mr = -1.0;  // residuals not formed
     o->chi_eff = keep;
     o->sigma0 = s0;
     o->max_resid = mr;
-    o->converged = (mr <= tol) ? 1 : 0;
+    o->converged = (nb > 0 && mr <= tol) ? 1 : 0;
     o->iters += 1;
     o->kcols = k;
   }
@@ -806,16 +807,18 @@ hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cuto
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   if (k > 256 || k < 1 || n < 1) return hipErrorInvalidValue;
-  int nb = (int)std::min<int64_t>(64, (n + 63) / 64);
+  const bool with_resid = Z.p[0] != nullptr;
+  int nb = with_resid ? (int)std::min<int64_t>(64, (n + 63) / 64) : 0;
   while (nb > 1 && (int64_t)nb * k * nprob > scratch_elems) nb /= 2;
   if ((int64_t)nb * k * nprob > scratch_elems) return hipErrorInvalidValue;
   for (int i = 0; i < nprob; ++i)
-    if (!span_ok(Z.p[i], (size_t)n * k * 8, "resid Z") || !span_ok(V.p[i], (size_t)n * k * 8, "resid V") ||
+    if ((with_resid && (!span_ok(Z.p[i], (size_t)n * k * 8, "resid Z") || !span_ok(V.p[i], (size_t)n * k * 8, "resid V"))) ||
         !span_ok(S.p[i], (size_t)k * 8, "resid S") || !span_ok(st.p[i], sizeof(SolveStatus), "resid st"))
       return hipErrorInvalidValue;
   if (!span_ok(scratch, (size_t)nb * k * nprob * 8, "resid scratch")) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(residual_partial_kernel, dim3(nb, nprob), dim3(256), 0, s, n, k, Z, V, S, scratch);
+  if (nb > 0)
+    hipLaunchKernelGGL(residual_partial_kernel, dim3(nb, nprob), dim3(256), 0, s, n, k, Z, V, S, scratch);
   hipLaunchKernelGGL(residual_final_kernel, dim3(nprob), dim3(256), 0, s, k, nb, chi, cutoff, tol, S, scratch, st);
   return hipGetLastError();
 }
