@@ -171,23 +171,23 @@ ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int
 }
 
 // ---------------------------------------------------------------------------
-// Register-streaming form for float32 with N <= 64 and k-fast A (A[m][k]):
-// one wave computes 64 rows x NT*16 columns over a K chunk with no LDS and no
-// barrier.  A is read in 16-byte pieces straight into registers (three
-// 16-wide K blocks in flight), B (small, L2-resident) element by element.
-// Lane l (row r = l % 16, group g = l / 16) reads A[m0 + 16 rb + r][k + 4 g ..
-// 4 g + 3]; value i feeds MFMA step i of the block, so step i contracts
-// k + 4 g + i over the groups g, and B is read with the same order:
-// B[k + 4 g + i][16 cb + r].  (For m-fast A the LDS-tiled form is faster.)
+// Register-streaming form for float32 with N <= 64: one wave computes 64
+// rows x NT*16 columns over a K chunk with no LDS and no barrier, three
+// 16-wide K blocks in flight in registers; B (small, L2-resident) is read
+// element by element.  Lane l (row r = l % 16, group g = l / 16) holds
+// A[m0 + 16 rb + r][k + 4 g + i], i = 0..3: one 16-byte piece for k-fast A
+// (A[m][k]), four loads of 16 consecutive rows for m-fast A (A[k][m]).
+// Value i feeds MFMA step i of the block, so step i contracts k + 4 g + i over
+// the groups g, and B is read with the same order: B[k + 4 g + i][16 cb + r].
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int NT>
+template <int NT, bool AK>
 __global__ void __launch_bounds__(256, 2)
-ts_stream_ak_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
-                    int32_t mtiles, int32_t ntasks, GemmGroup g, float* __restrict__ part) {
+ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
+                 int32_t mtiles, int32_t ntasks, GemmGroup g, float* __restrict__ part) {
   constexpr int R = 4;
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
@@ -199,10 +199,12 @@ ts_stream_ak_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, i
   const float* __restrict__ B = (const float*)g.B[gi];
   const int m0 = mt * 16 * R;
   const int kbeg = sk * kchunk, kend = min(K, kbeg + kchunk);
-  const int nblk = (kend - kbeg + 15) / 16;
   const float* arow[R];
 #pragma unroll
-  for (int rb = 0; rb < R; ++rb) arow[rb] = A + (int64_t)min(m0 + rb * 16 + lr, M - 1) * lda;
+  for (int rb = 0; rb < R; ++rb) {
+    const int m = min(m0 + rb * 16 + lr, M - 1);
+    arow[rb] = AK ? A + (int64_t)m * lda : A + m;
+  }
   int ncol[NT];
 #pragma unroll
   for (int cb = 0; cb < NT; ++cb) ncol[cb] = min(cb * 16 + lr, N - 1);
@@ -213,24 +215,36 @@ ts_stream_ak_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, i
     for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
   float4 a[3][R];
   float b[3][NT][4];
-  // K block t of the chunk into ring slot st (blocks past the chunk read
-  // clamped addresses and become zeros)
+  // K block t of the chunk into ring slot st.  Addresses are clamped to the
+  // chunk's last four columns, so the loads carry no condition and no select
+  // (either would make the wave wait for the ring right after issuing it);
+  // whole blocks are always in range, and a block past the chunk is loaded
+  // but never used.
   auto load = [&](int st, int t) {
-    const int k = kbeg + t * 16 + 4 * lg;  // kend and k are multiples of 4
-    const bool kin = k < kend;
-    const int kc = kin ? k : kend - 4;
+    const int kc = min(kbeg + t * 16 + 4 * lg, kend - 4);  // kend - kbeg >= 4, multiples of 4
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
-      const float4 v = *reinterpret_cast<const float4*>(arow[rb] + kc);
-      a[st][rb] = kin ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (AK) {
+        a[st][rb] = *reinterpret_cast<const float4*>(arow[rb] + kc);
+      } else {
+        const float* p = arow[rb] + (int64_t)kc * lda;
+        a[st][rb] = make_float4(p[0], p[lda], p[2 * lda], p[3 * lda]);
+      }
     }
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float v = B[(int64_t)(kc + i) * ldb + ncol[cb]];
-        b[st][cb][i] = kin ? v : 0.f;
-      }
+      for (int i = 0; i < 4; ++i) b[st][cb][i] = B[(int64_t)(kc + i) * ldb + ncol[cb]];
+  };
+  // ragged last block: lane groups past the chunk end contribute zeros
+  auto mask = [&](int st, bool kin) {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+      if (!kin) a[st][rb] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int cb = 0; cb < NT; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b[st][cb][i] = kin ? b[st][cb][i] : 0.f;
   };
   auto compute = [&](int st) {
 #pragma unroll
@@ -242,16 +256,53 @@ ts_stream_ak_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, i
         for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = mfma4(av, b[st][cb][i], acc[rb][cb]);
       }
   };
+  // A region loads the next block into the slot just freed and computes the
+  // following block, the loads spread evenly among its MFMAs: issued in a
+  // burst between MFMA blocks, the same loads leave the matrix cores idle
+  // about half the time
+  constexpr int NL = (AK ? R : 4 * R) + 4 * NT;  // loads per block
+  constexpr int NM = 4 * R * NT;                  // MFMAs per block
+  auto region = [&](int ls, int lt, int cs) {
+    load(ls, lt);
+    compute(cs);
+    if constexpr (NM >= NL) {
+      constexpr int per = NM / NL;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // one VMEM read
+        __builtin_amdgcn_sched_group_barrier(0x008, per, 0);  // then MFMAs
+      }
+      if constexpr (NM > per * NL) __builtin_amdgcn_sched_group_barrier(0x008, NM - per * NL, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  const int span = kend - kbeg;
+  const int nfull = span / 16;
+  __builtin_amdgcn_sched_barrier(0);
   load(0, 0);
   load(1, 1);
   load(2, 2);
-  for (int t = 0; t < nblk; t += 3) {
+  __builtin_amdgcn_sched_barrier(0);
+  // block bb lives in slot bb % 3; blocks past nfull are loaded and dropped
+  int bb = 0;
+  if (nfull > 0) {
     compute(0);
-    load(0, t + 3);
-    compute(1);
-    load(1, t + 4);
-    compute(2);
-    load(2, t + 5);
+    bb = 1;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  for (; bb + 3 <= nfull; bb += 3) {
+    region(0, bb + 2, 1);
+    region(1, bb + 3, 2);
+    region(2, bb + 4, 0);
+  }
+  if (bb < nfull) compute(1);
+  if (bb + 1 < nfull) compute(2);
+  // ragged last block (every slot is free by now): lane groups past the chunk
+  // end contribute zeros
+  if (nfull * 16 < span) {
+    load(0, nfull);
+    mask(0, kbeg + nfull * 16 + 4 * lg < kend);
+    compute(0);
   }
   float* __restrict__ P = part + ((int64_t)gi * nsplit + sk) * M * N;
 #pragma unroll
@@ -360,7 +411,7 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
   for (int i = 0; i < groups && vec; ++i) vec = ((uintptr_t)g.A[i] & 15) == 0;
   const int32_t M32 = (int32_t)M, N32 = (int32_t)N, K32 = (int32_t)K, kc32 = (int32_t)kchunk,
                 ns32 = (int32_t)nsplit, mt32 = (int32_t)mtiles;
-  if (ta == F32 && vec && N <= 64 && ak && stream_form()) {
+  if (ta == F32 && vec && N <= 64 && stream_form()) {
     // register-streaming form: 64 rows per wave, K chunks of whole
     // three-block groups, about 2048 waves
     const int64_t mt64 = (M + 63) / 64;
@@ -375,8 +426,12 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
       const int nt2 = (int)((N + 15) / 16);
 #define TS2_CASE(NTV)                                                                                        \
   case NTV:                                                                                                  \
-    hipLaunchKernelGGL((ts_stream_ak_kernel<NTV>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb, (int32_t)kc2,   \
-                       (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);                       \
+    if (ak)                                                                                                  \
+      hipLaunchKernelGGL((ts_stream_kernel<NTV, true>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb,          \
+                         (int32_t)kc2, (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);        \
+    else                                                                                                     \
+      hipLaunchKernelGGL((ts_stream_kernel<NTV, false>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb,         \
+                         (int32_t)kc2, (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);        \
     break;
       switch (nt2) {
         TS2_CASE(1) TS2_CASE(2) TS2_CASE(3) TS2_CASE(4)
