@@ -174,14 +174,20 @@ ts_partial_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int
 // Register-streaming form for float32 with N <= 64: one wave computes 64
 // rows x NT*16 columns over a K chunk with no LDS and no barrier, three
 // 16-wide K blocks in flight in registers; B (small, L2-resident) is read
-// element by element.  Lane l (row r = l % 16, group g = l / 16) holds
-// A[m0 + 16 rb + r][k + 4 g + i], i = 0..3: one 16-byte piece for k-fast A
-// (A[m][k]), four loads of 16 consecutive rows for m-fast A (A[k][m]).
-// Value i feeds MFMA step i of the block, so step i contracts k + 4 g + i over
-// the groups g, and B is read with the same order: B[k + 4 g + i][16 cb + r].
+// element by element.  MFMA step i of a 16-wide K block contracts
+// k + 4 g + i over the lane groups g = l / 16, and B is read in that order:
+// B[k + 4 g + i][16 cb + r], r = l % 16.  k-fast A (A[m][k]): lane l reads the
+// 16-byte piece A[m0 + 16 rb + r][k + 4 g .. + 3], value i feeding step i of
+// row block rb (rows m0 + 16 rb + 0..15).  m-fast A (A[k][m]): lane l reads
+// A[k + 4 g + i][m0 + 4 r .. + 3] for step i, value q feeding row block q,
+// which then holds the rows m0 + 4 r' + q, r' = 0..15 (16 lanes read 256
+// contiguous bytes of a row of A either way).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float comp(const float4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
 template <int NT, bool AK>
@@ -201,10 +207,8 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   const int kbeg = sk * kchunk, kend = min(K, kbeg + kchunk);
   const float* arow[R];
 #pragma unroll
-  for (int rb = 0; rb < R; ++rb) {
-    const int m = min(m0 + rb * 16 + lr, M - 1);
-    arow[rb] = AK ? A + (int64_t)m * lda : A + m;
-  }
+  for (int rb = 0; rb < R; ++rb)
+    arow[rb] = AK ? A + (int64_t)min(m0 + rb * 16 + lr, M - 1) * lda : A + min(m0 + 4 * lr, M - 4);
   int ncol[NT];
 #pragma unroll
   for (int cb = 0; cb < NT; ++cb) ncol[cb] = min(cb * 16 + lr, N - 1);
@@ -223,14 +227,8 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   auto load = [&](int st, int t) {
     const int kc = min(kbeg + t * 16 + 4 * lg, kend - 4);  // kend - kbeg >= 4, multiples of 4
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb) {
-      if (AK) {
-        a[st][rb] = *reinterpret_cast<const float4*>(arow[rb] + kc);
-      } else {
-        const float* p = arow[rb] + (int64_t)kc * lda;
-        a[st][rb] = make_float4(p[0], p[lda], p[2 * lda], p[3 * lda]);
-      }
-    }
+    for (int j = 0; j < R; ++j)
+      a[st][j] = *reinterpret_cast<const float4*>(AK ? arow[j] + kc : arow[0] + (int64_t)(kc + j) * lda);
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
@@ -251,7 +249,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int rb = 0; rb < R; ++rb) {
-        const float av = i == 0 ? a[st][rb].x : (i == 1 ? a[st][rb].y : (i == 2 ? a[st][rb].z : a[st][rb].w));
+        const float av = AK ? comp(a[st][rb], i) : comp(a[st][i], rb);
 #pragma unroll
         for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = mfma4(av, b[st][cb][i], acc[rb][cb]);
       }
@@ -260,7 +258,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   // following block, the loads spread evenly among its MFMAs: issued in a
   // burst between MFMA blocks, the same loads leave the matrix cores idle
   // about half the time
-  constexpr int NL = (AK ? R : 4 * R) + 4 * NT;  // loads per block
+  constexpr int NL = R + 4 * NT;                  // loads per block
   constexpr int NM = 4 * R * NT;                  // MFMAs per block
   auto region = [&](int ls, int lt, int cs) {
     load(ls, lt);
@@ -312,7 +310,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
       const int n = cb * 16 + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + rb * 16 + 4 * lg + q;
+        const int m = AK ? m0 + rb * 16 + 4 * lg + q : m0 + 16 * lg + 4 * q + rb;
         if (m < M && n < N) P[(int64_t)m * N + n] = acc[rb][cb][q];
       }
     }
