@@ -75,7 +75,10 @@ typedef struct {
   const int32_t* D;        /* host [n_inst]: bond dimension (all legs)             */
   const int32_t* chi;      /* host [n_inst]: environment dimension                 */
   int32_t prec;            /* ctm_prec of the bulk contractions                    */
-  int32_t svd_oversample;  /* extra subspace columns p (default 16)                */
+  int32_t svd_oversample;  /* extra subspace columns p (default 16); with
+                              svd_resid_tol = 0 and p >= 8, once chi_eff is known,
+                              p - 4 .. p of them, so that the width is a multiple
+                              of 16 where that range allows it                   */
   int32_t svd_max_iters;   /* subspace iterations per projector (default 30)       */
   double svd_resid_tol;    /* > 0: Rayleigh-Ritz every iteration, stop when every
                               kept residual < tol*sigma_1 (default 1e-13);

@@ -2055,7 +2055,11 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
         if (live[i]) ce = std::max(ce, hf[4 * i + 1]);
       Inst& J = x->inst[cls[0]];
       const int p = std::max(0, x->cfg.svd_oversample);
-      const int kn = std::max(1, std::min(J.k, ce + p));
+      int kw = ce + p;
+      // fixed-count mode: up to 4 of the p extra columns are dropped when
+      // that saves a partial 16-column tile of the half-system products
+      if (!(x->cfg.svd_resid_tol > 0) && p >= 8 && kw / 16 * 16 >= ce + p - 4) kw = kw / 16 * 16;
+      const int kn = std::max(1, std::min(J.k, kw));
       if (ce > 0 && kn != J.k_act) {
         for (int i : cls) x->inst[i].k_act = kn;
         eager_next = true;
