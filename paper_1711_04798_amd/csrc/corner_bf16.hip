@@ -174,7 +174,11 @@ __device__ __forceinline__ void wait_vm(int n) {
 }
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
 
-template <typename TO>
+// V4 (float output whose rows are contiguous in groups of 4: vc.r_ls = 1,
+// r_ext, r_hs, c_ls, c_hs and M multiples of 4, 16-byte aligned C): a lane's
+// four accumulator rows go out as one 16-byte store, so a transposed output
+// is written as densely as a row-major one
+template <typename TO, bool V4>
 __global__ void __launch_bounds__(256, 2)
 corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
                        int32_t tiles, int32_t per_xcd) {
@@ -269,6 +273,21 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     const int h = n / vc.c_ext, l = n - h * vc.c_ext;
     coff[j] = (int64_t)h * vc.c_hs + (int64_t)l * vc.c_ls;
   }
+  if constexpr (V4) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int m = m0 + wave * 64 + i * 16 + lr4;
+      if (m >= M) continue;
+      const int h = m / vc.r_ext, l = m - h * vc.r_ext;
+      const int64_t roff = (int64_t)h * vc.r_hs + l;
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (cok[j])
+          *reinterpret_cast<float4*>(C + roff + coff[j]) =
+              make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -311,12 +330,18 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
     return !(e && std::strcmp(e, "registers") == 0);
   }();
   const dim3 grid((unsigned)(8 * per_xcd));
+  bool v4 = tout == F32 && use_dma && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 && vc.c_ls % 4 == 0 &&
+            vc.c_hs % 4 == 0 && M % 4 == 0;
+  for (int i = 0; i < groups && v4; ++i) v4 = ((uintptr_t)g.C[i] & 15) == 0;
   if (tout == BF16)
-    hipLaunchKernelGGL(corner_bf16_dma_kernel<__bf16>, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K,
-                       ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, false>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+  else if (v4)
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, true>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
   else if (use_dma)
-    hipLaunchKernelGGL(corner_bf16_dma_kernel<float>, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K,
-                       ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, false>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
   else
     hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g,
                        (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);

@@ -946,9 +946,11 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // directly (~10x the energy error of bf16 enlarged corners, which only steer
   // the truncation).  In bf16 mode both are three-term products
   // hi.hi + hi.lo + lo.hi of bf16 splits (operand error ~2^-16) on the bf16
-  // kernel (the split of W1 also transposes it to [(g,c2)][(l,u)], through
-  // LDS); otherwise in the working type.
+  // kernel (W1 is stored split and transposed to [(g,c2)][(l,u)]); otherwise
+  // in the working type.
   const int64_t K4 = D2 * D2;
+  // W2 is written transposed (W2t, below) by its own product in bf16 mode
+  bool w2t_done = false;
   if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
     if (I0.rows[0].T3s && corner_bf16_supported(c * D2, D2 * c, 3 * c)) {
       // W1 as a three-term bf16 product too, split from the float64 masters:
@@ -971,6 +973,10 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
     } else {
       CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
     }
+    // W2[(g,c2), (dn,R)] stored as W2t[(g,dn)][(R,c2)] when the fp32 path
+    // below reads it that way: element (m, n) at (m / c) K4 c + m % c + n c
+    // (four consecutive c2 per 16-byte store)
+    const bool to_t = at == F32 && D2 >= 2 && I0.rows[0].W2t;
     G g3x;
     for (Inst* I : insts) {
       Roles ro{&x, I, k};
@@ -978,13 +984,15 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
         Row& R = I->rows[yp];
         // W1 as c matrices [(l,u)][c2] -> A3[(g,c2)][hi | hi | lo over (l,u)]
         HIPCHK(split3_transpose_bf16(s, (const float*)R.W1, c, K4, c, true, R.A3));
-        g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], R.W2);
+        g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], to_t ? R.W2t : R.W2);
       }
     }
+    const View vw2 = to_t ? View{c, 1, K4 * c, INT64_MAX / 4, c, 0} : rowmajor(K4);
     for (int j0 = 0; j0 < g3x.size(); j0 += MAXG) {
       int cnt = std::min(MAXG, g3x.size() - j0);
-      HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, rowmajor(K4), g3x.group(j0, cnt), cnt, F32));
+      HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, vw2, g3x.group(j0, cnt), cnt, F32));
     }
+    w2t_done = to_t;
   } else {
     CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
     CHK(gemm_run(s, at, at, c * c, K4, K4, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(K4), rowmajor(K4), g4));
@@ -993,8 +1001,9 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   //   B rows k = (g, dn): dn low (extent D2, stride D2), g high (stride chi*D2*D2)
   //   B cols n = (R, c2): c2 low (extent chi, stride D2*D2), R high (stride 1)
   if (at == F32 && D2 >= 2) {
-    // W2 read through that view touches one element per cache line: transpose
-    // it first (per g: [c2][(dn,R)] -> [(dn,R)][c2], i.e. W2t[(g,dn)][(R,c2)]).
+    // W2 read through that view touches one element per cache line: use it
+    // transposed (per g: [c2][(dn,R)] -> [(dn,R)][c2], i.e. W2t[(g,dn)][(R,c2)]),
+    // as stored by the bf16 product or transposed here.
     // The product is then tall and skinny in transposed form,
     //   T4'^T[(R,c2), c1] = sum_(g,dn) W2t[(g,dn),(R,c2)] P1[(g,dn), c1],
     // with chi output columns and a contraction of length n (the freed W2,
@@ -1003,7 +1012,7 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
     for (Inst* I : insts)
       for (int yp = 0; yp < ly; ++yp) {
         Row& R = I->rows[yp];
-        HIPCHK(transpose_batched(s, (const float*)R.W2, c, c, K4, (float*)R.W2t));
+        if (!w2t_done) HIPCHK(transpose_batched(s, (const float*)R.W2, c, c, K4, (float*)R.W2t));
         g5t.add(R.W2t, R.P1w, R.W2);
       }
     if (ts_gemm_supported(F32, F64, D2 * c, c, n, transposed(rowmajor(D2 * c)), rowmajor(c), rowmajor(c))) {
