@@ -780,11 +780,13 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     V[r] = R->V; Yb[r] = R->Yb; Qb[r] = R->Qb; Z[r] = R->Z; LV[r] = R->LV; UU[r] = R->UU;
     Ub[r] = R->Ub; Vpv[r] = R->Vp;
   }
-  // the start block (kept orthonormal columns and independent normals) is
-  // well conditioned: Cholesky-QR twice orthonormalises it to rounding level
-  CHK(orthonormalize(x, n, k, rows, V, 2));
   const int maxit = std::max(1, c.svd_max_iters);
   const bool adaptive = c.svd_resid_tol > 0;
+  // the start block (kept orthonormal columns and independent normals) is
+  // well conditioned: Cholesky-QR twice orthonormalises it to rounding level.
+  // The fixed-count iteration only takes its span (the first application of
+  // N is orthonormalised afresh), so one pass is enough there
+  CHK(orthonormalize(x, n, k, rows, V, adaptive ? 2 : 1));
   std::vector<SolveStatus> hst(P);
   auto copy_blocks = [&](std::vector<double*>& dst, const std::vector<double*>& src) -> ctm_status {
     Xfer cp;
@@ -863,13 +865,13 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   } else {
     // fixed count: plain subspace iterations V <- orth(N^T orth(N V)), then
     // one Rayleigh-Ritz step.  The inner basis only carries the span to
-    // N^T: two Cholesky-QR passes (the shifted one and one more) leave it well
-    // conditioned, which is all that step needs.  The residuals steer nothing
+    // N^T: the shifted Cholesky-QR pass alone leaves it conditioned well
+    // enough for that step.  The residuals steer nothing
     // here; they are formed on the last column step of a sweep (and of every
     // single move) as the accuracy record of the solver.
     for (int it = 0; it + 1 < maxit; ++it) {
       CHK(napply(x, n, k, rows, V, Yb, LV, false));
-      CHK(orthonormalize(x, n, k, rows, Yb, 2));
+      CHK(orthonormalize(x, n, k, rows, Yb, 1));
       CHK(napply(x, n, k, rows, Yb, Z, UU, true));
       CHK(copy_blocks(V, Z));
       CHK(orthonormalize(x, n, k, rows, V));
