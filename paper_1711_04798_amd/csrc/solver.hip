@@ -280,94 +280,88 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
 
 // ---------------------------------------------------------------------------
 // Y <- Y R^{-1} in place for n x k row-major Y and upper-triangular R (k <= 64):
-// one wave per 64 rows, one row per lane, right-looking substitution
+// right-looking substitution
 //   x_j = v_j / R_jj,  then v_l -= x_j R_jl for every l > j,
-// in blocks of 8 columns: a block is solved in registers, then each later
-// block of the row is loaded from LDS, updated (8 x 8 products with R read
-// as LDS broadcasts) and stored back.  The unrolled code is one block's worth,
-// the block loops run at run time (a fully unrolled 64-column form spends most
-// of its time fetching instructions).  Rows move between HBM and LDS
-// coalesced.
+// with four lanes per row: lane s of a quad holds the columns 4 t + s of its
+// row in registers, the owner of column j forms x_j and a DPP quad broadcast
+// hands it to the other three, which update their later columns (R read from
+// LDS, laid out so that a lane's entries of a row of R are contiguous).  The
+// dependent chain per column is a product, a broadcast and an FMA; 16 rows
+// per wave, 64 per work-group.  Columns past k are carried as identity (their
+// x stays 0 and never reaches a real column).
 // ---------------------------------------------------------------------------
-constexpr int TSB = 8;           // columns per block
-constexpr int TSL = CW + 1;      // LDS row stride of Y (odd: conflict-free row access by lane)
+// DPP move of a double across lanes (two 32-bit moves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
-__global__ void __launch_bounds__(64)
-trsm_rows_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
-  __shared__ double Rs[CW * CW];   // row-major, zero outside the upper triangle of the k x k block
-  __shared__ double rd[CW];        // 1 / R_jj (zero past k)
-  __shared__ double Vs[64 * TSL];  // the 64 rows of this wave
-  const int pb = blockIdx.y, lane = threadIdx.x;
-  const double* r = R.p[pb];
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int nrows = (int)min<int64_t>(64, n - row0);
-  double* y = Y.p[pb] + row0 * k;
-  // R and the rows: every load in flight before any store (indices clamped)
-  constexpr int PER = CW * CW / 64;
-  for (int t0 = 0; t0 < PER; t0 += 16) {
-    double rv[16];
+template <int KP>
+__global__ void __launch_bounds__(256)
+trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
+  constexpr int NT4 = KP / 4;
+  // Rq[(4 j + s) NT4 + t] = R[j][4 t + s] for j < 4 t + s < k, else 0
+  __shared__ __attribute__((aligned(16))) double Rq[KP * KP];
+  __shared__ double rdq[KP];  // 1 / R_jj (1 past k)
+  const int pb = blockIdx.y, tid = threadIdx.x;
+  const double* __restrict__ r = R.p[pb];
+  {
+    constexpr int PER = (KP * KP + 255) / 256;
+    double rv[PER];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = lane + 64 * (t0 + t), i = e / CW, j = e - i * CW;
-      rv[t] = r[min(i, k - 1) * k + min(j, k - 1)];
+    for (int q = 0; q < PER; ++q) {
+      const int e = min(tid + 256 * q, KP * KP - 1), j = e / KP, rem = e - j * KP;
+      const int l = 4 * (rem % NT4) + rem / NT4;
+      rv[q] = r[min(j, k - 1) * k + min(l, k - 1)];
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = lane + 64 * (t0 + t), i = e / CW, j = e - i * CW;
-      Rs[e] = (i < k && j < k && i <= j) ? rv[t] : 0.0;
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      if (e >= KP * KP) break;
+      const int j = e / KP, rem = e - j * KP;
+      const int l = 4 * (rem % NT4) + rem / NT4;
+      Rq[e] = (j < l && l < k) ? rv[q] : 0.0;
     }
-  }
-  const int tot = nrows * k;
-  for (int e0 = lane; e0 < 64 * CW; e0 += 64 * 16) {
-    double yv[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) yv[t] = y[min(e0 + 64 * t, tot - 1)];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = e0 + 64 * t, i = e / k, j = e - i * k;
-      if (e < tot) Vs[i * TSL + j] = yv[t];
+    if (tid < KP) {
+      const double d = r[min(tid, k - 1) * (k + 1)];
+      rdq[tid] = tid < k ? 1.0 / d : 1.0;
     }
   }
   __syncthreads();
-  if (lane < CW) rd[lane] = lane < k ? 1.0 / Rs[lane * CW + lane] : 0.0;
-  // columns k .. CW of the rows are never read into a result, but keep them finite
-  for (int e = lane; e < 64 * TSL; e += 64) {
-    const int j = e % TSL;
-    if (j >= k) Vs[e] = 0.0;
+  const int lane = tid & 63, s = lane & 3;
+  const int64_t row = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + (lane >> 2);
+  double* __restrict__ yr = Y.p[pb] + min<int64_t>(row, n - 1) * k;
+  double y[NT4];
+  {
+    double tv[NT4];
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) tv[t] = yr[min(4 * t + s, k - 1)];
+#pragma unroll
+    for (int t = 0; t < NT4; ++t) y[t] = 4 * t + s < k ? tv[t] : 0.0;
   }
-  __syncthreads();
-  double* vr = Vs + lane * TSL;
-  const int nb = (k + TSB - 1) / TSB;
-  for (int b = 0; b < nb; ++b) {
-    const int c0 = b * TSB;
-    double x[TSB];
+  const double* rq = Rq + s * NT4;
 #pragma unroll
-    for (int u = 0; u < TSB; ++u) x[u] = vr[c0 + u];
-#pragma unroll
-    for (int u = 0; u < TSB; ++u) {
-      x[u] *= rd[c0 + u];
-#pragma unroll
-      for (int w = u + 1; w < TSB; ++w) x[w] -= x[u] * Rs[(c0 + u) * CW + c0 + w];
+  for (int j = 0; j < KP; ++j) {
+    const int tj = j >> 2;
+    const double v = y[tj] * rdq[j];
+    double xj;
+    switch (j & 3) {
+      case 0: xj = dpp_f64<0x00>(v); break;
+      case 1: xj = dpp_f64<0x55>(v); break;
+      case 2: xj = dpp_f64<0xAA>(v); break;
+      default: xj = dpp_f64<0xFF>(v); break;
     }
+    if (s == (j & 3)) y[tj] = v;
 #pragma unroll
-    for (int u = 0; u < TSB; ++u) vr[c0 + u] = x[u];
-    for (int b2 = b + 1; b2 < nb; ++b2) {
-      const int c2 = b2 * TSB;
-      double w[TSB];
-#pragma unroll
-      for (int t = 0; t < TSB; ++t) w[t] = vr[c2 + t];
-#pragma unroll
-      for (int u = 0; u < TSB; ++u)
-#pragma unroll
-        for (int t = 0; t < TSB; ++t) w[t] -= x[u] * Rs[(c0 + u) * CW + c2 + t];
-#pragma unroll
-      for (int t = 0; t < TSB; ++t) vr[c2 + t] = w[t];
-    }
+    for (int t = tj; t < NT4; ++t) y[t] -= xj * rq[j * 4 * NT4 + t];
   }
-  __syncthreads();
-  for (int e = lane; e < tot; e += 64) {
-    const int i = e / k, j = e - i * k;
-    y[e] = Vs[i * TSL + j];
+  if (row < n) {
+#pragma unroll
+    for (int t = 0; t < NT4; ++t)
+      if (4 * t + s < k) yr[4 * t + s] = y[t];
   }
 }
 
@@ -379,7 +373,10 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)nprob);
-  hipLaunchKernelGGL(trsm_rows_kernel, grid, dim3(64), 0, s, n, k, Y, R);
+  if (k <= 16) hipLaunchKernelGGL(trsm_quad_kernel<16>, grid, dim3(256), 0, s, n, k, Y, R);
+  else if (k <= 32) hipLaunchKernelGGL(trsm_quad_kernel<32>, grid, dim3(256), 0, s, n, k, Y, R);
+  else if (k <= 48) hipLaunchKernelGGL(trsm_quad_kernel<48>, grid, dim3(256), 0, s, n, k, Y, R);
+  else hipLaunchKernelGGL(trsm_quad_kernel<64>, grid, dim3(256), 0, s, n, k, Y, R);
   return hipGetLastError();
 }
 
@@ -402,14 +399,6 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
 // ---------------------------------------------------------------------------
 constexpr int JMAX = 192;      // largest k
 constexpr int JR = JMAX / 16;  // rows per lane
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 // sum over the 16 lanes of a DPP row; every lane gets the same bits (each
 // step adds a value to its mirror image, and fp addition commutes)
