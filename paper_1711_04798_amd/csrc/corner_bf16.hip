@@ -174,14 +174,19 @@ __device__ __forceinline__ void wait_vm(int n) {
 }
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
 
-// V4 (float output whose rows are contiguous in groups of 4: vc.r_ls = 1,
-// r_ext, r_hs, c_ls, c_hs and M multiples of 4, 16-byte aligned C): a lane's
-// four accumulator rows go out as one 16-byte store, so a transposed output
-// is written as densely as a row-major one
-template <typename TO, bool V4>
+// Output modes.  OUT_V4 (float output whose rows are contiguous in groups of
+// 4: vc.r_ls = 1, r_ext, r_hs, c_ls, c_hs and M multiples of 4, 16-byte
+// aligned C): a lane's four accumulator rows go out as one 16-byte store, so a
+// transposed output is written as densely as a row-major one.  OUT_SPLIT
+// (bf16 output): each result x is stored as the A-side three-term split hi,
+// hi, lo (hi = bf16(x), lo = bf16(x - hi)) at offsets 0, sstride, 2 sstride
+// from its place in the view.
+constexpr int OUT_PLAIN = 0, OUT_V4 = 1, OUT_SPLIT = 2;
+
+template <typename TO, int MODE>
 __global__ void __launch_bounds__(256, 2)
 corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
-                       int32_t tiles, int32_t per_xcd) {
+                       int32_t tiles, int32_t per_xcd, int64_t sstride) {
   __shared__ __attribute__((aligned(16))) __bf16 smem[STAGES * STAGE_ELEMS];
   const int L = blockIdx.x;
   const int t = (L & 7) * per_xcd + (L >> 3);
@@ -273,7 +278,7 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     const int h = n / vc.c_ext, l = n - h * vc.c_ext;
     coff[j] = (int64_t)h * vc.c_hs + (int64_t)l * vc.c_ls;
   }
-  if constexpr (V4) {
+  if constexpr (MODE == OUT_V4) {
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int m = m0 + wave * 64 + i * 16 + lr4;
@@ -298,7 +303,18 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
       const int64_t roff = (int64_t)h * vc.r_hs + (int64_t)l * vc.r_ls;
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        if (cok[j]) C[roff + coff[j]] = (TO)acc[i][j][q];
+        if (cok[j]) {
+          if constexpr (MODE == OUT_SPLIT) {
+            const float x = acc[i][j][q];
+            const __bf16 hi = (__bf16)x;
+            TO* o = C + roff + coff[j];
+            o[0] = hi;
+            o[sstride] = hi;
+            o[2 * sstride] = (__bf16)(x - (float)hi);
+          } else {
+            C[roff + coff[j]] = (TO)acc[i][j][q];
+          }
+        }
     }
 }
 
@@ -309,10 +325,11 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K) {
 }
 
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups, int tout) {
-  if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || (tout != F32 && tout != BF16))
+                       int groups, int tout, int64_t split_stride) {
+  if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || (tout != F32 && tout != BF16) ||
+      split_stride < 0 || (split_stride > 0 && tout != BF16))
     return hipErrorInvalidValue;
-  const size_t sc = (size_t)(view_max(vc, M, N) + 1) * dtype_size(tout);
+  const size_t sc = (size_t)(view_max(vc, M, N) + 1 + 2 * split_stride) * dtype_size(tout);
   for (int i = 0; i < groups; ++i)
     if (!span_ok(g.A[i], (size_t)M * K * 2, "corner A") || !span_ok(g.B[i], (size_t)N * K * 2, "corner Bt") ||
         !span_ok(g.C[i], sc, "corner C") || ((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15))
@@ -333,15 +350,19 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   bool v4 = tout == F32 && use_dma && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 && vc.c_ls % 4 == 0 &&
             vc.c_hs % 4 == 0 && M % 4 == 0;
   for (int i = 0; i < groups && v4; ++i) v4 = ((uintptr_t)g.C[i] & 15) == 0;
-  if (tout == BF16)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, false>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+  const int64_t z = 0;
+  if (tout == BF16 && split_stride > 0)
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_SPLIT>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, split_stride);
+  else if (tout == BF16)
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_PLAIN>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
   else if (v4)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, true>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, OUT_V4>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
   else if (use_dma)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, false>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, OUT_PLAIN>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
   else
     hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g,
                        (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);

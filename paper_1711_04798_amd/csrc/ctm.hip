@@ -954,9 +954,15 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   // W2 is written transposed (W2t, below) by its own product in bf16 mode
   bool w2t_done = false;
   if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
+    bool a3_done = false;
     if (I0.rows[0].T3s && corner_bf16_supported(c * D2, D2 * c, 3 * c)) {
       // W1 as a three-term bf16 product too, split from the float64 masters:
-      //   A side T4[(g,l), p], B side (P2T as [p][(u,c2)])^T
+      //   A side T4[(g,l), p], B side (P2T as [p][(u,c2)])^T with its rows
+      //   taken in (c2, u) order.
+      // The product stores its result directly as the split operand of the
+      // next one, A3[(g,c2)][hi | hi | lo over (l,u)]: element ((g,l),(c2,u))
+      // at (g c + c2) 3 K4 + l D2 + u, the copies K4 apart; with u the fast
+      // output column, 16 lanes store 16 consecutive entries
       G g3b;
       for (Inst* I : insts) {
         Roles ro{&x, I, k};
@@ -964,14 +970,16 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
           Row& R = I->rows[yp];
           Row& Rp = I->rows[pmod(yp - 1, ly)];
           HIPCHK(split3_bf16(s, F64, ro.T(3, xp, yp), rowmajor(c), c * D2, c, true, R.T3s));
-          HIPCHK(split3_bf16(s, F64, Rp.P2T, transposed(rowmajor(D2 * c)), D2 * c, c, false, R.P3s));
-          g3b.add(R.T3s, R.P3s, R.W1);
+          HIPCHK(split3_bf16(s, F64, Rp.P2T, view2(D2, c, 1, BIG, D2 * c, 0), D2 * c, c, false, R.P3s));
+          g3b.add(R.T3s, R.P3s, R.A3);
         }
       }
+      const View va3 = view2(D2, D2, c * 3 * K4, D2, 1, 3 * K4);
       for (int j0 = 0; j0 < g3b.size(); j0 += MAXG) {
         int cnt = std::min(MAXG, g3b.size() - j0);
-        HIPCHK(corner_bf16(s, c * D2, D2 * c, 3 * c, rowmajor(D2 * c), g3b.group(j0, cnt), cnt, F32));
+        HIPCHK(corner_bf16(s, c * D2, D2 * c, 3 * c, va3, g3b.group(j0, cnt), cnt, BF16, K4));
       }
+      a3_done = true;
     } else {
       CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
     }
@@ -985,7 +993,7 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       for (int yp = 0; yp < ly; ++yp) {
         Row& R = I->rows[yp];
         // W1 as c matrices [(l,u)][c2] -> A3[(g,c2)][hi | hi | lo over (l,u)]
-        HIPCHK(split3_transpose_bf16(s, (const float*)R.W1, c, K4, c, true, R.A3));
+        if (!a3_done) HIPCHK(split3_transpose_bf16(s, (const float*)R.W1, c, K4, c, true, R.A3));
         g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], to_t ? R.W2t : R.W2);
       }
     }

@@ -101,9 +101,11 @@ hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, 
 hipError_t split3_transpose_bf16(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, bool a_side,
                                  void* out);
 // C (tout = F32 or BF16, through the view vc) = A Bt^T, A bf16 M x K and
-// Bt bf16 N x K row-major (16-byte aligned, K % 8 == 0), fp32 accumulation
+// Bt bf16 N x K row-major (16-byte aligned, K % 8 == 0), fp32 accumulation.
+// split_stride > 0 (tout = BF16): each result is stored as its A-side split
+// hi, hi, lo at offsets 0, split_stride, 2 split_stride from its view place.
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups, int tout = F32);
+                       int groups, int tout = F32, int64_t split_stride = 0);
 
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].
