@@ -822,16 +822,15 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P, true, true, &stj, 1e-2 * c.svd_cutoff));
     }
     {
-      G gu, gv, gl;
+      // three products of one shape per row, one grouped launch
+      G gq;
       for (size_t r = 0; r < P; ++r) {
         Row* R = rows[r].R;
-        gu.add(Qb[r], R->UR, Ub[r]);   // U  = Q U_R
-        gv.add(V[r], R->WR, Vpv[r]);   // V' = V W_R
-        gl.add(LV[r], R->WR, R->tmp);  // Lh^T V' = (Lh^T V) W_R
+        gq.add(Qb[r], R->UR, Ub[r]);   // U  = Q U_R
+        gq.add(V[r], R->WR, Vpv[r]);   // V' = V W_R
+        gq.add(LV[r], R->WR, R->tmp);  // Lh^T V' = (Lh^T V) W_R
       }
-      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gu));
-      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gv));
-      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gl));
+      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gq));
       Xfer cp;
       for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
       CHK(xfer_run(s, F64, F64, cp));
@@ -880,24 +879,26 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   }
   // projectors
   {
-    CPtrSet W{}, Sv{}, Id{};
-    PtrSet Wp{}, Up{};
-    StatSet st{};
+    // LV already holds Lh^T V' (rotated); Wp and Up = the diag-scaled
+    // selector, problems (row r, copy j) at j P + r, in as few launches as fit
+    for (size_t r0 = 0; r0 < 2 * P; r0 += MAXP) {
+      const size_t r1 = std::min(2 * P, r0 + MAXP);
+      CPtrSet Sv{}, Id{};
+      PtrSet Wu{};
+      StatSet st{};
+      for (size_t q = r0; q < r1; ++q) {
+        Row* R = rows[q % P].R;
+        Sv.p[q - r0] = R->S; Id.p[q - r0] = nullptr; Wu.p[q - r0] = q < P ? R->Wp : R->Up; st.p[q - r0] = R->st;
+      }
+      HIPCHK(scale_kept(s, k, chi, Id, Sv, Wu, st, (int)(r1 - r0)));
+    }
+    G gp;
     for (size_t r = 0; r < P; ++r) {
       Row* R = rows[r].R;
-      W.p[r] = R->WR; Sv.p[r] = R->S; Id.p[r] = nullptr; Wp.p[r] = R->Wp; Up.p[r] = R->Up; st.p[r] = R->st;
+      gp.add(LV[r], R->Wp, R->P1);
+      gp.add(UU[r], R->Up, R->P2T);
     }
-    // LV already holds Lh^T V' (rotated); Wp = diag-scaled selector
-    HIPCHK(scale_kept(s, k, chi, Id, Sv, Wp, st, (int)P));
-    HIPCHK(scale_kept(s, k, chi, Id, Sv, Up, st, (int)P));
-    G g1, g2;
-    for (size_t r = 0; r < P; ++r) {
-      Row* R = rows[r].R;
-      g1.add(LV[r], R->Wp, R->P1);
-      g2.add(UU[r], R->Up, R->P2T);
-    }
-    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g1));
-    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), g2));
+    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), gp));
     // keep the right vectors and status for the next solve on the same cut
     static_assert(sizeof(SolveStatus) % 8 == 0, "status copied as 8-byte words");
     Xfer cp;

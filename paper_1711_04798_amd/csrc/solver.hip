@@ -114,9 +114,11 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 }
 
 // s[b] -= sum_{l < n} x[l] * y[b * CWL + l], b = 0..3, n a multiple of 4;
-// eight columns of loads are issued before their products
+// eight columns of loads are issued before their products, which go to two
+// partial sums per b (even and odd columns) to halve the dependent chain
 __device__ __forceinline__ void dot4_lds(const double* x, const double* y, int n, double s[4]) {
   int l = 0;
+  double s2[4] = {0.0, 0.0, 0.0, 0.0};
   for (; l + 8 <= n; l += 8) {
     double xv[8], yv[4][8];
 #pragma unroll
@@ -128,8 +130,13 @@ __device__ __forceinline__ void dot4_lds(const double* x, const double* y, int n
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s[b] -= xv[u] * yv[b][u];
+      for (int u = 0; u < 8; u += 2) {
+        s[b] -= xv[u] * yv[b][u];
+        s2[b] -= xv[u + 1] * yv[b][u + 1];
+      }
   }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) s[b] += s2[b];
   if (l < n) {  // n - l == 4
     double xv[4], yv[4][4];
 #pragma unroll
@@ -189,7 +196,7 @@ chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st, i
         for (int m = 0; m < b; ++m) sb -= lb[m] * readlane_f64(lb[m], j);
         double d = readlane_f64(sb, j);
         if (!(d > floor_v)) { d = floor_v; fail = 1; }
-        const double r = sqrt(d), rinv = 1.0 / r;
+        const double rinv = rsqrt(d), r = d * rinv;
         lb[b] = lane == j ? r : (lane > j ? sb * rinv : 0.0);
         if (lane == 0) rpiv[j] = rinv;
       }
