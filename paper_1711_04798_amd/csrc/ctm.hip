@@ -782,6 +782,10 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   }
   const int maxit = std::max(1, c.svd_max_iters);
   const bool adaptive = c.svd_resid_tol > 0;
+  // full Cholesky-QR3 for the bases that enter Rayleigh-Ritz in float64; in
+  // the fixed-count (reduced-precision) mode the shifted pass and one more
+  // leave an orthogonality error well below that of the fp32 products
+  const int ortho_passes = adaptive ? 3 : 2;
   // the start block (kept orthonormal columns and independent normals) is
   // well conditioned: Cholesky-QR twice orthonormalises it to rounding level.
   // The fixed-count iteration only takes its span (the first application of
@@ -799,7 +803,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   auto rr_iteration = [&](bool want_resid) -> ctm_status {
     CHK(napply(x, n, k, rows, V, Yb, LV, false));          // Y = N V, LV = Lh^T V
     CHK(copy_blocks(Qb, Yb));
-    CHK(orthonormalize(x, n, k, rows, Qb));                // Q = orth(Y)
+    CHK(orthonormalize(x, n, k, rows, Qb, ortho_passes));  // Q = orth(Y)
     {
       G g;
       for (size_t r = 0; r < P; ++r) g.add(Qb[r], Yb[r], rows[r].R->Rm);
@@ -873,7 +877,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       CHK(orthonormalize(x, n, k, rows, Yb, 1));
       CHK(napply(x, n, k, rows, Yb, Z, UU, true));
       CHK(copy_blocks(V, Z));
-      CHK(orthonormalize(x, n, k, rows, V));
+      CHK(orthonormalize(x, n, k, rows, V, ortho_passes));
     }
     CHK(rr_iteration(x.resid_step));
   }
