@@ -522,7 +522,7 @@ __device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, doubl
           // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g)
           const double d = b - a;
           const double tn = (d >= 0 ? 2.0 * g : -2.0 * g) / (fabs(d) + sqrt(d * d + 4.0 * g * g));
-          const double c = 1.0 / sqrt(1.0 + tn * tn), sn = c * tn;
+          const double c = rsqrt(1.0 + tn * tn), sn = c * tn;
 #pragma unroll
           for (int t = 0; t < NRL; ++t) {
             cp[ql + 16 * t] = c * xp[t] - sn * xq[t];
