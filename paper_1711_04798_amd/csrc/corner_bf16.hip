@@ -157,7 +157,9 @@ corner_bf16_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int
 
 // Second form of the same contraction: the tiles go from HBM to LDS by 16-byte
 // direct-to-LDS loads (lane t of a wave fills bytes 16 t .. 16 t + 15 after the
-// wave-uniform base) into three LDS stages, issued two K steps ahead, with no
+// wave-uniform base) into three LDS stages, issued two K steps ahead (after
+// the current step's MFMAs, so that they do not compete with its fragment
+// reads; the stage they fill was released by the step's barrier), with no
 // register staging.  The chunk a lane loads is chosen so that its LDS slot
 // follows the lds_off swizzle.  Rows past the matrix edge load a clamped
 // (valid) row whose results are never stored; in a partial last K step the
@@ -255,7 +257,6 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     // next step (its fence drains every outstanding memory operation)
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (kt + 2 < nk) issue(kt + 2);
     v8bf av[TM], bv[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) bv[j] = *reinterpret_cast<const v8bf*>(&Bs[lds_off(j * 16 + lr, lc)]);
@@ -266,6 +267,7 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    if (kt + 2 < nk) issue(kt + 2);
   }
 
   const int lcol = lane & 15, lr4 = (lane >> 4) * 4;
