@@ -447,3 +447,106 @@ def test_fidelity_identities():
     assert abs(obs.fidelity(kap([A], [Ag]), kaa, kap([Ag], [Ag])) - 1) < 1e-9
     assert abs(kab - kba) < 1e-10 * abs(kab)
     assert obs.fidelity(kab, kaa, kbb) <= 1 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# the 2x2 checkerboard with A != B (multi-site cell, Sec. II C; Fig. 3(b))
+# ---------------------------------------------------------------------------
+def _orth(rng, n):
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return q
+
+
+def _checkerboard_gauge(A, O1, O2, O3, O4):
+    """Two tensors A' (sites with x + y even) and B' (odd) that describe the
+    same network as A on every site: each of the four bond types of the
+    checkerboard carries its own orthogonal gauge (O1 on A-right / B-left,
+    O2 on B-right / A-left, O3 on A-down / B-up, O4 on B-down / A-up), so
+    every bond contraction sum_r A[..r] B[r..] is unchanged (O O^T = 1)."""
+    Ap = np.einsum("suldr,uU,lL,dE,rR->sULER", A, O4, O2, O3, O1)
+    Bp = np.einsum("suldr,uU,lL,dE,rR->sULER", A, O3, O1, O4, O2)
+    return Ap, Bp
+
+
+@pytest.mark.parametrize("K", [0.3, 0.6])
+def test_onsager_checkerboard_distinct_tensors(K):
+    """Ising PEPS on the 2x2 checkerboard with A != B related by random
+    orthogonal bond gauges: the norm network is still the Ising model, so
+    kappa and <zz> on all four bonds of the cell must equal the exact
+    solution.  The two tensors differ, so the projectors of the two rows of
+    a column step differ and a wrong pairing of projector rows with edges
+    (or of sites with frames) changes the result: a planted pairing error in
+    the corner absorption gives kappa < 0 and <zz> off by 0.18 here."""
+    rng = np.random.default_rng(17 if K == 0.3 else 18)
+    Ap, Bp = _checkerboard_gauge(models.ising_peps(K), *[_orth(rng, 2) for _ in range(4)])
+    assert np.linalg.norm(Ap - Bp) > 1.0
+    cell = ctm.Cell(2, 2, [0, 1, 1, 0], [Ap, Bp])
+    env = ctm.init_trivial(cell, 32)
+    for _ in range(40):
+        ctm.sweep(cell, env)
+    assert abs(np.log(obs.kappa(cell, env)) - onsager_lnz_1d(K)) < 1e-9
+    zz = np.kron(models.SZ, models.SZ)
+    for vertical in (False, True):
+        for x, y in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            rho = obs.rdm(cell, env, x, y, vertical)
+            assert abs(np.trace(rho @ zz) - onsager_zz(K)) < 1e-9, (vertical, x, y)
+
+
+def test_product_state_checkerboard_positions():
+    """D = 1 product states phi_A, phi_B on the checkerboard: every bond
+    density matrix is the product of the two site states in the bond's order
+    (left/upper site first), which fixes where A and B sit."""
+    rng = np.random.default_rng(19)
+    pa, pb = rng.standard_normal(3), rng.standard_normal(3)
+    cell = ctm.Cell(2, 2, [0, 1, 1, 0], [models.product_peps(pa), models.product_peps(pb)])
+    env = ctm.init_trivial(cell, 3)
+    for _ in range(2):
+        ctm.sweep(cell, env)
+    na, nb = pa @ pa, pb @ pb
+    assert abs(obs.kappa(cell, env) - np.sqrt(na * nb)) < 1e-13 * np.sqrt(na * nb)
+    for vertical in (False, True):
+        for x, y in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            first, second = (pa, pb) if (x + y) % 2 == 0 else (pb, pa)
+            v = np.kron(first, second)
+            rho = obs.rdm(cell, env, x, y, vertical)
+            assert np.abs(rho - np.outer(v, v) / (v @ v)).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# diagonal start (learned warm start)
+# ---------------------------------------------------------------------------
+def _traced_boundary(A):
+    """a~[dn, r] = sum_(u, l) a[(u,u), (l,l), dn, r], from A directly: the
+    double layer with its up and left ket/bra pairs joined."""
+    d, D = A.shape[0], A.shape[1]
+    out = np.zeros((D * D, D * D))
+    for s in range(d):
+        for u in range(D):
+            for l in range(D):
+                for dn in range(D):
+                    for dn2 in range(D):
+                        for r in range(D):
+                            for r2 in range(D):
+                                out[dn * D + dn2, r * D + r2] += A[s, u, l, dn, r] * A[s, u, l, dn2, r2]
+    return out
+
+
+def test_init_diag_enlarged_corner_is_kronecker():
+    """With C = diag(s) / |s| and T[a, (u,u'), b] = delta_ab delta_uu' / sqrt(chi D)
+    the enlarged corner is exactly (C (x) a~) / (chi D), a~ the double layer
+    with its two boundary pairs traced: the edge carries no information
+    about the lattice beyond the corner's own spectrum."""
+    A = synth.cell_tensors(27, 2, 2, 1)[0]
+    cell = ctm.Cell(1, 1, [0], [A])
+    chi, D = 6, 2
+    rng = np.random.default_rng(27)
+    spec = {(0, 0): [np.sort(rng.uniform(0.1, 1.0, chi))[::-1] for _ in range(4)]}
+    env = ctm.init_diag(cell, chi, spec)
+    for i in range(4):
+        s = spec[(0, 0)][i]
+        assert np.abs(env.C[i][(0, 0)] - np.diag(s) / np.linalg.norm(s)).max() < 1e-15
+        assert abs(np.linalg.norm(env.T[i][(0, 0)]) - 1.0) < 1e-15
+    at = _traced_boundary(A)
+    Q = ctm.enlarged_corner(env.C[0][(0, 0)], env.T[0][(0, 0)], env.T[3][(0, 0)], cell.a(0, 0))
+    ref = np.kron(env.C[0][(0, 0)], at) / (chi * D)
+    assert np.abs(Q - ref).max() < 1e-15 * np.abs(ref).max() * 10
