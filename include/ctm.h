@@ -59,7 +59,9 @@ typedef enum {
 
 typedef enum { CTM_FP64 = 0, CTM_FP32 = 1, CTM_BF16 = 2 } ctm_prec;
 
-typedef enum { CTM_LEFT = 0, CTM_UP = 1, CTM_RIGHT = 2, CTM_DOWN = 3, CTM_SWEEP = 4 } ctm_dir;
+/* Direction of a move: the side of the cell whose environment absorbs the
+ * next column (row) of sites, as in the directional CTM of Sec. II C. */
+typedef enum { CTM_LEFT = 0, CTM_RIGHT = 1, CTM_UP = 2, CTM_DOWN = 3, CTM_SWEEP = 4 } ctm_dir;
 
 typedef enum { CTM_INIT_TRIVIAL = 0, CTM_INIT_DIAG = 1 } ctm_init_kind;
 
@@ -135,19 +137,28 @@ ctm_status ctm_init(const ctm_config* cfg, const double* const* A_dev,
 ctm_status ctm_move(ctm_ctx ctx, int32_t dir, int32_t count);
 
 /*
- * Sweeps until the largest l1 change of the normalised corner spectra
- * sigma(C)/sum sigma(C), over all corners and positions of an instance, is
- * below tol, or max_sweeps sweeps were done.  The change is read back to the
- * host every check_every sweeps; an instance stops sweeping at the first check
- * at which its change is below tol (the instances of a class that are still
- * sweeping move together).  sweeps_out, delta_out: host [n_inst] or NULL.
+ * Iterates the directional CTM of Sec. II C to its fixed point: sweeps until
+ * the largest l1 change of the normalised corner spectra sigma(C)/sum
+ * sigma(C), over all corners and positions of an instance, is below tol, or
+ * max_sweeps sweeps were done (the corner spectra as the convergence
+ * measure of the environment are this library's reading; the paper gives
+ * none).  The change is read back to the host every check_every sweeps; an
+ * instance stops sweeping at the first check at which its change is below
+ * tol (the instances of a class that are still sweeping move together).
+ * At each check the projector subspace width follows the kept count
+ * (chi_eff + svd_oversample); a check at which the kept count fills the
+ * width does not end the run (the width grows first).  The contractions run
+ * at the live extent min(chi, width) rounded up to 8: every index beyond it
+ * is an exact zero.  sweeps_out, delta_out: host [n_inst] or NULL.
  * Returns CTM_E_NOCONV (state valid) if some instance did not converge.
  */
 ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,
                         int32_t check_every, int32_t* sweeps_out, double* delta_out);
 
-/* Normalised corner spectra of instance `inst`, float64
- * [Lx*Ly][4][chi] (position y*Lx+x, corner C1..C4), zero-padded.  Syncs. */
+/* Singular values of the chi x chi corner matrices C1..C4 of Sec. II C
+ * (caption of Fig. 3(b)) of instance `inst`, each divided by their sum,
+ * float64 [Lx*Ly][4][chi] (position y*Lx+x, corner C1..C4, descending),
+ * zero-padded.  Syncs. */
 ctm_status ctm_spectra(ctm_ctx ctx, int32_t inst, double* out_host);
 
 /* Norm per site kappa = (Z11 Z00 / (Z10 Z01))^(1/(Lx Ly)) of instance `inst`:
@@ -157,8 +168,10 @@ ctm_status ctm_norm(ctm_ctx ctx, int32_t inst, double* kappa_out);
 
 /*
  * Two-site reduced density matrix of the bond from site (x, y) to its right
- * (vertical = 0) or lower (vertical = 1) neighbour, divided by its trace,
- * not symmetrised.  rho_host: float64 [(s1,s2)][(s1',s2')] (d^2 x d^2, row =
+ * (vertical = 0) or lower (vertical = 1) neighbour: the two sites with open
+ * physical indices in their environment (Sec. II C: local expectation values
+ * and nearest-neighbour correlators from the environment; Sec. VI), divided
+ * by its trace, not symmetrised.  rho_host: float64 [(s1,s2)][(s1',s2')] (d^2 x d^2, row =
  * ket indices, column = bra indices, first site = left/upper).  herm_defect
  * (may be NULL): ||rho - rho^T||_F / ||rho||_F.  Syncs.
  */
@@ -180,18 +193,38 @@ ctm_status ctm_expect(ctm_ctx ctx, int32_t inst, int32_t x, int32_t y,
  *   d = |kappa_AB| / sqrt(kappa_AA kappa_BB), all per site.
  * cfg must describe both tensor sets (n_inst must be 1).  d_out, ln_d_out:
  * host scalars.  sweeps_out (may be NULL): host [3] sweeps of the three runs.
+ * If a run does not converge within max_sweeps, d_out, ln_d_out and
+ * sweeps_out are still filled (from the last state) and CTM_E_NOCONV is
+ * returned.
  */
 ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev,
                         const double* const* B_dev, void* ws_dev, size_t ws_bytes,
                         void* stream, double tol, int32_t max_sweeps,
                         double* d_out, double* ln_d_out, int32_t* sweeps_out);
 
-/* Checkpoint: all corners and edges of instance `inst` as float64, in the
- * order C1..C4 then T1..T4, each for positions y*Lx+x; `bytes` must equal
- * ctm_env_bytes().  Import restores them exactly.  Both sync. */
+/* The environment of Sec. II C (corners C1..C4 chi x chi, edges T1..T4
+ * chi x D^2 x chi) of instance `inst` as float64, in the order C1..C4 then
+ * T1..T4, each for positions y*Lx+x, legs clockwise around the site,
+ * zero-padded to chi; `bytes` must equal ctm_env_bytes().  Import replaces
+ * the environment (e.g. with one computed elsewhere); it resets the
+ * projector subspaces (cold start of the next solves, full subspace width
+ * and extent).  Both sync. */
 size_t ctm_env_bytes(ctm_ctx ctx, int32_t inst);
 ctm_status ctm_env_export(ctm_ctx ctx, int32_t inst, void* host_buf, size_t bytes);
 ctm_status ctm_env_import(ctm_ctx ctx, int32_t inst, const void* host_buf, size_t bytes);
+
+/* Checkpoint of everything a later sweep of instance `inst` depends on: the
+ * environment at its live extent, the previous corner spectra, the kept
+ * projector subspaces of every cut with their solver statuses (the warm
+ * starts of the next solves), the subspace width and the move cursors.
+ * Loading it into a context created with the same configuration and tensors
+ * makes the following moves and sweeps bitwise equal to those of the saved
+ * context.  The layout is private to this library (a versioned header,
+ * then device images); `bytes` must equal ctm_checkpoint_bytes().  Both sync.
+ * Load returns CTM_E_INVALID for a checkpoint of another configuration. */
+size_t ctm_checkpoint_bytes(ctm_ctx ctx, int32_t inst);
+ctm_status ctm_checkpoint_save(ctm_ctx ctx, int32_t inst, void* host_buf, size_t bytes);
+ctm_status ctm_checkpoint_load(ctm_ctx ctx, int32_t inst, const void* host_buf, size_t bytes);
 
 /*
  * Kernel-time accounting, enabled (and reset) by ctm_set_timing: enable = 1
@@ -200,12 +233,15 @@ ctm_status ctm_env_import(ctm_ctx ctx, int32_t inst, const void* host_buf, size_
  * only the latter (fewer events in the stream); 0 switches it off.  The events
  * are read, and pending ones dropped, by ctm_get_timing / ctm_set_timing, which
  * then wait for them; nothing waits in between.
- * ctm_get_timing fills v[8]:
+ * ctm_get_timing fills v[10]:
  *   v[0] seconds in enlarged corners, v[1] in the projector solver,
  *   v[2] in absorption (zero with enable = 2), v[3] seconds inside the
  *   double-layer contraction launches of the enlarged corners, v[4] number of
- *   those launches, v[5] their algorithmic flop (2 chi^2 D^8 per corner),
- *   v[6] corner-chain launches, v[7] column steps timed.
+ *   those launches, v[5] their algorithmic flop at the live extent
+ *   (2 chi_live^2 D^8 per corner), v[6] corner-chain launches, v[7] column
+ *   steps timed, v[8] the same flop counted at the configured chi (nominal:
+ *   the zero-padded work the live extent skips), v[9] the live extent of the
+ *   last timed column step.
  */
 ctm_status ctm_set_timing(ctm_ctx ctx, int32_t enable);
 ctm_status ctm_get_timing(ctm_ctx ctx, double* v);

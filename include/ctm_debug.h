@@ -54,17 +54,29 @@ ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, doubl
                          double* work, void* stream);
 
 /*
- * Copies an internal buffer of the last column step of instance 0 to the host:
+ * Copies an internal buffer of the last column step of instance 0 to the host
+ * (n and chi at the live extent; equal to chi D^2 and chi while the subspace
+ * has its full width):
  *   what = 0: enlarged corner Q_(q+1) of row r, float64 n x n row-major,
  *             index = 4 r + q (float32 when the context's precision is not fp64);
  *   what = 1: projector P1 of row r (float64 n x chi), index = r;
  *   what = 2: projector P2^T of row r (float64 n x chi), index = r;
  *   what = 3: solver status of row r {chi_eff, converged, iters, chol_fail as
  *             int32, sigma0, max_resid as float64, Jacobi sweeps of the last
- *             Rayleigh-Ritz step, subspace columns as int32} (40 bytes), index = r.
+ *             Rayleigh-Ritz step, subspace columns, subspace rows, padding as
+ *             int32} (48 bytes), index = r.
  * `bytes` must equal the buffer size.  Syncs.
  */
 ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_buf, size_t bytes);
+
+/*
+ * Sets the projector subspace width of every instance to `width` (clamped
+ * to 1 .. chi + oversample) and re-lays the environment out at the live
+ * extent that follows, as the convergence loop does when the kept count
+ * changes; *live_out (may be NULL) receives the live extent of instance 0.
+ * Lets host-only runs (CTM_DRY_RUN) walk the narrowed-extent code paths.
+ */
+ctm_status ctm_debug_set_width(ctm_ctx ctx, int32_t width, int32_t* live_out);
 
 #ifdef __cplusplus
 }

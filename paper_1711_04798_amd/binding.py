@@ -15,13 +15,14 @@ LIB_PATH = os.path.join(_HERE, "libctm.so")
 CTM_OK, CTM_E_INVALID, CTM_E_NONFINITE, CTM_E_NOMEM, CTM_E_NOCONV, CTM_E_SOLVER, CTM_E_HIP, CTM_E_STATE = range(8)
 STATUS_NAMES = ["OK", "INVALID", "NONFINITE", "NOMEM", "NOCONV", "SOLVER", "HIP", "STATE"]
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
-DIRS = {"L": 0, "U": 1, "R": 2, "D": 3, "SWEEP": 4}
+DIRS = {"L": 0, "R": 1, "U": 2, "D": 3, "SWEEP": 4}
 INIT = {"trivial": 0, "diag": 1}
 
 EXPORTS = [
     "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
     "ctm_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
-    "ctm_env_export", "ctm_env_import", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
+    "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
+    "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
     "ctm_last_error", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
@@ -83,6 +84,10 @@ def load(path=LIB_PATH):
     lib.ctm_env_bytes.restype = SZ
     lib.ctm_env_export.argtypes = [VP, I32, VP, SZ]
     lib.ctm_env_import.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_checkpoint_bytes.argtypes = [VP, I32]
+    lib.ctm_checkpoint_bytes.restype = SZ
+    lib.ctm_checkpoint_save.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_checkpoint_load.argtypes = [VP, I32, VP, SZ]
     lib.ctm_set_timing.argtypes = [VP, I32]
     lib.ctm_get_timing.argtypes = [VP, P(F64)]
     lib.ctm_destroy.argtypes = [VP]
@@ -104,7 +109,8 @@ def load(path=LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge", "ctm_spectra",
                  "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_export",
-                 "ctm_env_import", "ctm_set_timing", "ctm_get_timing"):
+                 "ctm_env_import", "ctm_checkpoint_save", "ctm_checkpoint_load", "ctm_set_timing",
+                 "ctm_get_timing"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -259,16 +265,27 @@ class CTM:
         buf = np.ascontiguousarray(buf, dtype=np.float64)
         _check(load().ctm_env_import(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
 
+    def save_checkpoint(self, inst=0):
+        """Everything the next sweeps depend on (ctm_checkpoint_save), as bytes."""
+        n = load().ctm_checkpoint_bytes(self.ctx, inst)
+        buf = np.zeros(n, dtype=np.uint8)
+        _check(load().ctm_checkpoint_save(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), n))
+        return buf
+
+    def load_checkpoint(self, buf, inst=0):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(load().ctm_checkpoint_load(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
+
     def set_timing(self, mode=1):
         """1: phases and corner-kernel launches, 2: corner-kernel launches
         only, 0 / False: off (see ctm_set_timing)."""
         _check(load().ctm_set_timing(self.ctx, int(mode)))
 
     def timing(self):
-        v = (ctypes.c_double * 8)()
+        v = (ctypes.c_double * 10)()
         _check(load().ctm_get_timing(self.ctx, v))
         keys = ["corner_s", "solver_s", "absorb_s", "stage3_s", "stage3_launches", "stage3_flop",
-                "corner_launches", "moves"]
+                "corner_launches", "moves", "stage3_flop_nominal", "live_chi"]
         return dict(zip(keys, list(v)))
 
     def close(self):
@@ -286,7 +303,8 @@ class CTM:
 
 def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=1e-10,
              max_sweeps=200, device="cuda:0", **solver):
-    """Fidelity per site d and ln d between the states of two tensor sets."""
+    """Fidelity per site between the states of two tensor sets: (d, ln d,
+    sweeps of the three CTM runs, whether all three converged)."""
     import torch
     lib = load()
     if pattern is None:
@@ -302,13 +320,13 @@ def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=
     bt, bp = _dev_tensors(torch, B_list, dev)
     dv, lv = ctypes.c_double(), ctypes.c_double()
     sw = (ctypes.c_int32 * 3)()
-    _check(lib.ctm_fidelity(ctypes.byref(cfg), ctypes.cast(ap, ctypes.POINTER(ctypes.c_void_p)),
-                            ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)),
-                            ctypes.c_void_p(ws.data_ptr() + off), nbytes, _stream(torch, dev), tol,
-                            max_sweeps, ctypes.byref(dv), ctypes.byref(lv), sw))
+    st = _check(lib.ctm_fidelity(ctypes.byref(cfg), ctypes.cast(ap, ctypes.POINTER(ctypes.c_void_p)),
+                                 ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)),
+                                 ctypes.c_void_p(ws.data_ptr() + off), nbytes, _stream(torch, dev), tol,
+                                 max_sweeps, ctypes.byref(dv), ctypes.byref(lv), sw), allow=(CTM_E_NOCONV,))
     torch.cuda.synchronize(dev)
     del at, bt, ws
-    return dv.value, lv.value, list(sw)
+    return dv.value, lv.value, list(sw), st == CTM_OK
 
 
 class MLP:

@@ -147,7 +147,15 @@ struct Row {  // scratch for one row of a column step
 };
 
 struct Inst {
+  // chi_cap: the environment dimension chi of the configuration (buffers are
+  // sized for it); chi: the live extent, the number of leading indices of
+  // every corner / edge leg that can be nonzero.  Every kept projector column
+  // comes from a subspace of k_act columns, so beyond min(chi_cap, k_act) all
+  // entries of C and T are exact zeros; the tensors are stored compactly at
+  // the live extent and every contraction runs at it.  n = chi D^2 is the
+  // live cut dimension, n_cap = chi_cap D^2.
   int d = 0, D = 0, D2 = 0, chi = 0, n = 0, k = 0;
+  int chi_cap = 0, n_cap = 0;
   int k_act = 0;                 // subspace columns in use (<= k, follows chi_eff)
   double* A[MAXT] = {};
   double* B[MAXT] = {};
@@ -164,7 +172,7 @@ struct Inst {
   bool staleC[4][MAXPOS] = {};
   bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
-  double* spec_old = nullptr;  // [pos][4][chi]
+  double* spec_old = nullptr;  // [pos][4][chi_cap]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
   int* flag = nullptr;         // device: non-finite flag
@@ -184,6 +192,7 @@ struct Obs {  // float64 scratch of the observables
   double *t0 = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   double *rho = nullptr, *red = nullptr, *vals = nullptr;
   size_t big = 0;
+  bool rows_ok = false;  // t0..t3 are large enough for the row-transfer norm
 };
 
 }  // namespace
@@ -213,7 +222,8 @@ struct ctm_ctx_s {
   double* spec_tmp_J = nullptr;
   size_t ws_need = 0;
   bool timing = false;
-  double t_corner = 0, t_solver = 0, t_absorb = 0, t_stage3 = 0, stage3_flop = 0;
+  double t_corner = 0, t_solver = 0, t_absorb = 0, t_stage3 = 0, stage3_flop = 0, stage3_flop_nom = 0;
+  int live_chi = 0;
   int64_t corner_launches = 0, stage3_launches = 0, moves = 0;
   // timing (ctm_set_timing): one record of four phase events per timed column
   // step and one event pair per timed stage-3 launch, recorded without waiting
@@ -244,7 +254,7 @@ int subspace_dim(const ctm_config& c, int chi, int n) {
 
 void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   const size_t ws = dtype_size(x.wt), qs = dtype_size(x.qt);
-  const size_t n = I.n, k = I.k, chi = I.chi, D2 = I.D2;
+  const size_t n = I.n_cap, k = I.k, chi = I.chi_cap, D2 = I.D2;
   const size_t nk = n * k, c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
   for (int q = 0; q < 4; ++q) {
     R.Q[q] = ar.take_bytes(n * n * qs);
@@ -282,9 +292,9 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   size_t mx_n = 0, mx_k = 0, mx_chi = 0, mx_D2 = 0, mx_d = 0;
   for (int i = 0; i < x.ninst; ++i) {
     Inst& I = x.inst[i];
-    mx_n = std::max(mx_n, (size_t)I.n);
+    mx_n = std::max(mx_n, (size_t)I.n_cap);
     mx_k = std::max(mx_k, (size_t)I.k);
-    mx_chi = std::max(mx_chi, (size_t)I.chi);
+    mx_chi = std::max(mx_chi, (size_t)I.chi_cap);
     mx_D2 = std::max(mx_D2, (size_t)I.D2);
     mx_d = std::max(mx_d, (size_t)I.d);
   }
@@ -295,7 +305,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     Inst& I = x.inst[i];
     const size_t t5 = (size_t)I.d * I.D2 * I.D2;
     const size_t a8 = (size_t)I.D2 * I.D2 * I.D2 * I.D2;
-    const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+    const size_t c2 = (size_t)I.chi_cap * I.chi_cap, t3 = c2 * I.D2;
     for (int t = 0; t < x.ntens; ++t) {
       I.A[t] = ar.take<double>(t5);
       I.B[t] = ar.take<double>(t5);
@@ -320,14 +330,14 @@ void plan(ctm_ctx_s& x, Arena& ar) {
           I.TwR[c][p] = ar.take_bytes(t3 * dtype_size(BF16));
         }
       }
-    I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi);
-    I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi);
+    I.spec_old = ar.take<double>((size_t)npos * 4 * I.chi_cap);
+    I.spec_new = ar.take<double>((size_t)npos * 4 * I.chi_cap);
     I.delta = x.delta_all ? x.delta_all + i : nullptr;
     I.flag = x.flag_all ? x.flag_all + 4 * i : nullptr;
     I.skeep_all = ar.take<SolveStatus>((size_t)4 * npos);
     for (int c = 0; c < 4; ++c)
       for (int p = 0; p < npos; ++p) {
-        I.Vkeep[c][p] = ar.take<double>((size_t)I.n * I.k);
+        I.Vkeep[c][p] = ar.take<double>((size_t)I.n_cap * I.k);
         I.skeep[c][p] = I.skeep_all ? I.skeep_all + c * npos + p : nullptr;
       }
     // row scratch of this instance (all instances of a class step together)
@@ -373,6 +383,13 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   O.Rall = ar.take<double>(d * d * t3);
   O.Rp = ar.take<double>(d * d * t3);
   size_t big = std::max(y4, c2 * (size_t)std::pow((double)D2, (double)std::max(x.Lx, x.Ly)));
+  // the norm per site of cells other than 1x1 and 2x2 goes through row
+  // transfer (chi^2 D^(2 Lx + 2) entries), planned when that stays below
+  // 2^28 doubles per buffer
+  const bool square12 = (x.Lx == 1 && x.Ly == 1) || (x.Lx == 2 && x.Ly == 2);
+  const double rows_need = (double)c2 * std::pow((double)D2, (double)x.Lx + 1);
+  O.rows_ok = !square12 && rows_need <= (double)(1ull << 28);
+  if (O.rows_ok) big = std::max(big, (size_t)rows_need);
   O.big = big;
   O.t0 = ar.take<double>(big); O.t1 = ar.take<double>(big);
   O.t2 = ar.take<double>(big); O.t3 = ar.take<double>(big);
@@ -384,6 +401,13 @@ void plan(ctm_ctx_s& x, Arena& ar) {
 // ---------------------------------------------------------------------------
 // frames
 // ---------------------------------------------------------------------------
+// Number k of counter-clockwise quarter turns after which a move in direction
+// `dir` (ctm_dir) is a left move: left 0, up 1, right 2, down 3.
+int frame_of_dir(int dir) {
+  static const int k[4] = {0, 2, 1, 3};  // CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN
+  return k[dir & 3];
+}
+
 void frame_dims(int k, int Lx, int Ly, int& lx, int& ly) {
   if (k % 2 == 0) { lx = Lx; ly = Ly; } else { lx = Ly; ly = Lx; }
 }
@@ -771,7 +795,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     // the random columns of the start block depend only on the cut group
     // (direction, column, launch), not on how often it was solved, so a
     // captured sweep replays exactly what the eager sweep computes
-    HIPCHK(warm_start(s, n, k, I.k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (key + 1), (int)P));
+    HIPCHK(warm_start(s, n, I.n_cap, k, I.k, V0, Vp, pr, c.seed + 0x9E3779B97F4A7C15ull * (key + 1), (int)P));
     HIPCHK(reset_status(s, st, (int)P));
   }
   std::vector<double*> V(P), Yb(P), Qb(P), Z(P), LV(P), UU(P), Ub(P), Vpv(P);
@@ -1185,7 +1209,10 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
     tm.used = &x.sused;
     // algorithmic work of the (l,u)-contraction with the double layer:
     // 2 chi^2 D^8 flop per corner
-    x.stage3_flop += 2.0 * (double)I0.chi * I0.chi * (double)I0.D2 * I0.D2 * I0.D2 * I0.D2 * (double)jobs.size();
+    const double d8 = (double)I0.D2 * I0.D2 * I0.D2 * I0.D2;
+    x.stage3_flop += 2.0 * (double)I0.chi * I0.chi * d8 * (double)jobs.size();
+    x.stage3_flop_nom += 2.0 * (double)I0.chi_cap * I0.chi_cap * d8 * (double)jobs.size();
+    x.live_chi = I0.chi;
   }
   CHK(corner_chain(s, x.wt, x.qt, I0.chi, I0.D2, jobs, x.timing ? &tm : nullptr, x.prec == CTM_BF16));
   x.corner_launches += 3 * ((jobs.size() + MAXG - 1) / MAXG);
@@ -1246,15 +1273,18 @@ struct SpecSet {
   const SolveStatus* st[MAXP];  // the instance's kept-solve statuses, contiguous
 };
 
-// one block per instance; spec_new holds its ncorner spectra (descending, length chi)
-__global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int nstat, int first, int commit) {
+// one block per instance; spec_new holds its ncorner spectra (descending,
+// stride chi); entries from `live` on are the zero singular values of the
+// zero-padded corner and are written as such
+__global__ void spectra_delta_kernel(SpecSet ss, int chi, int live, int ncorner, int nstat, int first,
+                                     int commit) {
   __shared__ double red[256];
   double* __restrict__ spec_new = ss.spec_new[blockIdx.x];
   double* __restrict__ spec_old = ss.spec_old[blockIdx.x];
   double dmax = 0.0;
   for (int c = 0; c < ncorner; ++c) {
     double tot = 0.0;
-    for (int i = threadIdx.x; i < chi; i += blockDim.x) tot += spec_new[c * chi + i];
+    for (int i = threadIdx.x; i < live; i += blockDim.x) tot += spec_new[c * chi + i];
     red[threadIdx.x] = tot;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -1265,7 +1295,7 @@ __global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int nstat
     __syncthreads();
     double d = 0.0;
     for (int i = threadIdx.x; i < chi; i += blockDim.x) {
-      double v = tot > 0 ? spec_new[c * chi + i] / tot : spec_new[c * chi + i];
+      double v = i >= live ? 0.0 : (tot > 0 ? spec_new[c * chi + i] / tot : spec_new[c * chi + i]);
       if (!isfinite(v)) *ss.flag[blockIdx.x] = 1;
       spec_new[c * chi + i] = v;
       d += fabs(v - spec_old[c * chi + i]);
@@ -1295,11 +1325,12 @@ __global__ void spectra_delta_kernel(SpecSet ss, int chi, int ncorner, int nstat
 // to unit sum; Delta = largest l1 change against the previous spectra
 ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool first, bool commit) {
   hipStream_t s = x.stream;
-  const int npos = x.Lx * x.Ly, nc = 4 * npos, chi = insts[0]->chi;
+  // corners are live-extent matrices; spectra are stored at the full chi
+  const int npos = x.Lx * x.Ly, nc = 4 * npos, chi = insts[0]->chi, cs = insts[0]->chi_cap;
   const size_t c2 = (size_t)chi * chi;
   std::vector<std::pair<const double*, double*>> probs;  // (corner, output spectrum)
   for (Inst* I : insts)
-    for (int c = 0; c < nc; ++c) probs.push_back({I->C[c % 4][c / 4], I->spec_new + (size_t)c * chi});
+    for (int c = 0; c < nc; ++c) probs.push_back({I->C[c % 4][c / 4], I->spec_new + (size_t)c * cs});
   for (size_t c0 = 0; c0 < probs.size(); c0 += MAXP) {
     int cnt = (int)std::min<size_t>(MAXP, probs.size() - c0);
     CPtrSet M{};
@@ -1319,7 +1350,7 @@ ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool fi
     SpecSet ss{};
     for (int j = 0; j < cnt; ++j) {
       Inst* I = insts[i0 + j];
-      HIPCHK(spans({{I->spec_new, (size_t)nc * chi * 8}, {I->spec_old, (size_t)nc * chi * 8}, {I->delta, 8},
+      HIPCHK(spans({{I->spec_new, (size_t)nc * cs * 8}, {I->spec_old, (size_t)nc * cs * 8}, {I->delta, 8},
                     {I->flag, 8}, {I->skeep_all, (size_t)nc * sizeof(SolveStatus)}}, "spectra"));
       ss.spec_new[j] = I->spec_new;
       ss.spec_old[j] = I->spec_old;
@@ -1328,7 +1359,7 @@ ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool fi
       ss.st[j] = I->skeep_all;
     }
     if (!dry_run())
-      hipLaunchKernelGGL(spectra_delta_kernel, dim3(cnt), dim3(256), 0, s, ss, chi, nc, nc, first ? 1 : 0,
+      hipLaunchKernelGGL(spectra_delta_kernel, dim3(cnt), dim3(256), 0, s, ss, cs, chi, nc, nc, first ? 1 : 0,
                          commit ? 1 : 0);
     HIPCHK(last_err());
   }
@@ -1408,9 +1439,9 @@ ctm_status build_ctx(const ctm_config* cfg, ctm_ctx_s& x) {
     I.d = x.dv[i];
     I.D = x.Dv[i];
     I.D2 = I.D * I.D;
-    I.chi = x.chiv[i];
-    I.n = I.chi * I.D2;
-    I.k = subspace_dim(x.cfg, I.chi, I.n);
+    I.chi_cap = I.chi = x.chiv[i];
+    I.n_cap = I.n = I.chi * I.D2;
+    I.k = subspace_dim(x.cfg, I.chi_cap, I.n_cap);
     I.k_act = I.k;
   }
   // classes of instances with equal (d, D, chi), in order of first appearance
@@ -1419,7 +1450,7 @@ ctm_status build_ctx(const ctm_config* cfg, ctm_ctx_s& x) {
     bool placed = false;
     for (auto& cls : x.classes) {
       const Inst& J = x.inst[cls[0]];
-      if (J.d == x.inst[i].d && J.D == x.inst[i].D && J.chi == x.inst[i].chi) {
+      if (J.d == x.inst[i].d && J.D == x.inst[i].D && J.chi_cap == x.inst[i].chi_cap) {
         cls.push_back(i);
         placed = true;
         break;
@@ -1438,6 +1469,10 @@ ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double*
   const int npos = x.Lx * x.Ly;
   int chimax = 0;
   for (int v : x.chiv) chimax = std::max(chimax, v);
+  // a fresh environment is stored at the full extent
+  I.chi = I.chi_cap;
+  I.n = I.n_cap;
+  I.k_act = I.k;
   double* dspec = nullptr;
   std::vector<double> hs;
   if (init == CTM_INIT_DIAG) {
@@ -1476,14 +1511,98 @@ ctm_status init_env(ctm_ctx_s& x, Inst& I, int inst_idx, int init, const double*
   HIPCHK(dmemset(I.spec_old, 0, (size_t)npos * 4 * I.chi * 8, s));
   HIPCHK(dmemset(I.flag, 0, sizeof(int) * 4, s));
   HIPCHK(dmemset(I.skeep_all, 0, sizeof(SolveStatus) * 4 * npos, s));
+  for (Row& R : I.rows) HIPCHK(dmemset(R.st, 0, sizeof(SolveStatus), s));
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < npos; ++p) I.staleC[c][p] = I.staleT[c][p] = true;
-  I.k_act = I.k;
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < npos; ++p) I.has_keep[c][p] = false;
   for (int c = 0; c < 4; ++c) I.cursor[c] = 0;
   std::vector<Inst*> one{&I};
   CHK(corner_spectra(x, one, true, true));
+  return CTM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// live extent
+// ---------------------------------------------------------------------------
+// Every kept projector column comes from a subspace of k_act columns, so at
+// most min(chi_cap, k_act) leading indices of a corner or edge leg are
+// nonzero; rounded up to a multiple of 8 (the bf16 kernels contract over chi
+// in steps of 8; the extra indices are zero).
+int live_extent(const Inst& I, int k_act) {
+  const int r = (k_act + 7) / 8 * 8;
+  return std::max(1, std::min(I.chi_cap, r));
+}
+
+// out[a][U][b] (extent cn) = in[a][U][b] (extent co) where a, b < co, else 0;
+// with D2 = 1 the corner layout [a][b].
+__global__ void repack_kernel(const double* __restrict__ in, double* __restrict__ out, int co, int cn, int D2) {
+  const int64_t tot = (int64_t)cn * D2 * cn;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = e / ((int64_t)D2 * cn), rem = e % ((int64_t)D2 * cn);
+    const int u = (int)(rem / cn), b = (int)(rem % cn);
+    out[e] = (a < co && b < co) ? in[(a * D2 + u) * co + b] : 0.0;
+  }
+}
+
+// Re-lays every corner and edge of I out at the live extent cn (indices
+// dropped when shrinking are exact zeros; those added when growing are
+// zero), through the row scratch of the absorption.
+ctm_status set_live(ctm_ctx_s& x, Inst& I, int cn) {
+  cn = std::max(1, std::min(cn, I.chi_cap));
+  const int co = I.chi;
+  if (cn == co) return CTM_OK;
+  const int npos = x.Lx * x.Ly;
+  double* tmp = I.rows[0].nT4;  // chi_cap^2 D^2 doubles
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p)
+      for (int which = 0; which < 2; ++which) {
+        double* t = which == 0 ? I.C[c][p] : I.T[c][p];
+        const int D2 = which == 0 ? 1 : I.D2;
+        const size_t nin = (size_t)co * D2 * co, nout = (size_t)cn * D2 * cn;
+        HIPCHK(spans({{t, std::max(nin, nout) * 8}, {tmp, nout * 8}}, "repack"));
+        if (!dry_run()) {
+          const int blocks = (int)std::min<size_t>(1024, (nout + 255) / 256);
+          hipLaunchKernelGGL(repack_kernel, dim3(blocks), dim3(256), 0, x.stream, t, tmp, co, cn, D2);
+        }
+        HIPCHK(last_err());
+        HIPCHK(d2d(t, tmp, nout * 8, x.stream));
+      }
+  I.chi = cn;
+  I.n = cn * I.D2;
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p) I.staleC[c][p] = I.staleT[c][p] = true;
+  return CTM_OK;
+}
+
+// Subspace width of every instance of a class, and the live extent that
+// follows from it.
+ctm_status set_width(ctm_ctx_s& x, const std::vector<int>& cls, int kn) {
+  for (int i : cls) {
+    Inst& I = x.inst[i];
+    I.k_act = std::max(1, std::min(I.k, kn));
+    CHK(set_live(x, I, live_extent(I, I.k_act)));
+  }
+  return CTM_OK;
+}
+
+// Moves of ctm_move run outside the convergence loop: when a narrowed
+// subspace of a class was filled by the last solves (the width, not chi or
+// the cutoff, then set the truncation), the width grows by the oversampling.
+ctm_status grow_if_capped(ctm_ctx_s& x, const std::vector<int>& cls) {
+  Inst& J = x.inst[cls[0]];
+  if (J.k_act >= J.k) return CTM_OK;
+  int ce = 0;
+  for (int i : cls) {
+    Inst& I = x.inst[i];
+    for (Row& R : I.rows) {
+      SolveStatus st{};
+      HIPCHK(d2h(&st, R.st, sizeof(SolveStatus), x.stream));
+      HIPCHK(ssync(x.stream));
+      ce = std::max(ce, (int)st.chi_eff);
+    }
+  }
+  if (ce >= J.k_act) CHK(set_width(x, cls, J.k_act + std::max(1, x.cfg.svd_oversample)));
   return CTM_OK;
 }
 
@@ -1505,7 +1624,8 @@ ctm_status do_move(ctm_ctx_s& x, const std::vector<Inst*>& insts, int dir, int c
 }
 
 ctm_status do_sweep(ctm_ctx_s& x, const std::vector<Inst*>& insts) {
-  const int order[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
+  const int order[4] = {frame_of_dir(CTM_LEFT), frame_of_dir(CTM_RIGHT), frame_of_dir(CTM_UP),
+                        frame_of_dir(CTM_DOWN)};
   for (int o = 0; o < 4; ++o) {
     int lx, ly;
     frame_dims(order[o], x.Lx, x.Ly, lx, ly);
@@ -1759,6 +1879,63 @@ ctm_status z11_2x2(ctm_ctx_s& x, Inst& I, double* out) {
   return dot_dev(x, O.Uh, O.LhT, n * n, out);
 }
 
+// Z11 of a general Lx x Ly cell by row transfer: the top strip
+// [a, U_0 .. U_{Lx-1}, b] absorbs, row by row, the left edge T4, the double
+// layers of the row and the right edge T2; the result is joined to the
+// bottom strip (as in z10).  The largest intermediate holds chi^2 D^(2 Lx + 2)
+// entries, so this serves cells whose observables scratch was sized for it.
+ctm_status z11_rows(ctm_ctx_s& x, Inst& I, double* out) {
+  hipStream_t s = x.stream;
+  Obs& O = x.obs;
+  Roles ro{&x, &I, 0};
+  const int64_t c = I.chi, D2 = I.D2, D4 = D2 * D2;
+  const int Lx = x.Lx, Ly = x.Ly;
+  int64_t need = c * c * D2;
+  for (int i = 0; i < Lx; ++i) need *= D2;
+  if ((size_t)need > O.big || !O.rows_ok)
+    return fail(CTM_E_INVALID, "norm per site of this cell needs more observables scratch than was planned");
+  double* cur = O.t0;
+  double* nxt = O.t1;
+  CHK(top_strip(x, I, 0, 0, 0, Lx, cur, O.t2, O.t3));  // [a, U_0.., b]
+  int64_t Pw = 1;                                      // D2^Lx
+  for (int i = 0; i < Lx; ++i) Pw *= D2;
+  for (int y = 0; y < Ly; ++y) {
+    // [g, L, U_0.., b] = T4[(g, L), a] v[a, (U.., b)]
+    CHK(gemm1(s, F64, F64, c * D2, Pw * c, c, rowmajor(c), ro.T(3, 0, y), rowmajor(Pw * c), cur,
+              rowmajor(Pw * c), nxt));
+    std::swap(cur, nxt);
+    int64_t P = c, Q = Pw / D2 * c;  // prefix (g, Dn_0..Dn_{x-1}), suffix (U_{x+1}.., b)
+    for (int sx = 0; sx < Lx; ++sx) {
+      // out[p, (Dn, R), q] = sum_(L,U) v[p, (L, U_x), q] a[(L, U), (Dn, R)]
+      View va = view2(Q, 1, D4 * Q, BIG, Q, 0);
+      View vc = view2(Q, 1, D4 * Q, BIG, Q, 0);
+      CHK(gemm1(s, F64, F64, P * Q, D4, D4, va, cur, rowmajor(D4), ro.b64(sx, y, 0), vc, nxt));
+      std::swap(cur, nxt);
+      P *= D2;
+      Q /= D2;
+    }
+    // [g, Dn.., b'] = sum_(R, b) v[(g, Dn..), (R, b)] T2[b, R, b']
+    View vb = view2(c, D2 * c, c, BIG, 1, 0);
+    CHK(gemm1(s, F64, F64, c * Pw, c, D2 * c, rowmajor(D2 * c), cur, vb, ro.T(1, Lx - 1, y), rowmajor(c), nxt));
+    std::swap(cur, nxt);
+  }
+  // bottom strip: the top strip two turns on, legs reversed (as in z10)
+  double* bot = nxt;
+  int lx, ly;
+  frame_dims(2, x.Lx, x.Ly, lx, ly);
+  const int ax = pmod(-(Lx - 1), lx), ay = pmod(-(Ly - 1), ly);
+  CHK(top_strip(x, I, 2, ax, ay, Lx, O.t2, bot, O.t3));
+  int64_t dims[8];
+  int perm[8];
+  const int nd = Lx + 2;
+  dims[0] = c;
+  for (int i = 0; i < Lx; ++i) dims[1 + i] = D2;
+  dims[nd - 1] = c;
+  for (int i = 0; i < nd; ++i) perm[i] = nd - 1 - i;
+  HIPCHK(permute(x.stream, F64, O.t2, F64, bot, nd, dims, perm));
+  return dot_dev(x, cur, bot, c * c * Pw, out);
+}
+
 ctm_status kappa(ctm_ctx_s& x, Inst& I, double* kap) {
   Obs& O = x.obs;
   double* v = O.vals;
@@ -1767,7 +1944,7 @@ ctm_status kappa(ctm_ctx_s& x, Inst& I, double* kap) {
   } else if (x.Lx == 2 && x.Ly == 2) {
     CHK(z11_2x2(x, I, v + 0));
   } else {
-    return fail(CTM_E_INVALID, "norm per site is implemented for 1x1 and 2x2 cells");
+    CHK(z11_rows(x, I, v + 0));
   }
   CHK(z00(x, I, v + 1));
   CHK(z10(x, I, 0, 0, 0, x.Lx, x.Ly, v + 2));
@@ -2016,10 +2193,16 @@ ctm_status ctm_move(ctm_ctx x, int32_t dir, int32_t count) {
   for (auto& cls : x->classes) {
     std::vector<Inst*> insts = class_insts(*x, cls);
     if (dir == CTM_SWEEP) {
-      for (int i = 0; i < count; ++i) CHK(do_sweep(*x, insts));
+      for (int i = 0; i < count; ++i) {
+        CHK(do_sweep(*x, insts));
+        CHK(grow_if_capped(*x, cls));
+      }
     } else {
       x->resid_step = true;
-      CHK(do_move(*x, insts, dir, count));
+      for (int i = 0; i < count; ++i) {
+        CHK(do_move(*x, insts, frame_of_dir(dir), 1));
+        CHK(grow_if_capped(*x, cls));
+      }
     }
   }
   return CTM_OK;
@@ -2072,20 +2255,30 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
     HIPCHK(d2h(hf.data(), x->flag_all, (size_t)ni * 16, x->stream));
     HIPCHK(ssync(x->stream));
     // the subspace follows the number of kept singular values: chi_eff + p
-    // columns suffice, and chi_eff can grow by p per column step
+    // columns suffice, and chi_eff can grow by p per column step.  After a
+    // full sweep every corner and edge was produced by one of the solves
+    // whose kept counts are read here, so none extends past the largest of
+    // them, and the live extent can follow the new width.  A kept count
+    // equal to the width means the width, not chi or the cutoff, set the
+    // truncation: the subspace grows and that check cannot end the run.
+    std::vector<char> capped(ni, 0);
     for (auto& cls : x->classes) {
       int ce = 0;
       for (int i : cls)
         if (live[i]) ce = std::max(ce, hf[4 * i + 1]);
       Inst& J = x->inst[cls[0]];
+      const bool cap = ce > 0 && ce >= J.k_act && J.k_act < J.k;
+      if (cap)
+        for (int i : cls) capped[i] = 1;
       const int p = std::max(0, x->cfg.svd_oversample);
       int kw = ce + p;
       // fixed-count mode: up to 4 of the p extra columns are dropped when
       // that saves a partial 16-column tile of the half-system products
       if (!(x->cfg.svd_resid_tol > 0) && p >= 8 && kw / 16 * 16 >= ce + p - 4) kw = kw / 16 * 16;
+      if (cap) kw = std::max(kw, J.k_act + std::max(1, p));
       const int kn = std::max(1, std::min(J.k, kw));
       if (ce > 0 && kn != J.k_act) {
-        for (int i : cls) x->inst[i].k_act = kn;
+        CHK(set_width(*x, cls, kn));
         eager_next = true;
         drop_graph(*x);
       }
@@ -2096,7 +2289,7 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
       done[i] = sweep;
       dl[i] = hd[i];
       if (hf[4 * i] || !std::isfinite(hd[i])) bad = true;
-      else if (hd[i] < tol) {
+      else if (hd[i] < tol && !capped[i]) {
         conv[i] = 1;
         live[i] = 0;
         drop_graph(*x);  // the live set changed
@@ -2168,7 +2361,7 @@ ctm_status ctm_expect(ctm_ctx x, int32_t inst, int32_t sx, int32_t sy, int32_t v
 size_t ctm_env_bytes(ctm_ctx x, int32_t inst) {
   if (!x || inst < 0 || inst >= x->ninst) return 0;
   Inst& I = x->inst[inst];
-  const size_t npos = (size_t)x->Lx * x->Ly, c2 = (size_t)I.chi * I.chi;
+  const size_t npos = (size_t)x->Lx * x->Ly, c2 = (size_t)I.chi_cap * I.chi_cap;
   return npos * 4 * (c2 + c2 * I.D2) * 8;
 }
 
@@ -2177,13 +2370,27 @@ ctm_status ctm_env_export(ctm_ctx x, int32_t inst, void* buf, size_t bytes) {
   RegGuard guard(&x->reg);
   Inst& I = x->inst[inst];
   const int npos = x->Lx * x->Ly;
-  const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
-  char* p = (char*)buf;
+  const size_t cl = I.chi, cc = I.chi_cap, D2 = I.D2;
+  // device tensors are stored at the live extent; the buffer holds them
+  // zero-padded to chi
+  std::vector<double> t((size_t)cl * cl * D2);
+  std::memset(buf, 0, bytes);
+  double* p = (double*)buf;
   for (int c = 0; c < 4; ++c)
-    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.C[c][q], c2 * 8, x->stream)); p += c2 * 8; }
+    for (int q = 0; q < npos; ++q) {
+      HIPCHK(d2h(t.data(), I.C[c][q], cl * cl * 8, x->stream));
+      HIPCHK(ssync(x->stream));
+      for (size_t a = 0; a < cl; ++a) std::memcpy(p + a * cc, t.data() + a * cl, cl * 8);
+      p += cc * cc;
+    }
   for (int c = 0; c < 4; ++c)
-    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.T[c][q], t3 * 8, x->stream)); p += t3 * 8; }
-  HIPCHK(ssync(x->stream));
+    for (int q = 0; q < npos; ++q) {
+      HIPCHK(d2h(t.data(), I.T[c][q], cl * cl * D2 * 8, x->stream));
+      HIPCHK(ssync(x->stream));
+      for (size_t a = 0; a < cl; ++a)
+        for (size_t u = 0; u < D2; ++u) std::memcpy(p + (a * D2 + u) * cc, t.data() + (a * D2 + u) * cl, cl * 8);
+      p += cc * cc * D2;
+    }
   return CTM_OK;
 }
 
@@ -2192,8 +2399,13 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
   RegGuard guard(&x->reg);
   Inst& I = x->inst[inst];
   const int npos = x->Lx * x->Ly;
-  const size_t c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+  const size_t c2 = (size_t)I.chi_cap * I.chi_cap, t3 = c2 * I.D2;
   if (!finite_host((const double*)buf, bytes / 8)) return fail(CTM_E_NONFINITE, "non-finite environment");
+  // an imported environment may use every index up to chi: full extent and
+  // subspace width, no kept subspaces
+  I.chi = I.chi_cap;
+  I.n = I.n_cap;
+  I.k_act = I.k;
   const char* p = (const char*)buf;
   for (int c = 0; c < 4; ++c)
     for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.C[c][q], p, c2 * 8, x->stream)); p += c2 * 8; }
@@ -2204,7 +2416,110 @@ ctm_status ctm_env_import(ctm_ctx x, int32_t inst, const void* buf, size_t bytes
       I.has_keep[c][q] = false;
       I.staleC[c][q] = I.staleT[c][q] = true;
     }
+  HIPCHK(dmemset(I.skeep_all, 0, sizeof(SolveStatus) * 4 * npos, x->stream));
+  for (Row& R : I.rows) HIPCHK(dmemset(R.st, 0, sizeof(SolveStatus), x->stream));
   CHK(corner_spectra(*x, std::vector<Inst*>{&I}, true, true));
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+// Resumable state: a header, the corners and edges at the live extent, the
+// previous spectra, and every kept subspace with its status.
+namespace {
+struct CkptHeader {
+  int64_t magic, version, chi_cap, D, d, chi, k, k_act, npos, n_cap;
+  int64_t cursor[4];
+  int64_t has_keep[4 * MAXPOS];
+};
+constexpr int64_t CKPT_MAGIC = 0x43544d434b505431ll;  // "CTMCKPT1"
+size_t ckpt_bytes(const ctm_ctx_s& x, const Inst& I) {
+  const size_t npos = (size_t)x.Lx * x.Ly, cc = I.chi_cap;
+  return sizeof(CkptHeader) + npos * 4 * (cc * cc + cc * cc * I.D2) * 8 + npos * 4 * cc * 8 +
+         npos * 4 * sizeof(SolveStatus) + npos * 4 * (size_t)I.n_cap * I.k * 8;
+}
+}  // namespace
+
+size_t ctm_checkpoint_bytes(ctm_ctx x, int32_t inst) {
+  if (!x || inst < 0 || inst >= x->ninst) return 0;
+  return ckpt_bytes(*x, x->inst[inst]);
+}
+
+ctm_status ctm_checkpoint_save(ctm_ctx x, int32_t inst, void* buf, size_t bytes) {
+  if (!x || !buf || inst < 0 || inst >= x->ninst || bytes != ckpt_bytes(*x, x->inst[inst]))
+    return fail(CTM_E_INVALID, "args/bytes");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  const int npos = x->Lx * x->Ly;
+  CkptHeader h{};
+  h.magic = CKPT_MAGIC;
+  h.version = 1;
+  h.chi_cap = I.chi_cap; h.D = I.D; h.d = I.d; h.chi = I.chi; h.k = I.k; h.k_act = I.k_act;
+  h.npos = npos; h.n_cap = I.n_cap;
+  for (int c = 0; c < 4; ++c) h.cursor[c] = I.cursor[c];
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) h.has_keep[c * MAXPOS + q] = I.has_keep[c][q] ? 1 : 0;
+  char* p = (char*)buf;
+  std::memset(buf, 0, bytes);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t cc = I.chi_cap, c2 = (size_t)I.chi * I.chi, t3 = c2 * I.D2;
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.C[c][q], c2 * 8, x->stream)); p += cc * cc * 8; }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(d2h(p, I.T[c][q], t3 * 8, x->stream)); p += cc * cc * I.D2 * 8; }
+  HIPCHK(d2h(p, I.spec_old, (size_t)npos * 4 * cc * 8, x->stream));
+  p += (size_t)npos * 4 * cc * 8;
+  HIPCHK(d2h(p, I.skeep_all, (size_t)npos * 4 * sizeof(SolveStatus), x->stream));
+  p += (size_t)npos * 4 * sizeof(SolveStatus);
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) {
+      HIPCHK(d2h(p, I.Vkeep[c][q], (size_t)I.n_cap * I.k * 8, x->stream));
+      p += (size_t)I.n_cap * I.k * 8;
+    }
+  HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_checkpoint_load(ctm_ctx x, int32_t inst, const void* buf, size_t bytes) {
+  if (!x || !buf || inst < 0 || inst >= x->ninst || bytes != ckpt_bytes(*x, x->inst[inst]))
+    return fail(CTM_E_INVALID, "args/bytes");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  const int npos = x->Lx * x->Ly;
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != CKPT_MAGIC || h.version != 1 || h.chi_cap != I.chi_cap || h.D != I.D || h.d != I.d ||
+      h.k != I.k || h.npos != npos || h.n_cap != I.n_cap || h.chi < 1 || h.chi > I.chi_cap || h.k_act < 1 ||
+      h.k_act > I.k)
+    return fail(CTM_E_INVALID, "checkpoint does not match this context");
+  for (int c = 0; c < 4; ++c)
+    if (h.cursor[c] < 0 || h.cursor[c] >= std::max(x->Lx, x->Ly)) return fail(CTM_E_INVALID, "checkpoint cursor");
+  const char* p = (const char*)buf + sizeof(h);
+  const size_t cc = I.chi_cap, cl = (size_t)h.chi, c2 = cl * cl, t3 = c2 * I.D2;
+  if (!finite_host((const double*)p, npos * 4 * (cc * cc + cc * cc * I.D2 + cc)))
+    return fail(CTM_E_NONFINITE, "non-finite checkpoint");
+  I.chi = (int)h.chi;
+  I.n = I.chi * I.D2;
+  I.k_act = (int)h.k_act;
+  for (int c = 0; c < 4; ++c) I.cursor[c] = (int)h.cursor[c];
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) {
+      I.has_keep[c][q] = h.has_keep[c * MAXPOS + q] != 0;
+      I.staleC[c][q] = I.staleT[c][q] = true;
+    }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.C[c][q], p, c2 * 8, x->stream)); p += cc * cc * 8; }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) { HIPCHK(h2d(I.T[c][q], p, t3 * 8, x->stream)); p += cc * cc * I.D2 * 8; }
+  HIPCHK(h2d(I.spec_old, p, (size_t)npos * 4 * cc * 8, x->stream));
+  p += (size_t)npos * 4 * cc * 8;
+  HIPCHK(h2d(I.skeep_all, p, (size_t)npos * 4 * sizeof(SolveStatus), x->stream));
+  p += (size_t)npos * 4 * sizeof(SolveStatus);
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < npos; ++q) {
+      HIPCHK(h2d(I.Vkeep[c][q], p, (size_t)I.n_cap * I.k * 8, x->stream));
+      p += (size_t)I.n_cap * I.k * 8;
+    }
   HIPCHK(ssync(x->stream));
   return CTM_OK;
 }
@@ -2216,7 +2531,8 @@ ctm_status ctm_set_timing(ctm_ctx x, int32_t enable) {
   x->tused = x->sused = 0;
   x->timing = enable != 0;
   x->phase_timing = enable == 1;
-  x->t_corner = x->t_solver = x->t_absorb = x->t_stage3 = x->stage3_flop = 0;
+  x->t_corner = x->t_solver = x->t_absorb = x->t_stage3 = x->stage3_flop = x->stage3_flop_nom = 0;
+  x->live_chi = 0;
   x->corner_launches = x->stage3_launches = x->moves = 0;
   return CTM_OK;
 }
@@ -2232,6 +2548,8 @@ ctm_status ctm_get_timing(ctm_ctx x, double* v) {
   v[5] = x->stage3_flop;
   v[6] = (double)x->corner_launches;
   v[7] = (double)x->moves;
+  v[8] = x->stage3_flop_nom;
+  v[9] = (double)x->live_chi;
   return CTM_OK;
 }
 
@@ -2256,6 +2574,7 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const
   double kap[3];
   const double* const* kets[3] = {A_dev, B_dev, A_dev};
   const double* const* bras[3] = {A_dev, B_dev, B_dev};
+  bool all_conv = true;
   for (int r = 0; r < 3; ++r) {
     ctm_ctx x = nullptr;
     CHK(ctm_init(cfg, kets[r], bras[r], ws_dev, ws_bytes, stream, CTM_INIT_TRIVIAL, nullptr, &x));
@@ -2264,6 +2583,7 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const
     ctm_status s = ctm_converge(x, tol, max_sweeps, 1, &sw, &dl);
     if (sweeps_out) sweeps_out[r] = sw;
     if (s != CTM_OK && s != CTM_E_NOCONV) { ctm_destroy(x); return s; }
+    all_conv = all_conv && s == CTM_OK;
     s = ctm_norm(x, 0, &kap[r]);
     ctm_destroy(x);
     if (s != CTM_OK) return s;
@@ -2271,6 +2591,7 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const
   double dv = std::fabs(kap[2]) / std::sqrt(std::fabs(kap[0] * kap[1]));
   *d_out = dv;
   if (ln_d_out) *ln_d_out = std::log(dv);
+  if (!all_conv) return fail(CTM_E_NOCONV, "a CTM run of the fidelity did not converge within max_sweeps");
   return CTM_OK;
 }
 
@@ -2370,6 +2691,14 @@ ctm_status ctm_debug_dump(ctm_ctx x, int32_t what, int32_t index, void* buf, siz
   if (bytes != need) return fail(CTM_E_INVALID, "bytes must be " + std::to_string(need));
   HIPCHK(d2h(buf, src, bytes, x->stream));
   HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_set_width(ctm_ctx x, int32_t width, int32_t* live_out) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  RegGuard guard(&x->reg);
+  for (auto& cls : x->classes) CHK(set_width(*x, cls, width));
+  if (live_out) *live_out = x->inst[0].chi;
   return CTM_OK;
 }
 

@@ -16,6 +16,8 @@ struct SolveStatus {
   double max_resid;    // largest kept residual / sigma_0
   int32_t jsweeps;     // Jacobi sweeps of the last Rayleigh-Ritz step
   int32_t kcols;       // columns of the subspace this status belongs to
+  int32_t nrows;       // rows (cut dimension) of that subspace
+  int32_t pad_;
 };
 
 constexpr int MAXP = 32;  // problems per small-kernel launch
@@ -74,12 +76,13 @@ hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cuto
 hipError_t scale_kept(hipStream_t s, int k, int chi, const CPtrSet& W, const CPtrSet& S,
                       const PtrSet& Wp, const StatSet& st, int nprob);
 
-// V0 = random normals, then the first keep columns replaced by Vprev's, where
-// keep = prev->chi_eff (0 if prev is null or the context has no previous solve).
-// V0 (n x k) = the chi_eff kept columns of Vprev (stored n x prev->kcols,
-// buffer n x kmax), then counter-based normals
-hipError_t warm_start(hipStream_t s, int64_t n, int k, int kmax, const PtrSet& V0, const CPtrSet& Vprev,
-                      const StatSet& prev, uint64_t seed, int nprob);
+// V0 (n x k) = the chi_eff kept columns of Vprev (stored prev->nrows x
+// prev->kcols, buffer n_cap x kmax; rows past prev->nrows read as zero: the
+// kept vectors have no component along cut directions that were not live
+// when they were found), then counter-based normals.  keep = 0 if prev is
+// null or holds no previous solve.
+hipError_t warm_start(hipStream_t s, int64_t n, int64_t n_cap, int k, int kmax, const PtrSet& V0,
+                      const CPtrSet& Vprev, const StatSet& prev, uint64_t seed, int nprob);
 
 // Resets the iteration counters of the statuses.
 hipError_t reset_status(hipStream_t s, const StatSet& st, int nprob);

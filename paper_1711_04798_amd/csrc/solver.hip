@@ -765,8 +765,8 @@ residual_partial_kernel(int64_t n, int k, CPtrSet Z, CPtrSet V, CPtrSet S, doubl
 }
 
 __global__ void __launch_bounds__(256)
-residual_final_kernel(int k, int nb, int chi, double cutoff, double tol, CPtrSet S, const double* part,
-                      StatSet st) {
+residual_final_kernel(int64_t n, int k, int nb, int chi, double cutoff, double tol, CPtrSet S,
+                      const double* part, StatSet st) {
   const int pb = blockIdx.x;
   const double* sv = S.p[pb];
   __shared__ double s_res[256];
@@ -794,6 +794,7 @@ residual_final_kernel(int k, int nb, int chi, double cutoff, double tol, CPtrSet
     o->converged = (nb > 0 && mr <= tol) ? 1 : 0;
     o->iters += 1;
     o->kcols = k;
+    o->nrows = (int32_t)n;
   }
 }
 
@@ -815,7 +816,8 @@ hipError_t residual_status(hipStream_t s, int64_t n, int k, int chi, double cuto
   if (dry_run()) return hipSuccess;
   if (nb > 0)
     hipLaunchKernelGGL(residual_partial_kernel, dim3(nb, nprob), dim3(256), 0, s, n, k, Z, V, S, scratch);
-  hipLaunchKernelGGL(residual_final_kernel, dim3(nprob), dim3(256), 0, s, k, nb, chi, cutoff, tol, S, scratch, st);
+  hipLaunchKernelGGL(residual_final_kernel, dim3(nprob), dim3(256), 0, s, n, k, nb, chi, cutoff, tol, S, scratch,
+                     st);
   return hipGetLastError();
 }
 
@@ -852,7 +854,8 @@ __device__ __forceinline__ uint64_t sm64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ void warm_start_kernel(int64_t n, int k, int kmax, PtrSet V0, CPtrSet Vprev, StatSet prev, uint64_t seed) {
+__global__ void warm_start_kernel(int64_t n, int64_t n_cap, int k, int kmax, PtrSet V0, CPtrSet Vprev, StatSet prev,
+                                  uint64_t seed) {
   const int pb = blockIdx.y;
   double* v0 = V0.p[pb];
   const double* vp = Vprev.p[pb];
@@ -862,12 +865,19 @@ __global__ void warm_start_kernel(int64_t n, int k, int kmax, PtrSet V0, CPtrSet
   int keep = (prev.p[pb] && vp && kp > 0) ? prev.p[pb]->chi_eff : 0;
   if (keep > k) keep = k;
   if (keep > kp) keep = kp;
+  int64_t np = keep > 0 ? (int64_t)prev.p[pb]->nrows : 0;
+  if (np < 0) np = 0;
+  if (np > n_cap) np = n_cap;  // never read past the kept buffer (n_cap x kmax)
   const uint64_t sd = seed + 0x1000193ull * (uint64_t)pb * (uint64_t)n * (uint64_t)k * 2ull;
   const int64_t tot = n * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     int c = (int)(e % k);
-    if (c < keep) { v0[e] = vp[(e / k) * kp + c]; continue; }
+    if (c < keep) {
+      const int64_t r = e / k;
+      v0[e] = r < np ? vp[r * kp + c] : 0.0;
+      continue;
+    }
     uint64_t a = sm64(sd + 2ull * (uint64_t)e), b = sm64(sd + 2ull * (uint64_t)e + 1ull);
     double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);
     double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
@@ -875,21 +885,21 @@ __global__ void warm_start_kernel(int64_t n, int k, int kmax, PtrSet V0, CPtrSet
   }
 }
 
-hipError_t warm_start(hipStream_t s, int64_t n, int k, int kmax, const PtrSet& V0, const CPtrSet& Vprev,
-                      const StatSet& prev, uint64_t seed, int nprob) {
-  if (k > kmax) return hipErrorInvalidValue;
+hipError_t warm_start(hipStream_t s, int64_t n, int64_t n_cap, int k, int kmax, const PtrSet& V0,
+                      const CPtrSet& Vprev, const StatSet& prev, uint64_t seed, int nprob) {
+  if (k > kmax || n > n_cap) return hipErrorInvalidValue;
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(V0.p[i], (size_t)n * k * 8, "warm V0") ||
-        (Vprev.p[i] && !span_ok(Vprev.p[i], (size_t)n * kmax * 8, "warm Vprev")) ||
+        (Vprev.p[i] && !span_ok(Vprev.p[i], (size_t)n_cap * kmax * 8, "warm Vprev")) ||
         (prev.p[i] && !span_ok(prev.p[i], sizeof(SolveStatus), "warm prev")))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   int64_t blocks = (n * k + 255) / 256;
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(warm_start_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, n, k, kmax, V0, Vprev, prev,
-                     seed);
+  hipLaunchKernelGGL(warm_start_kernel, dim3((unsigned)blocks, nprob), dim3(256), 0, s, n, n_cap, k, kmax, V0, Vprev,
+                     prev, seed);
   return hipGetLastError();
 }
 

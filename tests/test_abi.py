@@ -38,6 +38,7 @@ def declared():
 def test_exports_every_declared_symbol(lib_path):
     names = declared()
     assert {"ctm_init", "ctm_move", "ctm_converge", "ctm_rdm", "ctm_fidelity"} <= names
+    assert {"ctm_checkpoint_save", "ctm_checkpoint_load", "ctm_checkpoint_bytes"} <= names
     lib = ctypes.CDLL(lib_path)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
@@ -66,11 +67,22 @@ for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
     st = [lib.ctm_init(ctypes.byref(cfg), ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), None,
                        ctypes.c_void_p(1 << 40), n, None, 0, None, ctypes.byref(ctx))]
     st.append(lib.ctm_move(ctx, 4, 1))
-    st.append(lib.ctm_move(ctx, 1, 3))
+    for dr in range(4):
+        st.append(lib.ctm_move(ctx, dr, 3))
     sw = (ctypes.c_int32 * len(d))(); dl = (ctypes.c_double * len(d))()
     st.append(lib.ctm_converge(ctx, 1e-10, 2, 1, sw, dl))
     k = ctypes.c_double()
-    if (Lx, Ly) in ((1, 1), (2, 2)):
+    # narrowed subspace: every stage at the live extent, under the bounds checks
+    live = ctypes.c_int32()
+    st.append(lib.ctm_debug_set_width(ctx, 9, ctypes.byref(live)))
+    st.append(lib.ctm_move(ctx, 4, 1))
+    for dr in range(4):
+        st.append(lib.ctm_move(ctx, dr, 1))
+    nb = lib.ctm_checkpoint_bytes(ctx, 0)
+    ck = (ctypes.c_char * nb)()
+    st.append(lib.ctm_checkpoint_save(ctx, 0, ck, nb))
+    st.append(lib.ctm_checkpoint_load(ctx, 0, ck, nb))
+    if True:
         st.append(lib.ctm_norm(ctx, 0, ctypes.byref(k)))
         rho = (ctypes.c_double * (d[0] ** 4))(); h = ctypes.c_double()
         for v in (0, 1):

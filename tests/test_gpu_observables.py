@@ -135,7 +135,8 @@ def test_fidelity_gpu(gpu):
     B = A + 0.3 * synth.peps_tensor(rng, 2, 2)
     B /= np.linalg.norm(B)
     print("case fidelity", flush=True)
-    dg, lg, sw = binding.fidelity([A], [B], chi=16, tol=1e-12, max_sweeps=300)
+    dg, lg, sw, conv = binding.fidelity([A], [B], chi=16, tol=1e-12, max_sweeps=300)
+    assert conv and max(sw) < 300, sw
     kap = {}
     for name, kets, bras in (("ab", [A], [B]), ("aa", [A], None), ("bb", [B], None)):
         cell = octm.Cell(1, 1, [0], kets, bras)
@@ -147,8 +148,12 @@ def test_fidelity_gpu(gpu):
     assert 0 < dg <= 1 + 1e-12
     assert abs(dg - do) <= 1e-10 * abs(do)
     assert abs(lg - np.log(dg)) < 1e-12
-    d1, l1, _ = binding.fidelity([A], [A], chi=16, tol=1e-12, max_sweeps=300)
+    d1, l1, sw1, conv1 = binding.fidelity([A], [A], chi=16, tol=1e-12, max_sweeps=300)
+    assert conv1 and max(sw1) < 300, sw1
     assert abs(d1 - 1.0) < 1e-10 and abs(l1) < 1e-10
+    # a budget too small to converge: the value is still returned, with the status
+    d2, _, sw2, conv2 = binding.fidelity([A], [B], chi=16, tol=1e-12, max_sweeps=2)
+    assert not conv2 and sw2 == [2, 2, 2] and np.isfinite(d2)
 
 
 def test_checkpoint_roundtrip(gpu):
@@ -173,6 +178,61 @@ def test_checkpoint_roundtrip(gpu):
     g2.close()
     assert np.abs(s1 - s2).max() < 1e-9
     assert abs(k1 - k2) <= 1e-10 * abs(k1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_checkpoint_resume_bitwise(gpu, prec):
+    """A run converged in two pieces, with a checkpoint saved after the first
+    and loaded into a fresh context, ends bitwise equal to the run done in
+    one piece: environment, spectra, kappa, sweep count and Delta."""
+    from paper_1711_04798_amd import CTM
+    if prec == "fp64":
+        A, B = synth.cell_tensors(2, 2, 3, 2)
+        kw = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=24, cutoff=1e-8)
+    else:
+        A, B = synth.cell_tensors(3, 8, 3, 2)
+        kw = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=32, prec="bf16", max_iters=2, resid_tol=0.0,
+                  cutoff=1e-6)
+    print("case checkpoint bitwise", prec, flush=True)
+    g1 = CTM([[A, B]], **kw)
+    g1.converge(tol=0.0, max_sweeps=3)
+    s_a, d_a, _ = g1.converge(tol=0.0, max_sweeps=3)
+    ref = (g1.export_env(), g1.spectra(), g1.norm(), d_a)
+    g2 = CTM([[A, B]], **kw)
+    g2.converge(tol=0.0, max_sweeps=3)
+    ck = g2.save_checkpoint()
+    g2.close()
+    g3 = CTM([[A, B]], **kw)
+    g3.load_checkpoint(ck)
+    s_b, d_b, _ = g3.converge(tol=0.0, max_sweeps=3)
+    got = (g3.export_env(), g3.spectra(), g3.norm(), d_b)
+    g1.close()
+    g3.close()
+    assert np.array_equal(ref[0], got[0])
+    assert np.array_equal(ref[1], got[1])
+    assert ref[2] == got[2] and ref[3] == got[3] and s_a == s_b
+
+
+def test_width_grows_when_filled(gpu):
+    """With two oversampling columns the subspace width (chi_eff + 2) is often
+    filled by the kept count; a converged run may then not stop at a check
+    where that happened, and moves after it grow the width: the converged
+    environment matches the oracle's (no width limit) and so do further
+    lock-step moves."""
+    from paper_1711_04798_amd import CTM
+    A, B = synth.cell_tensors(6, 2, 3, 2)
+    kw = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=24, cutoff=1e-8, oversample=2)
+    print("case width growth", flush=True)
+    g = CTM([[A, B]], **kw)
+    sw, dl, ok = g.converge(tol=1e-10, max_sweeps=200)
+    assert ok, (sw, dl)
+    cell = octm.Cell(2, 2, [0, 1, 1, 0], [A, B])
+    env = octm.init_trivial(cell, 24)
+    octm.converge(cell, env, tol=1e-10, max_sweeps=200, cutoff=1e-8)
+    so = _spec_oracle(env, 2, 2)
+    assert np.abs(g.spectra() - so).max() < 1e-7
+    assert abs(g.norm() - oobs.kappa(cell, env)) <= 1e-9 * abs(oobs.kappa(cell, env))
+    g.close()
 
 
 def test_deterministic(gpu):

@@ -76,7 +76,7 @@ def test_one_step_from_same_env(gpu, direction, case):
         P1o, P2o, info = octm.projectors(*Qo, chi, 1e-12, return_info=True)
         P1g = _dump(g, 1, yp, (n, chi))
         P2g = _dump(g, 2, yp, (n, chi)).T
-        stt = _dump(g, 3, yp, (10,), np.int32)
+        stt = _dump(g, 3, yp, (12,), np.int32)
         keep = info["keep"]
         # compare the truncated half-system operator Uh^T P1 P2 Lh^T (well
         # conditioned); P1 P2 alone amplifies the smallest kept direction by
