@@ -2315,7 +2315,7 @@ ctm_status ctm_spectra(ctm_ctx x, int32_t inst, double* out) {
   RegGuard guard(&x->reg);
   Inst& I = x->inst[inst];
   CHK(corner_spectra(*x, std::vector<Inst*>{&I}, false, false));
-  HIPCHK(d2h(out, I.spec_new, (size_t)x->Lx * x->Ly * 4 * I.chi * 8, x->stream));
+  HIPCHK(d2h(out, I.spec_new, (size_t)x->Lx * x->Ly * 4 * I.chi_cap * 8, x->stream));
   HIPCHK(ssync(x->stream));
   return CTM_OK;
 }

@@ -84,7 +84,7 @@ def test_one_step_from_same_env(gpu, direction, case):
         Uh, Lh = Qo[0] @ Qo[1], Qo[2] @ Qo[3]
         No, Ng = Uh.T @ P1o @ P2o @ Lh.T, Uh.T @ P1g @ P2g @ Lh.T
         err = np.abs(No - Ng).max() / np.abs(No).max()
-        res = _dump(g, 3, yp, (5,), np.float64)
+        res = _dump(g, 3, yp, (6,), np.float64)
         print("row %d keep oracle %d gpu %d iters %d jacobi sweeps %d max_resid %.2e, N_chi rel err %.2e"
               % (yp, keep, stt[0], stt[2], stt[8], res[3], err))
         assert stt[0] == keep
