@@ -202,6 +202,24 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev,
                         void* stream, double tol, int32_t max_sweeps,
                         double* d_out, double* ln_d_out, int32_t* sweeps_out);
 
+/*
+ * ctm_fidelity for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same three CTM runs and the same result, with the workspace taken
+ * from a file-scope device array of ctm_fidelity_noalloc_max_bytes() bytes
+ * (64 MiB) that each GPU holds from its first use until the process ends.
+ * The configuration's use_graph and autotune are ignored (treated as 0).
+ * Returns CTM_E_NOMEM when ctm_workspace_size(cfg) exceeds the array.  All
+ * calls on one GPU share its array: calls that overlap in time on the same
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Every buffer a call reads is written by that call first.
+ */
+ctm_status ctm_fidelity_noalloc(const ctm_config* cfg, const double* const* A_dev,
+                                const double* const* B_dev, void* stream, double tol,
+                                int32_t max_sweeps, double* d_out, double* ln_d_out,
+                                int32_t* sweeps_out);
+size_t ctm_fidelity_noalloc_max_bytes(void);
+
 /* The environment of Sec. II C (corners C1..C4 chi x chi, edges T1..T4
  * chi x D^2 x chi) of instance `inst` as float64, in the order C1..C4 then
  * T1..T4, each for positions y*Lx+x, legs clockwise around the site,

@@ -23,7 +23,7 @@ EXPORTS = [
     "ctm_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
-    "ctm_last_error", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
+    "ctm_last_error", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
 
@@ -80,6 +80,10 @@ def load(path=LIB_PATH):
     lib.ctm_rdm.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_expect.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_fidelity.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, F64, I32, P(F64), P(F64), P(I32)]
+    lib.ctm_fidelity_noalloc.argtypes = [cfgp, dpp, dpp, VP, F64, I32, P(F64), P(F64), P(I32)]
+    lib.ctm_fidelity_noalloc.restype = ctypes.c_int
+    lib.ctm_fidelity_noalloc_max_bytes.argtypes = []
+    lib.ctm_fidelity_noalloc_max_bytes.restype = SZ
     lib.ctm_env_bytes.argtypes = [VP, I32]
     lib.ctm_env_bytes.restype = SZ
     lib.ctm_env_export.argtypes = [VP, I32, VP, SZ]
@@ -326,6 +330,31 @@ def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=
                                  max_sweeps, ctypes.byref(dv), ctypes.byref(lv), sw), allow=(CTM_E_NOCONV,))
     torch.cuda.synchronize(dev)
     del at, bt, ws
+    return dv.value, lv.value, list(sw), st == CTM_OK
+
+
+def fidelity_noalloc(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=1e-10,
+                     max_sweeps=200, device="cuda:0", **solver):
+    """As fidelity(), through ctm_fidelity_noalloc: the library allocates
+    nothing (its workspace is a static device array); only the tensor copies
+    are made here."""
+    import torch
+    lib = load()
+    if pattern is None:
+        pattern = [0] * (Lx * Ly)
+    cfg, keep = make_config(Lx, Ly, pattern, len(A_list), [A_list[0].shape[0]], [A_list[0].shape[1]], [chi],
+                            prec, **solver)
+    dev = torch.device(device)
+    at, ap = _dev_tensors(torch, A_list, dev)
+    bt, bp = _dev_tensors(torch, B_list, dev)
+    dv, lv = ctypes.c_double(), ctypes.c_double()
+    sw = (ctypes.c_int32 * 3)()
+    st = _check(lib.ctm_fidelity_noalloc(ctypes.byref(cfg), ctypes.cast(ap, ctypes.POINTER(ctypes.c_void_p)),
+                                         ctypes.cast(bp, ctypes.POINTER(ctypes.c_void_p)), _stream(torch, dev),
+                                         tol, max_sweeps, ctypes.byref(dv), ctypes.byref(lv), sw),
+                allow=(CTM_E_NOCONV,))
+    torch.cuda.synchronize(dev)
+    del at, bt
     return dv.value, lv.value, list(sw), st == CTM_OK
 
 

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <functional>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <array>
 #include <vector>
@@ -2593,6 +2594,65 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const
   if (ln_d_out) *ln_d_out = std::log(dv);
   if (!all_conv) return fail(CTM_E_NOCONV, "a CTM run of the fidelity did not converge within max_sweeps");
   return CTM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// fidelity without allocation: the workspace is a file-scope device array
+// ===========================================================================
+namespace {
+
+constexpr size_t STATIC_WS_BYTES = (size_t)64 << 20;
+// Host code never uses this name as an address (it is a host-side stand-in):
+// the device address of each GPU's copy comes from hipGetSymbolAddress.
+__device__ __align__(256) char scratch[STATIC_WS_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the device address of `scratch` on the current device, looked up once per
+// device with that device current
+ctm_status scratch_ptr(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(CTM_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> l(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CTM_E_HIP, "no device address for the static workspace");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ctm_fidelity_noalloc_max_bytes(void) { return STATIC_WS_BYTES; }
+
+ctm_status ctm_fidelity_noalloc(const ctm_config* cfg, const double* const* A_dev, const double* const* B_dev,
+                                void* stream, double tol, int32_t max_sweeps, double* d_out, double* ln_d_out,
+                                int32_t* sweeps_out) {
+  if (!cfg || !A_dev || !B_dev || !d_out) return fail(CTM_E_INVALID, "args");
+  // no graph instantiation and no tile timing (both create runtime objects)
+  ctm_config c = *cfg;
+  c.use_graph = 0;
+  c.autotune = 0;
+  size_t need = 0;
+  CHK(ctm_workspace_size(&c, &need));
+  if (need > STATIC_WS_BYTES)
+    return fail(CTM_E_NOMEM, "configuration needs " + std::to_string(need) +
+                                 " bytes of workspace; the static workspace holds " +
+                                 std::to_string(STATIC_WS_BYTES));
+  void* ws = nullptr;
+  CHK(scratch_ptr(&ws));
+  return ctm_fidelity(&c, A_dev, B_dev, ws, STATIC_WS_BYTES, stream, tol, max_sweeps, d_out, ln_d_out,
+                      sweeps_out);
 }
 
 }  // extern "C"
