@@ -37,15 +37,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "corner_bf16_2x2_d8_D6_chi144_hbm_coun
 CORNER_SRC = os.path.join(ROOT, "paper_1711_04798_amd", "csrc", "corner_bf16.hip")
 
 
-def measured_traffic():
+def measured_traffic(live_chi):
     """HBM bytes per launch of the bf16 corner kernel from the committed
-    counter summary, or None when the kernel source changed since."""
+    counter summary, or None when the kernel source changed since or the
+    counters were taken at another live extent."""
     import hashlib
     try:
         sha = hashlib.sha1(open(CORNER_SRC, "rb").read()).hexdigest()
         fields = dict(l.split(":", 1) for l in open(COUNTERS).read().splitlines()
-                      if l.startswith(("source_sha1:", "hbm_bytes_per_launch:")))
+                      if l.startswith(("source_sha1:", "hbm_bytes_per_launch:", "live_chi:")))
         if fields.get("source_sha1", "").strip() != sha:
+            return None
+        if int(fields.get("live_chi", "-1").strip()) != int(live_chi):
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -114,21 +117,30 @@ def cpu_baseline(tensors):
                       % dt}
 
 
-BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, tol=1e-4, max_sweeps=40,
-               plain_sample=16)
+BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
+# float64 contractions reach Delta < 1e-6; float32 contractions do not (their
+# corner spectra keep changing by ~1e-5 .. 1e-4 per sweep), so the float32
+# form is run to 1e-4
+BATCHED_FORMS = [dict(prec="fp64", max_iters=3, tol=1e-6, plain_per_class=2),
+                 dict(prec="fp32", max_iters=2, tol=1e-4, plain_per_class=1)]
 
 
-def batched_leg():
+def batched_leg(form):
     """Batched form: 256 independent 1x1 instances, (D, chi) drawn per instance,
     float32 contractions, one captured HIP graph per sweep, converged to tol;
-    against the same instances run one plain context at a time (a sample)."""
+    against plain runs (one context per instance, eager) of a stratified
+    sample: the first `plain_per_class` instances of every (D, chi) class.
+    Rates count converged instances only; the plain rate is the sample's
+    converged count over its time, weighted to the batch's class mix."""
     import torch
     import synth
     from paper_1711_04798_amd import CTM
-    b = BATCHED
+    b = dict(BATCHED)
+    b.update(form)
     inst = synth.batched_instances(b["seed"], b["n_inst"], d=b["d"], Ds=b["Ds"], chis=b["chis"])
-    kw = dict(prec="fp32", max_iters=2, resid_tol=0.0, cutoff=1e-6)
-    log("bench: batched leg, %d instances" % len(inst))
+    kw = dict(prec=b["prec"], max_iters=b["max_iters"], resid_tol=0.0,
+              cutoff=1e-8 if b["prec"] == "fp64" else 1e-6)
+    log("bench: batched leg, %d instances, %s, tol %g" % (len(inst), b["prec"], b["tol"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = CTM([[A] for _, _, A in inst], chi=[c for _, c, _ in inst], use_graph=True, **kw)
@@ -140,44 +152,66 @@ def batched_leg():
     g.close()
     del g
     torch.cuda.empty_cache()
-    n_conv = sum(1 for d in dl if d < b["tol"])
+    conv = [d < b["tol"] for d in dl]
+    n_conv = sum(conv)
     log("bench: batched converge %.2f s (init %.2f s), %d/%d converged, sweeps max %d"
         % (t_b, t_init, n_conv, len(inst), max(sw)))
-    # plain: one context per instance, eager, the first plain_sample instances
-    t_p = 0.0
-    sw_p = []
-    for D, chi, A in inst[:b["plain_sample"]]:
-        p = CTM([[A]], chi=chi, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s1, d1, _ = p.converge(tol=b["tol"], max_sweeps=b["max_sweeps"])
-        torch.cuda.synchronize()
-        t_p += time.perf_counter() - t0
-        sw_p.append(s1[0])
-        p.close()
-    env_b = len(inst) / t_b
-    env_p = b["plain_sample"] / t_p
-    log("bench: plain %d instances %.2f s" % (b["plain_sample"], t_p))
-    return {"envs_per_s": env_b, "plain_envs_per_s": env_p, "speedup": env_b / env_p,
-            "unit": "converged environments/s", "n_inst": len(inst), "converged": n_conv,
-            "tol": b["tol"], "max_sweeps": b["max_sweeps"], "sweeps_mean": float(np.mean(sw)),
-            "sweeps_max": int(max(sw)), "plain_sample": b["plain_sample"],
-            "plain_sweeps_mean": float(np.mean(sw_p)), "dtype": "fp32",
+    # plain: stratified sample, per class time per instance
+    classes = sorted({(D, c) for D, c, _ in inst})
+    per_class = {}
+    for cls in classes:
+        members = [A for D, c, A in inst if (D, c) == cls][:b["plain_per_class"]]
+        t_c, n_c, sws = 0.0, 0, []
+        for A in members:
+            p = CTM([[A]], chi=cls[1], **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1, d1, _ = p.converge(tol=b["tol"], max_sweeps=b["max_sweeps"])
+            torch.cuda.synchronize()
+            t_c += time.perf_counter() - t0
+            n_c += int(d1[0] < b["tol"])
+            sws.append(s1[0])
+            p.close()
+        per_class[cls] = (t_c / len(members), n_c / len(members), float(np.mean(sws)))
+    # the plain method on the batch's instance mix: expected time and
+    # converged count from the per-class sample
+    mix = {cls: sum(1 for D, c, _ in inst if (D, c) == cls) for cls in classes}
+    t_plain = sum(mix[c] * per_class[c][0] for c in classes)
+    n_plain = sum(mix[c] * per_class[c][1] for c in classes)
+    env_b = n_conv / t_b
+    env_p = n_plain / t_plain if t_plain > 0 else 0.0
+    log("bench: plain sample (%d per class) extrapolated to the batch: %.2f s, %.1f converged"
+        % (b["plain_per_class"], t_plain, n_plain))
+    return {"envs_per_s": env_b, "plain_envs_per_s": env_p, "speedup": env_b / env_p if env_p > 0 else None,
+            "unit": "converged environments/s (converged instances only)", "n_inst": len(inst),
+            "converged": n_conv, "tol": b["tol"], "max_sweeps": b["max_sweeps"],
+            "delta_median": float(np.median(dl)), "time_s": t_b,
+            "sweeps_mean": float(np.mean(sw)), "sweeps_max": int(max(sw)),
+            "plain_sample": "%d per (D, chi) class, %d instances" % (b["plain_per_class"],
+                                                                     b["plain_per_class"] * len(classes)),
+            "plain_sweeps_mean_by_class": {"D%d_chi%d" % c: per_class[c][2] for c in classes},
+            "plain_converged_frac_by_class": {"D%d_chi%d" % c: per_class[c][1] for c in classes},
+            "dtype": b["prec"],
             "workload": "256 1x1 iPEPS, d=8, D in {3,4,5}, chi in {32,64,100} per instance (seed 0), "
-                        "fp32 contractions, one HIP graph per sweep; plain = one context per instance, "
-                        "eager, first %d instances" % b["plain_sample"]}
+                        "%s contractions, one HIP graph per sweep of every live instance; plain = one "
+                        % b["prec"] +
+                        "context per instance, eager, time per class from a stratified sample applied "
+                        "to the batch's class counts"}
 
 
-WARM = dict(d=8, D=4, chi=64, family_seed=0, train_seed=1, test_seed=2, n_train=512, n_test=64, tol=1e-10,
+WARM = dict(d=8, D=4, chi=64, family_seed=0, train_seed=1, test_seed=2, n_train=2000, n_test=200, tol=1e-10,
             max_sweeps=60, hidden=128, steps=4000, lr=2e-3)
 
 
 def warm_leg():
     """Learned warm start: plain runs from the trivial start converge the
     training members of the family A(theta) (their spectra are the targets);
-    the network trains on the device; held-out members then start from
-    diagonal corners with the predicted spectra (falling back to the trivial
-    start after a budget of twice the plain sweeps)."""
+    the network trains on the device; held-out members then start from the
+    predicted spectra, in two readings: (a) diagonal corners (CTM_INIT_DIAG),
+    falling back to the trivial start after a budget of twice the plain
+    sweeps; (b) a trivial run whose corners get the spectra after its first
+    sweep (ctm_set_corner_spectra).  The exact converged spectra in place of
+    the prediction bound what any predictor could gain."""
     import torch
     import synth
     from paper_1711_04798_amd import warmstart as ws
@@ -202,15 +236,29 @@ def warm_leg():
     s_w, sw_w, ok_w, k_w = ws.converge_with_fallback(T_te, w["chi"], w["tol"], w["max_sweeps"], pred,
                                                       warm_budget=2 * int(sw_tv.max()))
     t_warm = time.perf_counter() - t0
+    log("bench: warm-start leg, injected spectra")
+    t0 = time.perf_counter()
+    s_i, sw_i, d_i, k_i = ws.converge_injected(T_te, w["chi"], w["tol"], w["max_sweeps"], pred)
+    t_inj = time.perf_counter() - t0
+    s_x, sw_x, d_x, k_x = ws.converge_injected(T_te, w["chi"], w["tol"], w["max_sweeps"], s_tv)
+    _, sw_xd, d_xd, _ = ws.converge_batch(T_te, w["chi"], w["tol"], 2 * int(sw_tv.max()), spectra=s_tv)
     lg = lambda a: np.log10(np.maximum(a, ws.TARGET_FLOOR))
     mean_pred = lg(s_tr).mean(axis=0)[None]
-    return {"plain_sweeps_mean": float(sw_tv.mean()), "warm_sweeps_mean": float(sw_w.mean()),
-            "warm_converged": int(ok_w.sum()), "n_test": len(T_te), "plain_envs_per_s": len(T_te) / t_plain,
-            "warm_envs_per_s": len(T_te) / t_warm, "n_train": len(T_tr), "train_data_s": t_data,
+    conv = lambda d: int(np.sum(np.asarray(d) < w["tol"]))
+    return {"plain_sweeps_mean": float(sw_tv.mean()),
+            "mlp_diag_sweeps_mean_with_fallback": float(sw_w.mean()), "mlp_diag_converged": int(ok_w.sum()),
+            "mlp_injected_sweeps_mean": float(sw_i.mean()), "mlp_injected_converged": conv(d_i),
+            "exact_injected_sweeps_mean": float(sw_x.mean()), "exact_injected_converged": conv(d_x),
+            "exact_diag_converged": conv(d_xd), "exact_diag_budget": 2 * int(sw_tv.max()),
+            "n_test": len(T_te), "plain_envs_per_s": len(T_te) / t_plain,
+            "mlp_diag_envs_per_s": len(T_te) / t_warm, "mlp_injected_envs_per_s": conv(d_i) / t_inj,
+            "n_train": len(T_tr), "train_data_s": t_data, "train_converged": conv(d_tr),
             "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "pred_log10_err_top8": float(np.abs(lg(pred) - lg(s_tv))[:, :, :8].mean()),
             "mean_predictor_log10_err_top8": float(np.abs(mean_pred - lg(s_tv))[:, :, :8].mean()),
-            "kappa_max_rel_diff": float(np.max(np.abs(k_w - k_tv) / np.abs(k_tv))), "tol": w["tol"],
+            "kappa_max_rel_diff_mlp_diag": float(np.max(np.abs(k_w - k_tv) / np.abs(k_tv))),
+            "kappa_max_rel_diff_mlp_injected": float(np.max(np.abs(k_i - k_tv) / np.abs(k_tv))),
+            "tol": w["tol"],
             "workload": "family A(theta) d=8 D=4 chi=64 1x1, float64 contractions, %d training runs, "
                         "%d held-out" % (len(T_tr), len(T_te))}
 
@@ -284,9 +332,11 @@ def main():
     value = moves / elapsed
     launches = max(tm["stage3_launches"], 1)
     flop_per_launch = tm["stage3_flop"] / launches
+    flop_nominal = tm["stage3_flop_nominal"] / launches
     avg = tm["stage3_s"] / launches
     achieved = flop_per_launch / avg / 1e12 if avg > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
+    live_chi = int(tm["live_chi"])
     out = {
         "metric": "CTM moves/s + MFMA util at D=6 χ=144; converged envs/s batched vs plain",
         "value": value,
@@ -301,27 +351,36 @@ def main():
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": "2x2 checkerboard iPEPS d=8 D=6 chi=144, %s contractions, "
-                               "float64 projector SVD; step = 1 sweep (8 moves) + convergence check"
-                               % args.prec,
+                               "float64 projector SVD; step = 1 sweep (8 moves) + convergence check; "
+                               "contractions at the live extent (chi_live = %d: every index beyond "
+                               "is an exact zero)" % (args.prec, live_chi),
                    "Lx": 2, "Ly": 2, "d": 8, "D": 6, "chi": 144, "seed": 0,
                    "chi_eff": max([r["chi_eff"] for r in status] or [0]),
                    "cutoff": solver_opts(args.prec)["cutoff"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic() if args.prec == "bf16" else None,
+                     "traffic": measured_traffic(live_chi) if args.prec == "bf16" else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "enlarged-corner double-layer contraction (%s, 8 corners "
-                               "per launch, 2 chi^2 D^8 flop each)"
-                               % ("corner_bf16_kernel" if args.prec == "bf16" else "gemm_kernel"),
+                               "per launch, 2 chi_live^2 D^8 flop each)"
+                               % ("corner_bf16_dma_kernel" if args.prec == "bf16" else "gemm_kernel"),
+                     "live_chi": live_chi,
                      "flop_per_launch": flop_per_launch, "avg_launch_s": avg,
-                     "launches": int(launches)},
+                     "launches": int(launches),
+                     "nominal": {"note": "the same launches counted at chi = %d (2 chi^2 D^8 per corner): "
+                                         "work on indices that are exact zeros and are not computed"
+                                         % w["chi"],
+                                 "flop_per_launch": flop_nominal,
+                                 "achieved": flop_nominal / avg / 1e12 if avg > 0 else 0.0,
+                                 "frac": (flop_nominal / avg / 1e12 if avg > 0 else 0.0) / peak}},
         "phase_ms_per_step": {"corner": 1e3 * tp["corner_s"] / phase_steps,
                               "solver": 1e3 * tp["solver_s"] / phase_steps,
                               "absorb": 1e3 * tp["absorb_s"] / phase_steps,
                               "note": "from %d instrumented steps after the timed region" % phase_steps},
     }
     if not args.no_batched:
-        out["batched"] = batched_leg()
+        out["batched"] = batched_leg(BATCHED_FORMS[0])
+        out["batched_fp32"] = batched_leg(BATCHED_FORMS[1])
     if not args.no_warm:
         out["warm_start"] = warm_leg()
     if not args.no_cpu:

@@ -161,9 +161,23 @@ ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,
  * zero-padded.  Syncs. */
 ctm_status ctm_spectra(ctm_ctx ctx, int32_t inst, double* out_host);
 
+/*
+ * Gives every corner of instance `inst` new singular values and keeps its
+ * singular vectors: C = U S V^T becomes U diag(s) V^T, then divided by its
+ * Frobenius norm; the edges are unchanged (the warm-start reading in which
+ * predicted corner spectra are put into an environment mid-run, once the
+ * kept count has grown).  spectrum_host: float64 [Lx*Ly][4][chi] (position
+ * y*Lx+x, corner C1..C4, descending), >= 0; entries past the corner's rank
+ * are ignored.  The convergence measure restarts from the new spectra.  Syncs.
+ */
+ctm_status ctm_set_corner_spectra(ctm_ctx ctx, int32_t inst, const double* spectrum_host);
+
 /* Norm per site kappa = (Z11 Z00 / (Z10 Z01))^(1/(Lx Ly)) of instance `inst`:
  * the cell in its environment, the corners alone, and the two strip pairs
- * joined directly (Sec. III, Eq. "fidelity" and the paragraph after it).  Syncs. */
+ * joined directly (Sec. III, Eq. "fidelity" and the paragraph after it).
+ * 1x1 and 2x2 cells contract Z11 directly; other cells by row transfer, for
+ * which the workspace is planned when chi^2 D^(2 Lx + 2) <= 2^28 (else
+ * CTM_E_INVALID).  Syncs. */
 ctm_status ctm_norm(ctm_ctx ctx, int32_t inst, double* kappa_out);
 
 /*

@@ -20,7 +20,7 @@ INIT = {"trivial": 0, "diag": 1}
 
 EXPORTS = [
     "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
-    "ctm_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
+    "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
     "ctm_last_error", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
@@ -77,6 +77,8 @@ def load(path=LIB_PATH):
     lib.ctm_converge.argtypes = [VP, F64, I32, I32, P(I32), P(F64)]
     lib.ctm_spectra.argtypes = [VP, I32, P(F64)]
     lib.ctm_norm.argtypes = [VP, I32, P(F64)]
+    lib.ctm_set_corner_spectra.argtypes = [VP, I32, P(F64)]
+    lib.ctm_set_corner_spectra.restype = ctypes.c_int
     lib.ctm_rdm.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_expect.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_fidelity.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, F64, I32, P(F64), P(F64), P(I32)]
@@ -238,6 +240,11 @@ class CTM:
         out = np.zeros((self.Lx * self.Ly, 4, self.chi[inst]))
         _check(load().ctm_spectra(self.ctx, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def set_corner_spectra(self, spectra, inst=0):
+        """New singular values [Lx*Ly, 4, chi] for every corner, vectors kept."""
+        sp = np.ascontiguousarray(spectra, dtype=np.float64).reshape(self.Lx * self.Ly, 4, self.chi[inst])
+        _check(load().ctm_set_corner_spectra(self.ctx, inst, sp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def norm(self, inst=0):
         v = ctypes.c_double()

@@ -361,9 +361,12 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     x.ts_scratch = ar.take_bytes((size_t)x.ts_bytes);
   }
   // corner-spectrum SVD scratch (MAXP corners per launch)
+  // (the Jacobi kernel's working set with vectors: 2 chi chi16 per problem)
+  const size_t chi16 = (chi + 15) / 16 * 16;
   x.spec_tmp_U = ar.take<double>(MAXP * c2);
   x.spec_tmp_W = ar.take<double>(MAXP * c2);
-  x.spec_tmp_J = ar.take<double>(MAXP * 2 * c2);
+  x.spec_tmp_S = ar.take<double>(MAXP * chi);
+  x.spec_tmp_J = ar.take<double>(MAXP * 2 * chi * chi16);
   // observables (float64)
   const size_t d = mx_d, a8 = D2 * D2 * D2 * D2;
   Obs& O = x.obs;
@@ -1341,7 +1344,7 @@ ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool fi
       S.p[j] = probs[c0 + j].second;
       U.p[j] = x.spec_tmp_U + (size_t)j * c2;
       W.p[j] = x.spec_tmp_W + (size_t)j * c2;
-      J.p[j] = x.spec_tmp_J + (size_t)j * 2 * c2;
+      J.p[j] = x.spec_tmp_J + (size_t)j * 2 * chi * ((chi + 15) / 16 * 16);
     }
     // corner singular values far below the solver cutoff carry no information
     HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, cnt, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff));
@@ -2318,6 +2321,66 @@ ctm_status ctm_spectra(ctm_ctx x, int32_t inst, double* out) {
   CHK(corner_spectra(*x, std::vector<Inst*>{&I}, false, false));
   HIPCHK(d2h(out, I.spec_new, (size_t)x->Lx * x->Ly * 4 * I.chi_cap * 8, x->stream));
   HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// U[:, j] *= s[j] for the k x k row-major U of every problem
+__global__ void scale_cols_kernel(PtrSet U, CPtrSet S, int k) {
+  double* u = U.p[blockIdx.y];
+  const double* sv = S.p[blockIdx.y];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < k * k; e += gridDim.x * blockDim.x) u[e] *= sv[e % k];
+}
+}  // namespace
+
+extern "C" {
+
+ctm_status ctm_set_corner_spectra(ctm_ctx x, int32_t inst, const double* spec_host) {
+  if (!x || !spec_host || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  hipStream_t s = x->stream;
+  const int npos = x->Lx * x->Ly, nc = 4 * npos, cl = I.chi, cc = I.chi_cap;
+  const size_t c2 = (size_t)cl * cl, n16 = (size_t)2 * cl * ((cl + 15) / 16 * 16);
+  for (size_t i = 0; i < (size_t)nc * cc; ++i)
+    if (!std::isfinite(spec_host[i]) || spec_host[i] < 0) return fail(CTM_E_INVALID, "spectrum must be finite and >= 0");
+  // the new values, staged in spec_new (recomputed below)
+  HIPCHK(h2d(I.spec_new, spec_host, (size_t)nc * cc * 8, s));
+  for (int c0 = 0; c0 < nc; c0 += MAXP) {
+    const int cnt = std::min(MAXP, nc - c0);
+    CPtrSet M{}, Sn{};
+    PtrSet U{}, S{}, W{}, J{};
+    G g;
+    for (int j = 0; j < cnt; ++j) {
+      const int c = c0 + j;
+      double* C = I.C[c % 4][c / 4];
+      M.p[j] = C;
+      U.p[j] = x->spec_tmp_U + (size_t)j * c2;
+      W.p[j] = x->spec_tmp_W + (size_t)j * c2;
+      S.p[j] = x->spec_tmp_S + (size_t)j * cl;
+      J.p[j] = x->spec_tmp_J + (size_t)j * n16;
+      Sn.p[j] = I.spec_new + (size_t)c * cc;
+      g.add(U.p[j], W.p[j], C);
+    }
+    // C = U S W^T, then C <- U diag(s_new) W^T (directions of zero singular
+    // value have no left vector and stay zero)
+    HIPCHK(jacobi_svd(s, cl, M, U, S, W, J, cnt, true, false));
+    HIPCHK(spans({{U.p[0], c2 * cnt * 8}}, "scale cols"));
+    if (!dry_run()) hipLaunchKernelGGL(scale_cols_kernel, dim3(std::max(1, (int)std::min<size_t>(64, (c2 + 255) / 256)), cnt),
+                                       dim3(256), 0, s, U, Sn, cl);
+    HIPCHK(last_err());
+    CHK(gemm_run(s, F64, F64, cl, cl, cl, rowmajor(cl), transposed(rowmajor(cl)), rowmajor(cl), g));
+  }
+  std::vector<std::pair<double*, int64_t>> nt;
+  for (int c = 0; c < nc; ++c) nt.push_back({I.C[c % 4][c / 4], (int64_t)c2});
+  CHK(normalize_run(*x, nt));
+  for (int c = 0; c < 4; ++c)
+    for (int p = 0; p < npos; ++p) I.staleC[c][p] = true;
+  // the convergence measure restarts from the new spectra
+  CHK(corner_spectra(*x, std::vector<Inst*>{&I}, true, true));
+  HIPCHK(ssync(s));
   return CTM_OK;
 }
 

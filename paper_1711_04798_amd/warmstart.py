@@ -47,6 +47,37 @@ def converge_batch(tensors, chi, tol, max_sweeps, spectra=None, batch=256, use_g
     return out_s, out_sw, out_d, out_k
 
 
+def converge_injected(tensors, chi, tol, max_sweeps, spectra, pre_sweeps=1, batch=256, use_graph=True,
+                      device="cuda:0", **solver):
+    """The other reading of a spectrum warm start: every run starts trivially,
+    takes `pre_sweeps` sweeps, then its corners get the given singular values
+    (vectors kept, ctm_set_corner_spectra) and it converges from there.
+
+    Returns (spectra, sweeps including the pre-sweeps, deltas, kappa)."""
+    opts = dict(DEFAULT_SOLVER)
+    opts.update(solver)
+    N = len(tensors)
+    out_s = np.zeros((N, 4, chi))
+    out_sw = np.zeros(N, dtype=np.int64)
+    out_d = np.zeros(N)
+    out_k = np.zeros(N)
+    for i0 in range(0, N, batch):
+        part = tensors[i0:i0 + batch]
+        n = len(part)
+        g = CTM([[A] for A in part], chi=chi, use_graph=use_graph, device=device, **opts)
+        g.converge(tol=0.0, max_sweeps=pre_sweeps)
+        for j in range(n):
+            g.set_corner_spectra(np.asarray(spectra[i0 + j], dtype=np.float64).reshape(1, 4, chi), inst=j)
+        sw, dl, _ = g.converge(tol=tol, max_sweeps=max_sweeps)
+        for j in range(n):
+            out_s[i0 + j] = g.spectra(j)[0]
+            out_k[i0 + j] = g.norm(j)
+        out_sw[i0:i0 + n] = np.asarray(sw) + pre_sweeps
+        out_d[i0:i0 + n] = dl
+        g.close()
+    return out_s, out_sw, out_d, out_k
+
+
 def init_params(seed, n_in, n_hidden, n_out):
     """Initial parameters drawn on the host (normal, scaled by 1/sqrt(fan_in);
     biases zero), in the flat order W1, b1, W2, b2, W3, b3."""
