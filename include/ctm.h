@@ -234,6 +234,46 @@ ctm_status ctm_fidelity_noalloc(const ctm_config* cfg, const double* const* A_de
                                 int32_t* sweeps_out);
 size_t ctm_fidelity_noalloc_max_bytes(void);
 
+/*
+ * Boundary density operator and entanglement entropy of half an infinite
+ * cylinder of circumference nv (Sec. IV, Eq. "Eq:rho" and the paragraph
+ * after it): the reduced density matrix of the half cylinder has the
+ * spectrum of sigma_L^T sigma_R, where sigma_L (sigma_R) is the dominant left
+ * (right) eigenvector of the transfer matrix around the cylinder,
+ * approximated by the CTM edges wrapped around a circle of nv sites.
+ *   sigma_L: the left edges T4 of column `column`, rows y = 0 .. nv-1 (edge of
+ *            row y mod Ly), each edge's up-side chi leg joined to the
+ *            down-side leg of the edge above, the last to the first;
+ *   sigma_R: the same ring of the right edges T2 of column `column - 1`.
+ * Both act on the D^nv virtual indices (v_0 most significant) of the nv bonds
+ * that cross the cut between columns column-1 and column; sigma[(ket),(bra)].
+ * The eigenvalues are found by block Lanczos (`block` start vectors, at most
+ * `krylov` basis vectors, <= D^nv; krylov = D^nv gives the whole spectrum)
+ * on sigma_L^T sigma_R in the sigma_R inner product, which treats sigma_L and
+ * sigma_R as symmetric (exactly so for the fixed point; a truncated or
+ * unconverged environment deviates at the level of its own asymmetry).  All
+ * float64 on the device; the ring applications are GEMMs of the ring state
+ * (chi^2 D^nv doubles).  Results are divided by the exact trace of
+ * sigma_L^T sigma_R (the ring of the double transfer matrices).
+ *   nv: a multiple of Ly.  seed: the Lanczos start vectors.
+ *   ws_dev, ws_bytes: device workspace of ctm_boundary_workspace_size bytes.
+ *   eig_out: host [nev], the largest eigenvalues divided by the trace,
+ *            descending (nev <= krylov; entries past the basis are 0).
+ *   resid_out (may be NULL): host [nev], residual norm estimates of the Ritz
+ *            pairs, divided by the trace (0 when the basis is complete).
+ *   entropy_out (may be NULL): -sum p log p over the returned p > 0 (the
+ *            entanglement entropy when nev eigenvalues hold all the weight).
+ *   weight_out (may be NULL): sum of the returned p.
+ * Returns CTM_E_SOLVER if sigma_R is not positive on a start vector or the
+ * trace vanishes.  Syncs.
+ */
+ctm_status ctm_boundary_workspace_size(ctm_ctx ctx, int32_t inst, int32_t nv, int32_t krylov,
+                                       size_t* bytes);
+ctm_status ctm_boundary_spectrum(ctm_ctx ctx, int32_t inst, int32_t column, int32_t nv,
+                                 int32_t krylov, int32_t block, uint64_t seed, void* ws_dev,
+                                 size_t ws_bytes, int32_t nev, double* eig_out, double* resid_out,
+                                 double* entropy_out, double* weight_out);
+
 /* The environment of Sec. II C (corners C1..C4 chi x chi, edges T1..T4
  * chi x D^2 x chi) of instance `inst` as float64, in the order C1..C4 then
  * T1..T4, each for positions y*Lx+x, legs clockwise around the site,

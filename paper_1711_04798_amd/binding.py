@@ -23,7 +23,7 @@ EXPORTS = [
     "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
-    "ctm_last_error", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
+    "ctm_last_error", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
 
@@ -82,6 +82,11 @@ def load(path=LIB_PATH):
     lib.ctm_rdm.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_expect.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_fidelity.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, F64, I32, P(F64), P(F64), P(I32)]
+    lib.ctm_boundary_workspace_size.argtypes = [VP, I32, I32, I32, P(SZ)]
+    lib.ctm_boundary_workspace_size.restype = ctypes.c_int
+    lib.ctm_boundary_spectrum.argtypes = [VP, I32, I32, I32, I32, I32, ctypes.c_uint64, VP, SZ, I32, P(F64), P(F64),
+                                          P(F64), P(F64)]
+    lib.ctm_boundary_spectrum.restype = ctypes.c_int
     lib.ctm_fidelity_noalloc.argtypes = [cfgp, dpp, dpp, VP, F64, I32, P(F64), P(F64), P(I32)]
     lib.ctm_fidelity_noalloc.restype = ctypes.c_int
     lib.ctm_fidelity_noalloc_max_bytes.argtypes = []
@@ -286,6 +291,30 @@ class CTM:
     def load_checkpoint(self, buf, inst=0):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(load().ctm_checkpoint_load(self.ctx, inst, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
+
+    def boundary_spectrum(self, nv, column=0, krylov=None, block=4, nev=None, seed=7, inst=0):
+        """Leading eigenvalues of sigma_L^T sigma_R on an nv cylinder divided by
+        the trace (ctm_boundary_spectrum): (eigenvalues, residuals, entropy,
+        captured weight)."""
+        lib = load()
+        dim = self.D[inst] ** nv
+        krylov = dim if krylov is None else krylov
+        nev = krylov if nev is None else nev
+        nb = ctypes.c_size_t()
+        _check(lib.ctm_boundary_workspace_size(self.ctx, inst, nv, krylov, ctypes.byref(nb)))
+        ws = self._torch.empty(nb.value + 256, dtype=self._torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        ev = np.zeros(nev)
+        res = np.zeros(nev)
+        ent, wt = ctypes.c_double(), ctypes.c_double()
+        P = ctypes.POINTER(ctypes.c_double)
+        _check(lib.ctm_boundary_spectrum(self.ctx, inst, column, nv, krylov, block, seed,
+                                         ctypes.c_void_p(ws.data_ptr() + off), nb.value, nev,
+                                         ev.ctypes.data_as(P), res.ctypes.data_as(P), ctypes.byref(ent),
+                                         ctypes.byref(wt)))
+        self._torch.cuda.synchronize(self.device)
+        del ws
+        return ev, res, ent.value, wt.value
 
     def set_timing(self, mode=1):
         """1: phases and corner-kernel launches, 2: corner-kernel launches

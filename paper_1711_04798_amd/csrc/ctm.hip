@@ -30,6 +30,7 @@
 #include <array>
 #include <vector>
 
+#include "ctm_internal.h"
 #include "kernels.h"
 #include "solver.h"
 
@@ -2829,3 +2830,19 @@ ctm_status ctm_debug_set_width(ctm_ctx x, int32_t width, int32_t* live_out) {
 
 // error reporting for the other C entry points of the library
 ctm_status ctm_internal_fail(ctm_status s, const char* msg) { return fail(s, msg); }
+
+ctm_status ctm_internal_edge_ring(ctm_ctx x, int inst, int column, CtmEdgeRing* out) {
+  if (!x || !out || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  Inst& I = x->inst[inst];
+  out->stream = x->stream;
+  out->chi = I.chi;
+  out->D = I.D;
+  out->Ly = x->Ly;
+  out->dry = x->reg.dry;
+  const int xl = pmod(column, x->Lx), xr = pmod(column - 1, x->Lx);
+  for (int y = 0; y < x->Ly; ++y) {
+    out->T4[y] = I.T[3][y * x->Lx + xl];
+    out->T2[y] = I.T[1][y * x->Lx + xr];
+  }
+  return CTM_OK;
+}

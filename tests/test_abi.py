@@ -82,6 +82,15 @@ for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
     ck = (ctypes.c_char * nb)()
     st.append(lib.ctm_checkpoint_save(ctx, 0, ck, nb))
     st.append(lib.ctm_checkpoint_load(ctx, 0, ck, nb))
+    if Ly in (1, 2) and D[0] <= 4:
+        nv = 2 * Ly
+        kry = min(D[0] ** nv, 12)
+        wsb = ctypes.c_size_t()
+        st.append(lib.ctm_boundary_workspace_size(ctx, 0, nv, kry, ctypes.byref(wsb)))
+        ev = (ctypes.c_double * kry)(); rs = (ctypes.c_double * kry)()
+        ent = ctypes.c_double(); wt = ctypes.c_double()
+        st.append(lib.ctm_boundary_spectrum(ctx, 0, 0, nv, kry, min(2, kry), 3, ctypes.c_void_p(1 << 44), wsb.value,
+                                            kry, ev, rs, ctypes.byref(ent), ctypes.byref(wt)))
     if True:
         st.append(lib.ctm_norm(ctx, 0, ctypes.byref(k)))
         rho = (ctypes.c_double * (d[0] ** 4))(); h = ctypes.c_double()
