@@ -318,6 +318,30 @@ ctm_status ctm_checkpoint_load(ctm_ctx ctx, int32_t inst, const void* host_buf, 
 ctm_status ctm_set_timing(ctm_ctx ctx, int32_t enable);
 ctm_status ctm_get_timing(ctm_ctx ctx, double* v);
 
+/*
+ * Launch-variant table (process-wide): per kernel family and operand shape,
+ * the tile of the generic GEMM and the split counts of the tall-skinny and
+ * split-K products.  The project's tuner (paper_1711_04798_amd/tune.py) runs
+ * the benchmark workloads with tuning on and saves the table; a later
+ * process loads it (ctm_init loads the file named by the environment
+ * variable CTM_TILE_TABLE once; the Python binding loads the committed
+ * table).  Shapes not in the table use defaults (the generic GEMM still
+ * times its tiles on first use when a context's autotune is on; its
+ * variants give bitwise equal results).
+ *   load: entries of the file (written by save: JSON, one entry per line)
+ *         replace those of equal key; *entries_out = entries read.
+ *   save: writes every entry; *entries_out = entries written.
+ *   tune: on = 1 makes the first launch of every new shape of the split
+ *         products (outside graph capture) time each variant on its own
+ *         operands and store the fastest.  Their variants split the
+ *         contraction differently, so results change at the rounding level
+ *         with the table (a process with one table is deterministic).
+ */
+ctm_status ctm_tile_table_load(const char* path, int32_t* entries_out);
+ctm_status ctm_tile_table_save(const char* path, int32_t* entries_out);
+ctm_status ctm_tile_table_tune(int32_t on);
+ctm_status ctm_tile_table_clear(void);
+
 /* Releases the context (not the workspace). */
 void ctm_destroy(ctm_ctx ctx);
 

@@ -11,6 +11,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctm.so")
+# launch-variant table written by tune.py on an MI355X (loaded with the library)
+TILE_TABLE = os.path.join(_HERE, "tiles.json")
 
 CTM_OK, CTM_E_INVALID, CTM_E_NONFINITE, CTM_E_NOMEM, CTM_E_NOCONV, CTM_E_SOLVER, CTM_E_HIP, CTM_E_STATE = range(8)
 STATUS_NAMES = ["OK", "INVALID", "NONFINITE", "NOMEM", "NOCONV", "SOLVER", "HIP", "STATE"]
@@ -23,7 +25,8 @@ EXPORTS = [
     "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
-    "ctm_last_error", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
+    "ctm_last_error", "ctm_tile_table_load", "ctm_tile_table_save", "ctm_tile_table_tune",
+    "ctm_tile_table_clear", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
 
@@ -54,8 +57,9 @@ class CtmError(RuntimeError):
 _lib = None
 
 
-def load(path=LIB_PATH):
-    """Load libctm.so (raises if it has not been built)."""
+def load(path=LIB_PATH, tile_table=True):
+    """Load libctm.so (raises if it has not been built) and, with tile_table,
+    the committed launch-variant table."""
     global _lib
     if _lib is not None:
         return _lib
@@ -118,12 +122,22 @@ def load(path=LIB_PATH):
     for name in ("ctm_mlp_workspace_size", "ctm_mlp_features", "ctm_mlp_targets", "ctm_mlp_forward",
                  "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train"):
         getattr(lib, name).restype = ctypes.c_int
+    for name in ("ctm_tile_table_load", "ctm_tile_table_save"):
+        getattr(lib, name).argtypes = [ctypes.c_char_p, P(I32)]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.ctm_tile_table_tune.argtypes = [I32]
+    lib.ctm_tile_table_tune.restype = ctypes.c_int
+    lib.ctm_tile_table_clear.argtypes = []
+    lib.ctm_tile_table_clear.restype = ctypes.c_int
     for name in ("ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge", "ctm_spectra",
                  "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_export",
                  "ctm_env_import", "ctm_checkpoint_save", "ctm_checkpoint_load", "ctm_set_timing",
                  "ctm_get_timing"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
+    if tile_table and os.path.exists(TILE_TABLE):
+        n = ctypes.c_int32()
+        _check(lib.ctm_tile_table_load(TILE_TABLE.encode(), ctypes.byref(n)))
     return lib
 
 

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -2105,10 +2106,19 @@ ctm_status ctm_workspace_size(const ctm_config* cfg, size_t* bytes) {
   return CTM_OK;
 }
 
+static std::once_flag g_table_once;
+
 static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, const double* const* B_dev,
                             void* ws_dev, size_t ws_bytes, void* stream, int32_t init,
                             const double* spectrum_host, ctm_ctx* out) {
   if (!out) return fail(CTM_E_INVALID, "null out");
+  // a tile table named by CTM_TILE_TABLE is loaded at the first ctm_init
+  ctm_status tst = CTM_OK;
+  std::call_once(g_table_once, [&] {
+    const char* t = std::getenv("CTM_TILE_TABLE");
+    if (t && t[0]) tst = ctm_tile_table_load(t, nullptr);
+  });
+  if (tst != CTM_OK) return tst;
   *out = nullptr;
   if (!A_dev) return fail(CTM_E_INVALID, "null tensors");
   if (init != CTM_INIT_TRIVIAL && init != CTM_INIT_DIAG) return fail(CTM_E_INVALID, "init kind");
@@ -2815,6 +2825,79 @@ ctm_status ctm_debug_dump(ctm_ctx x, int32_t what, int32_t index, void* buf, siz
   if (bytes != need) return fail(CTM_E_INVALID, "bytes must be " + std::to_string(need));
   HIPCHK(d2h(buf, src, bytes, x->stream));
   HIPCHK(ssync(x->stream));
+  return CTM_OK;
+}
+
+ctm_status ctm_tile_table_load(const char* path, int32_t* entries_out) {
+  if (!path) return fail(CTM_E_INVALID, "null path");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(CTM_E_INVALID, std::string("cannot open ") + path);
+  static const char* names[3] = {"gemm", "ts", "splitk"};
+  char line[1024];
+  int n = 0;
+  auto num = [](const char* l, const char* key, int64_t* out) -> bool {
+    const char* p = std::strstr(l, key);
+    if (!p) return false;
+    p = std::strchr(p + std::strlen(key), ':');
+    if (!p) return false;
+    char* end = nullptr;
+    *out = std::strtoll(p + 1, &end, 10);
+    return end != p + 1;
+  };
+  while (std::fgets(line, sizeof line, f)) {
+    const char* kp = std::strstr(line, "\"kernel\"");
+    if (!kp) continue;
+    int kern = -1;
+    for (int k = 0; k < 3; ++k) {
+      std::string q = std::string("\"") + names[k] + "\"";
+      const char* v = std::strstr(kp + 8, q.c_str());
+      if (v) { kern = k; break; }
+    }
+    int64_t v[9];
+    const char* keys[9] = {"\"ta\"", "\"tc\"", "\"ak\"", "\"bk\"", "\"groups\"", "\"M\"", "\"N\"", "\"K\"",
+                           "\"variant\""};
+    bool ok = kern >= 0;
+    for (int i = 0; i < 9 && ok; ++i) ok = num(line, keys[i], &v[i]);
+    if (!ok || v[8] < 0 || v[8] >= TILE_VARIANTS[kern]) {
+      std::fclose(f);
+      return fail(CTM_E_INVALID, std::string("malformed tile table entry: ") + line);
+    }
+    tile_set(TileKey{kern, (int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], v[5], v[6], v[7]}, (int)v[8]);
+    ++n;
+  }
+  std::fclose(f);
+  if (entries_out) *entries_out = n;
+  return CTM_OK;
+}
+
+ctm_status ctm_tile_table_save(const char* path, int32_t* entries_out) {
+  if (!path) return fail(CTM_E_INVALID, "null path");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(CTM_E_INVALID, std::string("cannot write ") + path);
+  static const char* names[3] = {"gemm", "ts", "splitk"};
+  auto ent = tile_entries();
+  std::fprintf(f, "[\n");
+  for (size_t i = 0; i < ent.size(); ++i) {
+    const TileKey& k = ent[i].first;
+    std::fprintf(f,
+                 "{\"kernel\": \"%s\", \"ta\": %d, \"tc\": %d, \"ak\": %d, \"bk\": %d, \"groups\": %d, "
+                 "\"M\": %lld, \"N\": %lld, \"K\": %lld, \"variant\": %d}%s\n",
+                 names[k.kernel], k.ta, k.tc, k.ak, k.bk, k.groups, (long long)k.M, (long long)k.N, (long long)k.K,
+                 ent[i].second, i + 1 < ent.size() ? "," : "");
+  }
+  std::fprintf(f, "]\n");
+  std::fclose(f);
+  if (entries_out) *entries_out = (int32_t)ent.size();
+  return CTM_OK;
+}
+
+ctm_status ctm_tile_table_tune(int32_t on) {
+  tile_tuning(on != 0);
+  return CTM_OK;
+}
+
+ctm_status ctm_tile_table_clear(void) {
+  tile_clear();
   return CTM_OK;
 }
 

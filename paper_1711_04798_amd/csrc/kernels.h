@@ -119,6 +119,37 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
 void set_tuning(bool on);
 int tuned_entries();
 
+// ---------------------------------------------------------------------------
+// Tile table: the launch variant of each kernel family per operand shape,
+// written by the project's tuner and loaded from its file, or filled in
+// process (the generic GEMM's tile timing above; the split counts of the
+// tall-skinny and split-K products while table tuning is on).
+//   TK_GEMM:   generic GEMM tile (0..3: 64x64, 32x32, 128x64, 128x128)
+//   TK_TS:     tall-skinny split-K product, about 256 << v wave tasks
+//              (v = 0..4, default 3)
+//   TK_SPLITK: float64 split-K Gram products, about 128 << v work-groups
+//              (v = 0..3, default 2)
+// Variants of TK_TS / TK_SPLITK split K differently, so they change the
+// summation order (results differ at the rounding level); a process that
+// uses one table is deterministic.
+// ---------------------------------------------------------------------------
+enum TileKernel : int { TK_GEMM = 0, TK_TS = 1, TK_SPLITK = 2 };
+constexpr int TILE_VARIANTS[3] = {4, 5, 4};
+struct TileKey {
+  int kernel, ta, tc, ak, bk, groups;
+  int64_t M, N, K;
+  bool operator<(const TileKey& o) const;
+};
+// the stored variant of `k`, else dflt
+int tile_lookup(const TileKey& k, int dflt);
+void tile_set(const TileKey& k, int variant);
+void tile_clear();
+std::vector<std::pair<TileKey, int>> tile_entries();
+// while on (process-wide), the first launch of each TK_TS / TK_SPLITK shape
+// outside stream capture times every variant and stores the fastest
+void tile_tuning(bool on);
+bool tile_tuning_on();
+
 // Grouped element copy / conversion: dst[j][i] = (tout) src[j][i], i < n[j].
 constexpr int MAXJ = 32;
 struct XferSet {

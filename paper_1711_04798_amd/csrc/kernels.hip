@@ -6,6 +6,7 @@
 #include <hip/hip_bf16.h>
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -326,12 +327,53 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int ksplit
   }
 }
 
+static hipError_t gemm_splitk_v(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const View& va,
+                                const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
+                                double* scratch, int64_t scratch_elems, int64_t target);
+
 hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const View& va,
                        const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
                        double* scratch, int64_t scratch_elems) {
   if (M <= 0 || N <= 0 || groups <= 0) return hipSuccess;
+  // work-group target from the tile table (512 by default)
+  const TileKey key{TK_SPLITK, F64, F64, va.c_ls == 1, vb.r_ls == 1, groups, M, N, K};
+  int v = tile_lookup(key, -1);
+  if (v < 0 && tile_tuning_on() && beta == 0.0 && !dry_run()) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        float best_ms = 1e30f;
+        int best = 2;
+        for (int t = 0; t < TILE_VARIANTS[TK_SPLITK]; ++t) {
+          float ms_min = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess ||
+                gemm_splitk_v(s, M, N, K, alpha, va, vb, beta, vc, g, groups, scratch, scratch_elems,
+                              (int64_t)128 << t) != hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+              break;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+          }
+          if (ms_min < best_ms) { best_ms = ms_min; best = t; }
+        }
+        tile_set(key, best);
+        v = best;
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  }
+  if (v < 0 || v >= TILE_VARIANTS[TK_SPLITK]) v = 2;
+  return gemm_splitk_v(s, M, N, K, alpha, va, vb, beta, vc, g, groups, scratch, scratch_elems, (int64_t)128 << v);
+}
+
+static hipError_t gemm_splitk_v(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const View& va,
+                                const View& vb, double beta, const View& vc, const GemmGroup& g, int groups,
+                                double* scratch, int64_t scratch_elems, int64_t target) {
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * groups;
-  int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 64));
+  int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>(target / std::max<int64_t>(tiles, 1), K / 64));
   while (ksplit > 1 && ksplit * M * N * groups > scratch_elems) ksplit /= 2;
   if (ksplit <= 1) return gemm(s, F64, F64, M, N, K, alpha, va, vb, beta, vc, g, groups);
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || groups > MAXG) return hipErrorInvalidValue;
@@ -414,6 +456,36 @@ thread_local bool g_tune_on = false;
 }  // namespace
 
 void set_tuning(bool on) { g_tune_on = on; }
+
+namespace {
+std::map<TileKey, int> g_tiles;
+std::mutex g_tiles_mu;
+std::atomic<bool> g_tile_tuning{false};
+}  // namespace
+
+bool TileKey::operator<(const TileKey& o) const {
+  return std::tie(kernel, ta, tc, ak, bk, groups, M, N, K) <
+         std::tie(o.kernel, o.ta, o.tc, o.ak, o.bk, o.groups, o.M, o.N, o.K);
+}
+int tile_lookup(const TileKey& k, int dflt) {
+  std::lock_guard<std::mutex> l(g_tiles_mu);
+  auto it = g_tiles.find(k);
+  return it == g_tiles.end() ? dflt : it->second;
+}
+void tile_set(const TileKey& k, int variant) {
+  std::lock_guard<std::mutex> l(g_tiles_mu);
+  g_tiles[k] = variant;
+}
+void tile_clear() {
+  std::lock_guard<std::mutex> l(g_tiles_mu);
+  g_tiles.clear();
+}
+std::vector<std::pair<TileKey, int>> tile_entries() {
+  std::lock_guard<std::mutex> l(g_tiles_mu);
+  return std::vector<std::pair<TileKey, int>>(g_tiles.begin(), g_tiles.end());
+}
+void tile_tuning(bool on) { g_tile_tuning = on; }
+bool tile_tuning_on() { return g_tile_tuning; }
 int tuned_entries() {
   std::lock_guard<std::mutex> l(g_tune_mu);
   return (int)g_tune.size();
@@ -425,6 +497,11 @@ static int pick_tile(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_
   // one choice per shape, whatever the number of problems in the launch
   TuneKey key{0, ta, tc, va.c_ls == 1, vb.r_ls == 1, 0, M, N, K};
   (void)hipGetDevice(&key.dev);
+  const TileKey tk{TK_GEMM, ta, tc, va.c_ls == 1, vb.r_ls == 1, 0, M, N, K};
+  {
+    const int v = tile_lookup(tk, -1);
+    if (v >= 0 && v < NTILE) return v;
+  }
   {
     std::lock_guard<std::mutex> l(g_tune_mu);
     auto it = g_tune.find(key);
@@ -454,6 +531,7 @@ static int pick_tile(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  tile_set(tk, best);
   std::lock_guard<std::mutex> l(g_tune_mu);
   g_tune[key] = best;
   return best;

@@ -376,9 +376,51 @@ int64_t ts_gemm_scratch_elems(int64_t M, int64_t N, int groups, int nsplit) {
   return (int64_t)nsplit * M * N * groups;
 }
 
+static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
+                            const View& vb, const View& vc, const GemmGroup& g, int groups, void* scratch,
+                            int64_t scratch_bytes, int64_t target);
+
 hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                    const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes) {
   if (groups < 1 || groups > MAXG || !ts_gemm_supported(ta, tc, M, N, K, va, vb, vc)) return hipErrorInvalidValue;
+  // split count target from the tile table (about 2048 wave tasks by default)
+  const TileKey key{TK_TS, ta, tc, va.c_ls == 1, 1, groups, M, N, K};
+  int v = tile_lookup(key, -1);
+  if (v < 0 && tile_tuning_on() && !dry_run()) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      // every variant writes C from A and B only, so the trials are harmless
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        float best_ms = 1e30f;
+        int best = 3;
+        for (int t = 0; t < TILE_VARIANTS[TK_TS]; ++t) {
+          float ms_min = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess ||
+                ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << t) !=
+                    hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+              break;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+          }
+          if (ms_min < best_ms) { best_ms = ms_min; best = t; }
+        }
+        tile_set(key, best);
+        v = best;
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  }
+  if (v < 0 || v >= TILE_VARIANTS[TK_TS]) v = 3;
+  return ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << v);
+}
+
+static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
+                            const View& vb, const View& vc, const GemmGroup& g, int groups, void* scratch,
+                            int64_t scratch_bytes, int64_t target) {
   const bool ak = va.c_ls == 1;
   const int64_t lda = ak ? va.r_ls : va.c_ls, ldb = vb.r_ls, ldc = vc.r_ls;
   const size_t ea = dtype_size(ta), ec = dtype_size(tc);
@@ -391,7 +433,7 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
   // least 8 steps, and partials that fit the scratch
   const int BK = ta == F32 ? 32 : 16;
   const int64_t mtiles = (M + BM - 1) / BM;
-  int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>((2048 + mtiles * groups - 1) / (mtiles * groups),
+  int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>((target + mtiles * groups - 1) / (mtiles * groups),
                                                           K / (8 * BK)));
   while (nsplit > 1 && ts_gemm_scratch_elems(M, N, groups, (int)nsplit) * (int64_t)ea > scratch_bytes) nsplit /= 2;
   if (ts_gemm_scratch_elems(M, N, groups, (int)nsplit) * (int64_t)ea > scratch_bytes) return hipErrorInvalidValue;
@@ -413,7 +455,7 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
     // register-streaming form: 64 rows per wave, K chunks of whole
     // three-block groups, about 2048 waves
     const int64_t mt64 = (M + 63) / 64;
-    int64_t ns2 = std::max<int64_t>(1, std::min<int64_t>((2048 + mt64 * groups - 1) / (mt64 * groups), K / 48));
+    int64_t ns2 = std::max<int64_t>(1, std::min<int64_t>((target + mt64 * groups - 1) / (mt64 * groups), K / 48));
     while (ns2 > 1 && ts_gemm_scratch_elems(M, N, groups, (int)ns2) * 4 > scratch_bytes) ns2 /= 2;
     int64_t kc2 = ((K + ns2 - 1) / ns2 + 47) / 48 * 48;
     ns2 = (K + kc2 - 1) / kc2;

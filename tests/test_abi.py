@@ -4,6 +4,7 @@ orchestration passes the host-side bounds checks in dry-run mode (no GPU:
 every launch and copy is checked against the workspace allocations and then
 skipped)."""
 import ctypes
+import json
 import glob
 import os
 import re
@@ -139,3 +140,36 @@ def test_invalid_configs_rejected(lib_path):
         with pytest.raises(b.CtmError) as e:
             b.workspace_size(cfg)
         assert e.value.status == b.CTM_E_INVALID
+
+
+def test_tile_table_roundtrip(lib_path, tmp_path):
+    """The launch-variant table written by save reads back entry for entry;
+    a malformed entry is rejected."""
+    code = r'''
+import ctypes, json, sys
+sys.path.insert(0, %(root)r)
+from paper_1711_04798_amd import binding as b
+lib = b.load(tile_table=False)
+lib.ctm_tile_table_clear()
+src, dst, bad = sys.argv[1], sys.argv[2], sys.argv[3]
+n = ctypes.c_int32()
+assert lib.ctm_tile_table_load(src.encode(), ctypes.byref(n)) == 0 and n.value == 3
+assert lib.ctm_tile_table_save(dst.encode(), ctypes.byref(n)) == 0 and n.value == 3
+print(lib.ctm_tile_table_load(bad.encode(), ctypes.byref(n)))
+''' % {"root": ROOT}
+    entries = [
+        {"kernel": "ts", "ta": 1, "tc": 0, "ak": 1, "bk": 1, "groups": 2, "M": 1728, "N": 48, "K": 1728, "variant": 1},
+        {"kernel": "gemm", "ta": 0, "tc": 0, "ak": 1, "bk": 0, "groups": 0, "M": 48, "N": 1728, "K": 48, "variant": 3},
+        {"kernel": "splitk", "ta": 0, "tc": 0, "ak": 0, "bk": 1, "groups": 2, "M": 48, "N": 48, "K": 1728,
+         "variant": 0},
+    ]
+    src, dst, bad = tmp_path / "a.json", tmp_path / "b.json", tmp_path / "c.json"
+    src.write_text("[\n" + ",\n".join(json.dumps(e) for e in entries) + "\n]\n")
+    bad.write_text('[\n{"kernel": "ts", "ta": 1, "variant": 9}\n]\n')
+    r = subprocess.run([sys.executable, "-c", code, str(src), str(dst), str(bad)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"  # CTM_E_INVALID
+    key = lambda e: (e["kernel"], e["ta"], e["tc"], e["ak"], e["bk"], e["groups"], e["M"], e["N"], e["K"])
+    got = json.loads(dst.read_text())
+    assert sorted((key(e), e["variant"]) for e in got) == sorted((key(e), e["variant"]) for e in entries)
