@@ -121,8 +121,9 @@ BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sw
 # float64 contractions reach Delta < 1e-6; float32 contractions do not (their
 # corner spectra keep changing by ~1e-5 .. 1e-4 per sweep), so the float32
 # form is run to 1e-4
-BATCHED_FORMS = [dict(prec="fp64", max_iters=3, tol=1e-6, plain_per_class=2),
-                 dict(prec="fp32", max_iters=2, tol=1e-4, plain_per_class=1)]
+BATCHED_FORMS = [dict(prec="fp64", max_iters=3, tol=1e-6, plain_per_class=2, concurrent=True),
+                 dict(prec="fp64", max_iters=3, tol=1e-6, plain_per_class=0, concurrent=False),
+                 dict(prec="fp32", max_iters=2, tol=1e-4, plain_per_class=1, concurrent=True)]
 
 
 def batched_leg(form):
@@ -140,10 +141,12 @@ def batched_leg(form):
     inst = synth.batched_instances(b["seed"], b["n_inst"], d=b["d"], Ds=b["Ds"], chis=b["chis"])
     kw = dict(prec=b["prec"], max_iters=b["max_iters"], resid_tol=0.0,
               cutoff=1e-8 if b["prec"] == "fp64" else 1e-6)
-    log("bench: batched leg, %d instances, %s, tol %g" % (len(inst), b["prec"], b["tol"]))
+    log("bench: batched leg, %d instances, %s, tol %g, concurrent class branches %s"
+        % (len(inst), b["prec"], b["tol"], b["concurrent"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g = CTM([[A] for _, _, A in inst], chi=[c for _, c, _ in inst], use_graph=True, **kw)
+    g = CTM([[A] for _, _, A in inst], chi=[c for _, c, _ in inst], use_graph=True,
+            concurrent_classes=b["concurrent"], **kw)
     t_init = time.perf_counter() - t0
     t0 = time.perf_counter()
     sw, dl, ok = g.converge(tol=b["tol"], max_sweeps=b["max_sweeps"])
@@ -156,6 +159,11 @@ def batched_leg(form):
     n_conv = sum(conv)
     log("bench: batched converge %.2f s (init %.2f s), %d/%d converged, sweeps max %d"
         % (t_b, t_init, n_conv, len(inst), max(sw)))
+    if not b["plain_per_class"]:
+        return {"envs_per_s": n_conv / t_b, "converged": n_conv, "n_inst": len(inst), "tol": b["tol"],
+                "time_s": t_b, "sweeps_mean": float(np.mean(sw)), "dtype": b["prec"],
+                "concurrent_class_branches": b["concurrent"],
+                "unit": "converged environments/s (converged instances only)"}
     # plain: stratified sample, per class time per instance
     classes = sorted({(D, c) for D, c, _ in inst})
     per_class = {}
@@ -191,7 +199,7 @@ def batched_leg(form):
                                                                      b["plain_per_class"] * len(classes)),
             "plain_sweeps_mean_by_class": {"D%d_chi%d" % c: per_class[c][2] for c in classes},
             "plain_converged_frac_by_class": {"D%d_chi%d" % c: per_class[c][1] for c in classes},
-            "dtype": b["prec"],
+            "dtype": b["prec"], "concurrent_class_branches": b["concurrent"],
             "workload": "256 1x1 iPEPS, d=8, D in {3,4,5}, chi in {32,64,100} per instance (seed 0), "
                         "%s contractions, one HIP graph per sweep of every live instance; plain = one "
                         % b["prec"] +
@@ -380,7 +388,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
-        out["batched_fp32"] = batched_leg(BATCHED_FORMS[1])
+        out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])
+        out["batched_fp32"] = batched_leg(BATCHED_FORMS[2])
     if not args.no_warm:
         out["warm_start"] = warm_leg()
     if not args.no_cpu:

@@ -94,6 +94,11 @@ typedef struct {
                               timing off and a non-NULL stream (default 0)         */
   int32_t autotune;        /* 1: time the GEMM tile variants on first use of each
                               shape and keep the fastest (default 1)               */
+  int32_t concurrent_classes; /* graph mode with several shape classes: 1 makes
+                              each class's sweep a concurrent branch of the
+                              captured graph (own stream while capturing, own
+                              scratch), 0 captures the classes one after the
+                              other (default 1)                                   */
 } ctm_config;
 
 /* Fills *cfg with the defaults above for one instance (caller sets the rest). */

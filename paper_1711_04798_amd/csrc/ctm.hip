@@ -223,6 +223,17 @@ struct ctm_ctx_s {
   double* spec_tmp_W = nullptr;
   double* spec_tmp_S = nullptr;
   double* spec_tmp_J = nullptr;
+  // the scratch above (split-K partials, tall-skinny partials, normalisation
+  // partials, corner SVD) in sets: set 0 serves the eager path, and in graph
+  // mode with concurrent classes class i's branch of the captured sweep uses
+  // set i; use_scratch() points the fields above at one set
+  struct ScratchSet {
+    double *splitk, *norm_part, *U, *W, *S, *J;
+    void* ts;
+  };
+  std::vector<ScratchSet> scratch_sets;
+  std::vector<hipStream_t> class_streams;  // branches of the captured sweep
+  std::vector<hipEvent_t> class_events;    // fork (0) and joins (1 ..)
   size_t ws_need = 0;
   bool timing = false;
   double t_corner = 0, t_solver = 0, t_absorb = 0, t_stage3 = 0, stage3_flop = 0, stage3_flop_nom = 0;
@@ -253,6 +264,23 @@ int qtype_of(int prec) { return prec == CTM_FP64 ? F64 : F32; }
 int subspace_dim(const ctm_config& c, int chi, int n) {
   int p = c.svd_oversample > 0 ? c.svd_oversample : 0;
   return std::min(n, chi + p);
+}
+
+// graph mode with several shape classes: each class's sweep is a concurrent
+// branch of the captured graph, with a scratch set of its own
+bool concurrent_classes(const ctm_ctx_s& x) {
+  return x.cfg.use_graph && x.cfg.concurrent_classes && x.classes.size() > 1;
+}
+
+void use_scratch(ctm_ctx_s& x, size_t i) {
+  const auto& ss = x.scratch_sets[i];
+  x.splitk = ss.splitk;
+  x.ts_scratch = ss.ts;
+  x.norm_part = ss.norm_part;
+  x.spec_tmp_U = ss.U;
+  x.spec_tmp_W = ss.W;
+  x.spec_tmp_S = ss.S;
+  x.spec_tmp_J = ss.J;
 }
 
 void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
@@ -303,7 +331,6 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   }
   x.delta_all = ar.take<double>((size_t)x.ninst);
   x.flag_all = ar.take<int>((size_t)4 * x.ninst);
-  x.norm_part = ar.take<double>((size_t)MAXJ * 64);
   for (int i = 0; i < x.ninst; ++i) {
     Inst& I = x.inst[i];
     const size_t t5 = (size_t)I.d * I.D2 * I.D2;
@@ -354,21 +381,27 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   const size_t c2 = chi * chi, t3 = c2 * D2, y4 = t3 * D2;
   // split-K partials of the k x n x k products (all problems of a launch)
   x.splitk_elems = (int64_t)64 * k * k * x.max_prob;
-  x.splitk = ar.take<double>((size_t)x.splitk_elems);
   // K-chunk partials of the tall-skinny products (n x k and chi x chi outputs)
   {
     const int64_t cols = (int64_t)std::max(k, chi);
     const int64_t want = (int64_t)16 * (int64_t)std::max(n, chi) * cols * std::min(MAXG, x.max_prob) * 8;
     x.ts_bytes = std::min<int64_t>(want, (int64_t)256 << 20);
-    x.ts_scratch = ar.take_bytes((size_t)x.ts_bytes);
   }
   // corner-spectrum SVD scratch (MAXP corners per launch)
   // (the Jacobi kernel's working set with vectors: 2 chi chi16 per problem)
   const size_t chi16 = (chi + 15) / 16 * 16;
-  x.spec_tmp_U = ar.take<double>(MAXP * c2);
-  x.spec_tmp_W = ar.take<double>(MAXP * c2);
-  x.spec_tmp_S = ar.take<double>(MAXP * chi);
-  x.spec_tmp_J = ar.take<double>(MAXP * 2 * chi * chi16);
+  const size_t nsets = concurrent_classes(x) ? x.classes.size() : 1;
+  x.scratch_sets.assign(nsets, ctm_ctx_s::ScratchSet{});
+  for (auto& ss : x.scratch_sets) {
+    ss.splitk = ar.take<double>((size_t)x.splitk_elems);
+    ss.ts = ar.take_bytes((size_t)x.ts_bytes);
+    ss.norm_part = ar.take<double>((size_t)MAXJ * 64);
+    ss.U = ar.take<double>(MAXP * c2);
+    ss.W = ar.take<double>(MAXP * c2);
+    ss.S = ar.take<double>(MAXP * chi);
+    ss.J = ar.take<double>(MAXP * 2 * chi * chi16);
+  }
+  use_scratch(x, 0);
   // observables (float64)
   const size_t d = mx_d, a8 = D2 * D2 * D2 * D2;
   Obs& O = x.obs;
@@ -1664,20 +1697,50 @@ std::vector<Inst*> live_insts(ctm_ctx_s& x, const std::vector<int>& cls, const s
 // shape has been tuned.
 ctm_status capture_sweep(ctm_ctx_s& x, const std::vector<char>& live) {
   if (x.gexec) return CTM_OK;
+  const bool conc = concurrent_classes(x);
+  hipStream_t main = x.stream;
+  if (conc && x.class_streams.empty()) {
+    // default priority (no priority argument)
+    x.class_streams.assign(x.classes.size(), nullptr);
+    for (auto& cs : x.class_streams) HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    x.class_events.assign(x.classes.size() + 1, nullptr);
+    for (auto& ev : x.class_events) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
   hipGraph_t g = nullptr;
-  HIPCHK(hipStreamBeginCapture(x.stream, hipStreamCaptureModeThreadLocal));
+  HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
   ctm_status st = CTM_OK;
   const int64_t moves0 = x.moves;
-  for (auto& cls : x.classes) {
+  hipError_t ef = conc ? hipEventRecord(x.class_events[0], main) : hipSuccess;
+  std::vector<char> forked(x.classes.size(), 0);
+  for (size_t ci = 0; ci < x.classes.size() && ef == hipSuccess; ++ci) {
+    const auto& cls = x.classes[ci];
     std::vector<Inst*> insts = live_insts(x, cls, live);
     if (insts.empty()) continue;
+    if (conc) {
+      // a branch of its own: forked from the main stream, own scratch
+      ef = hipStreamWaitEvent(x.class_streams[ci], x.class_events[0], 0);
+      if (ef != hipSuccess) break;
+      forked[ci] = 1;
+      x.stream = x.class_streams[ci];
+      use_scratch(x, ci);
+    }
     st = do_sweep(x, insts);
-    if (st != CTM_OK) break;
-    st = corner_spectra(x, insts, false, true);
+    if (st == CTM_OK) st = corner_spectra(x, insts, false, true);
+    if (conc) {
+      ef = hipEventRecord(x.class_events[ci + 1], x.class_streams[ci]);
+      x.stream = main;
+      use_scratch(x, 0);
+    }
     if (st != CTM_OK) break;
   }
+  // join every branch back into the main stream (also after a failure, so
+  // that the capture ends cleanly)
+  for (size_t ci = 0; ci < x.classes.size(); ++ci)
+    if (forked[ci]) (void)hipStreamWaitEvent(main, x.class_events[ci + 1], 0);
+  x.stream = main;
   x.moves = moves0;
   hipError_t e = hipStreamEndCapture(x.stream, &g);
+  if (st == CTM_OK && ef != hipSuccess) st = hip_fail(ef, "graph branch fork/join");
   if (st != CTM_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
@@ -2096,6 +2159,7 @@ void ctm_config_default(ctm_config* c) {
   c->seed = 12345;
   c->use_graph = 0;
   c->autotune = 1;
+  c->concurrent_classes = 1;
 }
 
 ctm_status ctm_workspace_size(const ctm_config* cfg, size_t* bytes) {
@@ -2631,6 +2695,11 @@ ctm_status ctm_get_timing(ctm_ctx x, double* v) {
 void ctm_destroy(ctm_ctx x) {
   if (!x) return;
   if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
+  for (hipStream_t cs : x->class_streams) {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+  }
+  for (hipEvent_t ev : x->class_events) (void)hipEventDestroy(ev);
   if (x->tused || x->sused) (void)hipStreamSynchronize(x->stream);
   for (auto& r : x->tpool)
     for (hipEvent_t e : r) (void)hipEventDestroy(e);
@@ -2717,6 +2786,7 @@ ctm_status ctm_fidelity_noalloc(const ctm_config* cfg, const double* const* A_de
   ctm_config c = *cfg;
   c.use_graph = 0;
   c.autotune = 0;
+  c.concurrent_classes = 0;
   size_t need = 0;
   CHK(ctm_workspace_size(&c, &need));
   if (need > STATIC_WS_BYTES)
