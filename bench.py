@@ -33,7 +33,8 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
 WORKLOAD = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], d=8, D=6, chi=144, seed=0)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "corner_bf16_2x2_d8_D6_chi144_hbm_counters.md")
+# committed counter summaries, one per live extent of the corner kernel
+COUNTERS = os.path.join(ROOT, "profiles", "corner_bf16_2x2_d8_D6_chi144_live%d_hbm_counters.md")
 CORNER_SRC = os.path.join(ROOT, "paper_1711_04798_amd", "csrc", "corner_bf16.hip")
 
 
@@ -44,7 +45,7 @@ def measured_traffic(live_chi):
     import hashlib
     try:
         sha = hashlib.sha1(open(CORNER_SRC, "rb").read()).hexdigest()
-        fields = dict(l.split(":", 1) for l in open(COUNTERS).read().splitlines()
+        fields = dict(l.split(":", 1) for l in open(COUNTERS % int(live_chi)).read().splitlines()
                       if l.startswith(("source_sha1:", "hbm_bytes_per_launch:", "live_chi:")))
         if fields.get("source_sha1", "").strip() != sha:
             return None
@@ -115,6 +116,46 @@ def cpu_baseline(tensors):
             "sample": "one plaquette row (4 enlarged corners, dense float64 half-system "
                       "SVD of n=5184, absorption) of one column step, %.1f s; value = 1/(2 t)"
                       % dt}
+
+
+def dense_extent_leg(tensors, prec, warm=1, steps=3):
+    """The enlarged-corner kernel at the full extent chi = 144 (M = chi^2 =
+    20736 rows per corner): the subspace width is pinned at chi + 16 so that
+    every contraction runs at the configured chi, as it would for a state
+    whose kept rank reaches chi.  Timed like the main leg (HIP events around
+    each launch of the kernel)."""
+    import ctypes
+    import torch
+    from paper_1711_04798_amd import CTM, binding
+    w = WORKLOAD
+    lib = binding.load()
+    lib.ctm_debug_set_width.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.ctm_debug_set_width.restype = ctypes.c_int
+    g = CTM([tensors], Lx=w["Lx"], Ly=w["Ly"], pattern=w["pattern"], chi=w["chi"], prec=prec,
+            **solver_opts(prec))
+    g.converge(tol=0.0, max_sweeps=2)
+    live = ctypes.c_int32()
+    assert lib.ctm_debug_set_width(g.ctx, w["chi"] + 16, ctypes.byref(live)) == 0
+    for _ in range(warm):
+        g.converge(tol=0.0, max_sweeps=1)
+    torch.cuda.synchronize()
+    g.set_timing(2)
+    for _ in range(steps):
+        g.converge(tol=0.0, max_sweeps=1)
+    torch.cuda.synchronize()
+    tm = g.timing()
+    g.set_timing(0)
+    g.close()
+    launches = max(tm["stage3_launches"], 1)
+    flop = tm["stage3_flop"] / launches
+    avg = tm["stage3_s"] / launches
+    ach = flop / avg / 1e12 if avg > 0 else 0.0
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": ach / PEAK_TFLOPS[prec], "live_chi": int(tm["live_chi"]), "flop_per_launch": flop,
+            "avg_launch_s": avg, "launches": int(launches),
+            "traffic": measured_traffic(int(tm["live_chi"])) if prec == "bf16" else None,
+            "note": "enlarged-corner kernel at the full extent (subspace width pinned at chi + 16; "
+                    "8 corners of M = chi^2 = 20736 rows, N = K = D^4 = 1296 per launch)"}
 
 
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
@@ -280,6 +321,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-full", action="store_true", help="skip the full-extent corner-kernel leg")
+    ap.add_argument("--full-extent-only", action="store_true",
+                    help="only the corner kernel at the full extent (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -305,6 +349,9 @@ def main():
 
     w = WORKLOAD
     tensors = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)
+    if args.full_extent_only:
+        print(json.dumps({"roofline_full_extent": dense_extent_leg(tensors, args.prec)}), flush=True)
+        return
     log("bench: init chi=%d D=%d prec=%s" % (w["chi"], w["D"], args.prec))
     g = CTM([tensors], Lx=w["Lx"], Ly=w["Ly"], pattern=w["pattern"], chi=w["chi"],
             prec=args.prec, **solver_opts(args.prec))
@@ -386,6 +433,9 @@ def main():
                               "absorb": 1e3 * tp["absorb_s"] / phase_steps,
                               "note": "from %d instrumented steps after the timed region" % phase_steps},
     }
+    if not args.no_full:
+        log("bench: enlarged-corner kernel at the full extent")
+        out["roofline_full_extent"] = dense_extent_leg(tensors, args.prec)
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
         out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])

@@ -73,8 +73,10 @@ ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_b
  * Sets the projector subspace width of every instance to `width` (clamped
  * to 1 .. chi + oversample) and re-lays the environment out at the live
  * extent that follows, as the convergence loop does when the kept count
- * changes; *live_out (may be NULL) receives the live extent of instance 0.
- * Lets host-only runs (CTM_DRY_RUN) walk the narrowed-extent code paths.
+ * changes, and pins it (the convergence loop and moves keep it) until a
+ * call with width <= 0; *live_out (may be NULL) receives the live extent of
+ * instance 0.  Lets host-only runs (CTM_DRY_RUN) walk the narrowed-extent
+ * code paths, and timing runs hold the contractions at a chosen extent.
  */
 ctm_status ctm_debug_set_width(ctm_ctx ctx, int32_t width, int32_t* live_out);
 

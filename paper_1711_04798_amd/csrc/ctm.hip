@@ -245,6 +245,7 @@ struct ctm_ctx_s {
   // stream between column steps)
   bool phase_timing = false;
   bool resid_step = true;  // fixed-count solver: form the residuals in this column step
+  bool width_pinned = false;  // ctm_debug_set_width: the convergence loop keeps the width
   std::vector<std::array<hipEvent_t, 4>> tpool;
   std::vector<std::array<hipEvent_t, 2>> spool;
   size_t tused = 0, sused = 0;
@@ -1630,7 +1631,7 @@ ctm_status set_width(ctm_ctx_s& x, const std::vector<int>& cls, int kn) {
 // the cutoff, then set the truncation), the width grows by the oversampling.
 ctm_status grow_if_capped(ctm_ctx_s& x, const std::vector<int>& cls) {
   Inst& J = x.inst[cls[0]];
-  if (J.k_act >= J.k) return CTM_OK;
+  if (J.k_act >= J.k || x.width_pinned) return CTM_OK;
   int ce = 0;
   for (int i : cls) {
     Inst& I = x.inst[i];
@@ -2346,7 +2347,7 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
       for (int i : cls)
         if (live[i]) ce = std::max(ce, hf[4 * i + 1]);
       Inst& J = x->inst[cls[0]];
-      const bool cap = ce > 0 && ce >= J.k_act && J.k_act < J.k;
+      const bool cap = ce > 0 && ce >= J.k_act && J.k_act < J.k && !x->width_pinned;
       if (cap)
         for (int i : cls) capped[i] = 1;
       const int p = std::max(0, x->cfg.svd_oversample);
@@ -2356,7 +2357,7 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
       if (!(x->cfg.svd_resid_tol > 0) && p >= 8 && kw / 16 * 16 >= ce + p - 4) kw = kw / 16 * 16;
       if (cap) kw = std::max(kw, J.k_act + std::max(1, p));
       const int kn = std::max(1, std::min(J.k, kw));
-      if (ce > 0 && kn != J.k_act) {
+      if (ce > 0 && kn != J.k_act && !x->width_pinned) {
         CHK(set_width(*x, cls, kn));
         eager_next = true;
         drop_graph(*x);
@@ -2974,7 +2975,9 @@ ctm_status ctm_tile_table_clear(void) {
 ctm_status ctm_debug_set_width(ctm_ctx x, int32_t width, int32_t* live_out) {
   if (!x) return fail(CTM_E_INVALID, "null ctx");
   RegGuard guard(&x->reg);
-  for (auto& cls : x->classes) CHK(set_width(*x, cls, width));
+  x->width_pinned = width > 0;
+  if (width > 0)
+    for (auto& cls : x->classes) CHK(set_width(*x, cls, width));
   if (live_out) *live_out = x->inst[0].chi;
   return CTM_OK;
 }
