@@ -263,3 +263,30 @@ def test_set_corner_spectra_lockstep(gpu):
     ko, kg = oobs.kappa(cell, env), g.norm()
     g.close()
     assert abs(kg - ko) <= 1e-10 * abs(ko)
+
+
+def test_ruby_trivial_legs_by_padding(gpu):
+    """Ruby-faithful block tensors (d = 8: A with a trivial down leg, B with a
+    trivial up leg, the other legs D = 3) run on the GPU zero-padded to D = 3
+    on every leg, against the oracle with the true D = 1 legs: corner spectra
+    after every column step of two sweeps, then kappa and the eight bond
+    energies of the ruby model."""
+    from paper_1711_04798_amd import CTM
+    from test_oracle_pins import ruby_trivial_leg_tensors, pad_legs
+    A, B = ruby_trivial_leg_tensors(42, 8, 3)
+    print("case ruby trivial legs", flush=True)
+    g = CTM([[pad_legs(A, 3), pad_legs(B, 3)]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=24, cutoff=1e-8)
+    cell = octm.Cell(2, 2, [0, 1, 1, 0], [A, B])
+    env = octm.init_trivial(cell, 24)
+    worst = _lockstep(g, cell, env, 2, 2, 2, 1e-8)
+    ko, kg = oobs.kappa(cell, env), g.norm()
+    assert abs(kg - ko) <= 1e-10 * abs(ko)
+    bh = models.ruby_bond_h()
+    for v in (False, True):
+        for x, y in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            h = bh(x, y, v)
+            eo = float(np.real(np.trace(oobs.rdm(cell, env, x, y, v) @ h)))
+            eg = g.expect(x, y, v, h)
+            assert abs(eg - eo) <= 1e-10 * max(1.0, abs(eo)), (x, y, v, eg, eo)
+    g.close()
+    print("ruby trivial legs: worst spectra %.2e, kappa rel %.2e" % (worst, abs(kg - ko) / abs(ko)))

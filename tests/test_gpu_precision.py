@@ -98,3 +98,28 @@ def test_precision_benchmark_size(gpu, prec):
     """2x2 checkerboard, d=8, D=6, chi=144 (the benchmark workload)."""
     print("case precision c2", prec, flush=True)
     _check("c2", 6, 144, prec, 12)
+
+
+FID_BOUND = {"fp32": 1e-6, "bf16": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_precision_fidelity(gpu, prec):
+    """Fidelity per site of two nearby ruby-size checkerboard states (d=8,
+    D=4, chi=64; the second set is the first plus 0.1 times seeded noise):
+    the reduced-precision runs (fixed sweep count, their spectra fluctuate at
+    the rounding level) against the converged float64 run."""
+    from paper_1711_04798_amd import binding
+    A = synth.cell_tensors(0, 8, 4, 2)
+    rng = np.random.default_rng(50)
+    B = [a + 0.1 * synth.peps_tensor(rng, 8, 4) for a in A]
+    B = [b / np.linalg.norm(b) for b in B]
+    kw = dict(Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=64)
+    print("case precision fidelity", prec, flush=True)
+    d64, _, sw64, ok64 = binding.fidelity(A, B, tol=1e-10, max_sweeps=60, cutoff=1e-8, **kw)
+    assert ok64, sw64
+    dr, _, swr, _ = binding.fidelity(A, B, prec=prec, tol=0.0, max_sweeps=20, max_iters=2, resid_tol=0.0,
+                                     cutoff=1e-7, **kw)
+    rel = abs(dr - d64) / d64
+    print("fidelity per site: float64 %.12f (sweeps %s), %s %.12f, rel err %.2e" % (d64, sw64, prec, dr, rel))
+    assert rel < FID_BOUND[prec]

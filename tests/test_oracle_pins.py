@@ -550,3 +550,43 @@ def test_init_diag_enlarged_corner_is_kronecker():
     Q = ctm.enlarged_corner(env.C[0][(0, 0)], env.T[0][(0, 0)], env.T[3][(0, 0)], cell.a(0, 0))
     ref = np.kron(env.C[0][(0, 0)], at) / (chi * D)
     assert np.abs(Q - ref).max() < 1e-15 * np.abs(ref).max() * 10
+
+
+# ---------------------------------------------------------------------------
+# ruby-faithful block tensors: one trivial (D = 1) leg per block site
+# ---------------------------------------------------------------------------
+def ruby_trivial_leg_tensors(seed, d, D):
+    """Checkerboard tensors with the trivial bond of each block site (caption
+    of Fig. 2: three bonds of dimension D and one of dimension 1): A (x + y
+    even) has a trivial down leg, B a trivial up leg, so every other vertical
+    bond of the cell is absent (the brick-wall structure of the coarse-grained
+    lattice)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((d, D, D, 1, D))
+    B = rng.standard_normal((d, 1, D, D, D))
+    return A / np.linalg.norm(A), B / np.linalg.norm(B)
+
+
+def pad_legs(T, D):
+    """Zero-pad every bond leg of T[s, u, l, d, r] to D."""
+    out = np.zeros((T.shape[0], D, D, D, D), dtype=T.dtype)
+    out[:, :T.shape[1], :T.shape[2], :T.shape[3], :T.shape[4]] = T
+    return out
+
+
+def test_trivial_legs_equal_zero_padding():
+    """A D = 1 leg and the same leg zero-padded to D describe the same network:
+    with nothing truncated differently (padding adds only zero singular
+    values), kappa, every bond density matrix and the corner spectra agree
+    between the 2x2 cell with true trivial legs and the padded one."""
+    A, B = ruby_trivial_leg_tensors(41, 2, 2)
+    c1 = ctm.Cell(2, 2, [0, 1, 1, 0], [A, B])
+    c2 = ctm.Cell(2, 2, [0, 1, 1, 0], [pad_legs(A, 2), pad_legs(B, 2)])
+    e1, e2 = _converged(c1, 12, 20), _converged(c2, 12, 20)
+    assert abs(obs.kappa(c1, e1) - obs.kappa(c2, e2)) < 1e-12 * abs(obs.kappa(c1, e1))
+    for v in (False, True):
+        for x, y in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            assert np.abs(obs.rdm(c1, e1, x, y, v) - obs.rdm(c2, e2, x, y, v)).max() < 1e-11
+    s1, s2 = ctm.corner_spectra(e1), ctm.corner_spectra(e2)
+    for key in s1:
+        assert max(np.abs(a - b).max() for a, b in zip(s1[key], s2[key])) < 1e-11
