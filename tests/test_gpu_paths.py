@@ -270,7 +270,10 @@ def test_ruby_trivial_legs_by_padding(gpu):
     trivial up leg, the other legs D = 3) run on the GPU zero-padded to D = 3
     on every leg, against the oracle with the true D = 1 legs: corner spectra
     after every column step of two sweeps, then kappa and the eight bond
-    energies of the ruby model."""
+    energies of the ruby model.  (On this brick wall every corner matrix
+    stays rank 1 -- each corner absorbs its edges through a missing bond --
+    so the environment lives in the edges, and kappa and the energies are
+    the informative checks.)"""
     from paper_1711_04798_amd import CTM
     from test_oracle_pins import ruby_trivial_leg_tensors, pad_legs
     A, B = ruby_trivial_leg_tensors(42, 8, 3)
