@@ -58,7 +58,7 @@ DRY = r'''
 import ctypes, json, sys
 sys.path.insert(0, %(root)r)
 from paper_1711_04798_amd import binding as b
-lib = b.load()
+lib = b.load(%(lib)r)
 out = {}
 for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
     cfg, keep = b.make_config(Lx, Ly, pat, nt, d, D, chi, prec, max_iters=2)
@@ -83,6 +83,10 @@ for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
     ck = (ctypes.c_char * nb)()
     st.append(lib.ctm_checkpoint_save(ctx, 0, ck, nb))
     st.append(lib.ctm_checkpoint_load(ctx, 0, ck, nb))
+    eb = lib.ctm_env_bytes(ctx, 0)
+    eh = (ctypes.c_char * eb)()
+    st.append(lib.ctm_env_export(ctx, 0, eh, eb))
+    st.append(lib.ctm_env_import(ctx, 0, eh, eb))
     if Ly in (1, 2) and D[0] <= 4:
         nv = 2 * Ly
         kry = min(D[0] ** nv, 12)
@@ -119,7 +123,7 @@ CASES = [
 
 def test_dry_run_orchestration(lib_path):
     import json
-    code = DRY % {"root": ROOT, "cases": CASES}
+    code = DRY % {"root": ROOT, "cases": CASES, "lib": lib_path}
     env = dict(os.environ, CTM_DRY_RUN="1")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stderr
