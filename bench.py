@@ -79,11 +79,11 @@ def solver_status(g):
                                    ctypes.c_size_t]
     out = []
     for r in range(max(g.Lx, g.Ly)):
-        buf = np.zeros(12, dtype=np.int32)
+        buf = np.zeros(14, dtype=np.int32)
         if lib.ctm_debug_dump(g.ctx, 3, r, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes) == 0:
             f = buf.view(np.float64)
             out.append({"chi_eff": int(buf[0]), "iters": int(buf[2]), "jacobi_sweeps": int(buf[8]),
-                        "max_resid": float(f[3])})
+                        "max_resid": float(f[3]), "discarded": float(f[6])})
     return out
 
 

@@ -160,6 +160,24 @@ ctm_status ctm_move(ctm_ctx ctx, int32_t dir, int32_t count);
 ctm_status ctm_converge(ctm_ctx ctx, double tol, int32_t max_sweeps,
                         int32_t check_every, int32_t* sweeps_out, double* delta_out);
 
+/*
+ * Per-check metrics of ctm_converge as JSON lines, appended to the file at
+ * `path` ("-": standard error; NULL: off).  At every check, one line per
+ * instance that swept since the previous check: {"inst", "sweep", "delta"
+ * (the convergence measure above), "width" (subspace columns), "live_chi"
+ * (the live extent), "ms_per_sweep" (host wall time since the previous
+ * check per sweep), "kappa" (norm per site, Sec. III; only with flags & 1,
+ * at the cost of one norm evaluation), and per cut "chi_eff" (kept singular
+ * values of the half-system product, Sec. II C), "discarded" (sum over the
+ * subspace's values beyond the kept ones of s_i^2, divided by the sum over
+ * all of them: a lower bound on the truncated weight) and "max_resid"
+ * (largest kept residual / s_1; -1 where the residuals were not formed),
+ * each an object {"L": [...], "R": [...], "U": [...], "D": [...]} over the
+ * move directions, indexed by the site y*Lx+x that owns the cut}.  The file
+ * is flushed after every check and closed by ctm_destroy.
+ */
+ctm_status ctm_set_metrics(ctm_ctx ctx, const char* path, int32_t flags);
+
 /* Singular values of the chi x chi corner matrices C1..C4 of Sec. II C
  * (caption of Fig. 3(b)) of instance `inst`, each divided by their sum,
  * float64 [Lx*Ly][4][chi] (position y*Lx+x, corner C1..C4, descending),

@@ -64,7 +64,7 @@ ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, doubl
  *   what = 3: solver status of row r {chi_eff, converged, iters, chol_fail as
  *             int32, sigma0, max_resid as float64, Jacobi sweeps of the last
  *             Rayleigh-Ritz step, subspace columns, subspace rows, padding as
- *             int32} (48 bytes), index = r.
+ *             int32, discarded weight as float64} (56 bytes), index = r.
  * `bytes` must equal the buffer size.  Syncs.
  */
 ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_buf, size_t bytes);

@@ -24,7 +24,7 @@ EXPORTS = [
     "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
     "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
-    "ctm_checkpoint_load", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
+    "ctm_checkpoint_load", "ctm_set_metrics", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
     "ctm_last_error", "ctm_tile_table_load", "ctm_tile_table_save", "ctm_tile_table_tune",
     "ctm_tile_table_clear", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
@@ -104,6 +104,8 @@ def load(path=LIB_PATH, tile_table=True):
     lib.ctm_checkpoint_bytes.restype = SZ
     lib.ctm_checkpoint_save.argtypes = [VP, I32, VP, SZ]
     lib.ctm_checkpoint_load.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_set_metrics.argtypes = [VP, ctypes.c_char_p, I32]
+    lib.ctm_set_metrics.restype = ctypes.c_int
     lib.ctm_set_timing.argtypes = [VP, I32]
     lib.ctm_get_timing.argtypes = [VP, P(F64)]
     lib.ctm_destroy.argtypes = [VP]
@@ -331,6 +333,12 @@ class CTM:
         self._torch.cuda.synchronize(self.device)
         del ws
         return ev, res, ent.value, wt.value
+
+    def set_metrics(self, path, kappa=False):
+        """Per-check JSON metrics lines of converge appended to `path` ("-":
+        standard error, None: off); kappa adds the norm per site to each
+        line (ctm_set_metrics)."""
+        _check(load().ctm_set_metrics(self.ctx, None if path is None else str(path).encode(), 1 if kappa else 0))
 
     def set_timing(self, mode=1):
         """1: phases and corner-kernel launches, 2: corner-kernel launches

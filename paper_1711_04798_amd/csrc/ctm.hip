@@ -30,6 +30,7 @@
 #include <string>
 #include <array>
 #include <vector>
+#include <chrono>
 
 #include "ctm_internal.h"
 #include "kernels.h"
@@ -246,6 +247,10 @@ struct ctm_ctx_s {
   bool phase_timing = false;
   bool resid_step = true;  // fixed-count solver: form the residuals in this column step
   bool width_pinned = false;  // ctm_debug_set_width: the convergence loop keeps the width
+  // ctm_set_metrics: one JSON line per instance and convergence check
+  std::FILE* metrics = nullptr;
+  bool metrics_own = false;
+  int metrics_flags = 0;
   std::vector<std::array<hipEvent_t, 4>> tpool;
   std::vector<std::array<hipEvent_t, 2>> spool;
   size_t tused = 0, sused = 0;
@@ -2138,6 +2143,61 @@ ctm_status rdm(ctm_ctx_s& x, Inst& I, int sx, int sy, int vertical, const double
   return CTM_OK;
 }
 
+// One JSON line per instance that swept since the last check: the change of
+// the corner spectra, the subspace width and live extent, and per cut (keyed
+// by the move direction, indexed by the site that owns the cut) the kept
+// count, the weight of the subspace's singular values beyond it
+// (sum_{i >= chi_eff} s_i^2 / sum_i s_i^2 over the k computed values) and the
+// largest kept residual; with flag 1 also the norm per site.
+ctm_status write_metrics(ctm_ctx_s& x, int sweep, const std::vector<char>& live, const std::vector<double>& delta,
+                         double ms_per_sweep) {
+  const int npos = x.Lx * x.Ly;
+  std::vector<SolveStatus> st((size_t)4 * npos);
+  static const char* names[4] = {"L", "R", "U", "D"};
+  static const int dirs[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
+  for (int i = 0; i < x.ninst; ++i) {
+    if (!live[i]) continue;
+    Inst& I = x.inst[i];
+    HIPCHK(d2h(st.data(), I.skeep_all, st.size() * sizeof(SolveStatus), x.stream));
+    HIPCHK(ssync(x.stream));
+    double kap = NAN;
+    const bool want_kappa = (x.metrics_flags & 1) != 0;
+    if (want_kappa && kappa(x, I, &kap) != CTM_OK) kap = NAN;
+    std::string line = "{\"inst\": " + std::to_string(i) + ", \"sweep\": " + std::to_string(sweep);
+    char buf[64];
+    auto num = [&](double v) -> std::string {
+      if (!std::isfinite(v)) return "null";
+      std::snprintf(buf, sizeof buf, "%.6e", v);
+      return buf;
+    };
+    line += ", \"delta\": " + num(delta[i]);
+    line += ", \"width\": " + std::to_string(I.k_act) + ", \"live_chi\": " + std::to_string(I.chi);
+    line += ", \"ms_per_sweep\": " + num(ms_per_sweep);
+    if (want_kappa) line += ", \"kappa\": " + num(kap);
+    const char* fields[3] = {"chi_eff", "discarded", "max_resid"};
+    for (int f = 0; f < 3; ++f) {
+      line += std::string(", \"") + fields[f] + "\": {";
+      for (int o = 0; o < 4; ++o) {
+        const int k = frame_of_dir(dirs[o]);
+        line += std::string(o ? ", " : "") + "\"" + names[o] + "\": [";
+        for (int q = 0; q < npos; ++q) {
+          const SolveStatus& t = st[(size_t)k * npos + q];
+          if (q) line += ", ";
+          if (f == 0) line += std::to_string(t.chi_eff);
+          else if (f == 1) line += num(t.discarded);
+          else line += num(t.max_resid);
+        }
+        line += "]";
+      }
+      line += "}";
+    }
+    line += "}\n";
+    std::fputs(line.c_str(), x.metrics);
+  }
+  std::fflush(x.metrics);
+  return CTM_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2309,7 +2369,8 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
     for (int c = 0; c < 4; ++c) cursors0 = cursors0 && I.cursor[c] == 0;
   const bool graph = graph_usable(*x) && cursors0;
   drop_graph(*x);
-  int sweep = 0;
+  int sweep = 0, last_check = 0;
+  auto t_check = std::chrono::steady_clock::now();
   bool eager_next = true;  // an eager sweep tunes new GEMM shapes before a capture
   while (sweep < max_sweeps) {
     const bool use_graph = graph && !eager_next;
@@ -2334,6 +2395,13 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
     HIPCHK(d2h(hd.data(), x->delta_all, (size_t)ni * 8, x->stream));
     HIPCHK(d2h(hf.data(), x->flag_all, (size_t)ni * 16, x->stream));
     HIPCHK(ssync(x->stream));
+    if (x->metrics) {
+      const auto now = std::chrono::steady_clock::now();
+      const double ms = std::chrono::duration<double, std::milli>(now - t_check).count() / (sweep - last_check);
+      CHK(write_metrics(*x, sweep, live, hd, ms));
+      t_check = std::chrono::steady_clock::now();
+      last_check = sweep;
+    }
     // the subspace follows the number of kept singular values: chi_eff + p
     // columns suffice, and chi_eff can grow by p per column step.  After a
     // full sweep every corner and edge was produced by one of the solves
@@ -2387,6 +2455,23 @@ ctm_status ctm_converge(ctm_ctx x, double tol, int32_t max_sweeps, int32_t check
   }
   if (bad) return fail(CTM_E_NONFINITE, "non-finite corner spectrum");
   if (!all_ok) return fail(CTM_E_NOCONV, "not converged within max_sweeps");
+  return CTM_OK;
+}
+
+ctm_status ctm_set_metrics(ctm_ctx x, const char* path, int32_t flags) {
+  if (!x) return fail(CTM_E_INVALID, "null ctx");
+  if (x->metrics && x->metrics_own) std::fclose(x->metrics);
+  x->metrics = nullptr;
+  x->metrics_own = false;
+  x->metrics_flags = flags;
+  if (!path) return CTM_OK;
+  if (std::strcmp(path, "-") == 0) {
+    x->metrics = stderr;
+    return CTM_OK;
+  }
+  x->metrics = std::fopen(path, "a");
+  if (!x->metrics) return fail(CTM_E_INVALID, std::string("cannot open ") + path);
+  x->metrics_own = true;
   return CTM_OK;
 }
 
@@ -2572,6 +2657,8 @@ struct CkptHeader {
   int64_t has_keep[4 * MAXPOS];
 };
 constexpr int64_t CKPT_MAGIC = 0x43544d434b505431ll;  // "CTMCKPT1"
+// version 2: solver statuses carry the discarded weight (56 bytes each)
+constexpr int64_t CKPT_VERSION = 2;
 size_t ckpt_bytes(const ctm_ctx_s& x, const Inst& I) {
   const size_t npos = (size_t)x.Lx * x.Ly, cc = I.chi_cap;
   return sizeof(CkptHeader) + npos * 4 * (cc * cc + cc * cc * I.D2) * 8 + npos * 4 * cc * 8 +
@@ -2592,7 +2679,7 @@ ctm_status ctm_checkpoint_save(ctm_ctx x, int32_t inst, void* buf, size_t bytes)
   const int npos = x->Lx * x->Ly;
   CkptHeader h{};
   h.magic = CKPT_MAGIC;
-  h.version = 1;
+  h.version = CKPT_VERSION;
   h.chi_cap = I.chi_cap; h.D = I.D; h.d = I.d; h.chi = I.chi; h.k = I.k; h.k_act = I.k_act;
   h.npos = npos; h.n_cap = I.n_cap;
   for (int c = 0; c < 4; ++c) h.cursor[c] = I.cursor[c];
@@ -2628,7 +2715,7 @@ ctm_status ctm_checkpoint_load(ctm_ctx x, int32_t inst, const void* buf, size_t 
   const int npos = x->Lx * x->Ly;
   CkptHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != CKPT_MAGIC || h.version != 1 || h.chi_cap != I.chi_cap || h.D != I.D || h.d != I.d ||
+  if (h.magic != CKPT_MAGIC || h.version != CKPT_VERSION || h.chi_cap != I.chi_cap || h.D != I.D || h.d != I.d ||
       h.k != I.k || h.npos != npos || h.n_cap != I.n_cap || h.chi < 1 || h.chi > I.chi_cap || h.k_act < 1 ||
       h.k_act > I.k)
     return fail(CTM_E_INVALID, "checkpoint does not match this context");
@@ -2695,6 +2782,7 @@ ctm_status ctm_get_timing(ctm_ctx x, double* v) {
 
 void ctm_destroy(ctm_ctx x) {
   if (!x) return;
+  if (x->metrics && x->metrics_own) std::fclose(x->metrics);
   if (x->gexec) (void)hipGraphExecDestroy(x->gexec);
   for (hipStream_t cs : x->class_streams) {
     (void)hipStreamSynchronize(cs);

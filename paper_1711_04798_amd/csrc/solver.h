@@ -18,6 +18,7 @@ struct SolveStatus {
   int32_t kcols;       // columns of the subspace this status belongs to
   int32_t nrows;       // rows (cut dimension) of that subspace
   int32_t pad_;
+  double discarded;    // sum_{i >= chi_eff} s_i^2 / sum_i s_i^2 over the k computed values
 };
 
 constexpr int MAXP = 32;  // problems per small-kernel launch

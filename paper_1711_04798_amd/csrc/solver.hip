@@ -784,6 +784,12 @@ residual_final_kernel(int64_t n, int k, int nb, int chi, double cutoff, double t
     if (s0 > 0)
       for (int c = 0; c < k && c < chi; ++c)
         if (sv[c] > cutoff * s0) keep = c + 1;
+    double tot = 0.0, tail = 0.0;
+    for (int c = 0; c < k; ++c) {
+      tot += sv[c] * sv[c];
+      if (c >= keep) tail += sv[c] * sv[c];
+    }
+    o->discarded = tot > 0 ? tail / tot : 0.0;
     double mr = 0.0;
     for (int c = 0; c < keep; ++c) mr = fmax(mr, s_res[c]);
     mr = s0 > 0 ? mr / s0 : 0.0;

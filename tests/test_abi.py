@@ -55,7 +55,7 @@ def test_wrappers_call_the_runtime(lib_path):
 
 
 DRY = r'''
-import ctypes, json, sys
+import ctypes, json, os, sys, tempfile
 sys.path.insert(0, %(root)r)
 from paper_1711_04798_amd import binding as b
 lib = b.load(%(lib)r)
@@ -71,7 +71,14 @@ for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
     for dr in range(4):
         st.append(lib.ctm_move(ctx, dr, 3))
     sw = (ctypes.c_int32 * len(d))(); dl = (ctypes.c_double * len(d))()
+    mf = tempfile.mktemp(suffix=".jsonl")
+    st.append(lib.ctm_set_metrics(ctx, mf.encode(), 1))
     st.append(lib.ctm_converge(ctx, 1e-10, 2, 1, sw, dl))
+    st.append(lib.ctm_set_metrics(ctx, None, 0))
+    # the dry run reads back zeros: every instance stops at the first check
+    ml = [json.loads(l) for l in open(mf)]
+    os.remove(mf)
+    st.append(0 if len(ml) == len(d) and all(set(m["chi_eff"]) == set("LRUD") for m in ml) else 99)
     k = ctypes.c_double()
     # narrowed subspace: every stage at the live extent, under the bounds checks
     live = ctypes.c_int32()

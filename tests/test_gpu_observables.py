@@ -235,6 +235,41 @@ def test_width_grows_when_filled(gpu):
     g.close()
 
 
+def test_metrics_lines(gpu, tmp_path):
+    """Per-check metrics of a float64 run to convergence (2x2, d=8, D=4,
+    chi=64): one JSON line per sweep, whose last change and norm per site are
+    the ones the run returns, with kept counts within the width and
+    discarded weights in [0, 1)."""
+    from paper_1711_04798_amd import CTM
+    gold = _golden("c1")
+    w = gold["workload"]
+    A, B = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)
+    print("case metrics", flush=True)
+    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=w["chi"], cutoff=w["cutoff"])
+    path = tmp_path / "m.jsonl"
+    g.set_metrics(path, kappa=True)
+    sw, dl, ok = g.converge(tol=w["tol"], max_sweeps=w["max_sweeps"])
+    g.set_metrics(None)
+    kg = g.norm()
+    g.close()
+    lines = [json.loads(l) for l in path.read_text().splitlines()]
+    assert ok and len(lines) == sw[0]
+    assert [m["sweep"] for m in lines] == list(range(1, sw[0] + 1))
+    last = lines[-1]
+    print("metrics: %d lines, last delta %.3e kappa %.12f width %d live %d chi_eff %s discarded %s"
+          % (len(lines), last["delta"], last["kappa"], last["width"], last["live_chi"], last["chi_eff"]["L"],
+             last["discarded"]["L"]))
+    assert abs(last["delta"] - dl[0]) <= 1e-6 * dl[0]
+    assert abs(last["kappa"] - kg) <= 1e-6 * kg
+    for m in lines:
+        assert m["width"] <= w["chi"] + 16 and m["live_chi"] <= w["chi"]
+        for dn in "LRUD":
+            assert len(m["chi_eff"][dn]) == 4
+            assert all(0 < c <= m["width"] for c in m["chi_eff"][dn])
+            assert all(0 <= v < 1 for v in m["discarded"][dn])
+            assert all(0 <= v < 1e-6 for v in m["max_resid"][dn])
+
+
 def test_deterministic(gpu):
     """Two contexts on the same input give bit-identical spectra and kappa."""
     from paper_1711_04798_amd import CTM

@@ -76,7 +76,7 @@ def test_one_step_from_same_env(gpu, direction, case):
         P1o, P2o, info = octm.projectors(*Qo, chi, 1e-12, return_info=True)
         P1g = _dump(g, 1, yp, (n, chi))
         P2g = _dump(g, 2, yp, (n, chi)).T
-        stt = _dump(g, 3, yp, (12,), np.int32)
+        stt = _dump(g, 3, yp, (14,), np.int32)
         keep = info["keep"]
         # compare the truncated half-system operator Uh^T P1 P2 Lh^T (well
         # conditioned); P1 P2 alone amplifies the smallest kept direction by
@@ -84,11 +84,17 @@ def test_one_step_from_same_env(gpu, direction, case):
         Uh, Lh = Qo[0] @ Qo[1], Qo[2] @ Qo[3]
         No, Ng = Uh.T @ P1o @ P2o @ Lh.T, Uh.T @ P1g @ P2g @ Lh.T
         err = np.abs(No - Ng).max() / np.abs(No).max()
-        res = _dump(g, 3, yp, (6,), np.float64)
+        res = _dump(g, 3, yp, (7,), np.float64)
         print("row %d keep oracle %d gpu %d iters %d jacobi sweeps %d max_resid %.2e, N_chi rel err %.2e"
               % (yp, keep, stt[0], stt[2], stt[8], res[3], err))
         assert stt[0] == keep
         assert err < 1e-11
+        # discarded weight over the subspace's k values (k = stt[10] columns):
+        # the oracle's over its top k singular values
+        So = np.asarray(info["S"], dtype=np.float64)[:stt[10]]
+        do = float((So[keep:] ** 2).sum() / (So ** 2).sum())
+        print("row %d discarded weight oracle %.3e gpu %.3e" % (yp, do, res[6]))
+        assert abs(res[6] - do) <= 1e-3 * do + 1e-15
     ref = env.copy()
     octm.column_step(cell, ref, k, 0)
     genv = flat_to_env(g.export_env(), Lx, Ly, chi, 4)
