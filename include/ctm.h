@@ -99,6 +99,14 @@ typedef struct {
                               captured graph (own stream while capturing, own
                               scratch), 0 captures the classes one after the
                               other (default 1)                                   */
+  int32_t single_layer;    /* 1: the double-layer contractions of a move (the
+                              enlarged corners of Sec. II C, Fig. 3(b), and the
+                              edge absorption) take the ket tensor A and the bra
+                              tensor one at a time, never forming the D^8 double
+                              layer in the contraction: 4 chi^2 d D^6 instead of
+                              2 chi^2 D^8 flop per corner, the route to large D
+                              (Sec. II D).  CTM_FP64 or CTM_FP32 only
+                              (default 0)                                         */
 } ctm_config;
 
 /* Fills *cfg with the defaults above for one instance (caller sets the rest). */

@@ -41,7 +41,7 @@ class CtmConfig(ctypes.Structure):
         ("svd_max_iters", ctypes.c_int32), ("svd_resid_tol", ctypes.c_double),
         ("svd_cutoff", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-        ("concurrent_classes", ctypes.c_int32),
+        ("concurrent_classes", ctypes.c_int32), ("single_layer", ctypes.c_int32),
     ]
 
 
@@ -156,7 +156,7 @@ def _i32arr(v):
 
 def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=16,
                 max_iters=30, resid_tol=1e-13, cutoff=1e-12, seed=12345, use_graph=False,
-                autotune=True, concurrent_classes=True):
+                autotune=True, concurrent_classes=True, single_layer=False):
     """ctm_config plus the ctypes arrays it points into (keep both alive)."""
     lib = load()
     cfg = CtmConfig()
@@ -175,6 +175,7 @@ def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=1
     cfg.use_graph = int(bool(use_graph))
     cfg.autotune = int(bool(autotune))
     cfg.concurrent_classes = int(bool(concurrent_classes))
+    cfg.single_layer = int(bool(single_layer))
     return cfg, keep
 
 

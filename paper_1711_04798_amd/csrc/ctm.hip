@@ -176,6 +176,10 @@ struct Inst {
   bool staleC[4][MAXPOS] = {};
   bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
+  // single-layer mode: the ket (Sk) and bra (Sb) tensor of each rotation in
+  // the working type, legs [L'][U'][s][D'][R'] of the rotated frame
+  void* Sk[MAXT][4] = {};
+  void* Sb[MAXT][4] = {};
   double* spec_old = nullptr;  // [pos][4][chi_cap]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
@@ -224,6 +228,8 @@ struct ctm_ctx_s {
   double* spec_tmp_W = nullptr;
   double* spec_tmp_S = nullptr;
   double* spec_tmp_J = nullptr;
+  void *sl_y = nullptr, *sl_z = nullptr, *sl_p = nullptr;  // single-layer scratch (current set)
+  size_t sl_ybytes = 0, sl_zbytes = 0;                      // capacity of sl_y / sl_p and of sl_z
   // the scratch above (split-K partials, tall-skinny partials, normalisation
   // partials, corner SVD) in sets: set 0 serves the eager path, and in graph
   // mode with concurrent classes class i's branch of the captured sweep uses
@@ -231,6 +237,7 @@ struct ctm_ctx_s {
   struct ScratchSet {
     double *splitk, *norm_part, *U, *W, *S, *J;
     void* ts;
+    void *sl_y, *sl_z, *sl_p;  // single-layer products: permuted input, intermediate, output
   };
   std::vector<ScratchSet> scratch_sets;
   std::vector<hipStream_t> class_streams;  // branches of the captured sweep
@@ -287,6 +294,9 @@ void use_scratch(ctm_ctx_s& x, size_t i) {
   x.spec_tmp_W = ss.W;
   x.spec_tmp_S = ss.S;
   x.spec_tmp_J = ss.J;
+  x.sl_y = ss.sl_y;
+  x.sl_z = ss.sl_z;
+  x.sl_p = ss.sl_p;
 }
 
 void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
@@ -347,7 +357,12 @@ void plan(ctm_ctx_s& x, Arena& ar) {
       I.B[t] = ar.take<double>(t5);
       for (int r = 0; r < 4; ++r) {
         I.b64[t][r] = ar.take<double>(a8);
-        I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : ar.take_bytes(a8 * ws);
+        // the single-layer mode contracts with Sk / Sb instead of a working copy
+        I.bw[t][r] = (x.wt == F64) ? (void*)I.b64[t][r] : (x.cfg.single_layer ? nullptr : ar.take_bytes(a8 * ws));
+        if (x.cfg.single_layer) {
+          I.Sk[t][r] = ar.take_bytes(t5 * ws);
+          I.Sb[t][r] = ar.take_bytes(t5 * ws);
+        }
         if (x.prec == CTM_BF16) {
           I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
           I.bT3[t][r] = ar.take_bytes(3 * a8 * dtype_size(BF16));
@@ -396,6 +411,20 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   // corner-spectrum SVD scratch (MAXP corners per launch)
   // (the Jacobi kernel's working set with vectors: 2 chi chi16 per problem)
   const size_t chi16 = (chi + 15) / 16 * 16;
+  // single-layer products at the full extent: as many jobs per pass as fit
+  // 1 GiB of intermediates, at least one
+  if (x.cfg.single_layer) {
+    size_t yb = 0, zb = 0;
+    for (const Inst& I : x.inst) {
+      const size_t y = (size_t)I.chi_cap * I.chi_cap * I.D2 * I.D2 * ws;
+      yb = std::max(yb, y);
+      zb = std::max(zb, y * (size_t)I.d);
+    }
+    const size_t per = 2 * yb + zb;
+    const size_t nb = std::max<size_t>(1, std::min<size_t>(MAXG, ((size_t)1 << 30) / std::max<size_t>(per, 1)));
+    x.sl_ybytes = nb * yb;
+    x.sl_zbytes = nb * zb;
+  }
   const size_t nsets = concurrent_classes(x) ? x.classes.size() : 1;
   x.scratch_sets.assign(nsets, ctm_ctx_s::ScratchSet{});
   for (auto& ss : x.scratch_sets) {
@@ -406,6 +435,12 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     ss.W = ar.take<double>(MAXP * c2);
     ss.S = ar.take<double>(MAXP * chi);
     ss.J = ar.take<double>(MAXP * 2 * chi * chi16);
+    ss.sl_y = ss.sl_z = ss.sl_p = nullptr;
+    if (x.cfg.single_layer) {
+      ss.sl_y = ar.take_bytes(x.sl_ybytes);
+      ss.sl_z = ar.take_bytes(x.sl_zbytes);
+      ss.sl_p = ar.take_bytes(x.sl_ybytes);
+    }
   }
   use_scratch(x, 0);
   // observables (float64)
@@ -620,6 +655,7 @@ struct CornerJob {
   void *X, *Y, *Q;
   const void *TnP = nullptr, *bT = nullptr;  // bf16 path: permuted edge, transposed double layer
   const void* TnR = nullptr;                 // bf16 path: bf16 edge as [next][inner][prev]
+  const void *Sk = nullptr, *Sb = nullptr;   // single-layer mode: ket and bra of the rotation
 };
 
 struct Stage3Timer {
@@ -646,8 +682,62 @@ ctm_status stage3_timed(hipStream_t s, const Stage3Timer* tm, const std::functio
 // bf16: the double-layer stage (stage 3) takes bf16 operands (stage 2 writes
 // Y in bf16, the double layer is the transposed bf16 copy) with fp32
 // accumulation; stages 1 and 2 run in `tin`.
+// ---------------------------------------------------------------------------
+// Single-layer form of a double-layer product (Sec. II D: A and its conjugate
+// absorbed one at a time).  With the fused legs ket-major (l = (l_k, l_b), ...)
+// and a[(l,u),(dn,r)] = sum_s A[s,u_k,l_k,d_k,r_k] B[s,u_b,l_b,d_b,r_b],
+//   P[(g,b),(dn,r)] = sum_(l,u) Y[(g,b),(l,u)] a[(l,u),(dn,r)]
+// is taken as
+//   Y' [(g,b,l_b,u_b),(l_k,u_k)]   = Y with its legs permuted
+//   Z  [(g,b,l_b,u_b),(s,d_k,r_k)] = Y' Sk,  Sk[(l_k,u_k),(s,d_k,r_k)] = A
+//   P' [(g,b,d_k,r_k),(d_b,r_b)]   = sum_(l_b,u_b,s) Z Sb,  Sb[(l_b,u_b,s),(d_b,r_b)] = B
+//   P  = P' with its legs permuted into the consumer's layout,
+// 4 c^2 d D^6 flop instead of 2 c^2 D^8 (c the extent of g and b).  Y is
+// given by its 6-d storage dims and the permutation that orders them as
+// (g, b, l_b, u_b, l_k, u_k); P' has dims (g, b, d_k, r_k, d_b, r_b) and
+// out_perm orders them as the consumer stores them.  Sk and Sb are the
+// tensors' [L'][U'][s][D'][R'] copies, read as D^2 x d D^2 and d D^2 x D^2
+// matrices.  Jobs go in passes of as many as the scratch holds.
+// ---------------------------------------------------------------------------
+struct SlJob {
+  const void *y, *sk, *sb;
+  void* out;
+};
+
+ctm_status sl_product(ctm_ctx_s& x, int64_t c, int D, int d, const std::vector<SlJob>& jobs, const int64_t ydims[6],
+                      const int yperm[6], const int out_perm[6], int tout) {
+  hipStream_t s = x.stream;
+  const int wt = x.wt;
+  const int64_t D2 = (int64_t)D * D, M = c * c * D2;
+  const size_t yb = (size_t)M * D2 * dtype_size(wt), zb = yb * (size_t)d;
+  if (!x.sl_y || yb == 0) return fail(CTM_E_STATE, "single-layer scratch missing");
+  const size_t nb = std::max<size_t>(1, std::min<size_t>({(size_t)MAXG, x.sl_ybytes / yb, x.sl_zbytes / zb}));
+  if (nb * yb > x.sl_ybytes || nb * zb > x.sl_zbytes) return fail(CTM_E_STATE, "single-layer scratch too small");
+  const int64_t pdims[6] = {c, c, D, D, D, D};
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += nb) {
+    const size_t j1 = std::min(jobs.size(), j0 + nb);
+    G ga, gb;
+    for (size_t j = j0; j < j1; ++j) {
+      char* yj = (char*)x.sl_y + (j - j0) * yb;
+      char* zj = (char*)x.sl_z + (j - j0) * zb;
+      char* pj = (char*)x.sl_p + (j - j0) * yb;
+      HIPCHK(permute(s, wt, jobs[j].y, wt, yj, 6, ydims, yperm));
+      ga.add(yj, jobs[j].sk, zj);
+      gb.add(zj, jobs[j].sb, pj);
+    }
+    CHK(gemm_run(s, wt, wt, M, (int64_t)d * D2, D2, rowmajor(D2), rowmajor((int64_t)d * D2),
+                 rowmajor((int64_t)d * D2), ga));
+    // Z read as rows (g,b | d_k,r_k) -> gb d D^4 + (d_k,r_k), columns (l_b,u_b,s) -> stride D^2
+    CHK(gemm_run(s, wt, wt, M, D2, (int64_t)d * D2, view2(D2, 1, (int64_t)d * D2 * D2, BIG, D2, 0), rowmajor(D2),
+                 rowmajor(D2), gb));
+    for (size_t j = j0; j < j1; ++j)
+      HIPCHK(permute(s, wt, (char*)x.sl_p + (j - j0) * yb, tout, jobs[j].out, 6, pdims, out_perm));
+  }
+  return CTM_OK;
+}
+
 ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs,
-                        const Stage3Timer* tm, bool bf16) {
+                        const Stage3Timer* tm, bool bf16, ctm_ctx_s* slx = nullptr, int D = 0, int d = 0) {
   const int64_t c = chi, n = (int64_t)chi * D2;
   const int64_t K4 = (int64_t)D2 * D2;
   const bool fast = bf16 && tq == F32 && !jobs.empty() && jobs[0].TnP && jobs[0].bT &&
@@ -696,6 +786,17 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
     }
     CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
     CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), rowmajor(n), g2));
+    if (slx) {
+      // Y[g][l_k][l_b][u_k][u_b][b] -> (g, b, l_b, u_b, l_k, u_k); P' (g, b, d_k, r_k, d_b, r_b)
+      // -> Q[(g,dn),(b,r)] = [g][d_k][d_b][b][r_k][r_b]
+      const int64_t ydims[6] = {c, D, D, D, D, c};
+      const int yperm[6] = {0, 5, 2, 4, 1, 3};
+      const int operm[6] = {0, 2, 4, 1, 3, 5};
+      std::vector<SlJob> sj;
+      for (size_t j = j0; j < j1; ++j) sj.push_back(SlJob{jobs[j].Y, jobs[j].Sk, jobs[j].Sb, jobs[j].Q});
+      CHK(stage3_timed(s, tm, [&]() { return sl_product(*slx, c, D, d, sj, ydims, yperm, operm, tq); }));
+      continue;
+    }
     // A: rows m = (g, b): b low (extent chi, stride 1), g high (stride D2*D2*chi);
     //    cols k = (l, u): stride chi
     View va = view2(c, 1, (int64_t)D2 * D2 * c, BIG, c, 0);
@@ -1077,6 +1178,26 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, vw2, g3x.group(j0, cnt), cnt, F32));
     }
     w2t_done = to_t;
+  } else if (x.cfg.single_layer) {
+    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+    // W1[g][l_k][l_b][u_k][u_b][c2] -> (g, c2, l_b, u_b, l_k, u_k); P' (g, c2, d_k, R_k, d_b, R_b)
+    // -> W2[(g,c2)][(dn,R)], or straight into W2t[(g,dn)][(R,c2)] in float32
+    const int64_t ydims[6] = {c, I0.D, I0.D, I0.D, I0.D, c};
+    const int yperm[6] = {0, 5, 2, 4, 1, 3};
+    const bool to_t = at == F32 && D2 >= 2 && I0.rows[0].W2t;
+    const int operm_w2[6] = {0, 1, 2, 4, 3, 5};
+    const int operm_w2t[6] = {0, 2, 4, 3, 5, 1};
+    std::vector<SlJob> sj;
+    for (Inst* I : insts) {
+      Roles ro{&x, I, k};
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        const int t = ro.tid(xp, yp);
+        sj.push_back(SlJob{R.W1, I->Sk[t][k % 4], I->Sb[t][k % 4], to_t ? R.W2t : R.W2});
+      }
+    }
+    CHK(sl_product(x, c, I0.D, I0.d, sj, ydims, yperm, to_t ? operm_w2t : operm_w2, at));
+    w2t_done = to_t;
   } else {
     CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
     CHK(gemm_run(s, at, at, c * c, K4, K4, view2(c, 1, D2 * D2 * c, BIG, c, 0), rowmajor(K4), rowmajor(K4), g4));
@@ -1236,6 +1357,10 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
         j.Tn = ro.Tw(q, cx[q], cy[q]);
         j.Tp = ro.Tw((q + 3) % 4, cx[q], cy[q]);
         j.b = ro.bw(cx[q], cy[q], q);
+        if (x.cfg.single_layer) {
+          j.Sk = I->Sk[ro.tid(cx[q], cy[q])][(k + q) % 4];
+          j.Sb = I->Sb[ro.tid(cx[q], cy[q])][(k + q) % 4];
+        }
         j.X = R.X[q];
         j.Y = R.Y[q];
         j.Q = R.Q[q];
@@ -1253,13 +1378,15 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
     tm.pool = &x.spool;
     tm.used = &x.sused;
     // algorithmic work of the (l,u)-contraction with the double layer:
-    // 2 chi^2 D^8 flop per corner
+    // 2 chi^2 D^8 flop per corner; single-layer: 4 chi^2 d D^6
     const double d8 = (double)I0.D2 * I0.D2 * I0.D2 * I0.D2;
-    x.stage3_flop += 2.0 * (double)I0.chi * I0.chi * d8 * (double)jobs.size();
-    x.stage3_flop_nom += 2.0 * (double)I0.chi_cap * I0.chi_cap * d8 * (double)jobs.size();
+    const double w = x.cfg.single_layer ? 4.0 * I0.d * d8 / I0.D2 : 2.0 * d8;
+    x.stage3_flop += w * (double)I0.chi * I0.chi * (double)jobs.size();
+    x.stage3_flop_nom += w * (double)I0.chi_cap * I0.chi_cap * (double)jobs.size();
     x.live_chi = I0.chi;
   }
-  CHK(corner_chain(s, x.wt, x.qt, I0.chi, I0.D2, jobs, x.timing ? &tm : nullptr, x.prec == CTM_BF16));
+  CHK(corner_chain(s, x.wt, x.qt, I0.chi, I0.D2, jobs, x.timing ? &tm : nullptr, x.prec == CTM_BF16,
+                   x.cfg.single_layer ? &x : nullptr, I0.D, I0.d));
   x.corner_launches += 3 * ((jobs.size() + MAXG - 1) / MAXG);
   x.moves += 1;
   ev_record(x, 1);
@@ -1448,6 +1575,8 @@ ctm_status validate(const ctm_config* c) {
   for (int i = 0; i < c->Lx * c->Ly; ++i)
     if (c->pattern[i] < 0 || c->pattern[i] >= c->n_tensors) return fail(CTM_E_INVALID, "pattern entry out of range");
   if (c->prec < 0 || c->prec > 2) return fail(CTM_E_INVALID, "prec");
+  if (c->single_layer && c->prec == CTM_BF16)
+    return fail(CTM_E_INVALID, "single_layer runs in CTM_FP64 or CTM_FP32");
   for (int i = 0; i < c->n_inst; ++i) {
     int d = c->d[i], D = c->D[i], chi = c->chi[i];
     if (d < 1 || D < 1 || chi < 1 || d > 64 || D > 16) return fail(CTM_E_INVALID, "d in 1..64, D in 1..16, chi >= 1");
@@ -2294,11 +2423,21 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
     for (int t = 0; t < x->ntens; ++t) {
       if (double_layer(x->stream, I.A[t], I.B[t], I.d, I.D, I.b64[t], 0) != hipSuccess)
         return cleanup(fail(CTM_E_HIP, "double layer"));
-      if (x->wt != F64)
+      if (x->wt != F64 && !x->cfg.single_layer)
         for (int r = 0; r < 4; ++r)
           if (convert(x->stream, F64, I.b64[t][r], x->wt, I.bw[t][r], (int64_t)I.D2 * I.D2 * I.D2 * I.D2) !=
               hipSuccess)
             return cleanup(fail(CTM_E_HIP, "convert"));
+      if (x->cfg.single_layer)
+        for (int r = 0; r < 4; ++r) {
+          // rotation r of the frame: A[s][u][l][d][r] -> [L'][U'][s][D'][R'], with
+          // the legs relabelled as in the rotated double layer
+          static const int perm[4][5] = {{2, 1, 0, 3, 4}, {1, 4, 0, 2, 3}, {4, 3, 0, 1, 2}, {3, 2, 0, 4, 1}};
+          const int64_t dims[5] = {I.d, I.D, I.D, I.D, I.D};
+          if (permute(x->stream, F64, I.A[t], x->wt, I.Sk[t][r], 5, dims, perm[r]) != hipSuccess ||
+              permute(x->stream, F64, I.B[t], x->wt, I.Sb[t][r], 5, dims, perm[r]) != hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "single-layer tensors"));
+        }
       if (x->prec == CTM_BF16)
         for (int r = 0; r < 4; ++r) {
           int64_t dims[2] = {(int64_t)I.D2 * I.D2, (int64_t)I.D2 * I.D2};

@@ -60,8 +60,10 @@ sys.path.insert(0, %(root)r)
 from paper_1711_04798_amd import binding as b
 lib = b.load(%(lib)r)
 out = {}
-for name, Lx, Ly, pat, nt, d, D, chi, prec in %(cases)r:
-    cfg, keep = b.make_config(Lx, Ly, pat, nt, d, D, chi, prec, max_iters=2)
+for case in %(cases)r:
+    name, Lx, Ly, pat, nt, d, D, chi, prec = case[:9]
+    extra = case[9] if len(case) > 9 else {}
+    cfg, keep = b.make_config(Lx, Ly, pat, nt, d, D, chi, prec, max_iters=2, **extra)
     n = b.workspace_size(cfg)
     ptrs = (ctypes.c_void_p * (nt * len(d)))(*[(1 << 30) + 4096 * i for i in range(nt * len(d))])
     ctx = ctypes.c_void_p()
@@ -125,6 +127,12 @@ CASES = [
     ("rect_2x1", 2, 1, [0, 1], 2, [2], [2], [8], "fp64"),
     # batched form: classes of equal (d, D, chi) moved in lock-step
     ("batched", 1, 1, [0], 1, [8] * 40, [3, 4, 5, 3] * 10, [32, 64, 100, 32] * 10, "fp32"),
+    # single-layer contractions (no double layer in the moves)
+    ("c1_single", 2, 2, [0, 1, 1, 0], 2, [8], [4], [64], "fp64", {"single_layer": True}),
+    ("c2_single", 2, 2, [0, 1, 1, 0], 2, [8], [6], [144], "fp32", {"single_layer": True}),
+    ("large_D_single", 2, 2, [0, 1, 1, 0], 2, [8], [12], [100], "fp32", {"single_layer": True}),
+    ("batched_single", 1, 1, [0], 1, [8] * 6, [3, 4, 5] * 2, [32, 64, 100] * 2, "fp32",
+     {"single_layer": True, "use_graph": True}),
 ]
 
 
