@@ -158,6 +158,50 @@ def dense_extent_leg(tensors, prec, warm=1, steps=3):
                     "8 corners of M = chi^2 = 20736 rows, N = K = D^4 = 1296 per launch)"}
 
 
+SINGLE_LAYER_SHAPES = [(6, 144), (8, 64), (10, 64)]
+
+
+def single_layer_leg(warm=2, steps=3):
+    """Double-layer against single-layer contractions of the moves (float32
+    contractions, float64 solver), 2x2 checkerboard, d = 8, at growing D:
+    column steps per second over `steps` sweeps after `warm`, and the
+    enlarged-corner and absorption phases of one more, instrumented sweep.
+    The double layer costs 2 chi^2 D^8 flop per corner, the single-layer
+    route 4 chi^2 d D^6 plus its d chi^2 D^4 intermediate through HBM."""
+    import torch
+    import synth
+    from paper_1711_04798_amd import CTM
+    out = []
+    for D, chi in SINGLE_LAYER_SHAPES:
+        tens = synth.cell_tensors(0, 8, D, 2)
+        row = {"D": D, "chi": chi}
+        for route in ("double", "single"):
+            log("bench: single-layer leg D=%d chi=%d %s" % (D, chi, route))
+            g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec="fp32",
+                    single_layer=(route == "single"), **solver_opts("fp32"))
+            for _ in range(warm):
+                g.converge(tol=0.0, max_sweeps=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.converge(tol=0.0, max_sweeps=1)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            g.set_timing(1)
+            g.converge(tol=0.0, max_sweeps=1)
+            tp = g.timing()
+            g.set_timing(0)
+            g.close()
+            row[route] = {"moves_per_s": 8 * steps / el, "ms_per_sweep": 1e3 * el / steps,
+                          "corner_ms_per_sweep": 1e3 * tp["corner_s"], "absorb_ms_per_sweep": 1e3 * tp["absorb_s"],
+                          "solver_ms_per_sweep": 1e3 * tp["solver_s"], "live_chi": int(tp["live_chi"])}
+        row["speedup_moves"] = row["single"]["moves_per_s"] / row["double"]["moves_per_s"]
+        row["speedup_corner"] = row["double"]["corner_ms_per_sweep"] / max(row["single"]["corner_ms_per_sweep"], 1e-9)
+        out.append(row)
+    return {"rows": out, "prec": "fp32",
+            "note": "2x2 checkerboard, d=8, random tensors (seed 0), cutoff 1e-7; contractions at the live extent"}
+
+
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
 # float64 contractions reach Delta < 1e-6; float32 contractions do not (their
 # corner spectra keep changing by ~1e-5 .. 1e-4 per sweep), so the float32
@@ -324,6 +368,8 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-extent corner-kernel leg")
     ap.add_argument("--full-extent-only", action="store_true",
                     help="only the corner kernel at the full extent (for profiling runs)")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-layer comparison leg")
+    ap.add_argument("--single-only", action="store_true", help="only the single-layer comparison leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -349,6 +395,9 @@ def main():
 
     w = WORKLOAD
     tensors = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)
+    if args.single_only:
+        print(json.dumps({"single_layer": single_layer_leg()}), flush=True)
+        return
     if args.full_extent_only:
         print(json.dumps({"roofline_full_extent": dense_extent_leg(tensors, args.prec)}), flush=True)
         return
@@ -436,6 +485,8 @@ def main():
     if not args.no_full:
         log("bench: enlarged-corner kernel at the full extent")
         out["roofline_full_extent"] = dense_extent_leg(tensors, args.prec)
+    if not args.no_single:
+        out["single_layer"] = single_layer_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
         out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])

@@ -40,14 +40,14 @@ def _energy(g):
     return sum(g.expect(x, y, v, bh(x, y, v)) for (x, y, v) in BONDS) / 12.0
 
 
-def _converged(D, chi, prec, sweeps):
+def _converged(D, chi, prec, sweeps, single_layer=False):
     from paper_1711_04798_amd import CTM
     A, B = synth.cell_tensors(0, 8, D, 2)
     if prec == "fp64":
         kw, tol = dict(cutoff=1e-8), 1e-10
     else:
         kw, tol = dict(max_iters=2, resid_tol=0.0, cutoff=1e-7), 0.0
-    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec=prec, **kw)
+    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec=prec, single_layer=single_layer, **kw)
     sw, dl, ok = g.converge(tol=tol, max_sweeps=sweeps)
     out = dict(sweeps=sw[0], delta=dl[0], E=_energy(g), kappa=g.norm(), spec=g.spectra())
     g.close()
@@ -73,27 +73,30 @@ def _reference(name, D, chi, max_sweeps):
 
 
 def _check(name, D, chi, prec, max_sweeps):
+    # "fp32-single": float32 contractions through the single-layer route
+    single = prec.endswith("-single")
+    prec = prec.split("-")[0]
     ref = _reference(name, D, chi, max_sweeps)
-    got = _converged(D, chi, prec, max_sweeps)
+    got = _converged(D, chi, prec, max_sweeps, single)
     e_rel = abs(got["E"] - ref["E"]) / abs(ref["E"])
     k_rel = abs(got["kappa"] - ref["kappa"]) / abs(ref["kappa"])
     ratio = lambda sp: sp[:, :, :8] / sp[:, :, :1]
     s_err = np.abs(ratio(got["spec"]) - ratio(ref["spec"])).max()
-    print("precision %s D=%d chi=%d vs %s: sweeps %d delta %.1e  E/spin %.12f (ref %.12f) rel %.2e  "
-          "kappa rel %.2e  spectrum ratios %.2e" % (prec, D, chi, ref["src"], got["sweeps"], got["delta"], got["E"],
+    print("precision %s%s D=%d chi=%d vs %s: sweeps %d delta %.1e  E/spin %.12f (ref %.12f) rel %.2e  "
+          "kappa rel %.2e  spectrum ratios %.2e" % (prec, " single-layer" if single else "", D, chi, ref["src"], got["sweeps"], got["delta"], got["E"],
                                            ref["E"], e_rel, k_rel, s_err), flush=True)
     be, bk, bs = BOUNDS[prec]
     assert e_rel < be and k_rel < bk and s_err < bs
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single"])
 def test_precision_ruby_size(gpu, prec):
     """2x2 checkerboard, d=8, D=4, chi=64."""
     print("case precision c1", prec, flush=True)
     _check("c1", 4, 64, prec, 20)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single"])
 def test_precision_benchmark_size(gpu, prec):
     """2x2 checkerboard, d=8, D=6, chi=144 (the benchmark workload)."""
     print("case precision c2", prec, flush=True)
