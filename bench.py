@@ -161,9 +161,10 @@ def dense_extent_leg(tensors, prec, warm=1, steps=3):
 SINGLE_LAYER_SHAPES = [(6, 144), (8, 64), (10, 64)]
 
 
-def single_layer_leg(warm=2, steps=3):
+def single_layer_leg(warm=2, steps=3, precs=("fp32", "bf16")):
     """Double-layer against single-layer contractions of the moves (float32
-    contractions, float64 solver), 2x2 checkerboard, d = 8, at growing D:
+    contractions, or the bf16 form; float64 solver), 2x2 checkerboard, d = 8,
+    at growing D:
     column steps per second over `steps` sweeps after `warm`, and the
     enlarged-corner and absorption phases of one more, instrumented sweep.
     The double layer costs 2 chi^2 D^8 flop per corner, the single-layer
@@ -172,13 +173,13 @@ def single_layer_leg(warm=2, steps=3):
     import synth
     from paper_1711_04798_amd import CTM
     out = []
-    for D, chi in SINGLE_LAYER_SHAPES:
+    for prec, (D, chi) in [(p, sh) for p in precs for sh in SINGLE_LAYER_SHAPES]:
         tens = synth.cell_tensors(0, 8, D, 2)
-        row = {"D": D, "chi": chi}
+        row = {"D": D, "chi": chi, "prec": prec}
         for route in ("double", "single"):
-            log("bench: single-layer leg D=%d chi=%d %s" % (D, chi, route))
-            g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec="fp32",
-                    single_layer=(route == "single"), **solver_opts("fp32"))
+            log("bench: single-layer leg %s D=%d chi=%d %s" % (prec, D, chi, route))
+            g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec=prec,
+                    single_layer=(route == "single"), **solver_opts(prec))
             for _ in range(warm):
                 g.converge(tol=0.0, max_sweeps=1)
             torch.cuda.synchronize()
@@ -198,8 +199,10 @@ def single_layer_leg(warm=2, steps=3):
         row["speedup_moves"] = row["single"]["moves_per_s"] / row["double"]["moves_per_s"]
         row["speedup_corner"] = row["double"]["corner_ms_per_sweep"] / max(row["single"]["corner_ms_per_sweep"], 1e-9)
         out.append(row)
-    return {"rows": out, "prec": "fp32",
-            "note": "2x2 checkerboard, d=8, random tensors (seed 0), cutoff 1e-7; contractions at the live extent"}
+    return {"rows": out,
+            "note": "2x2 checkerboard, d=8, random tensors (seed 0), cutoff 1e-7; contractions at the live extent; "
+                    "bf16: the double layer on the bf16 corner kernel, the single-layer products on bf16 MFMA "
+                    "(the absorption in float32 on both routes' own paths)"}
 
 
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)

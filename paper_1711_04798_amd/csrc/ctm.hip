@@ -180,6 +180,8 @@ struct Inst {
   // the working type, legs [L'][U'][s][D'][R'] of the rotated frame
   void* Sk[MAXT][4] = {};
   void* Sb[MAXT][4] = {};
+  void* Sk16[MAXT][4] = {};      // single-layer in CTM_BF16: bf16 copies for the enlarged corners
+  void* Sb16[MAXT][4] = {};
   double* spec_old = nullptr;  // [pos][4][chi_cap]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
@@ -323,7 +325,7 @@ void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   R.P2Tw = (x.wt == F64) ? (void*)R.P2T : ar.take_bytes(n * chi * ws);
   R.CT = ar.take_bytes(t3 * ws); R.W1 = ar.take_bytes(y4 * ws); R.W2 = ar.take_bytes(y4 * ws);
   R.X6 = ar.take_bytes(t3 * ws);
-  if (x.prec == CTM_BF16) {
+  if (x.prec == CTM_BF16 && !x.cfg.single_layer) {
     R.A3 = ar.take_bytes(3 * y4 * dtype_size(BF16));
     R.T3s = ar.take_bytes(3 * t3 * dtype_size(BF16));
     R.P3s = ar.take_bytes(3 * t3 * dtype_size(BF16));
@@ -362,8 +364,12 @@ void plan(ctm_ctx_s& x, Arena& ar) {
         if (x.cfg.single_layer) {
           I.Sk[t][r] = ar.take_bytes(t5 * ws);
           I.Sb[t][r] = ar.take_bytes(t5 * ws);
+          if (x.prec == CTM_BF16) {
+            I.Sk16[t][r] = ar.take_bytes(t5 * dtype_size(BF16));
+            I.Sb16[t][r] = ar.take_bytes(t5 * dtype_size(BF16));
+          }
         }
-        if (x.prec == CTM_BF16) {
+        if (x.prec == CTM_BF16 && !x.cfg.single_layer) {
           I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
           I.bT3[t][r] = ar.take_bytes(3 * a8 * dtype_size(BF16));
         }
@@ -705,14 +711,18 @@ struct SlJob {
 };
 
 ctm_status sl_product(ctm_ctx_s& x, int64_t c, int D, int d, const std::vector<SlJob>& jobs, const int64_t ydims[6],
-                      const int yperm[6], const int out_perm[6], int tout) {
+                      const int yperm[6], const int out_perm[6], int tin, int tz, int tout) {
+  // tin: type of Y; tz: operand type of both products (and of Z); P' is
+  // float64 for float64 operands, else float32 (fp32 accumulation)
   hipStream_t s = x.stream;
-  const int wt = x.wt;
+  const int tp = tz == F64 ? F64 : F32;
   const int64_t D2 = (int64_t)D * D, M = c * c * D2;
-  const size_t yb = (size_t)M * D2 * dtype_size(wt), zb = yb * (size_t)d;
+  const size_t yb = (size_t)M * D2 * dtype_size(tz), zb = yb * (size_t)d, pb = (size_t)M * D2 * dtype_size(tp);
   if (!x.sl_y || yb == 0) return fail(CTM_E_STATE, "single-layer scratch missing");
-  const size_t nb = std::max<size_t>(1, std::min<size_t>({(size_t)MAXG, x.sl_ybytes / yb, x.sl_zbytes / zb}));
-  if (nb * yb > x.sl_ybytes || nb * zb > x.sl_zbytes) return fail(CTM_E_STATE, "single-layer scratch too small");
+  const size_t nb = std::max<size_t>(1, std::min<size_t>({(size_t)MAXG, x.sl_ybytes / std::max(yb, pb),
+                                                          x.sl_zbytes / zb}));
+  if (nb * std::max(yb, pb) > x.sl_ybytes || nb * zb > x.sl_zbytes)
+    return fail(CTM_E_STATE, "single-layer scratch too small");
   const int64_t pdims[6] = {c, c, D, D, D, D};
   for (size_t j0 = 0; j0 < jobs.size(); j0 += nb) {
     const size_t j1 = std::min(jobs.size(), j0 + nb);
@@ -720,18 +730,18 @@ ctm_status sl_product(ctm_ctx_s& x, int64_t c, int D, int d, const std::vector<S
     for (size_t j = j0; j < j1; ++j) {
       char* yj = (char*)x.sl_y + (j - j0) * yb;
       char* zj = (char*)x.sl_z + (j - j0) * zb;
-      char* pj = (char*)x.sl_p + (j - j0) * yb;
-      HIPCHK(permute(s, wt, jobs[j].y, wt, yj, 6, ydims, yperm));
+      char* pj = (char*)x.sl_p + (j - j0) * pb;
+      HIPCHK(permute(s, tin, jobs[j].y, tz, yj, 6, ydims, yperm));
       ga.add(yj, jobs[j].sk, zj);
       gb.add(zj, jobs[j].sb, pj);
     }
-    CHK(gemm_run(s, wt, wt, M, (int64_t)d * D2, D2, rowmajor(D2), rowmajor((int64_t)d * D2),
+    CHK(gemm_run(s, tz, tz, M, (int64_t)d * D2, D2, rowmajor(D2), rowmajor((int64_t)d * D2),
                  rowmajor((int64_t)d * D2), ga));
     // Z read as rows (g,b | d_k,r_k) -> gb d D^4 + (d_k,r_k), columns (l_b,u_b,s) -> stride D^2
-    CHK(gemm_run(s, wt, wt, M, D2, (int64_t)d * D2, view2(D2, 1, (int64_t)d * D2 * D2, BIG, D2, 0), rowmajor(D2),
+    CHK(gemm_run(s, tz, tp, M, D2, (int64_t)d * D2, view2(D2, 1, (int64_t)d * D2 * D2, BIG, D2, 0), rowmajor(D2),
                  rowmajor(D2), gb));
     for (size_t j = j0; j < j1; ++j)
-      HIPCHK(permute(s, wt, (char*)x.sl_p + (j - j0) * yb, tout, jobs[j].out, 6, pdims, out_perm));
+      HIPCHK(permute(s, tp, (char*)x.sl_p + (j - j0) * pb, tout, jobs[j].out, 6, pdims, out_perm));
   }
   return CTM_OK;
 }
@@ -794,7 +804,8 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
       const int operm[6] = {0, 2, 4, 1, 3, 5};
       std::vector<SlJob> sj;
       for (size_t j = j0; j < j1; ++j) sj.push_back(SlJob{jobs[j].Y, jobs[j].Sk, jobs[j].Sb, jobs[j].Q});
-      CHK(stage3_timed(s, tm, [&]() { return sl_product(*slx, c, D, d, sj, ydims, yperm, operm, tq); }));
+      // bf16: both products on the bf16 MFMA (Y and Z in bf16, fp32 accumulation)
+      CHK(stage3_timed(s, tm, [&]() { return sl_product(*slx, c, D, d, sj, ydims, yperm, operm, ty, ty, tq); }));
       continue;
     }
     // A: rows m = (g, b): b low (extent chi, stride 1), g high (stride D2*D2*chi);
@@ -1128,7 +1139,28 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
   const int64_t K4 = D2 * D2;
   // W2 is written transposed (W2t, below) by its own product in bf16 mode
   bool w2t_done = false;
-  if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
+  if (x.cfg.single_layer) {
+    // the new edge itself: float32 (or float64) operands also in CTM_BF16
+    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
+    // W1[g][l_k][l_b][u_k][u_b][c2] -> (g, c2, l_b, u_b, l_k, u_k); P' (g, c2, d_k, R_k, d_b, R_b)
+    // -> W2[(g,c2)][(dn,R)], or straight into W2t[(g,dn)][(R,c2)] in float32
+    const int64_t ydims[6] = {c, I0.D, I0.D, I0.D, I0.D, c};
+    const int yperm[6] = {0, 5, 2, 4, 1, 3};
+    const bool to_t = at == F32 && D2 >= 2 && I0.rows[0].W2t;
+    const int operm_w2[6] = {0, 1, 2, 4, 3, 5};
+    const int operm_w2t[6] = {0, 2, 4, 3, 5, 1};
+    std::vector<SlJob> sj;
+    for (Inst* I : insts) {
+      Roles ro{&x, I, k};
+      for (int yp = 0; yp < ly; ++yp) {
+        Row& R = I->rows[yp];
+        const int t = ro.tid(xp, yp);
+        sj.push_back(SlJob{R.W1, I->Sk[t][k % 4], I->Sb[t][k % 4], to_t ? R.W2t : R.W2});
+      }
+    }
+    CHK(sl_product(x, c, I0.D, I0.d, sj, ydims, yperm, to_t ? operm_w2t : operm_w2, at, at, at));
+    w2t_done = to_t;
+  } else if (x.prec == CTM_BF16 && I0.rows[0].A3 && corner_bf16_supported(c * c, K4, 3 * K4)) {
     bool a3_done = false;
     if (I0.rows[0].T3s && corner_bf16_supported(c * D2, D2 * c, 3 * c)) {
       // W1 as a three-term bf16 product too, split from the float64 masters:
@@ -1177,26 +1209,6 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       int cnt = std::min(MAXG, g3x.size() - j0);
       HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, vw2, g3x.group(j0, cnt), cnt, F32));
     }
-    w2t_done = to_t;
-  } else if (x.cfg.single_layer) {
-    CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
-    // W1[g][l_k][l_b][u_k][u_b][c2] -> (g, c2, l_b, u_b, l_k, u_k); P' (g, c2, d_k, R_k, d_b, R_b)
-    // -> W2[(g,c2)][(dn,R)], or straight into W2t[(g,dn)][(R,c2)] in float32
-    const int64_t ydims[6] = {c, I0.D, I0.D, I0.D, I0.D, c};
-    const int yperm[6] = {0, 5, 2, 4, 1, 3};
-    const bool to_t = at == F32 && D2 >= 2 && I0.rows[0].W2t;
-    const int operm_w2[6] = {0, 1, 2, 4, 3, 5};
-    const int operm_w2t[6] = {0, 2, 4, 3, 5, 1};
-    std::vector<SlJob> sj;
-    for (Inst* I : insts) {
-      Roles ro{&x, I, k};
-      for (int yp = 0; yp < ly; ++yp) {
-        Row& R = I->rows[yp];
-        const int t = ro.tid(xp, yp);
-        sj.push_back(SlJob{R.W1, I->Sk[t][k % 4], I->Sb[t][k % 4], to_t ? R.W2t : R.W2});
-      }
-    }
-    CHK(sl_product(x, c, I0.D, I0.d, sj, ydims, yperm, to_t ? operm_w2t : operm_w2, at));
     w2t_done = to_t;
   } else {
     CHK(gemm_run(s, at, at, c * D2, D2 * c, c, rowmajor(c), rowmajor(D2 * c), rowmajor(D2 * c), g3));
@@ -1358,8 +1370,9 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
         j.Tp = ro.Tw((q + 3) % 4, cx[q], cy[q]);
         j.b = ro.bw(cx[q], cy[q], q);
         if (x.cfg.single_layer) {
-          j.Sk = I->Sk[ro.tid(cx[q], cy[q])][(k + q) % 4];
-          j.Sb = I->Sb[ro.tid(cx[q], cy[q])][(k + q) % 4];
+          const int t = ro.tid(cx[q], cy[q]), r = (k + q) % 4;
+          j.Sk = x.prec == CTM_BF16 ? I->Sk16[t][r] : I->Sk[t][r];
+          j.Sb = x.prec == CTM_BF16 ? I->Sb16[t][r] : I->Sb[t][r];
         }
         j.X = R.X[q];
         j.Y = R.Y[q];
@@ -1575,8 +1588,6 @@ ctm_status validate(const ctm_config* c) {
   for (int i = 0; i < c->Lx * c->Ly; ++i)
     if (c->pattern[i] < 0 || c->pattern[i] >= c->n_tensors) return fail(CTM_E_INVALID, "pattern entry out of range");
   if (c->prec < 0 || c->prec > 2) return fail(CTM_E_INVALID, "prec");
-  if (c->single_layer && c->prec == CTM_BF16)
-    return fail(CTM_E_INVALID, "single_layer runs in CTM_FP64 or CTM_FP32");
   for (int i = 0; i < c->n_inst; ++i) {
     int d = c->d[i], D = c->D[i], chi = c->chi[i];
     if (d < 1 || D < 1 || chi < 1 || d > 64 || D > 16) return fail(CTM_E_INVALID, "d in 1..64, D in 1..16, chi >= 1");
@@ -2437,8 +2448,12 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           if (permute(x->stream, F64, I.A[t], x->wt, I.Sk[t][r], 5, dims, perm[r]) != hipSuccess ||
               permute(x->stream, F64, I.B[t], x->wt, I.Sb[t][r], 5, dims, perm[r]) != hipSuccess)
             return cleanup(fail(CTM_E_HIP, "single-layer tensors"));
+          if (x->prec == CTM_BF16 &&
+              (permute(x->stream, F64, I.A[t], BF16, I.Sk16[t][r], 5, dims, perm[r]) != hipSuccess ||
+               permute(x->stream, F64, I.B[t], BF16, I.Sb16[t][r], 5, dims, perm[r]) != hipSuccess))
+            return cleanup(fail(CTM_E_HIP, "single-layer tensors"));
         }
-      if (x->prec == CTM_BF16)
+      if (x->prec == CTM_BF16 && !x->cfg.single_layer)
         for (int r = 0; r < 4; ++r) {
           int64_t dims[2] = {(int64_t)I.D2 * I.D2, (int64_t)I.D2 * I.D2};
           int perm[2] = {1, 0};

@@ -130,6 +130,7 @@ CASES = [
     # single-layer contractions (no double layer in the moves)
     ("c1_single", 2, 2, [0, 1, 1, 0], 2, [8], [4], [64], "fp64", {"single_layer": True}),
     ("c2_single", 2, 2, [0, 1, 1, 0], 2, [8], [6], [144], "fp32", {"single_layer": True}),
+    ("c2_single_bf16", 2, 2, [0, 1, 1, 0], 2, [8], [6], [144], "bf16", {"single_layer": True}),
     ("large_D_single", 2, 2, [0, 1, 1, 0], 2, [8], [12], [100], "fp32", {"single_layer": True}),
     ("batched_single", 1, 1, [0], 1, [8] * 6, [3, 4, 5] * 2, [32, 64, 100] * 2, "fp32",
      {"single_layer": True, "use_graph": True}),

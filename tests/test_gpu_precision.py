@@ -73,7 +73,7 @@ def _reference(name, D, chi, max_sweeps):
 
 
 def _check(name, D, chi, prec, max_sweeps):
-    # "fp32-single": float32 contractions through the single-layer route
+    # "fp32-single", "bf16-single": through the single-layer route
     single = prec.endswith("-single")
     prec = prec.split("-")[0]
     ref = _reference(name, D, chi, max_sweeps)
@@ -89,14 +89,14 @@ def _check(name, D, chi, prec, max_sweeps):
     assert e_rel < be and k_rel < bk and s_err < bs
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single", "bf16-single"])
 def test_precision_ruby_size(gpu, prec):
     """2x2 checkerboard, d=8, D=4, chi=64."""
     print("case precision c1", prec, flush=True)
     _check("c1", 4, 64, prec, 20)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp32-single", "bf16-single"])
 def test_precision_benchmark_size(gpu, prec):
     """2x2 checkerboard, d=8, D=6, chi=144 (the benchmark workload)."""
     print("case precision c2", prec, flush=True)

@@ -6,8 +6,8 @@ the ket, the batched form in graph mode, and a bond dimension D = 8.
 
 Tolerances: float64 as in the double-layer parity tests (corners 1e-13 of
 the largest element, truncated half-system operator 1e-11, norm per site
-1e-10, lock-step spectra 1e-8); float32 element by element against the
-rounding bound of the contraction chain.
+1e-10, lock-step spectra 1e-8); float32 and bf16 element by element
+against the rounding bound of the contraction chain.
 """
 import numpy as np
 import pytest
@@ -76,15 +76,18 @@ def test_single_layer_one_step(gpu, direction, d, D, chi, bra):
     g.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("D,chi", [(2, 16), (4, 12)])
-def test_single_layer_fp32_corners_elementwise(gpu, D, chi):
-    """float32 single-layer corners from an imported oracle environment, element
-    by element.  Each stage rounds its output once to float32 (X, Y, the
-    ket-layer intermediate Z) after accumulating in float32, and the tensors
-    are rounded once; every rounding error of an element is at most u times
-    the same contraction over absolute values, the double layer replaced by
-    sum_s |A| |B|.  Bound: (8 u + K u) (|C| |T| |T| |a|)_ij with u = 2^-24
-    and K = 2 chi + D^2 + d D^2 the total contraction length."""
+def test_single_layer_reduced_corners_elementwise(gpu, prec, D, chi):
+    """Reduced-precision single-layer corners from an imported oracle
+    environment, element by element.  Each stage rounds its output once
+    after accumulating in float32 (X in float32; Y and the ket-layer
+    intermediate Z in the working type: float32, or bf16 in the bf16 form),
+    and the tensors are rounded once; every rounding error of an element is
+    at most u times the same contraction over absolute values, the double
+    layer replaced by sum_s |A| |B|.  Bound: (8 u + K u_fp32)
+    (|C| |T| |T| |a|)_ij with u the unit roundoff of the working type and
+    K = 2 chi + D^2 + d D^2 the total contraction length."""
     from paper_1711_04798_amd import CTM
     from test_gpu_stages import _dump, env_to_flat
     d = 2
@@ -95,13 +98,13 @@ def test_single_layer_fp32_corners_elementwise(gpu, D, chi):
     env = octm.init_trivial(cell, chi)
     for _ in range(3):
         octm.sweep(cell, env)
-    print("case single layer fp32 corners", D, chi, flush=True)
-    g = CTM([tens], Lx=Lx, Ly=Ly, pattern=pat, chi=chi, prec="fp32", max_iters=2, resid_tol=0.0, cutoff=1e-6,
+    print("case single layer reduced corners", prec, D, chi, flush=True)
+    g = CTM([tens], Lx=Lx, Ly=Ly, pattern=pat, chi=chi, prec=prec, max_iters=2, resid_tol=0.0, cutoff=1e-6,
             single_layer=True)
     g.import_env(env_to_flat(env, Lx, Ly))
     g.move("L", 1)
     n = chi * D * D
-    u = 2.0 ** -24
+    u = 2.0 ** -8 if prec == "bf16" else 2.0 ** -24
     K = 2 * chi + D * D + d * D * D
     fr = octm._Frame(cell, env, 0)
     abs_cell = octm.Cell(Lx, Ly, pat, [np.abs(t) for t in tens])
@@ -114,7 +117,7 @@ def test_single_layer_fp32_corners_elementwise(gpu, D, chi):
             Qabs = octm.enlarged_corner(np.abs(fr.C(q, cx[q], cy[q])), np.abs(fr.T(q, cx[q], cy[q])),
                                         np.abs(fr.T((q + 3) % 4, cx[q], cy[q])), a_abs)
             Qg = _dump(g, 0, 4 * yp + q, (n, n), np.float32).astype(np.float64)
-            bound = (8 * u + K * u) * Qabs
+            bound = (8 * u + K * 2.0 ** -24) * Qabs
             ratio = np.max(np.abs(Qg - Qo[q]) / (bound + 1e-300))
             print("Q%d row %d: max |dQ| / bound %.3f" % (q + 1, yp, ratio))
             assert np.all(np.abs(Qg - Qo[q]) <= bound)
