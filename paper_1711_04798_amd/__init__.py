@@ -3,4 +3,4 @@
 The computation lives in ``libctm.so`` (hand-written HIP kernels behind the C
 interface declared in ``include/ctm.h``); this package only marshals arguments.
 """
-from .binding import CTM, MLP, CtmError, fidelity, load, LIB_PATH, EXPORTS  # noqa: F401
+from .binding import CTM, MLP, SimpleUpdate, CtmError, fidelity, load, LIB_PATH, EXPORTS  # noqa: F401

@@ -26,7 +26,8 @@ EXPORTS = [
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_metrics", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
     "ctm_last_error", "ctm_tile_table_load", "ctm_tile_table_save", "ctm_tile_table_tune",
-    "ctm_tile_table_clear", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
+    "ctm_tile_table_clear", "ctm_su_workspace_size", "ctm_su_init", "ctm_su_set_gates", "ctm_su_evolve",
+    "ctm_su_state", "ctm_su_peps", "ctm_su_destroy", "ctm_boundary_workspace_size", "ctm_boundary_spectrum", "ctm_fidelity_noalloc", "ctm_fidelity_noalloc_max_bytes", "ctm_mlp_param_count", "ctm_mlp_workspace_size", "ctm_mlp_features",
     "ctm_mlp_targets", "ctm_mlp_forward", "ctm_mlp_loss_grad", "ctm_mlp_adam", "ctm_mlp_train",
 ]
 
@@ -104,6 +105,17 @@ def load(path=LIB_PATH, tile_table=True):
     lib.ctm_checkpoint_bytes.restype = SZ
     lib.ctm_checkpoint_save.argtypes = [VP, I32, VP, SZ]
     lib.ctm_checkpoint_load.argtypes = [VP, I32, VP, SZ]
+    lib.ctm_su_workspace_size.argtypes = [I32, I32, I32, P(SZ)]
+    lib.ctm_su_init.argtypes = [I32, I32, I32, VP, VP, VP, SZ, VP, P(VP)]
+    lib.ctm_su_set_gates.argtypes = [VP, VP, F64]
+    lib.ctm_su_evolve.argtypes = [VP, I32, F64, I32, P(I32), P(F64)]
+    lib.ctm_su_state.argtypes = [VP, VP, VP]
+    lib.ctm_su_peps.argtypes = [VP, VP]
+    lib.ctm_su_destroy.argtypes = [VP]
+    lib.ctm_su_destroy.restype = None
+    for name in ("ctm_su_workspace_size", "ctm_su_init", "ctm_su_set_gates", "ctm_su_evolve", "ctm_su_state",
+                 "ctm_su_peps"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.ctm_set_metrics.argtypes = [VP, ctypes.c_char_p, I32]
     lib.ctm_set_metrics.restype = ctypes.c_int
     lib.ctm_set_timing.argtypes = [VP, I32]
@@ -498,3 +510,71 @@ class MLP:
                                     self.stream))
         self.step += steps
         return hist[:steps].cpu().numpy()
+
+
+class SimpleUpdate:
+    """Simple update of n 2x2-checkerboard states in lock-step (ctm_su_*).
+    `tensors`: n pairs (A, B) of numpy arrays [s, u, l, d, r] (the Gamma
+    tensors); `weights`: array [n][4][D] over the bonds h0, h1, v0, v1."""
+
+    def __init__(self, tensors, weights, device="cuda:0"):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.device = torch.device(device)
+        self.n = len(tensors)
+        self.d, self.D = int(tensors[0][0].shape[0]), int(tensors[0][0].shape[1])
+        T = np.ascontiguousarray(np.stack([np.stack(inst) for inst in tensors]), dtype=np.float64)
+        L = np.ascontiguousarray(weights, dtype=np.float64)
+        assert T.shape == (self.n, 2, self.d) + (self.D,) * 4 and L.shape == (self.n, 4, self.D)
+        tT = torch.as_tensor(T, device=self.device)
+        tL = torch.as_tensor(L, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(lib.ctm_su_workspace_size(self.n, self.d, self.D, ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.stream = _stream(torch, self.device)
+        self.ctx = ctypes.c_void_p()
+        _check(lib.ctm_su_init(self.n, self.d, self.D, ctypes.c_void_p(tT.data_ptr()), ctypes.c_void_p(tL.data_ptr()),
+                               ctypes.c_void_p(self.ws.data_ptr() + off), nb.value, self.stream,
+                               ctypes.byref(self.ctx)))
+        torch.cuda.synchronize(self.device)
+
+    def set_gates(self, h, dtau):
+        """Gates exp(-dtau h) from bond Hamiltonians h [n][4][d^2][d^2]."""
+        th = self._torch.as_tensor(np.ascontiguousarray(h, dtype=np.float64), device=self.device)
+        _check(load().ctm_su_set_gates(self.ctx, ctypes.c_void_p(th.data_ptr()), float(dtau)))
+
+    def evolve(self, max_steps, tol=0.0, check_every=10):
+        """Trotter steps (ctm_su_evolve): (steps done, last weight change per instance)."""
+        steps = ctypes.c_int32()
+        ch = (ctypes.c_double * self.n)()
+        _check(load().ctm_su_evolve(self.ctx, int(max_steps), float(tol), int(check_every), ctypes.byref(steps), ch))
+        return steps.value, np.array(ch[:])
+
+    def state(self):
+        """(Gamma tensors [n][2][d, D, D, D, D], weights [n][4][D])."""
+        torch = self._torch
+        T = torch.empty((self.n, 2, self.d) + (self.D,) * 4, dtype=torch.float64, device=self.device)
+        L = torch.empty((self.n, 4, self.D), dtype=torch.float64, device=self.device)
+        _check(load().ctm_su_state(self.ctx, ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(L.data_ptr())))
+        return T.cpu().numpy(), L.cpu().numpy()
+
+    def peps(self):
+        """iPEPS tensors with sqrt(weights) on every leg [n][2][d, D, D, D, D]."""
+        torch = self._torch
+        T = torch.empty((self.n, 2, self.d) + (self.D,) * 4, dtype=torch.float64, device=self.device)
+        _check(load().ctm_su_peps(self.ctx, ctypes.c_void_p(T.data_ptr())))
+        return T.cpu().numpy()
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self._torch.cuda.synchronize(self.device)
+            load().ctm_su_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,7 +11,7 @@ SRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libctm.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kernels.hip", "solver.hip", "corner_bf16.hip", "tsgemm.hip", "ctm.hip", "mlp.hip", "boundary.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "corner_bf16.hip", "tsgemm.hip", "ctm.hip", "mlp.hip", "boundary.hip", "su.hip"]
 
 HIPFLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -193,3 +193,50 @@ print(lib.ctm_tile_table_load(bad.encode(), ctypes.byref(n)))
     key = lambda e: (e["kernel"], e["ta"], e["tc"], e["ak"], e["bk"], e["groups"], e["M"], e["N"], e["K"])
     got = json.loads(dst.read_text())
     assert sorted((key(e), e["variant"]) for e in got) == sorted((key(e), e["variant"]) for e in entries)
+
+
+DRY_SU = r'''
+import ctypes, json, sys
+sys.path.insert(0, %(root)r)
+from paper_1711_04798_amd import binding as b
+lib = b.load(%(lib)r, tile_table=False)
+out = []
+for n, d, D in ((1, 2, 3), (3, 8, 2), (40, 2, 4), (2, 8, 3)):
+    nb = ctypes.c_size_t()
+    st = [lib.ctm_su_workspace_size(n, d, D, ctypes.byref(nb))]
+    ctx = ctypes.c_void_p()
+    st.append(lib.ctm_su_init(n, d, D, ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31), ctypes.c_void_p(1 << 40),
+                              nb.value, None, ctypes.byref(ctx)))
+    st.append(lib.ctm_su_set_gates(ctx, ctypes.c_void_p(1 << 32), 0.05))
+    steps = ctypes.c_int32()
+    ch = (ctypes.c_double * n)()
+    st.append(lib.ctm_su_evolve(ctx, 3, 0.0, 1, ctypes.byref(steps), ch))
+    st.append(lib.ctm_su_state(ctx, ctypes.c_void_p(1 << 33), ctypes.c_void_p(1 << 34)))
+    st.append(lib.ctm_su_peps(ctx, ctypes.c_void_p(1 << 35)))
+    out.append([n, d, D, st, steps.value, lib.ctm_last_error().decode()])
+    lib.ctm_su_destroy(ctx)
+nb = ctypes.c_size_t()
+out.append(["too big", lib.ctm_su_workspace_size(1, 8, 4, ctypes.byref(nb))])
+print(json.dumps(out))
+'''
+
+
+def run_su_dry(lib, extra_env=None):
+    import json
+    env = dict(os.environ, CTM_DRY_RUN="1", **(extra_env or {}))
+    r = subprocess.run([sys.executable, "-c", DRY_SU % {"root": ROOT, "lib": lib}], capture_output=True, text=True,
+                       env=env, timeout=600)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return json.loads(r.stdout.strip().splitlines()[-1]), r
+
+
+def test_su_dry_run(lib_path):
+    """The simple update's orchestration (gate construction, Trotter steps,
+    state and iPEPS export) passes the host-side bounds checks; d^2 D above
+    the theta SVD limit is rejected."""
+    res, _ = run_su_dry(lib_path)
+    for row in res[:-1]:
+        n, d, D, st, steps, err = row
+        assert all(v == 0 for v in st), row
+        assert steps == 3
+    assert res[-1][1] == 1  # CTM_E_INVALID: d^2 D = 256 > 192

@@ -120,3 +120,13 @@ def test_fidelity_and_tile_table_under_sanitizers(san_lib, tmp_path):
     assert lines["bad"][0] != "0"
     for prec in ("fp64", "bf16"):
         assert lines[prec][0] in ("0", "4"), lines[prec]  # CTM_OK or CTM_E_NOCONV
+
+
+def test_simple_update_under_sanitizers(san_lib):
+    import test_abi
+    env = dict(LD_PRELOAD=asan_runtime(), ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    res, r = test_abi.run_su_dry(san_lib, env)
+    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error:" not in r.stderr, r.stderr[-3000:]
+    for row in res[:-1]:
+        assert all(v == 0 for v in row[3]), row
