@@ -111,7 +111,9 @@ def cpu_baseline(tensors):
     octm.absorb_corner_down(fr.C(3, 0, 0), fr.T(2, 0, 0), P2)
     dt = time.perf_counter() - t0
     # a column step of the 2x2 cell has two rows
+    su_rates = su_oracle_rates()
     return {"value": 1.0 / (2.0 * dt), "unit": "moves/s", "cores": threads or cores,
+            "simple_update_steps_per_s_by_D": su_rates,
             "kind": "oracle",
             "sample": "one plaquette row (4 enlarged corners, dense float64 half-system "
                       "SVD of n=5184, absorption) of one column step, %.1f s; value = 1/(2 t)"
@@ -203,6 +205,58 @@ def single_layer_leg(warm=2, steps=3, precs=("fp32", "bf16")):
             "note": "2x2 checkerboard, d=8, random tensors (seed 0), cutoff 1e-7; contractions at the live extent; "
                     "bf16: the double layer on the bf16 corner kernel, the single-layer products on bf16 MFMA "
                     "(the absorption in float32 on both routes' own paths)"}
+
+
+SU_FORMS = [dict(n=64, D=2), dict(n=64, D=3), dict(n=1, D=3)]
+
+
+def su_leg(steps=40):
+    """Simple update of ruby-model states (d = 8; couplings J = (s, s, 2 - s)
+    over a scan of n points) in lock-step on the GPU: instance Trotter steps
+    per second.  The oracle's single-instance rate is measured in the CPU
+    baseline leg."""
+    import torch
+    import synth
+    from paper_1711_04798_amd import SimpleUpdate
+    from paper_1711_04798_amd.models import ruby_bond_hamiltonians
+    rows = []
+    for f in SU_FORMS:
+        n, D = f["n"], f["D"]
+        rng = np.random.default_rng(7)
+        tens = [[synth.peps_tensor(rng, 8, D) for _ in range(2)] for _ in range(n)]
+        lam = np.full((n, 4, D), 1.0 / np.sqrt(D))
+        hs = np.array([ruby_bond_hamiltonians((0.5 + i / n, 0.5 + i / n, 1.5 - i / n)) for i in range(n)])
+        log("bench: simple update n=%d D=%d" % (n, D))
+        g = SimpleUpdate(tens, lam)
+        g.set_gates(hs, 0.01)
+        g.evolve(3, 0.0, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.evolve(steps, 0.0, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.close()
+        rows.append({"n_inst": n, "d": 8, "D": D, "steps": steps, "ms_per_step": 1e3 * el / steps,
+                     "instance_steps_per_s": n * steps / el})
+    return {"rows": rows, "note": "ruby model (d = 8), dtau = 0.01, random start; one step = 4 bond updates"}
+
+
+def su_oracle_rates(steps=5):
+    """The oracle's simple update (float64 NumPy, one instance) in steps per
+    second, for the bond dimensions of the simple-update leg."""
+    import synth
+    from oracle import models, su as osu
+    out = {}
+    for D in sorted({f["D"] for f in SU_FORMS}):
+        rng = np.random.default_rng(7)
+        T = [synth.peps_tensor(rng, 8, D) for _ in range(2)]
+        lam = {b: np.full(D, 1.0 / np.sqrt(D)) for b in osu.BONDS}
+        gates = osu.gates_from(models.ruby_bond_h((0.5, 0.5, 1.5)), 0.01)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            osu.step(T, lam, gates, D)
+        out[str(D)] = steps / (time.perf_counter() - t0)
+    return out
 
 
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
@@ -373,6 +427,8 @@ def main():
                     help="only the corner kernel at the full extent (for profiling runs)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-layer comparison leg")
     ap.add_argument("--single-only", action="store_true", help="only the single-layer comparison leg")
+    ap.add_argument("--no-su", action="store_true", help="skip the simple-update leg")
+    ap.add_argument("--su-only", action="store_true", help="only the simple-update leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -400,6 +456,9 @@ def main():
     tensors = synth.cell_tensors(w["seed"], w["d"], w["D"], 2)
     if args.single_only:
         print(json.dumps({"single_layer": single_layer_leg()}), flush=True)
+        return
+    if args.su_only:
+        print(json.dumps({"simple_update": su_leg()}), flush=True)
         return
     if args.full_extent_only:
         print(json.dumps({"roofline_full_extent": dense_extent_leg(tensors, args.prec)}), flush=True)
@@ -490,6 +549,8 @@ def main():
         out["roofline_full_extent"] = dense_extent_leg(tensors, args.prec)
     if not args.no_single:
         out["single_layer"] = single_layer_leg()
+    if not args.no_su:
+        out["simple_update"] = su_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
         out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])
@@ -499,6 +560,10 @@ def main():
     if not args.no_cpu:
         log("bench: cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(tensors)
+        if "simple_update" in out:
+            rates = out["cpu_baseline"]["simple_update_steps_per_s_by_D"]
+            for r in out["simple_update"]["rows"]:
+                r["speedup_vs_oracle"] = r["instance_steps_per_s"] / rates[str(r["D"])]
     print(json.dumps(out), flush=True)
 
 

@@ -18,7 +18,12 @@
 //   semidefinite), R = diag(sqrt S) W^T, so that Xm = Q R with orthonormal
 //   Q = Xm W diag(S^-1/2) on the support of G;
 //   theta[(a,i),(b,j)] = sum_(k,l) g[(i,j),(k,l)] sum_p R_X[a,(k,p)] lam_p R_Y[b,(l,p)]
-//   (m x m), theta = U diag(sv) V^T (one-sided Jacobi);
+//   with a, b below the rank bound r = min(D^3, k) of Xm (m = r d square);
+//   its D leading singular triplets: one-sided Jacobi of the whole theta
+//   when its working set fits LDS (m <= 80), otherwise subspace iteration
+//   on a block of b = min(m, D + 16) counter-based normal columns (six
+//   rounds of theta and theta^T products, each followed by Cholesky-QR) and
+//   Rayleigh-Ritz through a Jacobi SVD of the b x b R factor of theta V;
 //   new weights: the D largest sv above 1e-12 sv_1, divided by their norm;
 //   X' = Q U[:, :D] = Xm (W diag(S^-1/2) R'_X) with R'_X[a,(i,p)] = U[(a,i),p],
 //   then the weights of the other legs divided out (weights below 1e-12 of
@@ -93,6 +98,12 @@ struct Inst {
   double* Wt;
   double* St;        // m
   double* jw;        // Jacobi working columns: 2 m m16
+  double* Vb;        // subspace iteration: m x b blocks
+  double* Yb;
+  double* Gb;        // b x b Gram, R factors
+  double* Rb1;
+  double* Rb2;
+  double* Rb;
   double* Rn[2];     // k x k new R factors
   double* S1[2];     // k x k
   double* Xn[2];     // D^3 x k
@@ -108,6 +119,9 @@ struct Inst {
 
 struct ctm_su_s {
   int n = 0, d = 0, D = 0, k = 0, m = 0, D3 = 0;
+  int r = 0;          // rank bound of the reduced tensors: min(D^3, k); m = r d
+  int b = 0;          // subspace block of the truncated SVD (0: full Jacobi)
+  uint64_t updates = 0;  // bond updates done (seeds the subspace start)
   hipStream_t stream = nullptr;
   Registry reg;
   std::vector<Inst> inst;
@@ -155,6 +169,14 @@ void plan(ctm_su_s& x, Carve& c) {
     I.Ut = c.take(m * m);
     I.Wt = c.take(m * m);
     I.St = c.take(m);
+    if (x.b) {
+      I.Vb = c.take(m * x.b);
+      I.Yb = c.take(m * x.b);
+      I.Gb = c.take((size_t)x.b * x.b);
+      I.Rb1 = c.take((size_t)x.b * x.b);
+      I.Rb2 = c.take((size_t)x.b * x.b);
+      I.Rb = c.take((size_t)x.b * x.b);
+    }
     I.jw = c.take(2 * std::max({m * m16, k * k16, d * d * dd16}));
     I.change = c.take(1);
     I.hs = c.take(d4 + 1);  // h + c I, then the shift c
@@ -271,12 +293,13 @@ __global__ void su_weights_kernel(Ptrs St, Ptrs lam, Ptrs change, int D, int res
   *change.p[i] = ch;
 }
 
-// R'_X[a, (i, p)] = U[(a, i), p] for p < keep (zero beyond); the Y side from W
-__global__ void su_newr_kernel(Ptrs U, Ptrs lam, Ptrs Rn, int k, int d, int D, int m) {
+// R'_X[a, (i, p)] = U[(a, i), p] for a < r and p < keep (zero beyond); U has
+// row stride ldu; the Y side from the right singular vectors
+__global__ void su_newr_kernel(Ptrs U, Ptrs lam, Ptrs Rn, int k, int d, int D, int ldu, int r) {
   const int i = blockIdx.y;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < k * k; e += gridDim.x * blockDim.x) {
     const int a = e / k, c = e % k, s = c / D, p = c % D;
-    Rn.p[i][e] = lam.p[i][p] > 0.0 ? U.p[i][(int64_t)(a * d + s) * m + p] : 0.0;
+    Rn.p[i][e] = (a < r && lam.p[i][p] > 0.0) ? U.p[i][(int64_t)(a * d + s) * ldu + p] : 0.0;
   }
 }
 
@@ -361,11 +384,106 @@ ctm_status gemm64(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& va
   return CTM_OK;
 }
 
+// Y <- Y R^{-1} with R from the shifted Cholesky factor of Y^T Y, `passes`
+// times (Cholesky-QR with shifts, as in the projector solver); with keep_r
+// (two passes) the product R2 R1 of the factors is left in Rb (b x b).
+ctm_status cholqr(ctm_su_s& x, const Chunk& ch, const std::vector<double*>& Y, int passes, bool keep_r) {
+  hipStream_t s = x.stream;
+  const int b = x.b, m = x.m;
+  const double u = 1.1102230246251565e-16;
+  for (int pass = 0; pass < passes; ++pass) {
+    const double coef = pass == 0 ? 11.0 * ((double)m * b + (double)b * (b + 1)) * u : 4.0 * u;
+    std::vector<const double*> A;
+    std::vector<double*> C;
+    CPtrSet Gp{}, Rc{};
+    PtrSet Rp{}, Yp{};
+    for (int j = 0; j < ch.cnt; ++j) {
+      Inst& I = x.inst[ch.i0 + j];
+      A.push_back(Y[j]);
+      C.push_back(I.Gb);
+      double* R = pass == 0 ? I.Rb1 : I.Rb2;
+      Gp.p[j] = I.Gb;
+      Rp.p[j] = R;
+      Rc.p[j] = R;
+      Yp.p[j] = Y[j];
+    }
+    SOK(gemm64(s, b, b, m, transposed(rowmajor(b)), rowmajor(b), rowmajor(b), A, A, C));
+    StatSet none{};
+    SCHK(chol_shift_inv(s, b, coef, Gp, Rp, none, ch.cnt, false));
+    SCHK(trsm_rows(s, m, b, Yp, Rc, ch.cnt));
+  }
+  if (keep_r) {
+    // R = R2 R1 (both upper triangular)
+    std::vector<const double*> A, B;
+    std::vector<double*> C;
+    for (int j = 0; j < ch.cnt; ++j) {
+      Inst& I = x.inst[ch.i0 + j];
+      A.push_back(I.Rb2);
+      B.push_back(I.Rb1);
+      C.push_back(I.Rb);
+    }
+    SOK(gemm64(s, b, b, b, rowmajor(b), rowmajor(b), rowmajor(b), A, B, C));
+  }
+  return CTM_OK;
+}
+
+// The D leading singular triplets of every theta of the chunk by subspace
+// iteration: V (m x b) counter-based normals; six rounds of Y = theta V,
+// V = theta^T Y, each orthonormalised; then theta V = Y R, R = U_r S W_r^T
+// (Jacobi), left vectors Y U_r, right vectors V W_r (both m x b, into th0
+// and thp), values S into St.
+ctm_status truncated_svd(ctm_su_s& x, const Chunk& ch, std::vector<double*>& lu, std::vector<double*>& lv) {
+  hipStream_t s = x.stream;
+  const int b = x.b, m = x.m;
+  std::vector<double*> V(ch.cnt), Y(ch.cnt);
+  std::vector<const double*> th(ch.cnt), Vc(ch.cnt), Yc(ch.cnt);
+  for (int j = 0; j < ch.cnt; ++j) {
+    Inst& I = x.inst[ch.i0 + j];
+    V[j] = I.Vb;
+    Y[j] = I.Yb;
+    th[j] = I.th;
+    Vc[j] = I.Vb;
+    Yc[j] = I.Yb;
+    SCHK(randn(s, I.Vb, (int64_t)m * b, 0x5eed5eedull ^ (x.updates * 0x9E3779B97F4A7C15ull) ^ (uint64_t)(ch.i0 + j)));
+  }
+  for (int round = 0; round < 6; ++round) {
+    SOK(gemm64(s, m, b, m, rowmajor(m), rowmajor(b), rowmajor(b), th, Vc, Y));
+    SOK(cholqr(x, ch, Y, 1, false));
+    SOK(gemm64(s, m, b, m, transposed(rowmajor(m)), rowmajor(b), rowmajor(b), th, Yc, V));
+    SOK(cholqr(x, ch, V, round == 5 ? 2 : 1, false));
+  }
+  SOK(gemm64(s, m, b, m, rowmajor(m), rowmajor(b), rowmajor(b), th, Vc, Y));
+  SOK(cholqr(x, ch, Y, 2, true));
+  CPtrSet M{};
+  PtrSet U{}, Sv{}, W{}, J{};
+  for (int j = 0; j < ch.cnt; ++j) {
+    Inst& I = x.inst[ch.i0 + j];
+    M.p[j] = I.Rb;
+    U.p[j] = I.Ut;
+    Sv.p[j] = I.St;
+    W.p[j] = I.Wt;
+    J.p[j] = I.jw;
+  }
+  SCHK(jacobi_svd(s, b, M, U, Sv, W, J, ch.cnt, true, false));
+  std::vector<const double*> Ur(ch.cnt), Wr(ch.cnt);
+  for (int j = 0; j < ch.cnt; ++j) {
+    Inst& I = x.inst[ch.i0 + j];
+    Ur[j] = I.Ut;
+    Wr[j] = I.Wt;
+    lu[j] = I.th0;
+    lv[j] = I.thp;
+  }
+  SOK(gemm64(s, m, b, b, rowmajor(b), rowmajor(b), rowmajor(b), Yc, Ur, lu));
+  SOK(gemm64(s, m, b, b, rowmajor(b), rowmajor(b), rowmajor(b), Vc, Wr, lv));
+  return CTM_OK;
+}
+
 ctm_status bond_update(ctm_su_s& x, int bond, bool reset) {
   hipStream_t s = x.stream;
-  const int d = x.d, D = x.D, k = x.k, m = x.m, D3 = x.D3;
+  const int d = x.d, D = x.D, k = x.k, m = x.m, D3 = x.D3, r = x.r;
   const int64_t t5 = (int64_t)d * D * D * D * D;
   const dim3 blk(256);
+  ++x.updates;
   for (const Chunk& ch : chunks(x.n)) {
     auto tab = [&](auto f) {
       Ptrs p{};
@@ -420,7 +538,7 @@ ctm_status bond_update(ctm_su_s& x, int bond, bool reset) {
       }
       SCHK(dry_run() ? hipSuccess : hipGetLastError());
     }
-    // theta0[(a,i),(b,j)] = sum_p (R_X lam)[(a,i),p] R_Y[(b,j),p]
+    // theta0[(a,i),(b,j)] = sum_p (R_X lam)[(a,i),p] R_Y[(b,j),p], a, b < r
     {
       std::vector<const double*> A, B;
       std::vector<double*> C;
@@ -434,9 +552,9 @@ ctm_status bond_update(ctm_su_s& x, int bond, bool reset) {
     }
     // gate: [a][k][b][l] -> [(k,l)][(a,b)], times g, back to [a][i][b][j]
     {
-      const int64_t dims1[4] = {k, d, k, d};
+      const int64_t dims1[4] = {r, d, r, d};
       const int perm1[4] = {1, 3, 0, 2};
-      const int64_t dims2[4] = {d, d, k, k};
+      const int64_t dims2[4] = {d, d, r, r};
       const int perm2[4] = {2, 0, 3, 1};
       for (int j = 0; j < ch.cnt; ++j) {
         Inst& I = x.inst[ch.i0 + j];
@@ -450,15 +568,18 @@ ctm_status bond_update(ctm_su_s& x, int bond, bool reset) {
         B.push_back(I.thp);
         C.push_back(I.th0);
       }
-      SOK(gemm64(s, (int64_t)d * d, (int64_t)k * k, (int64_t)d * d, rowmajor((int64_t)d * d),
-                 rowmajor((int64_t)k * k), rowmajor((int64_t)k * k), A, B, C));
+      SOK(gemm64(s, (int64_t)d * d, (int64_t)r * r, (int64_t)d * d, rowmajor((int64_t)d * d),
+                 rowmajor((int64_t)r * r), rowmajor((int64_t)r * r), A, B, C));
       for (int j = 0; j < ch.cnt; ++j) {
         Inst& I = x.inst[ch.i0 + j];
         SCHK(permute(s, F64, I.th0, F64, I.th, 4, dims2, perm2));
       }
     }
-    // theta = U diag(sv) V^T; new weights, new R factors
-    {
+    // the D leading singular triplets of theta: left vectors in `lu`, right
+    // vectors in `lv` (row stride ldu), values in St (descending)
+    std::vector<double*> lu(ch.cnt), lv(ch.cnt);
+    int ldu = m;
+    if (x.b == 0) {
       CPtrSet M{};
       PtrSet U{}, Sv{}, W{}, J{};
       for (int j = 0; j < ch.cnt; ++j) {
@@ -468,21 +589,32 @@ ctm_status bond_update(ctm_su_s& x, int bond, bool reset) {
         Sv.p[j] = I.St;
         W.p[j] = I.Wt;
         J.p[j] = I.jw;
+        lu[j] = I.Ut;
+        lv[j] = I.Wt;
       }
       SCHK(jacobi_svd(s, m, M, U, Sv, W, J, ch.cnt, true, false));
+    } else {
+      SOK(truncated_svd(x, ch, lu, lv));
+      ldu = x.b;
+    }
+    {
       Ptrs St = tab([&](Inst& I) { return I.St; });
       Ptrs Ch = tab([&](Inst& I) { return I.change; });
-      Ptrs Ut = tab([&](Inst& I) { return I.Ut; });
-      Ptrs Wt = tab([&](Inst& I) { return I.Wt; });
+      Ptrs Lu{}, Lv{};
+      for (int j = 0; j < ch.cnt; ++j) {
+        Lu.p[j] = lu[j];
+        Lv.p[j] = lv[j];
+      }
       Ptrs R0 = tab([&](Inst& I) { return I.Rn[0]; });
       Ptrs R1 = tab([&](Inst& I) { return I.Rn[1]; });
       for (int j = 0; j < ch.cnt; ++j)
-        SCHK(check_spans({{St.p[j], (size_t)m * 8}, {lamb.p[j], (size_t)D * 8}, {Ch.p[j], 8}}, "su weights"));
+        SCHK(check_spans({{St.p[j], (size_t)D * 8}, {lamb.p[j], (size_t)D * 8}, {Ch.p[j], 8},
+                          {Lu.p[j], (size_t)m * ldu * 8}, {Lv.p[j], (size_t)m * ldu * 8}}, "su weights"));
       if (!dry_run()) {
         hipLaunchKernelGGL(su_weights_kernel, dim3(ch.cnt), dim3(64), 0, s, St, lamb, Ch, D, reset ? 1 : 0);
         const dim3 g((unsigned)std::max(1, std::min(64, (k * k + 255) / 256)), ch.cnt);
-        hipLaunchKernelGGL(su_newr_kernel, g, blk, 0, s, Ut, lamb, R0, k, d, D, m);
-        hipLaunchKernelGGL(su_newr_kernel, g, blk, 0, s, Wt, lamb, R1, k, d, D, m);
+        hipLaunchKernelGGL(su_newr_kernel, g, blk, 0, s, Lu, lamb, R0, k, d, D, ldu, r);
+        hipLaunchKernelGGL(su_newr_kernel, g, blk, 0, s, Lv, lamb, R1, k, d, D, ldu, r);
       }
       SCHK(dry_run() ? hipSuccess : hipGetLastError());
     }
@@ -525,9 +657,12 @@ ctm_status build(int n, int d, int D, ctm_su_s& x) {
   x.d = d;
   x.D = D;
   x.k = d * D;
-  x.m = d * d * D;
   x.D3 = D * D * D;
-  if (x.m > 192) return ctm_internal_fail(CTM_E_INVALID, "d^2 D must be <= 192 (theta SVD size)");
+  x.r = std::min(x.D3, x.k);
+  x.m = x.r * d;
+  x.b = x.m <= 80 ? 0 : std::min(x.m, D + 16);
+  if (x.k > 192) return ctm_internal_fail(CTM_E_INVALID, "d D must be <= 192 (reduced-tensor factor size)");
+  if (x.m > 4096) return ctm_internal_fail(CTM_E_INVALID, "min(D^3, d D) d must be <= 4096");
   if (d * d > 192) return ctm_internal_fail(CTM_E_INVALID, "d^2 must be <= 192 (gate eigensolver size)");
   Carve c;
   plan(x, c);

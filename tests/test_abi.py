@@ -201,7 +201,7 @@ sys.path.insert(0, %(root)r)
 from paper_1711_04798_amd import binding as b
 lib = b.load(%(lib)r, tile_table=False)
 out = []
-for n, d, D in ((1, 2, 3), (3, 8, 2), (40, 2, 4), (2, 8, 3)):
+for n, d, D in ((1, 2, 3), (3, 8, 2), (40, 2, 4), (2, 8, 3), (2, 8, 5)):
     nb = ctypes.c_size_t()
     st = [lib.ctm_su_workspace_size(n, d, D, ctypes.byref(nb))]
     ctx = ctypes.c_void_p()
@@ -216,7 +216,7 @@ for n, d, D in ((1, 2, 3), (3, 8, 2), (40, 2, 4), (2, 8, 3)):
     out.append([n, d, D, st, steps.value, lib.ctm_last_error().decode()])
     lib.ctm_su_destroy(ctx)
 nb = ctypes.c_size_t()
-out.append(["too big", lib.ctm_su_workspace_size(1, 8, 4, ctypes.byref(nb))])
+out.append(["too big", lib.ctm_su_workspace_size(1, 64, 4, ctypes.byref(nb))])
 print(json.dumps(out))
 '''
 
@@ -232,11 +232,12 @@ def run_su_dry(lib, extra_env=None):
 
 def test_su_dry_run(lib_path):
     """The simple update's orchestration (gate construction, Trotter steps,
-    state and iPEPS export) passes the host-side bounds checks; d^2 D above
-    the theta SVD limit is rejected."""
+    state and iPEPS export, the full Jacobi and the subspace-iteration
+    truncation) passes the host-side bounds checks; d D above the factor
+    size limit is rejected."""
     res, _ = run_su_dry(lib_path)
     for row in res[:-1]:
         n, d, D, st, steps, err = row
         assert all(v == 0 for v in st), row
         assert steps == 3
-    assert res[-1][1] == 1  # CTM_E_INVALID: d^2 D = 256 > 192
+    assert res[-1][1] == 1  # CTM_E_INVALID: d D = 256 > 192

@@ -6,8 +6,11 @@ fixes singular vectors only up to sign, and degenerate ones up to a
 rotation): the bond weights, and the one-site and two-site densities of the
 weighted tensors.  Tolerances: weights and densities 1e-10 after one Trotter
 step, 1e-8 after ten (the GPU factors each tensor through the eigenvalues
-of its Gram matrix where the oracle takes a QR decomposition: the two agree
-to rounding relative to the smallest kept singular value).
+of its Gram matrix where the oracle takes a QR decomposition, and above
+d^2 D = 80 takes the leading singular triplets of theta by subspace
+iteration where the oracle takes a full SVD: both agree to rounding
+relative to the smallest kept singular value).  (8, 3) and (8, 4) run the
+subspace-iteration path.
 """
 import numpy as np
 import pytest
@@ -92,7 +95,7 @@ def _compare(gT, gL, T, lam, tol, what):
     assert werr < tol and derr < tol
 
 
-@pytest.mark.parametrize("d,D", [(2, 3), (2, 6), (8, 2), (3, 4)])
+@pytest.mark.parametrize("d,D", [(2, 3), (2, 6), (8, 2), (3, 4), (8, 3), (8, 4)])
 def test_su_matches_oracle(gpu, d, D):
     """Random states and random symmetric bond Hamiltonians: one Trotter step
     (1e-10), then nine more (1e-8)."""
