@@ -183,6 +183,8 @@ __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F
 // (bf16 output): each result x is stored as the A-side three-term split hi,
 // hi, lo (hi = bf16(x), lo = bf16(x - hi)) at offsets 0, sstride, 2 sstride
 // from its place in the view.
+// OUT_V4 with bf16 output (the same conditions, 8-byte aligned C): the four
+// rows go out as one 8-byte store.
 constexpr int OUT_PLAIN = 0, OUT_V4 = 1, OUT_SPLIT = 2;
 
 template <typename TO, int MODE>
@@ -289,9 +291,17 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
       const int64_t roff = (int64_t)h * vc.r_hs + l;
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        if (cok[j])
-          *reinterpret_cast<float4*>(C + roff + coff[j]) =
-              make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        if (cok[j]) {
+          if constexpr (sizeof(TO) == 4) {
+            *reinterpret_cast<float4*>(C + roff + coff[j]) =
+                make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+          } else {
+            union { __bf16 h[4]; uint2 u; } pk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pk.h[q] = (__bf16)acc[i][j][q];
+            *reinterpret_cast<uint2*>(C + roff + coff[j]) = pk.u;
+          }
+        }
     }
     return;
   }
@@ -349,13 +359,16 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
     return !(e && std::strcmp(e, "registers") == 0);
   }();
   const dim3 grid((unsigned)(8 * per_xcd));
-  bool v4 = tout == F32 && use_dma && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 && vc.c_ls % 4 == 0 &&
-            vc.c_hs % 4 == 0 && M % 4 == 0;
-  for (int i = 0; i < groups && v4; ++i) v4 = ((uintptr_t)g.C[i] & 15) == 0;
+  bool v4 = use_dma && split_stride == 0 && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 &&
+            vc.c_ls % 4 == 0 && vc.c_hs % 4 == 0 && M % 4 == 0;
+  for (int i = 0; i < groups && v4; ++i) v4 = ((uintptr_t)g.C[i] & (tout == F32 ? 15 : 7)) == 0;
   const int64_t z = 0;
   if (tout == BF16 && split_stride > 0)
     hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_SPLIT>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
                        (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, split_stride);
+  else if (tout == BF16 && v4)
+    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_V4>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
+                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
   else if (tout == BF16)
     hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_PLAIN>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
                        (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);

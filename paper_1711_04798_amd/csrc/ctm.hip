@@ -182,6 +182,10 @@ struct Inst {
   void* Sb[MAXT][4] = {};
   void* Sk16[MAXT][4] = {};      // single-layer in CTM_BF16: bf16 copies for the enlarged corners
   void* Sb16[MAXT][4] = {};
+  // ... and as operands of the bf16 corner kernel:
+  // SkT16[(D',R',s)][(L',U') padded to a multiple of 8], SbT16[(D',R')][(L',U',s)]
+  void* SkT16[MAXT][4] = {};
+  void* SbT16[MAXT][4] = {};
   double* spec_old = nullptr;  // [pos][4][chi_cap]
   double* spec_new = nullptr;
   double* delta = nullptr;     // device scalar
@@ -367,6 +371,9 @@ void plan(ctm_ctx_s& x, Arena& ar) {
           if (x.prec == CTM_BF16) {
             I.Sk16[t][r] = ar.take_bytes(t5 * dtype_size(BF16));
             I.Sb16[t][r] = ar.take_bytes(t5 * dtype_size(BF16));
+            const size_t kp = ((size_t)I.D2 + 7) / 8 * 8;
+            I.SkT16[t][r] = ar.take_bytes((size_t)I.d * I.D2 * kp * dtype_size(BF16));
+            I.SbT16[t][r] = ar.take_bytes(t5 * dtype_size(BF16));
           }
         }
         if (x.prec == CTM_BF16 && !x.cfg.single_layer) {
@@ -662,6 +669,7 @@ struct CornerJob {
   const void *TnP = nullptr, *bT = nullptr;  // bf16 path: permuted edge, transposed double layer
   const void* TnR = nullptr;                 // bf16 path: bf16 edge as [next][inner][prev]
   const void *Sk = nullptr, *Sb = nullptr;   // single-layer mode: ket and bra of the rotation
+  const void *SkT = nullptr, *SbT = nullptr; // ... as operands of the bf16 corner kernel
 };
 
 struct Stage3Timer {
@@ -746,6 +754,101 @@ ctm_status sl_product(ctm_ctx_s& x, int64_t c, int D, int d, const std::vector<S
   return CTM_OK;
 }
 
+// out[r][0 .. kp) = in[r][0 .. K) followed by zeros, bf16, r < rows
+__global__ void pad_rows_kernel(const __bf16* __restrict__ in, int64_t rows, int K, int kp, __bf16* __restrict__ out) {
+  const int64_t n = rows * kp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / kp;
+    const int c = (int)(e - r * kp);
+    out[e] = c < K ? in[r * K + c] : (__bf16)0.0f;
+  }
+}
+
+hipError_t pad_rows_bf16(hipStream_t s, const void* in, int64_t rows, int K, int kp, void* out) {
+  if (!span_ok(in, (size_t)rows * K * 2, "pad in") || !span_ok(out, (size_t)rows * kp * 2, "pad out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(4096, (rows * kp + 255) / 256);
+  hipLaunchKernelGGL(pad_rows_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, s,
+                     (const __bf16*)in, rows, K, kp, (__bf16*)out);
+  return hipGetLastError();
+}
+
+// Y'[(g,b,l_b,u_b)][(l_k,u_k) padded to kp] from the enlarged corner's
+// Y[g][l_k][l_b][u_k][u_b][b] (bf16); the padding is zero.  For fixed
+// (g, l_b, u_b) this is the transpose of the D^2 x c matrix over ((l_k,u_k), b):
+// a work-group takes 64 consecutive b, reads each (l_k,u_k) row along b and
+// writes each b row along (l_k,u_k) through LDS.
+__global__ void __launch_bounds__(256) sl_gather_kernel(const __bf16* __restrict__ Y, int c, int D, int kp,
+                                                        __bf16* __restrict__ out) {
+  __shared__ __bf16 tile[64][152 + 2];  // [b][(l_k,u_k)], D^2 <= 144 < 152
+  const int D2 = D * D;
+  const int nbt = (c + 63) / 64;
+  const int64_t grp = blockIdx.x / nbt;  // (g, l_b, u_b)
+  const int b0 = (int)(blockIdx.x % nbt) * 64;
+  const int64_t g = grp / D2;
+  const int lb = (int)((grp / D) % D), ub = (int)(grp % D);
+  const int tid = threadIdx.x;
+  // read: 64 b per (l_k,u_k) row, four rows per pass
+  for (int e = tid; e < D2 * 64; e += 256) {
+    const int col = e / 64, bb = e % 64, b = b0 + bb;
+    const int lk = col / D, uk = col % D;
+    tile[bb][col] = b < c ? Y[((((g * D + lk) * D + lb) * D + uk) * D + ub) * (int64_t)c + b] : (__bf16)0.0f;
+  }
+  __syncthreads();
+  // write: kp consecutive entries per b row
+  for (int e = tid; e < 64 * kp; e += 256) {
+    const int bb = e / kp, col = e % kp, b = b0 + bb;
+    if (b >= c) continue;
+    const int64_t row = ((g * c + b) * D + lb) * D + ub;
+    out[row * kp + col] = col < D2 ? tile[bb][col] : (__bf16)0.0f;
+  }
+}
+
+// The single-layer product in the bf16 form on the bf16 corner kernel (see
+// sl_product): Y' gathered with zero-padded rows; the first product taken
+// transposed, Z^T[(d_k,r_k,s),(g,b,l_b,u_b)] = SkT Y'^T, written through the
+// output view straight into Z[(g,b,d_k,r_k)][(l_b,u_b,s)] (four consecutive
+// s per 8-byte store), the row-major A operand of the second product; P'
+// float32, then permuted into the consumer's layout.
+ctm_status sl_product_bf16(ctm_ctx_s& x, int64_t c, int D, int d, const std::vector<SlJob>& jobs,
+                           const int out_perm[6], int tout) {
+  hipStream_t s = x.stream;
+  const int64_t D2 = (int64_t)D * D, M = c * c * D2, kp = (D2 + 7) / 8 * 8, N1 = (int64_t)d * D2;
+  const size_t yb = (size_t)M * kp * 2, zb = (size_t)M * N1 * 2, pb = (size_t)M * D2 * 4;
+  if (!x.sl_y || yb == 0) return fail(CTM_E_STATE, "single-layer scratch missing");
+  if (D2 > 144) return fail(CTM_E_INVALID, "single-layer bf16 form: D <= 12");
+  const size_t nb = std::max<size_t>(1, std::min<size_t>({(size_t)MAXG, x.sl_ybytes / std::max(yb, pb),
+                                                          x.sl_zbytes / zb}));
+  if (nb * std::max(yb, pb) > x.sl_ybytes || nb * zb > x.sl_zbytes)
+    return fail(CTM_E_STATE, "single-layer scratch too small");
+  const int64_t pdims[6] = {c, c, D, D, D, D};
+  // Z element (row (dr_k, s), column (gb, lu_b)) at dr_k d D^2 + s + gb d D^4 + lu_b d
+  const View vzt{d, 1, N1, D2, d, D2 * D2 * d};
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += nb) {
+    const size_t j1 = std::min(jobs.size(), j0 + nb);
+    G ga, gb;
+    for (size_t j = j0; j < j1; ++j) {
+      char* yj = (char*)x.sl_y + (j - j0) * yb;
+      char* zj = (char*)x.sl_z + (j - j0) * zb;
+      char* pj = (char*)x.sl_p + (j - j0) * pb;
+      HIPCHK(spans({{jobs[j].y, (size_t)M * D2 * 2}, {yj, yb}}, "sl gather"));
+      const int64_t blocks = c * D2 * ((c + 63) / 64);
+      if (!dry_run())
+        hipLaunchKernelGGL(sl_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16*)jobs[j].y,
+                           (int)c, D, (int)kp, (__bf16*)yj);
+      HIPCHK(last_err());
+      ga.add(jobs[j].sk, yj, zj);
+      gb.add(zj, jobs[j].sb, pj);
+    }
+    HIPCHK(corner_bf16(s, N1, M, kp, vzt, ga.group(0, ga.size()), ga.size(), BF16));
+    HIPCHK(corner_bf16(s, M, D2, N1, rowmajor(D2), gb.group(0, gb.size()), gb.size(), F32));
+    for (size_t j = j0; j < j1; ++j)
+      HIPCHK(permute(s, F32, (char*)x.sl_p + (j - j0) * pb, tout, jobs[j].out, 6, pdims, out_perm));
+  }
+  return CTM_OK;
+}
+
 ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const std::vector<CornerJob>& jobs,
                         const Stage3Timer* tm, bool bf16, ctm_ctx_s* slx = nullptr, int D = 0, int d = 0) {
   const int64_t c = chi, n = (int64_t)chi * D2;
@@ -802,10 +905,17 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
       const int64_t ydims[6] = {c, D, D, D, D, c};
       const int yperm[6] = {0, 5, 2, 4, 1, 3};
       const int operm[6] = {0, 2, 4, 1, 3, 5};
+      // bf16: both products on the bf16 MFMA (Y and Z in bf16, fp32
+      // accumulation), on the corner kernel where its K % 8 == 0 holds
+      const bool fast_sl = bf16 && jobs[0].SkT && ((int64_t)d * D * D) % 8 == 0 && d % 4 == 0 && D * D <= 144;
       std::vector<SlJob> sj;
-      for (size_t j = j0; j < j1; ++j) sj.push_back(SlJob{jobs[j].Y, jobs[j].Sk, jobs[j].Sb, jobs[j].Q});
-      // bf16: both products on the bf16 MFMA (Y and Z in bf16, fp32 accumulation)
-      CHK(stage3_timed(s, tm, [&]() { return sl_product(*slx, c, D, d, sj, ydims, yperm, operm, ty, ty, tq); }));
+      for (size_t j = j0; j < j1; ++j)
+        sj.push_back(fast_sl ? SlJob{jobs[j].Y, jobs[j].SkT, jobs[j].SbT, jobs[j].Q}
+                             : SlJob{jobs[j].Y, jobs[j].Sk, jobs[j].Sb, jobs[j].Q});
+      CHK(stage3_timed(s, tm, [&]() {
+        return fast_sl ? sl_product_bf16(*slx, c, D, d, sj, operm, tq)
+                       : sl_product(*slx, c, D, d, sj, ydims, yperm, operm, ty, ty, tq);
+      }));
       continue;
     }
     // A: rows m = (g, b): b low (extent chi, stride 1), g high (stride D2*D2*chi);
@@ -1373,6 +1483,8 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
           const int t = ro.tid(cx[q], cy[q]), r = (k + q) % 4;
           j.Sk = x.prec == CTM_BF16 ? I->Sk16[t][r] : I->Sk[t][r];
           j.Sb = x.prec == CTM_BF16 ? I->Sb16[t][r] : I->Sb[t][r];
+          j.SkT = I->SkT16[t][r];
+          j.SbT = I->SbT16[t][r];
         }
         j.X = R.X[q];
         j.Y = R.Y[q];
@@ -2452,6 +2564,17 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
               (permute(x->stream, F64, I.A[t], BF16, I.Sk16[t][r], 5, dims, perm[r]) != hipSuccess ||
                permute(x->stream, F64, I.B[t], BF16, I.Sb16[t][r], 5, dims, perm[r]) != hipSuccess))
             return cleanup(fail(CTM_E_HIP, "single-layer tensors"));
+          if (x->prec == CTM_BF16) {
+            // [L'][U'][s][D'][R'] -> [D'][R'][s][L'][U'] (through the single-layer
+            // scratch), rows padded to a multiple of 8; and -> [D'][R'][L'][U'][s]
+            const int64_t sdims[5] = {I.D, I.D, I.d, I.D, I.D};
+            const int pk[5] = {3, 4, 2, 0, 1}, pb[5] = {3, 4, 0, 1, 2};
+            const int64_t kp = ((int64_t)I.D2 + 7) / 8 * 8;
+            if (permute(x->stream, BF16, I.Sk16[t][r], BF16, x->sl_y, 5, sdims, pk) != hipSuccess ||
+                pad_rows_bf16(x->stream, x->sl_y, (int64_t)I.d * I.D2, I.D2, kp, I.SkT16[t][r]) != hipSuccess ||
+                permute(x->stream, BF16, I.Sb16[t][r], BF16, I.SbT16[t][r], 5, sdims, pb) != hipSuccess)
+              return cleanup(fail(CTM_E_HIP, "single-layer bf16 operands"));
+          }
         }
       if (x->prec == CTM_BF16 && !x->cfg.single_layer)
         for (int r = 0; r < 4; ++r) {

@@ -76,9 +76,9 @@ def test_single_layer_one_step(gpu, direction, d, D, chi, bra):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec,d", [("fp32", 2), ("bf16", 2), ("bf16", 4)])
 @pytest.mark.parametrize("D,chi", [(2, 16), (4, 12)])
-def test_single_layer_reduced_corners_elementwise(gpu, prec, D, chi):
+def test_single_layer_reduced_corners_elementwise(gpu, prec, d, D, chi):
     """Reduced-precision single-layer corners from an imported oracle
     environment, element by element.  Each stage rounds its output once
     after accumulating in float32 (X in float32; Y and the ket-layer
@@ -87,10 +87,11 @@ def test_single_layer_reduced_corners_elementwise(gpu, prec, D, chi):
     at most u times the same contraction over absolute values, the double
     layer replaced by sum_s |A| |B|.  Bound: (8 u + K u_fp32)
     (|C| |T| |T| |a|)_ij with u the unit roundoff of the working type and
-    K = 2 chi + D^2 + d D^2 the total contraction length."""
+    K = 2 chi + D^2 + d D^2 the total contraction length.  bf16 with d = 4 runs
+    the products on the bf16 corner kernel (Y gathered, the first product
+    transposed), d = 2 on the generic GEMM."""
     from paper_1711_04798_amd import CTM
     from test_gpu_stages import _dump, env_to_flat
-    d = 2
     tens = synth.cell_tensors(7, d, D, 2)
     Lx = Ly = 2
     pat = [0, 1, 1, 0]
@@ -98,7 +99,7 @@ def test_single_layer_reduced_corners_elementwise(gpu, prec, D, chi):
     env = octm.init_trivial(cell, chi)
     for _ in range(3):
         octm.sweep(cell, env)
-    print("case single layer reduced corners", prec, D, chi, flush=True)
+    print("case single layer reduced corners", prec, d, D, chi, flush=True)
     g = CTM([tens], Lx=Lx, Ly=Ly, pattern=pat, chi=chi, prec=prec, max_iters=2, resid_tol=0.0, cutoff=1e-6,
             single_layer=True)
     g.import_env(env_to_flat(env, Lx, Ly))
