@@ -580,9 +580,41 @@ __global__ void permute_kernel(const TI* __restrict__ in, TO* __restrict__ out, 
   }
 }
 
+// The same when the innermost output index is also the innermost input
+// index (stride 1): each thread copies four consecutive elements of a row of
+// L, with the row's offset decoded once (ndim - 1 outer indices).
+template <typename TI, typename TO>
+__global__ void permute_run_kernel(const TI* __restrict__ in, TO* __restrict__ out, int64_t rows, PermArgs p) {
+  const int nd = p.ndim - 1;
+  const int64_t L = p.out_dims[nd], nq = (L + 3) / 4;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * nq;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = t / nq, j0 = (t - row * nq) * 4;
+    int64_t rem = row, off = 0;
+    for (int i = nd - 1; i >= 0; --i) {
+      const int64_t q = rem / p.out_dims[i];
+      off += (rem - q * p.out_dims[i]) * p.in_stride_of_out[i];
+      rem = q;
+    }
+    const TI* src = in + off + j0;
+    TO* dst = out + row * L + j0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j0 + j < L) dst[j] = from_double<TO>(to_double<TI>(src[j]));
+  }
+}
+
 template <typename TI, typename TO>
 static hipError_t launch_perm(hipStream_t s, const void* in, void* out, int64_t n, const PermArgs& p) {
   if (n == 0) return hipSuccess;
+  const int64_t L = p.out_dims[p.ndim - 1];
+  if (p.ndim >= 2 && p.in_stride_of_out[p.ndim - 1] == 1 && L >= 4) {
+    const int64_t rows = n / L, work = rows * ((L + 3) / 4);
+    const int64_t blocks = std::min<int64_t>(65536, (work + 255) / 256);
+    hipLaunchKernelGGL((permute_run_kernel<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, s, (const TI*)in,
+                       (TO*)out, rows, p);
+    return hipGetLastError();
+  }
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL((permute_kernel<TI, TO>), dim3((unsigned)blocks), dim3(256), 0, s,
