@@ -112,8 +112,10 @@ def cpu_baseline(tensors):
     dt = time.perf_counter() - t0
     # a column step of the 2x2 cell has two rows
     su_rates = su_oracle_rates()
+    bd = boundary_oracle_rate()
     return {"value": 1.0 / (2.0 * dt), "unit": "moves/s", "cores": threads or cores,
             "simple_update_steps_per_s_by_D": su_rates,
+            "boundary_full_spectrum": bd,
             "kind": "oracle",
             "sample": "one plaquette row (4 enlarged corners, dense float64 half-system "
                       "SVD of n=5184, absorption) of one column step, %.1f s; value = 1/(2 t)"
@@ -257,6 +259,90 @@ def su_oracle_rates(steps=5):
             osu.step(T, lam, gates, D)
         out[str(D)] = steps / (time.perf_counter() - t0)
     return out
+
+
+# boundary density operator: the cylinder of the paper's entropies (D = 8,
+# chi = 80, N_v = 6) and a small full-spectrum form the oracle also times
+BOUNDARY_FORMS = [dict(D=4, chi=32, nv=4, krylov=256), dict(D=8, chi=80, nv=4, krylov=32),
+                  dict(D=8, chi=80, nv=6, krylov=16)]
+
+
+def boundary_flop(chi, D, Ly, nv, krylov):
+    """Float64 flop of one spectrum: 2 krylov ring applications (sigma_R and
+    sigma_L^T per basis vector, below the full dimension; the full basis
+    adds its block's start vectors, at most 4 more) of nv sites each
+    (2 chi^3 D^(nv+1) per site), plus the trace (Ly double transfer matrices,
+    2 chi^4 D^2 each, and nv - 1 products of chi^2 x chi^2 matrices)."""
+    ring = nv * 2.0 * chi ** 3 * D ** (nv + 1)
+    trace = Ly * 2.0 * chi ** 4 * D ** 2 + (nv - 1) * 2.0 * chi ** 6
+    return ring, trace
+
+
+def boundary_leg():
+    """Boundary density operator on the cylinder (ctm_boundary_spectrum):
+    seconds per spectrum for the leading `krylov` Ritz values (block 4) on a
+    CTM environment of the 2x2 cell (d = 8, random tensors, bf16
+    single-layer moves, 10 sweeps), and the float64 rate of its ring GEMMs."""
+    import torch
+    import synth
+    from paper_1711_04798_amd import CTM, binding
+    rows = []
+    env_of = {}
+    for f in BOUNDARY_FORMS:
+        D, chi, nv, m = f["D"], f["chi"], f["nv"], f["krylov"]
+        key = (D, chi)
+        if key not in env_of:
+            for k in list(env_of):
+                env_of.pop(k).close()
+            log("bench: boundary leg environment D=%d chi=%d" % (D, chi))
+            tens = synth.cell_tensors(3, 8, D, 2)
+            g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec="bf16", single_layer=True,
+                    **solver_opts("bf16"))
+            g.converge(tol=0.0, max_sweeps=10)
+            env_of[key] = g
+        g = env_of[key]
+        log("bench: boundary leg D=%d chi=%d nv=%d krylov=%d" % (D, chi, nv, m))
+        row = {"D": D, "chi": chi, "nv": nv, "dim": D ** nv, "krylov": m, "block": 4}
+        try:
+            g.boundary_spectrum(nv, krylov=1, block=1, nev=1)  # shapes tuned, buffers touched
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, res, S, wt = g.boundary_spectrum(nv, krylov=m, block=4, nev=min(m, 8))
+            el = time.perf_counter() - t0
+        except binding.CtmError as e:
+            row["error"] = str(e)
+            rows.append(row)
+            continue
+        rings = 2 * m if m < D ** nv else 2 * m + 4
+        ring, trace = boundary_flop(chi, D, 2, nv, m)
+        tf = (rings * ring + trace) / el / 1e12
+        row.update({"s_per_spectrum": el, "ring_applications": rings, "ms_per_ring": 1e3 * el / rings,
+                    "flop": rings * ring + trace, "tflops": tf, "frac_fp64_peak": tf / PEAK_TFLOPS["fp64"],
+                    "leading_p": [float(v) for v in ev[:4]], "max_resid_leading": float(np.max(res[:4])),
+                    "captured_weight": wt})
+        rows.append(row)
+    for g in env_of.values():
+        g.close()
+    return {"rows": rows,
+            "note": "2x2 checkerboard, d = 8, random tensors (seed 3), environment from 10 bf16 single-layer "
+                    "sweeps; all boundary arithmetic float64; the rate counts the ring GEMMs and the trace "
+                    "over the whole call (syncs and Gram-Schmidt included)"}
+
+
+def boundary_oracle_rate():
+    """The oracle's boundary spectrum (dense sigma_L, sigma_R and eigenvalues,
+    float64 NumPy) for the small full-spectrum form, on its own trivially
+    initialised environment of that shape (the cost does not depend on the
+    values)."""
+    import synth
+    from oracle import ctm as octm, boundary as obd
+    f = BOUNDARY_FORMS[0]
+    tens = synth.cell_tensors(3, 8, f["D"], 2)
+    cell = octm.Cell(2, 2, [0, 1, 1, 0], tens)
+    env = octm.init_trivial(cell, f["chi"])
+    t0 = time.perf_counter()
+    obd.boundary_spectrum(cell, env, 0, f["nv"])
+    return {"D": f["D"], "chi": f["chi"], "nv": f["nv"], "s_per_spectrum": time.perf_counter() - t0}
 
 
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
@@ -429,6 +515,8 @@ def main():
     ap.add_argument("--single-only", action="store_true", help="only the single-layer comparison leg")
     ap.add_argument("--no-su", action="store_true", help="skip the simple-update leg")
     ap.add_argument("--su-only", action="store_true", help="only the simple-update leg")
+    ap.add_argument("--no-boundary", action="store_true", help="skip the boundary-operator leg")
+    ap.add_argument("--boundary-only", action="store_true", help="only the boundary-operator leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -459,6 +547,9 @@ def main():
         return
     if args.su_only:
         print(json.dumps({"simple_update": su_leg()}), flush=True)
+        return
+    if args.boundary_only:
+        print(json.dumps({"boundary": boundary_leg()}), flush=True)
         return
     if args.full_extent_only:
         print(json.dumps({"roofline_full_extent": dense_extent_leg(tensors, args.prec)}), flush=True)
@@ -551,6 +642,8 @@ def main():
         out["single_layer"] = single_layer_leg()
     if not args.no_su:
         out["simple_update"] = su_leg()
+    if not args.no_boundary:
+        out["boundary"] = boundary_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
         out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])
@@ -564,6 +657,11 @@ def main():
             rates = out["cpu_baseline"]["simple_update_steps_per_s_by_D"]
             for r in out["simple_update"]["rows"]:
                 r["speedup_vs_oracle"] = r["instance_steps_per_s"] / rates[str(r["D"])]
+        if "boundary" in out:
+            bd = out["cpu_baseline"]["boundary_full_spectrum"]
+            for r in out["boundary"]["rows"]:
+                if (r["D"], r["chi"], r["nv"]) == (bd["D"], bd["chi"], bd["nv"]) and "s_per_spectrum" in r:
+                    r["speedup_vs_oracle"] = bd["s_per_spectrum"] / r["s_per_spectrum"]
     print(json.dumps(out), flush=True)
 
 

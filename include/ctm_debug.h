@@ -80,6 +80,17 @@ ctm_status ctm_debug_dump(ctm_ctx ctx, int32_t what, int32_t index, void* host_b
  */
 ctm_status ctm_debug_set_width(ctm_ctx ctx, int32_t width, int32_t* live_out);
 
+/*
+ * Rows per GEMM launch of the boundary operator's ring application
+ * (ctm_boundary_spectrum): rows <= 0 restores the default, 65535 x 32 (the
+ * grid's row-tile dimension at the smallest tile); a smaller cap splits each
+ * ring site into more launches (whole groups of rows with the same leading
+ * indices, or pieces of one group when the group alone is longer), so that
+ * tests reach the split path at small sizes.  Process-wide; the split does
+ * not change any output element's summation.
+ */
+ctm_status ctm_debug_set_ring_rows(int64_t rows);
+
 #ifdef __cplusplus
 }
 #endif

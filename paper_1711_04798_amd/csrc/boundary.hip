@@ -25,6 +25,7 @@
 //     matrices E_y[(cL, cR), (cL', cR')] = sum over both virtual indices of
 //     the two edges, a product of nv chi^2 x chi^2 matrices.
 #include "ctm.h"
+#include "ctm_debug.h"
 
 #include <hip/hip_runtime.h>
 
@@ -40,6 +41,10 @@
 using namespace ctmk;
 
 namespace {
+
+// rows per ring GEMM launch: 65535 row tiles of the smallest (32-row) tile
+constexpr int64_t kRingRowsDefault = 65535LL * 32;
+int64_t g_ring_rows = kRingRowsDefault;
 
 #define BCHK(x)                                                                         \
   do {                                                                                  \
@@ -230,8 +235,19 @@ ctm_status ring_apply(const Ctx& c, double* const* W, const double* x, double* o
     const View va{Q1, 1, (int64_t)chi * Q, D, Q1, Q};
     const View vb{D, chi, (int64_t)D * D * chi, chi, 1, (int64_t)D * chi};
     const View vc{Q1, 1, (int64_t)D * chi * Q1, chi, Q1, (int64_t)chi * Q1};
-    BOK(gemm1(c, (int64_t)chi * P * Q1, (int64_t)D * chi, (int64_t)chi * D, va, p.S[cur], vb, W[y % p.Ly], vc,
-              p.S[cur ^ 1]));
+    // rows (h, l) = ((a, P), Q1): input row offset h chi Q + l, output
+    // h D chi Q1 + l.  Launches of at most g_ring_rows rows (the GEMM grid's
+    // second dimension counts row tiles of 32 or more), whole h at a time,
+    // or pieces of one h when Q1 alone is longer.
+    const int64_t H = (int64_t)chi * P, cap = g_ring_rows;
+    const int64_t hc = Q1 <= cap ? cap / Q1 : 1;
+    const int64_t lc = Q1 <= cap ? Q1 : cap;
+    for (int64_t h0 = 0; h0 < H; h0 += hc)
+      for (int64_t l0 = 0; l0 < Q1; l0 += lc) {
+        const int64_t rows = Q1 <= cap ? std::min(hc, H - h0) * Q1 : std::min(lc, Q1 - l0);
+        BOK(gemm1(c, rows, (int64_t)D * chi, (int64_t)chi * D, va, p.S[cur] + h0 * chi * Q + l0, vb,
+                  W[y % p.Ly], vc, p.S[cur ^ 1] + h0 * D * chi * Q1 + l0));
+      }
     cur ^= 1;
     P *= D;
     Q = Q1;
@@ -297,6 +313,11 @@ void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vect
 }  // namespace
 
 extern "C" {
+
+ctm_status ctm_debug_set_ring_rows(int64_t rows) {
+  g_ring_rows = rows <= 0 ? kRingRowsDefault : std::min(rows, kRingRowsDefault);
+  return CTM_OK;
+}
 
 ctm_status ctm_boundary_workspace_size(ctm_ctx x, int32_t inst, int32_t nv, int32_t krylov, size_t* bytes) {
   if (!bytes) return ctm_internal_fail(CTM_E_INVALID, "null bytes");

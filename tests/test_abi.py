@@ -62,7 +62,8 @@ lib = b.load(%(lib)r)
 out = {}
 for case in %(cases)r:
     name, Lx, Ly, pat, nt, d, D, chi, prec = case[:9]
-    extra = case[9] if len(case) > 9 else {}
+    extra = dict(case[9]) if len(case) > 9 else {}
+    bnv = extra.pop("boundary_nv", None)
     cfg, keep = b.make_config(Lx, Ly, pat, nt, d, D, chi, prec, max_iters=2, **extra)
     n = b.workspace_size(cfg)
     ptrs = (ctypes.c_void_p * (nt * len(d)))(*[(1 << 30) + 4096 * i for i in range(nt * len(d))])
@@ -96,8 +97,8 @@ for case in %(cases)r:
     eh = (ctypes.c_char * eb)()
     st.append(lib.ctm_env_export(ctx, 0, eh, eb))
     st.append(lib.ctm_env_import(ctx, 0, eh, eb))
-    if Ly in (1, 2) and D[0] <= 4:
-        nv = 2 * Ly
+    if bnv or (Ly in (1, 2) and D[0] <= 4):
+        nv = bnv or 2 * Ly
         kry = min(D[0] ** nv, 12)
         wsb = ctypes.c_size_t()
         st.append(lib.ctm_boundary_workspace_size(ctx, 0, nv, kry, ctypes.byref(wsb)))
@@ -134,6 +135,9 @@ CASES = [
     ("large_D_single", 2, 2, [0, 1, 1, 0], 2, [8], [12], [100], "fp32", {"single_layer": True}),
     ("batched_single", 1, 1, [0], 1, [8] * 6, [3, 4, 5] * 2, [32, 64, 100] * 2, "fp32",
      {"single_layer": True, "use_graph": True}),
+    # the cylinder of Sec. V's entropies: D = 8, chi = 80, N_v = 6 (ring
+    # state of 1.7e9 doubles, its GEMMs in several launches)
+    ("boundary_D8", 2, 2, [0, 1, 1, 0], 2, [8], [8], [80], "bf16", {"single_layer": True, "boundary_nv": 6}),
 ]
 
 

@@ -10,7 +10,8 @@ against the closed form of the dimer state.
   the same edges): the whole spectrum (Krylov dimension D^nv) element by
   element, and the leading eigenvalues of a partial Krylov space within
   their residual estimates;
-* a GPU-converged environment exported to the oracle: the whole spectrum.
+* each side's own converged environment of the same tensors: the whole
+  spectrum to the convergence level.
 
 Tolerances: on eigenvalues divided by the trace and on S, 1e-10 or ten
 times the relative asymmetry of the two rings (the Lanczos treats them as
@@ -23,7 +24,7 @@ import synth
 from oracle import ctm as octm
 from oracle import boundary as obd
 
-from test_gpu_stages import env_to_flat, flat_to_env
+from test_gpu_stages import env_to_flat
 
 pytestmark = pytest.mark.gpu
 
@@ -94,21 +95,57 @@ def test_imported_env_full_spectrum(gpu, d, D, chi, nvs):
     g.close()
 
 
+@pytest.mark.parametrize("cap", [10, 100])
+def test_ring_split_launches(gpu, cap):
+    """The ring GEMMs split into launches of at most `cap` rows (pieces of one
+    row group at cap = 10 < 27, several groups per launch at cap = 100): the
+    whole spectrum against the unsplit run (the split does not change any
+    element's summation) and against the oracle on the same imported
+    environment (d = 8, D = 3, chi = 24, N_v = 4)."""
+    import ctypes
+    from paper_1711_04798_amd import CTM, binding
+    lib = binding.load()
+    lib.ctm_debug_set_ring_rows.argtypes = [ctypes.c_int64]
+    tens, cell, env = _oracle_env(40, 8, 3, 24, 30)
+    print("case boundary split", cap, flush=True)
+    g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=24)
+    g.import_env(env_to_flat(env, 2, 2))
+    ev0, _, S0, _ = g.boundary_spectrum(4)
+    try:
+        assert lib.ctm_debug_set_ring_rows(cap) == 0
+        ev, _, S, _ = g.boundary_spectrum(4)
+    finally:
+        lib.ctm_debug_set_ring_rows(0)
+    g.close()
+    po, _ = obd.boundary_spectrum(cell, env, 0, 4)
+    d_split = np.abs(ev - ev0).max()
+    err = np.abs(np.sort(ev)[::-1] - po).max()
+    print("cap %d: max |split - unsplit| %.2e, max |dp| vs oracle %.2e" % (cap, d_split, err))
+    assert d_split <= 1e-14 and abs(S - S0) <= 1e-13
+    assert err < _tol(cell, env, 0, 4)
+
+
 def test_gpu_env_full_spectrum(gpu):
-    """The ruby-size checkerboard (d = 8, D = 4, chi = 64) converged on the GPU
-    in float64; its environment exported to the oracle; nv = 4 (dim 256)."""
+    """Each side converges its own environment from the same tensors (2x2,
+    d = 2, D = 3, chi = 24, float64, to a change of 1e-12 per sweep), then
+    the whole spectrum at nv = 4 (dimension 81): the two agree to the
+    convergence level (1e-8), the GPU's own float64 CTM feeding the GPU
+    boundary operator."""
     from paper_1711_04798_amd import CTM
-    A, B = synth.cell_tensors(0, 8, 4, 2)
-    print("case boundary c1", flush=True)
-    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=64, cutoff=1e-8)
-    sw, dl, ok = g.converge(tol=1e-10, max_sweeps=60)
-    assert ok
+    A, B = synth.cell_tensors(41, 2, 3, 2)
+    print("case boundary own environments", flush=True)
+    g = CTM([[A, B]], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=24, cutoff=1e-10)
+    sw, dl, ok = g.converge(tol=1e-12, max_sweeps=200)
+    assert ok, (sw, dl)
     cell = octm.Cell(2, 2, [0, 1, 1, 0], [A, B])
-    env = flat_to_env(g.export_env(), 2, 2, 64, 16)
+    env = octm.init_trivial(cell, 24)
+    so, do, oko = octm.converge(cell, env, tol=1e-12, max_sweeps=200, cutoff=1e-10)
+    assert oko
     po, _ = obd.boundary_spectrum(cell, env, 0, 4)
     ev, res, S, wt = g.boundary_spectrum(4)
     g.close()
     err = np.abs(np.sort(ev)[::-1] - po).max()
-    tol = _tol(cell, env, 0, 4)
-    print("c1 nv 4: max |dp| %.2e (bound %.1e), S gpu %.12f oracle %.12f" % (err, tol, S, obd.entropy(po)))
+    tol = max(_tol(cell, env, 0, 4), 1e-8)
+    print("own environments nv 4: sweeps gpu %d oracle %d; max |dp| %.2e (bound %.1e), S gpu %.12f oracle %.12f"
+          % (sw[0], so, err, tol, S, obd.entropy(po)))
     assert err < tol and abs(S - obd.entropy(po)) < tol
