@@ -46,6 +46,16 @@ ctm_status ctm_debug_corner_bf16(int64_t M, int64_t N, int64_t K, const void* A,
                                  void* C, void* stream);
 
 /*
+ * The same product with Bt first packed into the kernel's fragment layout
+ * (the form the CTM moves use for the double layer): `packed` is a device
+ * buffer of ctm_debug_corner_bf16_packed_bytes(N, K) bytes that receives
+ * the packed Bt.  The result is bitwise equal to ctm_debug_corner_bf16's.
+ */
+size_t ctm_debug_corner_bf16_packed_bytes(int64_t N, int64_t K);
+ctm_status ctm_debug_corner_bf16_packed(int64_t M, int64_t N, int64_t K, const void* A, const void* Bt,
+                                        void* packed, void* C, void* stream);
+
+/*
  * One-sided Jacobi SVD of the k x k float64 row-major matrix M (1 <= k <= 192):
  * M W = U diag(S), singular values descending.  U, W: k x k row-major; S: k.
  * work: 3 k^2 doubles.

@@ -13,6 +13,7 @@
 
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -185,12 +186,36 @@ __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F
 // from its place in the view.
 // OUT_V4 with bf16 output (the same conditions, 8-byte aligned C): the four
 // rows go out as one 8-byte store.
-constexpr int OUT_PLAIN = 0, OUT_V4 = 1, OUT_SPLIT = 2;
+// OUT_PACKA (bf16 output): the product is the enlarged corner's intermediate
+// Y of the next product, element (m, n) = ((b, u), (g, l)) with m = b D2 + u
+// and n = g D2 + l going to row R = g chi + b, column k = l D2 + u of Y, and Y
+// is stored in the packed fragment layout that the next product reads as its
+// A operand (see corner_bf16_packed_a_elems).  A lane's four accumulator rows
+// are four consecutive u (D2 % 4 == 0), i.e. four consecutive k of one packed
+// lane slot: one 8-byte store.
+constexpr int OUT_PLAIN = 0, OUT_V4 = 1, OUT_SPLIT = 2, OUT_PACKA = 3;
 
-template <typename TO, int MODE>
+struct Aux {
+  int64_t sstride;   // OUT_SPLIT: offset of the second and third terms
+  int32_t chi, d2;   // OUT_PACKA: R = g chi + b, k = l d2 + u
+  int32_t kb;        // OUT_PACKA: k blocks of 32 per 16-row block of Y
+};
+
+// BF: B is held in the packed fragment layout of corner_bf16_pack_b (1 KiB
+// blocks of 16 rows x 32 k in MFMA operand order, k blocks outermost): each
+// B block of a K step is one contiguous 1 KiB direct-to-LDS load, and the
+// fragment read of an LDS block is lane l at byte 16 l (no bank conflicts;
+// the row-major form reads 16 rows at one 16-byte column, which the LDS
+// serves at half rate).  Rows past N and k past K are zeros in the packed
+// layout, so no clamping or zeroing is needed on the B side.
+// AF: A is held in the packed layout of OUT_PACKA ([M / 16][K / 32] blocks
+// of 1 KiB in MFMA operand order, rows padded to whole 256-row tiles): the
+// same contiguous loads and linear fragment reads as BF; the k past K of a
+// partial last step are zeroed in LDS (the padding is never written).
+template <typename TO, int MODE, bool BF, bool AF>
 __global__ void __launch_bounds__(256, 2)
 corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
-                       int32_t tiles, int32_t per_xcd, int64_t sstride) {
+                       int32_t tiles, int32_t per_xcd, Aux aux) {
   __shared__ __attribute__((aligned(16))) __bf16 smem[STAGES * STAGE_ELEMS];
   const int L = blockIdx.x;
   const int t = (L & 7) * per_xcd + (L >> 3);
@@ -214,19 +239,31 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     const int k0 = kt * BK;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int blk = j * 4 + wave, e = blk * 64 + lane, row = e >> 2;
-      const int chunk = (e & 3) ^ swz(row);
-      const int m = min(m0 + row, M - 1), k = min(k0 + chunk * 8, K - 8);
-      __builtin_amdgcn_global_load_lds(A + (int64_t)m * K + k, As + blk * 512, 16, 0, 0);
+      const int blk = j * 4 + wave;
+      if constexpr (AF) {
+        const int64_t pb = (int64_t)(m0 / 16 + blk) * nk + kt;
+        __builtin_amdgcn_global_load_lds(A + pb * 512 + lane * 8, As + blk * 512, 16, 0, 0);
+      } else {
+        const int e = blk * 64 + lane, row = e >> 2;
+        const int chunk = (e & 3) ^ swz(row);
+        const int m = min(m0 + row, M - 1), k = min(k0 + chunk * 8, K - 8);
+        __builtin_amdgcn_global_load_lds(A + (int64_t)m * K + k, As + blk * 512, 16, 0, 0);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const int blk = j * 4 + wave;
       if (blk < 9) {
-        const int e = blk * 64 + lane, row = e >> 2;
-        const int chunk = (e & 3) ^ swz(row);
-        const int n = min(n0 + row, N - 1), k = min(k0 + chunk * 8, K - 8);
-        __builtin_amdgcn_global_load_lds(Bt + (int64_t)n * K + k, Bs + blk * 512, 16, 0, 0);
+        if constexpr (BF) {
+          // packed block (kt, n0 / 16 + blk) of nt * 9 row blocks per k block
+          const int64_t pb = (int64_t)kt * (nt * 9) + n0 / 16 + blk;
+          __builtin_amdgcn_global_load_lds(Bt + pb * 512 + lane * 8, Bs + blk * 512, 16, 0, 0);
+        } else {
+          const int e = blk * 64 + lane, row = e >> 2;
+          const int chunk = (e & 3) ^ swz(row);
+          const int n = min(n0 + row, N - 1), k = min(k0 + chunk * 8, K - 8);
+          __builtin_amdgcn_global_load_lds(Bt + (int64_t)n * K + k, Bs + blk * 512, 16, 0, 0);
+        }
       }
     }
   };
@@ -247,11 +284,20 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     wait_vm(kt + 1 < nk ? n_issue : 0);
     __bf16* As = smem + (kt % STAGES) * STAGE_ELEMS;
     __bf16* Bs = As + BM * BK;
-    if (partial && kt == nk - 1) {
+    if (!BF && partial && kt == nk - 1) {
       const int k0 = kt * BK;
       for (int e = tid; e < BN * 4; e += 256) {
         const int row = e >> 2, c = e & 3;
         if (k0 + c * 8 >= K) *reinterpret_cast<u32x4*>(&Bs[lds_off(row, c)]) = u32x4{0u, 0u, 0u, 0u};
+      }
+      wait_lgkm0();
+    }
+    if (AF && partial && kt == nk - 1) {
+      // lane slot t of each block holds k = 8 (t / 16) .. + 7 of the step
+      const int k0 = kt * BK;
+      for (int e = tid; e < BM * 4; e += 256) {
+        const int blk = e >> 6, t = e & 63;
+        if (k0 + (t >> 4) * 8 >= K) *reinterpret_cast<u32x4*>(&As[blk * 512 + t * 8]) = u32x4{0u, 0u, 0u, 0u};
       }
       wait_lgkm0();
     }
@@ -261,9 +307,13 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     asm volatile("" ::: "memory");
     v8bf av[TM], bv[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) bv[j] = *reinterpret_cast<const v8bf*>(&Bs[lds_off(j * 16 + lr, lc)]);
+    for (int j = 0; j < TN; ++j)
+      bv[j] = BF ? *reinterpret_cast<const v8bf*>(&Bs[j * 512 + lane * 8])
+                 : *reinterpret_cast<const v8bf*>(&Bs[lds_off(j * 16 + lr, lc)]);
 #pragma unroll
-    for (int i = 0; i < TM; ++i) av[i] = *reinterpret_cast<const v8bf*>(&As[lds_off(wave * 64 + i * 16 + lr, lc)]);
+    for (int i = 0; i < TM; ++i)
+      av[i] = AF ? *reinterpret_cast<const v8bf*>(&As[(wave * 4 + i) * 512 + lane * 8])
+                 : *reinterpret_cast<const v8bf*>(&As[lds_off(wave * 64 + i * 16 + lr, lc)]);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -273,6 +323,34 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
   }
 
   const int lcol = lane & 15, lr4 = (lane >> 4) * 4;
+  if constexpr (MODE == OUT_PACKA) {
+    // column n = (g, l): row R = g chi + b, column k = l D2 + u
+    int gj[TN], lj[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + j * 16 + lcol;
+      gj[j] = n < N ? n / aux.d2 : -1;
+      lj[j] = n - gj[j] * aux.d2;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int m = m0 + wave * 64 + i * 16 + lr4;  // rows m .. m + 3: u .. u + 3 of one b
+      if (m >= M) continue;
+      const int b = m / aux.d2, u = m - b * aux.d2;
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (gj[j] >= 0) {
+          const int R = gj[j] * aux.chi + b, k = lj[j] * aux.d2 + u;
+          const int64_t off =
+              ((int64_t)(R >> 4) * aux.kb + (k >> 5)) * 512 + ((R & 15) + 16 * ((k >> 3) & 3)) * 8 + (k & 7);
+          union { __bf16 h[4]; uint2 u2; } pk;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pk.h[q] = (__bf16)acc[i][j][q];
+          *reinterpret_cast<uint2*>(C + off) = pk.u2;
+        }
+    }
+    return;
+  }
   int64_t coff[TN];
   bool cok[TN];
 #pragma unroll
@@ -321,8 +399,8 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
             const __bf16 hi = (__bf16)x;
             TO* o = C + roff + coff[j];
             o[0] = hi;
-            o[sstride] = hi;
-            o[2 * sstride] = (__bf16)(x - (float)hi);
+            o[aux.sstride] = hi;
+            o[2 * aux.sstride] = (__bf16)(x - (float)hi);
           } else {
             C[roff + coff[j]] = (TO)acc[i][j][q];
           }
@@ -330,20 +408,128 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     }
 }
 
+// out[kb][rb][l][j] = bT[16 rb + l % 16][32 kb + 8 (l / 16) + j], zero past
+// N rows or K columns; rb < rbp (N padded to whole 144-row tiles).
+__global__ void pack_b_kernel(const __bf16* __restrict__ bT, int64_t N, int64_t K, int64_t rbp, int64_t total,
+                              __bf16* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
+    const int64_t blk = e >> 9, rb = blk % rbp, kb = blk / rbp;
+    const int64_t row = rb * 16 + (l & 15), k = kb * 32 + (l >> 4) * 8 + j;
+    out[e] = (row < N && k < K) ? bT[row * K + k] : (__bf16)0.0f;
+  }
+}
+
+struct Launch {
+  dim3 grid;
+  hipStream_t s;
+  int32_t M, N, K;
+  OutView ov;
+  GemmGroup g;
+  int32_t mt, nt, tiles, per_xcd;
+  Aux aux;
+};
+
+template <typename TO, int MODE, bool BF, bool AF>
+void launch(const Launch& l) {
+  hipLaunchKernelGGL((corner_bf16_dma_kernel<TO, MODE, BF, AF>), l.grid, dim3(256), 0, l.s, l.M, l.N, l.K, l.ov, l.g,
+                     l.mt, l.nt, l.tiles, l.per_xcd, l.aux);
+}
+
 }  // namespace
+
+static bool corner_use_dma() {
+  static const bool v = [] {
+    const char* e = std::getenv("CTM_CORNER_STAGING");  // "registers" selects the first form (fp32 output)
+    return !(e && std::strcmp(e, "registers") == 0);
+  }();
+  return v;
+}
+
+bool corner_packed_b() {
+  static const bool v = [] {
+    const char* e = std::getenv("CTM_CORNER_B");  // "rowmajor" keeps the double layer row-major
+    return corner_use_dma() && !(e && std::strcmp(e, "rowmajor") == 0);
+  }();
+  return v;
+}
+
+bool corner_packed_a() {
+  static const bool v = [] {
+    const char* e = std::getenv("CTM_CORNER_A");  // "rowmajor" keeps the intermediate Y row-major
+    return corner_packed_b() && !(e && std::strcmp(e, "rowmajor") == 0);
+  }();
+  return v;
+}
+
+int64_t corner_bf16_packed_b_elems(int64_t N, int64_t K) {
+  if (N <= 0 || K <= 0) return 0;
+  return ((K + BK - 1) / BK) * ((N + BN - 1) / BN * (BN / 16)) * 512;
+}
+
+hipError_t corner_bf16_pack_b(hipStream_t s, const void* bT, int64_t N, int64_t K, void* out) {
+  const int64_t total = corner_bf16_packed_b_elems(N, K);
+  if (total <= 0 || (K % 8) != 0) return hipErrorInvalidValue;
+  if (!span_ok(bT, (size_t)N * K * 2, "pack_b in") || !span_ok(out, (size_t)total * 2, "pack_b out"))
+    return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const int64_t rbp = (N + BN - 1) / BN * (BN / 16);
+  const int blocks = (int)std::min<int64_t>(8192, (total + 255) / 256);
+  hipLaunchKernelGGL(pack_b_kernel, dim3(blocks), dim3(256), 0, s, (const __bf16*)bT, N, K, rbp, total,
+                     (__bf16*)out);
+  return hipGetLastError();
+}
+
+int64_t corner_bf16_packed_a_elems(int64_t M, int64_t K) {
+  if (M <= 0 || K <= 0) return 0;
+  return ((M + BM - 1) / BM * (BM / 16)) * ((K + BK - 1) / BK) * 512;
+}
+
+hipError_t corner_bf16_to_packed_a(hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t chi, int64_t d2,
+                                   const GemmGroup& g, int groups) {
+  // the output is Y (chi^2 x d2^2) of the next product: M = N = chi d2, rows
+  // (b, u) with d2 % 4 == 0 so that a lane's four rows stay in one b
+  if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || M != chi * d2 || N != chi * d2 ||
+      d2 % 4 != 0 || chi * chi > INT32_MAX || d2 * d2 > INT32_MAX)
+    return hipErrorInvalidValue;
+  for (int i = 0; i < groups; ++i)
+    if ((uintptr_t)g.C[i] & 7) return hipErrorInvalidValue;
+  const int64_t ym = chi * chi, yk = d2 * d2;
+  const size_t sc = (size_t)corner_bf16_packed_a_elems(ym, yk) * 2;
+  for (int i = 0; i < groups; ++i)
+    if (!span_ok(g.A[i], (size_t)M * K * 2, "corner A") || !span_ok(g.B[i], (size_t)N * K * 2, "corner Bt") ||
+        !span_ok(g.C[i], sc, "corner packed Y") || ((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15))
+      return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  if (!corner_use_dma()) return hipErrorInvalidValue;
+  OutView ov{};
+  ov.r_ext = (int32_t)std::min<int64_t>(M, INT32_MAX);
+  ov.c_ext = (int32_t)std::min<int64_t>(N, INT32_MAX);
+  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
+  if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
+  const int64_t per_xcd = (tiles + 7) / 8;
+  Aux aux{0, (int32_t)chi, (int32_t)d2, (int32_t)((yk + BK - 1) / BK)};
+  const Launch L{dim3((unsigned)(8 * per_xcd)), s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt,
+                 (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, aux};
+  launch<__bf16, OUT_PACKA, false, false>(L);
+  return hipGetLastError();
+}
 
 bool corner_bf16_supported(int64_t M, int64_t N, int64_t K) {
   return M > 0 && N > 0 && K > 0 && (K % 8) == 0 && M <= INT32_MAX && N <= INT32_MAX;
 }
 
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups, int tout, int64_t split_stride) {
+                       int groups, int tout, int64_t split_stride, bool b_packed, bool a_packed) {
   if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || (tout != F32 && tout != BF16) ||
-      split_stride < 0 || (split_stride > 0 && tout != BF16))
+      split_stride < 0 || (split_stride > 0 && tout != BF16) || (b_packed && (tout != F32 || split_stride)) ||
+      (a_packed && !b_packed))
     return hipErrorInvalidValue;
   const size_t sc = (size_t)(view_max(vc, M, N) + 1 + 2 * split_stride) * dtype_size(tout);
+  const size_t sb = b_packed ? (size_t)corner_bf16_packed_b_elems(N, K) * 2 : (size_t)N * K * 2;
+  const size_t sa = a_packed ? (size_t)corner_bf16_packed_a_elems(M, K) * 2 : (size_t)M * K * 2;
   for (int i = 0; i < groups; ++i)
-    if (!span_ok(g.A[i], (size_t)M * K * 2, "corner A") || !span_ok(g.B[i], (size_t)N * K * 2, "corner Bt") ||
+    if (!span_ok(g.A[i], sa, "corner A") || !span_ok(g.B[i], sb, "corner Bt") ||
         !span_ok(g.C[i], sc, "corner C") || ((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
@@ -354,30 +540,24 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
   if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
   const int64_t per_xcd = (tiles + 7) / 8;
-  static const bool use_dma = [] {
-    const char* e = std::getenv("CTM_CORNER_STAGING");  // "registers" selects the first form (fp32 output)
-    return !(e && std::strcmp(e, "registers") == 0);
-  }();
+  const bool use_dma = corner_use_dma();
+  if (b_packed && !use_dma) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * per_xcd));
   bool v4 = use_dma && split_stride == 0 && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 &&
             vc.c_ls % 4 == 0 && vc.c_hs % 4 == 0 && M % 4 == 0;
   for (int i = 0; i < groups && v4; ++i) v4 = ((uintptr_t)g.C[i] & (tout == F32 ? 15 : 7)) == 0;
-  const int64_t z = 0;
-  if (tout == BF16 && split_stride > 0)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_SPLIT>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, split_stride);
-  else if (tout == BF16 && v4)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_V4>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
-  else if (tout == BF16)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<__bf16, OUT_PLAIN>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
-  else if (v4)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, OUT_V4>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
-  else if (use_dma)
-    hipLaunchKernelGGL((corner_bf16_dma_kernel<float, OUT_PLAIN>), grid, dim3(256), 0, s, (int32_t)M, (int32_t)N,
-                       (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, z);
+  Aux aux{split_stride, 0, 0, 0};
+  const Launch L{grid, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles,
+                 (int32_t)per_xcd, aux};
+  if (tout == BF16 && split_stride > 0) launch<__bf16, OUT_SPLIT, false, false>(L);
+  else if (tout == BF16 && v4) launch<__bf16, OUT_V4, false, false>(L);
+  else if (tout == BF16) launch<__bf16, OUT_PLAIN, false, false>(L);
+  else if (b_packed && a_packed && v4) launch<float, OUT_V4, true, true>(L);
+  else if (b_packed && a_packed) launch<float, OUT_PLAIN, true, true>(L);
+  else if (b_packed && v4) launch<float, OUT_V4, true, false>(L);
+  else if (b_packed) launch<float, OUT_PLAIN, true, false>(L);
+  else if (v4) launch<float, OUT_V4, false, false>(L);
+  else if (use_dma) launch<float, OUT_PLAIN, false, false>(L);
   else
     hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g,
                        (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);

@@ -176,6 +176,7 @@ struct Inst {
   bool staleC[4][MAXPOS] = {};
   bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
+  void* bTp[MAXT][4] = {};       // bf16 mode: bT in the corner kernel's packed fragment layout
   // single-layer mode: the ket (Sk) and bra (Sb) tensor of each rotation in
   // the working type, legs [L'][U'][s][D'][R'] of the rotated frame
   void* Sk[MAXT][4] = {};
@@ -312,7 +313,10 @@ void plan_row(ctm_ctx_s& x, Arena& ar, const Inst& I, Row& R) {
   for (int q = 0; q < 4; ++q) {
     R.Q[q] = ar.take_bytes(n * n * qs);
     R.X[q] = ar.take_bytes(t3 * ws);
-    R.Y[q] = ar.take_bytes(y4 * ws);
+    // bf16: also room for Y in the corner kernel's packed layout
+    R.Y[q] = ar.take_bytes(x.prec == CTM_BF16
+                               ? std::max(y4 * ws, (size_t)corner_bf16_packed_a_elems(c2, D2 * D2) * 2)
+                               : y4 * ws);
   }
   R.V = ar.take<double>(nk); R.Yb = ar.take<double>(nk); R.Qb = ar.take<double>(nk);
   R.Z = ar.take<double>(nk); R.LV = ar.take<double>(nk); R.UU = ar.take<double>(nk);
@@ -379,6 +383,8 @@ void plan(ctm_ctx_s& x, Arena& ar) {
         if (x.prec == CTM_BF16 && !x.cfg.single_layer) {
           I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
           I.bT3[t][r] = ar.take_bytes(3 * a8 * dtype_size(BF16));
+          const int64_t K4 = (int64_t)I.D2 * I.D2;
+          if (K4 % 8 == 0) I.bTp[t][r] = ar.take_bytes((size_t)corner_bf16_packed_b_elems(K4, K4) * 2);
         }
       }
     }
@@ -556,6 +562,7 @@ struct Roles {
   void* TwP(int i, int xp, int yp) const { return I->TwP[(i + k) % 4][pos(xp, yp)]; }
   void* TwR(int i, int xp, int yp) const { return I->TwR[(i + k) % 4][pos(xp, yp)]; }
   void* bT(int xp, int yp, int r) const { return I->bT[tid(xp, yp)][(k + r) % 4]; }
+  void* bTp(int xp, int yp, int r) const { return I->bTp[tid(xp, yp)][(k + r) % 4]; }
   // double layer of the site in this frame, additionally turned by r
   double* b64(int xp, int yp, int r) const { return I->b64[tid(xp, yp)][(k + r) % 4]; }
   void* bw(int xp, int yp, int r) const { return I->bw[tid(xp, yp)][(k + r) % 4]; }
@@ -667,6 +674,7 @@ struct CornerJob {
   const void *C, *Tn, *Tp, *b;
   void *X, *Y, *Q;
   const void *TnP = nullptr, *bT = nullptr;  // bf16 path: permuted edge, transposed double layer
+  const void* bTp = nullptr;                 // ... and the latter packed for the corner kernel
   const void* TnR = nullptr;                 // bf16 path: bf16 edge as [next][inner][prev]
   const void *Sk = nullptr, *Sb = nullptr;   // single-layer mode: ket and bra of the rotation
   const void *SkT = nullptr, *SbT = nullptr; // ... as operands of the bf16 corner kernel
@@ -857,9 +865,12 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
                     corner_bf16_supported(c * c, K4, K4);
   const int ty = bf16 ? BF16 : tin;  // type of Y
   const bool fast2 = fast && jobs[0].TnR && corner_bf16_supported(n, n, c);
+  bool packed = fast && corner_packed_b();
+  for (const CornerJob& j : jobs) packed = packed && j.bTp;
   for (size_t j0 = 0; j0 < jobs.size(); j0 += MAXG) {
     size_t j1 = std::min(jobs.size(), j0 + MAXG);
     G g1, g2, g3;
+    bool packed_a = false;
     if (fast) {
       // stage 2 writes Y as [(g,b)][(l,u)], so that stage 3 has both operands
       // contiguous in the contracted index; rows m = (g, l) -> g chi D^4 + l D^2,
@@ -871,23 +882,31 @@ ctm_status corner_chain(hipStream_t s, int tin, int tq, int chi, int D2, const s
         for (size_t j = j0; j < j1; ++j) {
           g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
           g2.add(jobs[j].X, jobs[j].TnR, jobs[j].Y);
-          g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
+          g3.add(jobs[j].Y, packed ? jobs[j].bTp : jobs[j].bT, jobs[j].Q);
         }
         CHK(gemm_run(s, tin, BF16, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
-        HIPCHK(corner_bf16(s, n, n, c, vy, g2.group(0, g2.size()), g2.size(), BF16));
+        if (packed && corner_packed_a() && D2 % 4 == 0) {
+          // taken transposed: the edge rows (b, u) times X rows (g, l)
+          packed_a = true;
+          G g2t;
+          for (size_t j = j0; j < j1; ++j) g2t.add(jobs[j].TnR, jobs[j].X, jobs[j].Y);
+          HIPCHK(corner_bf16_to_packed_a(s, n, n, c, c, D2, g2t.group(0, g2t.size()), g2t.size()));
+        } else {
+          HIPCHK(corner_bf16(s, n, n, c, vy, g2.group(0, g2.size()), g2.size(), BF16));
+        }
       } else {
         // stage 2 reads the edge as [n][(b,u)]
         for (size_t j = j0; j < j1; ++j) {
           g1.add(jobs[j].Tp, jobs[j].C, jobs[j].X);
           g2.add(jobs[j].X, jobs[j].TnP, jobs[j].Y);
-          g3.add(jobs[j].Y, jobs[j].bT, jobs[j].Q);
+          g3.add(jobs[j].Y, packed ? jobs[j].bTp : jobs[j].bT, jobs[j].Q);
         }
         CHK(gemm_run(s, tin, tin, n, c, c, rowmajor(c), rowmajor(c), rowmajor(c), g1));
         CHK(gemm_run(s, tin, ty, n, n, c, rowmajor(c), rowmajor(n), vy, g2));
       }
       View vc = view2(c, D2, (int64_t)D2 * n, D2, 1, n);
       CHK(stage3_timed(s, tm, [&]() -> ctm_status {
-        HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.group(0, g3.size()), g3.size()));
+        HIPCHK(corner_bf16(s, c * c, K4, K4, vc, g3.group(0, g3.size()), g3.size(), F32, 0, packed, packed_a));
         return CTM_OK;
       }));
       continue;
@@ -1493,6 +1512,7 @@ ctm_status column_step(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
           j.TnR = ro.TwR(q, cx[q], cy[q]);
           j.TnP = ro.TwP(q, cx[q], cy[q]);
           j.bT = ro.bT(cx[q], cy[q], q);
+          j.bTp = ro.bTp(cx[q], cy[q], q);
         }
         jobs.push_back(j);
       }
@@ -2582,6 +2602,8 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           int perm[2] = {1, 0};
           if (permute(x->stream, F64, I.b64[t][r], BF16, I.bT[t][r], 2, dims, perm) != hipSuccess)
             return cleanup(fail(CTM_E_HIP, "transpose double layer"));
+          if (I.bTp[t][r] && corner_bf16_pack_b(x->stream, I.bT[t][r], dims[0], dims[1], I.bTp[t][r]) != hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "pack double layer"));
           // B side of the three-term product: rows (dn,R), columns (l,u)
           const int64_t K4 = (int64_t)I.D2 * I.D2;
           if (split3_bf16(x->stream, F64, I.b64[t][r], transposed(rowmajor(K4)), K4, K4, false, I.bT3[t][r]) !=
@@ -3217,6 +3239,26 @@ ctm_status ctm_debug_corner_bf16(int64_t M, int64_t N, int64_t K, const void* A,
   g.B[0] = Bt;
   g.C[0] = C;
   hipError_t e = corner_bf16(s, M, N, K, rowmajor(N), g, 1);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "alignment");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+size_t ctm_debug_corner_bf16_packed_bytes(int64_t N, int64_t K) {
+  return (size_t)corner_bf16_packed_b_elems(N, K) * 2;
+}
+
+ctm_status ctm_debug_corner_bf16_packed(int64_t M, int64_t N, int64_t K, const void* A, const void* Bt, void* packed,
+                                        void* C, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!corner_bf16_supported(M, N, K) || !A || !Bt || !packed || !C) return fail(CTM_E_INVALID, "sizes");
+  HIPCHK(corner_bf16_pack_b(s, Bt, N, K, packed));
+  GemmGroup g{};
+  g.A[0] = A;
+  g.B[0] = packed;
+  g.C[0] = C;
+  hipError_t e = corner_bf16(s, M, N, K, rowmajor(N), g, 1, F32, 0, true);
   if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "alignment");
   HIPCHK(e);
   HIPCHK(ssync(s));

@@ -104,8 +104,34 @@ hipError_t split3_transpose_bf16(hipStream_t s, const float* in, int64_t nb, int
 // Bt bf16 N x K row-major (16-byte aligned, K % 8 == 0), fp32 accumulation.
 // split_stride > 0 (tout = BF16): each result is stored as its A-side split
 // hi, hi, lo at offsets 0, split_stride, 2 split_stride from its view place.
+// b_packed (tout = F32, no split): Bt is in the packed fragment layout of
+// corner_bf16_pack_b instead of row-major.
+// a_packed (with b_packed): A is in the packed layout that
+// corner_bf16_to_packed_a writes.
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
-                       int groups, int tout = F32, int64_t split_stride = 0);
+                       int groups, int tout = F32, int64_t split_stride = 0, bool b_packed = false,
+                       bool a_packed = false);
+// The enlarged corner's second product, taken transposed: the edge (A,
+// rows (b, u)) times X (Bt, rows (g, l)), both bf16 row-major with K = chi,
+// M = N = chi d2, d2 % 4 == 0, written as Y = [(g, b)][(l, u)] (chi^2 x d2^2,
+// from element ((b, u), (g, l))) in bf16 in the packed A layout of the next
+// product: [chi^2 / 16, padded to whole 256-row tiles][d2^2 / 32 rounded
+// up][64 lanes][8], block (rb, kb) lane t holding Y[16 rb + t % 16][32 kb +
+// 8 (t / 16) .. + 7]; the padding is not written.
+int64_t corner_bf16_packed_a_elems(int64_t M, int64_t K);
+hipError_t corner_bf16_to_packed_a(hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t chi, int64_t d2,
+                                   const GemmGroup& g, int groups);
+// Packed fragment layout of a bf16 N x K row-major Bt for the corner kernel:
+// [K / 32 (rounded up)][N / 16 (rounded up to whole 144-row tiles)][64 lanes][8],
+// block (kb, rb) lane l holding Bt[16 rb + l % 16][32 kb + 8 (l / 16) .. + 7]
+// (zeros past N and K).  Elements of the packed form, and the packing.
+int64_t corner_bf16_packed_b_elems(int64_t N, int64_t K);
+// Whether the moves use the packed form (default; environment variable
+// CTM_CORNER_B=rowmajor, or CTM_CORNER_STAGING=registers, selects row-major).
+bool corner_packed_b();
+// The same for the intermediate Y (CTM_CORNER_A=rowmajor keeps it row-major).
+bool corner_packed_a();
+hipError_t corner_bf16_pack_b(hipStream_t s, const void* bT, int64_t N, int64_t K, void* out);
 
 // out[perm-ordered] = in, generic permutation of an up-to-8-d row-major tensor
 // with type conversion.  out dims are in_dims[perm[i]].

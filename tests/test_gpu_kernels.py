@@ -3,6 +3,7 @@ the MFMA GEMM (float64, float32, bfloat16 operand layouts) and the split-K
 GEMM for few columns against NumPy, and the one-sided Jacobi SVD against
 LAPACK."""
 import ctypes
+import json
 
 import numpy as np
 import pytest
@@ -23,6 +24,10 @@ def _lib():
     lib.ctm_debug_tsgemm.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
     lib.ctm_debug_corner_bf16.restype = ctypes.c_int
+    lib.ctm_debug_corner_bf16_packed.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 5
+    lib.ctm_debug_corner_bf16_packed.restype = ctypes.c_int
+    lib.ctm_debug_corner_bf16_packed_bytes.argtypes = [ctypes.c_int64] * 2
+    lib.ctm_debug_corner_bf16_packed_bytes.restype = ctypes.c_size_t
     lib.ctm_debug_svd.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 6
     lib.ctm_debug_svd.restype = ctypes.c_int
     return lib
@@ -117,6 +122,41 @@ def test_corner_bf16(gpu, M, N, K):
     assert np.abs(got - ref).max() <= 1e-5 * np.sqrt(K) * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("M,N,K", [(20736, 1296, 1296), (2304, 1296, 1296), (300, 200, 296), (7, 5, 8),
+                                   (256, 144, 32), (513, 289, 1040)])
+def test_corner_bf16_packed(gpu, M, N, K):
+    """The double-layer kernel with B in the packed fragment layout (the form
+    the moves use) against the row-major form, bitwise: the same K order and
+    the same MFMA sequence; full and ragged tiles, a partial last K step."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(M + 7 * N + K)
+    A = torch.tensor(rng.standard_normal((M, K)), dtype=torch.bfloat16, device="cuda")
+    Bt = torch.tensor(rng.standard_normal((N, K)), dtype=torch.bfloat16, device="cuda")
+    C0 = torch.full((M, N), 3.0, dtype=torch.float32, device="cuda")
+    C1 = torch.full((M, N), -3.0, dtype=torch.float32, device="cuda")
+    nb = lib.ctm_debug_corner_bf16_packed_bytes(N, K)
+    assert nb == ((K + 31) // 32) * ((N + 143) // 144 * 9) * 1024
+    P = torch.full((nb // 2,), 7.0, dtype=torch.bfloat16, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    print("corner_bf16 packed case", M, N, K, flush=True)
+    assert lib.ctm_debug_corner_bf16(M, N, K, A.data_ptr(), Bt.data_ptr(), C0.data_ptr(), stream) == 0
+    assert lib.ctm_debug_corner_bf16_packed(M, N, K, A.data_ptr(), Bt.data_ptr(), P.data_ptr(), C1.data_ptr(),
+                                            stream) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1)
+    # the packed layout itself: block (kb, rb), lane l holds Bt[16 rb + l % 16][32 kb + 8 (l / 16) + j]
+    rbp = (N + 143) // 144 * 9
+    pk = P.view(-1, rbp, 64, 8).to(torch.float32).cpu().numpy()
+    Bn = Bt.to(torch.float32).cpu().numpy()
+    for kb, rb, l in [(0, 0, 0), (0, 0, 17), (K // 32, (N - 1) // 16, 63), ((K - 1) // 32, rbp - 1, 5)]:
+        for j in range(8):
+            row, k = 16 * rb + l % 16, 32 * kb + 8 * (l // 16) + j
+            want = Bn[row, k] if row < N and k < K else 0.0
+            if kb < pk.shape[0]:
+                assert pk[kb, rb, l, j] == want
+
+
 @pytest.mark.parametrize("k", [1, 2, 7, 16, 33, 80, 144, 160])
 def test_jacobi_svd(gpu, k):
     import torch
@@ -143,3 +183,49 @@ def test_jacobi_svd(gpu, k):
     # accumulated rotations: O(k * sweeps * u) loss of orthogonality
     assert np.abs(W.T @ W - np.eye(k)).max() < 4e-15 * max(k, 8)
     assert np.abs(M @ W - U * S).max() < 4e-15 * max(k, 8) * sref[0]
+
+
+PACKED_RUN = r'''
+import hashlib, json, sys
+sys.path.insert(0, %(root)r)
+sys.path.insert(0, %(tests)r)
+import numpy as np
+import synth
+from paper_1711_04798_amd import CTM
+out = {}
+for D, chi in ((6, 144), (4, 64), (6, 36)):
+    tens = synth.cell_tensors(0, 8, D, 2)
+    g = CTM([tens], Lx=2, Ly=2, pattern=[0, 1, 1, 0], chi=chi, prec="bf16", max_iters=2, resid_tol=0.0,
+            cutoff=1e-7)
+    g.sweep(2)
+    sp = g.spectra()
+    out["%%d_%%d" %% (D, chi)] = [hashlib.sha1(sp.tobytes()).hexdigest(), g.norm()]
+    g.close()
+print(json.dumps(out))
+'''
+
+
+def test_packed_layouts_bitwise(gpu):
+    """The moves with the double layer and the intermediate Y in the packed
+    fragment layouts (the default), with only the double layer packed, and
+    with both row-major give bitwise-equal spectra and norms after two bf16
+    sweeps: the benchmark workload (d = 8, D = 6, chi = 144, live extent
+    below chi), D = 4 (K = 256, whole K steps) and chi = 36 (a live extent
+    that is not a multiple of 8 sends the second product to the generic GEMM,
+    so only the double layer is packed)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = PACKED_RUN % {"root": root, "tests": os.path.join(root, "tests")}
+    res = {}
+    for name, extra in (("packed", {}), ("b_only", {"CTM_CORNER_A": "rowmajor"}),
+                        ("rowmajor", {"CTM_CORNER_B": "rowmajor"})):
+        env = dict(os.environ)
+        env.update(extra)
+        print("packed layouts run", name, flush=True)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        res[name] = json.loads(r.stdout.strip().splitlines()[-1])
+    print(res)
+    assert res["packed"] == res["b_only"] == res["rowmajor"]
