@@ -351,8 +351,10 @@ ctm_status ctm_get_timing(ctm_ctx ctx, double* v);
 
 /*
  * Launch-variant table (process-wide): per kernel family and operand shape,
- * the tile of the generic GEMM and the split counts of the tall-skinny and
- * split-K products.  The project's tuner (paper_1711_04798_amd/tune.py) runs
+ * the tile of the generic GEMM, the split counts of the tall-skinny and
+ * split-K products ("gemm", "ts", "splitk"), and the rows per work-group of
+ * the bf16 enlarged-corner product ("corner": 256, 192 or 128 for variants
+ * 0, 1, 2; bitwise-equal results).  The project's tuner (paper_1711_04798_amd/tune.py) runs
  * the benchmark workloads with tuning on and saves the table; a later
  * process loads it (ctm_init loads the file named by the environment
  * variable CTM_TILE_TABLE once; the Python binding loads the committed
@@ -363,8 +365,9 @@ ctm_status ctm_get_timing(ctm_ctx ctx, double* v);
  *         replace those of equal key; *entries_out = entries read.
  *   save: writes every entry; *entries_out = entries written.
  *   tune: on = 1 makes the first launch of every new shape of the split
- *         products (outside graph capture) time each variant on its own
- *         operands and store the fastest.  Their variants split the
+ *         products and the corner product (outside graph capture) time
+ *         each variant on its own operands and store the fastest.  The
+ *         split products' variants split the
  *         contraction differently, so results change at the rounding level
  *         with the table (a process with one table is deterministic).
  */

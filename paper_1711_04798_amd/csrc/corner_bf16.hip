@@ -170,10 +170,18 @@ constexpr int STAGES = 3;
 constexpr int STAGE_ELEMS = (BM + BN) * BK;
 
 __device__ __forceinline__ void wait_vm(int n) {
-  // s_waitcnt vmcnt(n), other counters unconstrained (gfx9 encoding)
-  if (n >= 7) __builtin_amdgcn_s_waitcnt(0xF77);
-  else if (n == 6) __builtin_amdgcn_s_waitcnt(0xF76);
-  else __builtin_amdgcn_s_waitcnt(0xF70);
+  // s_waitcnt vmcnt(n) for n <= 7 (larger n wait for 7), other counters
+  // unconstrained (gfx9 encoding)
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0xF70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0xF71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0xF72); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0xF73); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0xF74); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0xF75); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0xF76); break;
+    default: __builtin_amdgcn_s_waitcnt(0xF77); break;
+  }
 }
 __device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
 
@@ -212,33 +220,35 @@ struct Aux {
 // of 1 KiB in MFMA operand order, rows padded to whole 256-row tiles): the
 // same contiguous loads and linear fragment reads as BF; the k past K of a
 // partial last step are zeroed in LDS (the padding is never written).
-template <typename TO, int MODE, bool BF, bool AF>
+template <typename TO, int MODE, bool BF, bool AF, int RT = 4>
 __global__ void __launch_bounds__(256, 2)
 corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g, int32_t mt, int32_t nt,
                        int32_t tiles, int32_t per_xcd, Aux aux) {
-  __shared__ __attribute__((aligned(16))) __bf16 smem[STAGES * STAGE_ELEMS];
+  // RT row tiles of 16 per wave: BM = 64 RT rows per work-group
+  constexpr int BMR = 64 * RT, SE = (BMR + BN) * BK;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[STAGES * SE];
   const int L = blockIdx.x;
   const int t = (L & 7) * per_xcd + (L >> 3);
   if (t >= tiles) return;
   const int gi = t / (mt * nt);
   const int rem = t - gi * (mt * nt);
-  const int m0 = (rem / nt) * BM, n0 = (rem % nt) * BN;
+  const int m0 = (rem / nt) * BMR, n0 = (rem % nt) * BN;
   const __bf16* __restrict__ A = (const __bf16*)g.A[gi];
   const __bf16* __restrict__ Bt = (const __bf16*)g.B[gi];
   TO* __restrict__ C = (TO*)g.C[gi];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nk = (K + BK - 1) / BK;
   const bool partial = (K % BK) != 0;
-  const int n_issue = wave == 0 ? 7 : 6;  // loads per wave per K step
+  const int n_issue = wave == 0 ? RT + 3 : RT + 2;  // loads per wave per K step
 
-  // loads of K step kt into stage kt % 3.  A: 16 blocks of 64 chunks (4 per
-  // wave); B: 9 blocks (waves take blocks w, w + 4, w + 8 < 9)
+  // loads of K step kt into stage kt % 3.  A: 4 RT blocks of 64 chunks (RT
+  // per wave); B: 9 blocks (waves take blocks w, w + 4, w + 8 < 9)
   auto issue = [&](int kt) {
-    __bf16* As = smem + (kt % STAGES) * STAGE_ELEMS;
-    __bf16* Bs = As + BM * BK;
+    __bf16* As = smem + (kt % STAGES) * SE;
+    __bf16* Bs = As + BMR * BK;
     const int k0 = kt * BK;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < RT; ++j) {
       const int blk = j * 4 + wave;
       if constexpr (AF) {
         const int64_t pb = (int64_t)(m0 / 16 + blk) * nk + kt;
@@ -268,9 +278,9 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     }
   };
 
-  v4f acc[TM][TN];
+  v4f acc[RT][TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
@@ -282,8 +292,8 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     // are outstanding; the barrier then covers every wave's loads, and every
     // wave's reads of the stage that step kt + 2 refills
     wait_vm(kt + 1 < nk ? n_issue : 0);
-    __bf16* As = smem + (kt % STAGES) * STAGE_ELEMS;
-    __bf16* Bs = As + BM * BK;
+    __bf16* As = smem + (kt % STAGES) * SE;
+    __bf16* Bs = As + BMR * BK;
     if (!BF && partial && kt == nk - 1) {
       const int k0 = kt * BK;
       for (int e = tid; e < BN * 4; e += 256) {
@@ -295,7 +305,7 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     if (AF && partial && kt == nk - 1) {
       // lane slot t of each block holds k = 8 (t / 16) .. + 7 of the step
       const int k0 = kt * BK;
-      for (int e = tid; e < BM * 4; e += 256) {
+      for (int e = tid; e < BMR * 4; e += 256) {
         const int blk = e >> 6, t = e & 63;
         if (k0 + (t >> 4) * 8 >= K) *reinterpret_cast<u32x4*>(&As[blk * 512 + t * 8]) = u32x4{0u, 0u, 0u, 0u};
       }
@@ -305,17 +315,17 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     // next step (its fence drains every outstanding memory operation)
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    v8bf av[TM], bv[TN];
+    v8bf av[RT], bv[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j)
       bv[j] = BF ? *reinterpret_cast<const v8bf*>(&Bs[j * 512 + lane * 8])
                  : *reinterpret_cast<const v8bf*>(&Bs[lds_off(j * 16 + lr, lc)]);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
-      av[i] = AF ? *reinterpret_cast<const v8bf*>(&As[(wave * 4 + i) * 512 + lane * 8])
-                 : *reinterpret_cast<const v8bf*>(&As[lds_off(wave * 64 + i * 16 + lr, lc)]);
+    for (int i = 0; i < RT; ++i)
+      av[i] = AF ? *reinterpret_cast<const v8bf*>(&As[(wave * RT + i) * 512 + lane * 8])
+                 : *reinterpret_cast<const v8bf*>(&As[lds_off(wave * RT * 16 + i * 16 + lr, lc)]);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
@@ -333,8 +343,8 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
       lj[j] = n - gj[j] * aux.d2;
     }
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int m = m0 + wave * 64 + i * 16 + lr4;  // rows m .. m + 3: u .. u + 3 of one b
+    for (int i = 0; i < RT; ++i) {
+      const int m = m0 + wave * RT * 16 + i * 16 + lr4;  // rows m .. m + 3: u .. u + 3 of one b
       if (m >= M) continue;
       const int b = m / aux.d2, u = m - b * aux.d2;
 #pragma unroll
@@ -362,8 +372,8 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
   }
   if constexpr (MODE == OUT_V4) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int m = m0 + wave * 64 + i * 16 + lr4;
+    for (int i = 0; i < RT; ++i) {
+      const int m = m0 + wave * RT * 16 + i * 16 + lr4;
       if (m >= M) continue;
       const int h = m / vc.r_ext, l = m - h * vc.r_ext;
       const int64_t roff = (int64_t)h * vc.r_hs + l;
@@ -384,10 +394,10 @@ corner_bf16_dma_kernel(int32_t M, int32_t N, int32_t K, OutView vc, GemmGroup g,
     return;
   }
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int m = m0 + wave * 64 + i * 16 + lr4 + q;
+      const int m = m0 + wave * RT * 16 + i * 16 + lr4 + q;
       if (m >= M) continue;
       const int h = m / vc.r_ext, l = m - h * vc.r_ext;
       const int64_t roff = (int64_t)h * vc.r_hs + (int64_t)l * vc.r_ls;
@@ -430,10 +440,17 @@ struct Launch {
   Aux aux;
 };
 
-template <typename TO, int MODE, bool BF, bool AF>
+template <typename TO, int MODE, bool BF, bool AF, int RT = 4>
 void launch(const Launch& l) {
-  hipLaunchKernelGGL((corner_bf16_dma_kernel<TO, MODE, BF, AF>), l.grid, dim3(256), 0, l.s, l.M, l.N, l.K, l.ov, l.g,
-                     l.mt, l.nt, l.tiles, l.per_xcd, l.aux);
+  hipLaunchKernelGGL((corner_bf16_dma_kernel<TO, MODE, BF, AF, RT>), l.grid, dim3(256), 0, l.s, l.M, l.N, l.K, l.ov,
+                     l.g, l.mt, l.nt, l.tiles, l.per_xcd, l.aux);
+}
+
+// the packed-operand product in float32 with 64 rt rows per work-group
+template <int RT>
+void launch_packed(const Launch& l, bool v4) {
+  if (v4) launch<float, OUT_V4, true, true, RT>(l);
+  else launch<float, OUT_PLAIN, true, true, RT>(l);
 }
 
 }  // namespace
@@ -482,7 +499,9 @@ hipError_t corner_bf16_pack_b(hipStream_t s, const void* bT, int64_t N, int64_t 
 
 int64_t corner_bf16_packed_a_elems(int64_t M, int64_t K) {
   if (M <= 0 || K <= 0) return 0;
-  return ((M + BM - 1) / BM * (BM / 16)) * ((K + BK - 1) / BK) * 512;
+  // whole 256-row tiles and one more: the row tiles of every variant (64,
+  // 128, 192 or 256 rows per work-group) stay inside
+  return ((M + BM - 1) / BM + 1) * (BM / 16) * ((K + BK - 1) / BK) * 512;
 }
 
 hipError_t corner_bf16_to_packed_a(hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t chi, int64_t d2,
@@ -519,6 +538,71 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K) {
   return M > 0 && N > 0 && K > 0 && (K % 8) == 0 && M <= INT32_MAX && N <= INT32_MAX;
 }
 
+// The packed-operand float32 product with 64 rt rows per work-group (the
+// variants compute every element with the same K order: bitwise equal).
+static hipError_t launch_packed_rt(hipStream_t s, int64_t M, int64_t N, int64_t K, const OutView& ov, bool v4,
+                                   const GemmGroup& g, int groups, int rt) {
+  const int64_t bm = 64 * rt;
+  const int64_t mt = (M + bm - 1) / bm, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
+  if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
+  const int64_t per_xcd = (tiles + 7) / 8;
+  const Launch L{dim3((unsigned)(8 * per_xcd)), s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt,
+                 (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, Aux{0, 0, 0, 0}};
+  if (rt == 2) launch_packed<2>(L, v4);
+  else if (rt == 3) launch_packed<3>(L, v4);
+  else launch_packed<4>(L, v4);
+  return hipGetLastError();
+}
+
+// TK_CORNER variant v -> rows per work-group 64 rt: v = 0, 1, 2 -> rt = 4, 3, 2
+static int rt_of(int v) { return v == 2 ? 2 : v == 1 ? 3 : 4; }
+
+// Rows per work-group of the packed product: the tile table's entry; else,
+// while table tuning is on (outside capture), the fastest variant timed on
+// the call's own operands (each overwrites C); else 256 rows, or 128 when
+// 256-row tiles would not fill two rounds of two work-groups per CU (the
+// tail round of a small live extent).
+static int corner_rows(hipStream_t s, int64_t M, int64_t N, int64_t K, const OutView& ov, bool v4,
+                       const GemmGroup& g, int groups) {
+  static const int forced = [] {  // CTM_CORNER_ROWS=256|192|128 overrides the choice
+    const char* e = std::getenv("CTM_CORNER_ROWS");
+    const int r = e ? std::atoi(e) : 0;
+    return r == 256 ? 4 : r == 192 ? 3 : r == 128 ? 2 : 0;
+  }();
+  if (forced) return forced;
+  const TileKey key{TK_CORNER, BF16, F32, 1, 1, groups, M, N, K};
+  int v = tile_lookup(key, -1);
+  if (v >= 0 && v < TILE_VARIANTS[TK_CORNER]) return rt_of(v);
+  if (tile_tuning_on() && !dry_run()) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+        hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      float best_ms = 1e30f;
+      int best = 0;
+      for (int t = 0; t < TILE_VARIANTS[TK_CORNER]; ++t) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          if (hipEventRecord(e0, s) != hipSuccess || launch_packed_rt(s, M, N, K, ov, v4, g, groups, rt_of(t)) !=
+                                                         hipSuccess ||
+              hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            break;
+          float ms = 0;
+          if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < best_ms) { best_ms = ms_min; best = t; }
+      }
+      tile_set(key, best);
+      v = best;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (v >= 0) return rt_of(v);
+  }
+  const int64_t tiles256 = (M + 255) / 256 * ((N + BN - 1) / BN) * groups;
+  return tiles256 < 4 * 256 ? 2 : 4;
+}
+
 hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const View& vc, const GemmGroup& g,
                        int groups, int tout, int64_t split_stride, bool b_packed, bool a_packed) {
   if (!corner_bf16_supported(M, N, K) || groups < 1 || groups > MAXG || (tout != F32 && tout != BF16) ||
@@ -537,10 +621,10 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   ov.r_ext = (int32_t)(vc.r_ext > M ? M : vc.r_ext);
   ov.c_ext = (int32_t)(vc.c_ext > N ? N : vc.c_ext);
   ov.r_ls = vc.r_ls; ov.r_hs = vc.r_hs; ov.c_ls = vc.c_ls; ov.c_hs = vc.c_hs;
+  const bool use_dma = corner_use_dma();
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
   if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
   const int64_t per_xcd = (tiles + 7) / 8;
-  const bool use_dma = corner_use_dma();
   if (b_packed && !use_dma) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(8 * per_xcd));
   bool v4 = use_dma && split_stride == 0 && vc.r_ls == 1 && ov.r_ext % 4 == 0 && vc.r_hs % 4 == 0 &&
@@ -552,8 +636,8 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   if (tout == BF16 && split_stride > 0) launch<__bf16, OUT_SPLIT, false, false>(L);
   else if (tout == BF16 && v4) launch<__bf16, OUT_V4, false, false>(L);
   else if (tout == BF16) launch<__bf16, OUT_PLAIN, false, false>(L);
-  else if (b_packed && a_packed && v4) launch<float, OUT_V4, true, true>(L);
-  else if (b_packed && a_packed) launch<float, OUT_PLAIN, true, true>(L);
+  else if (b_packed && a_packed)
+    return launch_packed_rt(s, M, N, K, ov, v4, g, groups, corner_rows(s, M, N, K, ov, v4, g, groups));
   else if (b_packed && v4) launch<float, OUT_V4, true, false>(L);
   else if (b_packed) launch<float, OUT_PLAIN, true, false>(L);
   else if (v4) launch<float, OUT_V4, false, false>(L);

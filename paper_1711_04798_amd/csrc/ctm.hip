@@ -3310,7 +3310,7 @@ ctm_status ctm_tile_table_load(const char* path, int32_t* entries_out) {
   if (!path) return fail(CTM_E_INVALID, "null path");
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(CTM_E_INVALID, std::string("cannot open ") + path);
-  static const char* names[3] = {"gemm", "ts", "splitk"};
+  static const char* names[TILE_KINDS] = {"gemm", "ts", "splitk", "corner"};
   char line[1024];
   int n = 0;
   auto num = [](const char* l, const char* key, int64_t* out) -> bool {
@@ -3326,7 +3326,7 @@ ctm_status ctm_tile_table_load(const char* path, int32_t* entries_out) {
     const char* kp = std::strstr(line, "\"kernel\"");
     if (!kp) continue;
     int kern = -1;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < TILE_KINDS; ++k) {
       std::string q = std::string("\"") + names[k] + "\"";
       const char* v = std::strstr(kp + 8, q.c_str());
       if (v) { kern = k; break; }
@@ -3352,7 +3352,7 @@ ctm_status ctm_tile_table_save(const char* path, int32_t* entries_out) {
   if (!path) return fail(CTM_E_INVALID, "null path");
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(CTM_E_INVALID, std::string("cannot write ") + path);
-  static const char* names[3] = {"gemm", "ts", "splitk"};
+  static const char* names[TILE_KINDS] = {"gemm", "ts", "splitk", "corner"};
   auto ent = tile_entries();
   std::fprintf(f, "[\n");
   for (size_t i = 0; i < ent.size(); ++i) {

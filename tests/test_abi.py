@@ -177,8 +177,8 @@ lib = b.load(tile_table=False)
 lib.ctm_tile_table_clear()
 src, dst, bad = sys.argv[1], sys.argv[2], sys.argv[3]
 n = ctypes.c_int32()
-assert lib.ctm_tile_table_load(src.encode(), ctypes.byref(n)) == 0 and n.value == 3
-assert lib.ctm_tile_table_save(dst.encode(), ctypes.byref(n)) == 0 and n.value == 3
+assert lib.ctm_tile_table_load(src.encode(), ctypes.byref(n)) == 0 and n.value == 4
+assert lib.ctm_tile_table_save(dst.encode(), ctypes.byref(n)) == 0 and n.value == 4
 print(lib.ctm_tile_table_load(bad.encode(), ctypes.byref(n)))
 ''' % {"root": ROOT}
     entries = [
@@ -186,6 +186,8 @@ print(lib.ctm_tile_table_load(bad.encode(), ctypes.byref(n)))
         {"kernel": "gemm", "ta": 0, "tc": 0, "ak": 1, "bk": 0, "groups": 0, "M": 48, "N": 1728, "K": 48, "variant": 3},
         {"kernel": "splitk", "ta": 0, "tc": 0, "ak": 0, "bk": 1, "groups": 2, "M": 48, "N": 48, "K": 1728,
          "variant": 0},
+        {"kernel": "corner", "ta": 2, "tc": 1, "ak": 1, "bk": 1, "groups": 8, "M": 2304, "N": 1296, "K": 1296,
+         "variant": 2},
     ]
     src, dst, bad = tmp_path / "a.json", tmp_path / "b.json", tmp_path / "c.json"
     src.write_text("[\n" + ",\n".join(json.dumps(e) for e in entries) + "\n]\n")

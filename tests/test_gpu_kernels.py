@@ -207,9 +207,9 @@ print(json.dumps(out))
 
 def test_packed_layouts_bitwise(gpu):
     """The moves with the double layer and the intermediate Y in the packed
-    fragment layouts (the default), with only the double layer packed, and
-    with both row-major give bitwise-equal spectra and norms after two bf16
-    sweeps: the benchmark workload (d = 8, D = 6, chi = 144, live extent
+    fragment layouts (the default, and with 128, 192 and 256 rows per
+    work-group forced), with only the double layer packed, and with both
+    row-major give bitwise-equal spectra and norms after two bf16 sweeps: the benchmark workload (d = 8, D = 6, chi = 144, live extent
     below chi), D = 4 (K = 256, whole K steps) and chi = 36 (a live extent
     that is not a multiple of 8 sends the second product to the generic GEMM,
     so only the double layer is packed)."""
@@ -220,7 +220,8 @@ def test_packed_layouts_bitwise(gpu):
     code = PACKED_RUN % {"root": root, "tests": os.path.join(root, "tests")}
     res = {}
     for name, extra in (("packed", {}), ("b_only", {"CTM_CORNER_A": "rowmajor"}),
-                        ("rowmajor", {"CTM_CORNER_B": "rowmajor"})):
+                        ("rowmajor", {"CTM_CORNER_B": "rowmajor"}), ("rows128", {"CTM_CORNER_ROWS": "128"}),
+                        ("rows192", {"CTM_CORNER_ROWS": "192"}), ("rows256", {"CTM_CORNER_ROWS": "256"})):
         env = dict(os.environ)
         env.update(extra)
         print("packed layouts run", name, flush=True)
@@ -228,4 +229,5 @@ def test_packed_layouts_bitwise(gpu):
         assert r.returncode == 0, r.stderr[-2000:]
         res[name] = json.loads(r.stdout.strip().splitlines()[-1])
     print(res)
-    assert res["packed"] == res["b_only"] == res["rowmajor"]
+    for name in res:
+        assert res[name] == res["rowmajor"], name
