@@ -105,8 +105,26 @@ typedef struct {
                               tensor one at a time, never forming the D^8 double
                               layer in the contraction: 4 chi^2 d D^6 instead of
                               2 chi^2 D^8 flop per corner, the route to large D
-                              (Sec. II D).  CTM_FP64 or CTM_FP32 only
-                              (default 0)                                         */
+                              (Sec. II D); any precision (default 0)              */
+  int32_t complex_tensors; /* 1: the kets are complex (Sec. II A: d D^4 complex
+                              coefficients per tensor): A_dev[t] holds float64
+                              [d][D][D][D][D][2] (real, imaginary interleaved),
+                              B_dev must be NULL (the bra is the conjugate of
+                              the ket).  The double layer sum_s A_s (x) conj A_s
+                              is stored in a real form: on every doubled leg
+                              (x, x') the unitary basis slot (x, x) <- e_(x,x),
+                              for x < x' slot (x, x') <- (e_(x,x') + e_(x',x))
+                              / sqrt 2 and slot (x', x) <- i (e_(x,x') -
+                              e_(x',x)) / sqrt 2 on the down and right legs, the
+                              conjugate basis on the up and left legs, which
+                              makes every tensor of the network real without
+                              changing any contraction.  Spectra, norms and
+                              ctm_expect are those of the complex state; the
+                              environment (ctm_env_export) is in the real pair
+                              basis; density matrices come from
+                              ctm_rdm_complex.  Not with single_layer,
+                              ctm_fidelity or ctm_boundary_spectrum
+                              (CTM_E_INVALID) (default 0)                         */
 } ctm_config;
 
 /* Fills *cfg with the defaults above for one instance (caller sets the rest). */
@@ -222,6 +240,15 @@ ctm_status ctm_norm(ctm_ctx ctx, int32_t inst, double* kappa_out);
  */
 ctm_status ctm_rdm(ctm_ctx ctx, int32_t inst, int32_t x, int32_t y,
                    int32_t vertical, double* rho_host, double* herm_defect);
+
+/* The same for complex kets (complex_tensors = 1): rho_host float64
+ * [(s1,s2)][(s1',s2')][2] (real, imaginary interleaved), divided by its
+ * trace; herm_defect (may be NULL): ||rho - rho^H||_F / ||rho||_F.  The
+ * physical pairs are contracted in the real pair basis of the legs and
+ * transformed back.  CTM_E_INVALID for a context of real tensors (and
+ * ctm_rdm for a complex one).  Syncs. */
+ctm_status ctm_rdm_complex(ctm_ctx ctx, int32_t inst, int32_t x, int32_t y, int32_t vertical, double* rho_host,
+                           double* herm_defect);
 
 /*
  * Expectation value tr(rho h) of a two-site operator on the same bond, with

@@ -22,7 +22,8 @@ INIT = {"trivial": 0, "diag": 1}
 
 EXPORTS = [
     "ctm_config_default", "ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge",
-    "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_bytes",
+    "ctm_spectra", "ctm_set_corner_spectra", "ctm_norm", "ctm_rdm", "ctm_rdm_complex", "ctm_expect", "ctm_fidelity",
+    "ctm_env_bytes",
     "ctm_env_export", "ctm_env_import", "ctm_checkpoint_bytes", "ctm_checkpoint_save",
     "ctm_checkpoint_load", "ctm_set_metrics", "ctm_set_timing", "ctm_get_timing", "ctm_destroy",
     "ctm_last_error", "ctm_tile_table_load", "ctm_tile_table_save", "ctm_tile_table_tune",
@@ -43,6 +44,7 @@ class CtmConfig(ctypes.Structure):
         ("svd_cutoff", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
         ("concurrent_classes", ctypes.c_int32), ("single_layer", ctypes.c_int32),
+        ("complex_tensors", ctypes.c_int32),
     ]
 
 
@@ -86,6 +88,7 @@ def load(path=LIB_PATH, tile_table=True):
     lib.ctm_set_corner_spectra.argtypes = [VP, I32, P(F64)]
     lib.ctm_set_corner_spectra.restype = ctypes.c_int
     lib.ctm_rdm.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
+    lib.ctm_rdm_complex.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_expect.argtypes = [VP, I32, I32, I32, I32, P(F64), P(F64)]
     lib.ctm_fidelity.argtypes = [cfgp, dpp, dpp, VP, SZ, VP, F64, I32, P(F64), P(F64), P(I32)]
     lib.ctm_boundary_workspace_size.argtypes = [VP, I32, I32, I32, P(SZ)]
@@ -145,7 +148,7 @@ def load(path=LIB_PATH, tile_table=True):
     lib.ctm_tile_table_clear.argtypes = []
     lib.ctm_tile_table_clear.restype = ctypes.c_int
     for name in ("ctm_workspace_size", "ctm_init", "ctm_move", "ctm_converge", "ctm_spectra",
-                 "ctm_norm", "ctm_rdm", "ctm_expect", "ctm_fidelity", "ctm_env_export",
+                 "ctm_norm", "ctm_rdm", "ctm_rdm_complex", "ctm_expect", "ctm_fidelity", "ctm_env_export",
                  "ctm_env_import", "ctm_checkpoint_save", "ctm_checkpoint_load", "ctm_set_timing",
                  "ctm_get_timing"):
         getattr(lib, name).restype = ctypes.c_int
@@ -168,7 +171,7 @@ def _i32arr(v):
 
 def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=16,
                 max_iters=30, resid_tol=1e-13, cutoff=1e-12, seed=12345, use_graph=False,
-                autotune=True, concurrent_classes=True, single_layer=False):
+                autotune=True, concurrent_classes=True, single_layer=False, complex_tensors=False):
     """ctm_config plus the ctypes arrays it points into (keep both alive)."""
     lib = load()
     cfg = CtmConfig()
@@ -188,6 +191,7 @@ def make_config(Lx, Ly, pattern, n_tensors, d, D, chi, prec="fp64", oversample=1
     cfg.autotune = int(bool(autotune))
     cfg.concurrent_classes = int(bool(concurrent_classes))
     cfg.single_layer = int(bool(single_layer))
+    cfg.complex_tensors = int(bool(complex_tensors))
     return cfg, keep
 
 
@@ -198,7 +202,10 @@ def workspace_size(cfg):
     return n.value
 
 
-def _dev_tensors(torch, arrays, device):
+def _dev_tensors(torch, arrays, device, cplx=False):
+    # complex tensors travel as float64 (real, imaginary) pairs
+    if cplx:
+        arrays = [np.ascontiguousarray(a, dtype=np.complex128).view(np.float64) for a in arrays]
     ts = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device) for a in arrays]
     ptrs = (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
     return ts, ptrs
@@ -228,14 +235,19 @@ class CTM:
         d = [k[0].shape[0] for k in kets]
         D = [k[0].shape[1] for k in kets]
         self.Lx, self.Ly, self.d, self.D, self.chi = Lx, Ly, d, D, list(chis)
-        self.cfg, self._keep = make_config(Lx, Ly, pattern, nt, d, D, chis, prec, **solver)
+        # complex kets: the bra is their conjugate (no separate bras)
+        self.complex = any(np.iscomplexobj(a) for inst in kets for a in inst)
+        if self.complex and bras is not None:
+            raise ValueError("complex kets take no bras (the bra is the conjugate of the ket)")
+        self.cfg, self._keep = make_config(Lx, Ly, pattern, nt, d, D, chis, prec, complex_tensors=self.complex,
+                                           **solver)
         self.device = torch.device(device)
         nbytes = workspace_size(self.cfg)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         off = (-base) % 256
         flat_k = [a for inst in kets for a in inst]
-        self._kt, kp = _dev_tensors(torch, flat_k, self.device)
+        self._kt, kp = _dev_tensors(torch, flat_k, self.device, self.complex)
         bp = None
         if bras is not None:
             flat_b = [a for inst in bras for a in inst]
@@ -288,9 +300,16 @@ class CTM:
         return v.value
 
     def rdm(self, x, y, vertical=False, inst=0):
+        """(rho, hermiticity defect); rho complex for complex kets."""
         m = self.d[inst] ** 2
-        out = np.zeros((m, m))
         h = ctypes.c_double()
+        if self.complex:
+            out = np.zeros((m, m), dtype=np.complex128)
+            _check(load().ctm_rdm_complex(self.ctx, inst, x, y, int(vertical),
+                                          out.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.byref(h)))
+            return out, h.value
+        out = np.zeros((m, m))
         _check(load().ctm_rdm(self.ctx, inst, x, y, int(vertical),
                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
         return out, h.value
@@ -384,6 +403,8 @@ def fidelity(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp64", tol=
     sweeps of the three CTM runs, whether all three converged)."""
     import torch
     lib = load()
+    if any(np.iscomplexobj(a) for a in list(A_list) + list(B_list)):
+        raise ValueError("fidelity needs real tensors (the mixed network of complex states has no real form)")
     if pattern is None:
         pattern = [0] * (Lx * Ly)
     d = [A_list[0].shape[0]]
@@ -413,6 +434,8 @@ def fidelity_noalloc(A_list, B_list, Lx=1, Ly=1, pattern=None, chi=16, prec="fp6
     are made here."""
     import torch
     lib = load()
+    if any(np.iscomplexobj(a) for a in list(A_list) + list(B_list)):
+        raise ValueError("fidelity needs real tensors (the mixed network of complex states has no real form)")
     if pattern is None:
         pattern = [0] * (Lx * Ly)
     cfg, keep = make_config(Lx, Ly, pattern, len(A_list), [A_list[0].shape[0]], [A_list[0].shape[1]], [chi],

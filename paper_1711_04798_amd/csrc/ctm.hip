@@ -177,6 +177,7 @@ struct Inst {
   bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
   void* bTp[MAXT][4] = {};       // bf16 mode: bT in the corner kernel's packed fragment layout
+  double* Ac[MAXT] = {};         // complex kets (real, imaginary interleaved)
   // single-layer mode: the ket (Sk) and bra (Sb) tensor of each rotation in
   // the working type, legs [L'][U'][s][D'][R'] of the rotated frame
   void* Sk[MAXT][4] = {};
@@ -365,6 +366,7 @@ void plan(ctm_ctx_s& x, Arena& ar) {
     for (int t = 0; t < x.ntens; ++t) {
       I.A[t] = ar.take<double>(t5);
       I.B[t] = ar.take<double>(t5);
+      if (x.cfg.complex_tensors) I.Ac[t] = ar.take<double>(2 * t5);
       for (int r = 0; r < 4; ++r) {
         I.b64[t][r] = ar.take<double>(a8);
         // the single-layer mode contracts with Sk / Sb instead of a working copy
@@ -492,7 +494,8 @@ void plan(ctm_ctx_s& x, Arena& ar) {
   O.big = big;
   O.t0 = ar.take<double>(big); O.t1 = ar.take<double>(big);
   O.t2 = ar.take<double>(big); O.t3 = ar.take<double>(big);
-  O.rho = ar.take<double>(d * d * d * d * 2);
+  // rho, then the raw contraction (complex tensors: a complex rho first)
+  O.rho = ar.take<double>(d * d * d * d * (x.cfg.complex_tensors ? 3 : 2));
   O.red = ar.take<double>(256);
   O.vals = ar.take<double>(16);
 }
@@ -1720,6 +1723,9 @@ ctm_status validate(const ctm_config* c) {
   for (int i = 0; i < c->Lx * c->Ly; ++i)
     if (c->pattern[i] < 0 || c->pattern[i] >= c->n_tensors) return fail(CTM_E_INVALID, "pattern entry out of range");
   if (c->prec < 0 || c->prec > 2) return fail(CTM_E_INVALID, "prec");
+  if (c->complex_tensors != 0 && c->complex_tensors != 1) return fail(CTM_E_INVALID, "complex_tensors must be 0 or 1");
+  if (c->complex_tensors && c->single_layer)
+    return fail(CTM_E_INVALID, "complex tensors run on the real form of the double layer, not the single-layer route");
   for (int i = 0; i < c->n_inst; ++i) {
     int d = c->d[i], D = c->D[i], chi = c->chi[i];
     if (d < 1 || D < 1 || chi < 1 || d > 64 || D > 16) return fail(CTM_E_INVALID, "d in 1..64, D in 1..16, chi >= 1");
@@ -2362,6 +2368,87 @@ __global__ void rdm_finalize_kernel(const double* __restrict__ raw, int d1, int 
   }
 }
 
+// Complex kets: raw[sigma1, sigma2] is the contraction in the real basis V of
+// the physical pairs (slot (x, x) <- e_(x,x); for x < x' slot (x, x') <-
+// (e_(x,x') + e_(x',x)) / sqrt 2 and slot (x', x) <- i (e_(x,x') - e_(x',x)) /
+// sqrt 2).  The pair p = (s, s') comes back as sum over sigma of
+// conj(V[sigma, p]) raw[sigma, .]:  x < x': raw[upper] / sqrt 2 - i raw[lower] /
+// sqrt 2;  x > x': raw[upper] / sqrt 2 + i raw[lower] / sqrt 2.
+// rho[(s1,s2),(s1',s2')] (complex, interleaved) = R[(s1,s1'),(s2,s2')] / trace;
+// out3 = {hermiticity defect ||rho - rho^H|| / ||rho||, Re tr(rho h), trace}.
+__device__ __forceinline__ int back_terms(int x, int xp, int d, int* slot, double* cr, double* ci) {
+  const double h = 0.70710678118654752440;
+  if (x == xp) { slot[0] = x * d + x; cr[0] = 1.0; ci[0] = 0.0; return 1; }
+  const int lo = x < xp ? x : xp, hi = x < xp ? xp : x;
+  slot[0] = lo * d + hi; cr[0] = h; ci[0] = 0.0;          // upper slot
+  slot[1] = hi * d + lo; cr[1] = 0.0; ci[1] = x < xp ? -h : h;  // lower slot
+  return 2;
+}
+
+__global__ void rdm_cplx_finalize_kernel(const double* __restrict__ raw, int d, double* __restrict__ rho,
+                                         const double* __restrict__ h, double* __restrict__ out3) {
+  __shared__ double red[256];
+  __shared__ double s_tr;
+  const int m = d * d, m2 = m * m;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int s1 = i / d, s2 = i % d;
+    tr += raw[(s1 * d + s1) * m + s2 * d + s2];
+  }
+  red[threadIdx.x] = tr;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s_tr = red[0];
+  __syncthreads();
+  const double t = s_tr;
+  for (int e = threadIdx.x; e < m2; e += blockDim.x) {
+    const int r = e / m, cc = e % m;
+    const int s1 = r / d, s2 = r % d, p1 = cc / d, p2 = cc % d;
+    int sa[2], sb[2];
+    double ar[2], ai[2], br[2], bi[2];
+    const int na = back_terms(s1, p1, d, sa, ar, ai), nb = back_terms(s2, p2, d, sb, br, bi);
+    double vr = 0.0, vi = 0.0;
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const double w = raw[(int64_t)sa[i] * m + sb[j]];
+        const double cr = ar[i] * br[j] - ai[i] * bi[j], ci = ar[i] * bi[j] + ai[i] * br[j];
+        vr += cr * w;
+        vi += ci * w;
+      }
+    rho[2 * e] = vr / t;
+    rho[2 * e + 1] = vi / t;
+  }
+  __syncthreads();
+  double num = 0.0, den = 0.0, ev = 0.0;
+  for (int e = threadIdx.x; e < m2; e += blockDim.x) {
+    const int r = e / m, cc = e % m;
+    const double xr = rho[2 * e], xi = rho[2 * e + 1];
+    const double yr = rho[2 * (cc * m + r)], yi = -rho[2 * (cc * m + r) + 1];  // (rho^H)[r][cc]
+    num += (xr - yr) * (xr - yr) + (xi - yi) * (xi - yi);
+    den += xr * xr + xi * xi;
+    if (h) ev += xr * h[cc * m + r];
+  }
+  double vals[3] = {num, den, ev};
+  for (int q = 0; q < 3; ++q) {
+    __syncthreads();
+    red[threadIdx.x] = vals[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    vals[q] = red[0];
+  }
+  if (threadIdx.x == 0) {
+    out3[0] = vals[1] > 0 ? sqrt(vals[0] / vals[1]) : 0.0;
+    out3[1] = vals[2];
+    out3[2] = t;
+  }
+}
+
 // Two-site density matrix of the bond from (x, y) to the right (vertical = 0)
 // or lower neighbour, left in O.rho (d^2 x d^2) with O.vals[4..6] = {herm
 // defect, tr(rho h), trace}.  Built from left blocks with open physical legs:
@@ -2383,6 +2470,9 @@ ctm_status rdm(ctm_ctx_s& x, Inst& I, int sx, int sy, int vertical, const double
   const int D = I.D, d = I.d;
   const int64_t t5s = (int64_t)D * D * D * D;  // one physical slice of A
   const int64_t blk = c * D2 * c;
+  const bool cplx = x.cfg.complex_tensors != 0;
+  const int64_t d4 = (int64_t)d * d * d * d;
+  double* raw = O.rho + (cplx ? 2 : 1) * d4;
   for (int side = 0; side < 2; ++side) {
     int kk = side == 0 ? k : (k + 2) % 4;
     int px = side == 0 ? xp : rx, py = side == 0 ? yp : ry;
@@ -2392,7 +2482,9 @@ ctm_status rdm(ctm_ctx_s& x, Inst& I, int sx, int sy, int vertical, const double
     for (int s1 = 0; s1 < d; ++s1)
       for (int s2 = 0; s2 < d; ++s2) {
         double* outs[4] = {O.ab, O.ab + a8, O.ab + 2 * a8, O.ab + 3 * a8};
-        HIPCHK(double_layer(s, I.A[t] + s1 * t5s, I.B[t] + s2 * t5s, 1, D, outs, 0));
+        // complex kets: the real open double layer of physical slot (s1, s2)
+        if (cplx) HIPCHK(double_layer_cplx(s, I.Ac[t], d, D, s1 * d + s2, outs));
+        else HIPCHK(double_layer(s, I.A[t] + s1 * t5s, I.B[t] + s2 * t5s, 1, D, outs, 0));
         CHK(left_block(x, I, kk, px, py, O.ab + (kk % 4) * a8, dst + (int64_t)(s1 * d + s2) * blk,
                        s1 == 0 && s2 == 0));
       }
@@ -2405,12 +2497,15 @@ ctm_status rdm(ctm_ctx_s& x, Inst& I, int sx, int sy, int vertical, const double
   }
   // raw[(s1,s1'),(s2,s2')] = Lall . Rp^T
   CHK(gemm1(s, F64, F64, (int64_t)d * d, (int64_t)d * d, blk, rowmajor(blk), O.Lall, transposed(rowmajor(blk)),
-            O.Rp, rowmajor((int64_t)d * d), O.rho + (int64_t)d * d * d * d));
-  HIPCHK(spans({{O.rho, (size_t)2 * d * d * d * d * 8}, {hdev, hdev ? (size_t)d * d * d * d * 8 : 0},
+            O.Rp, rowmajor((int64_t)d * d), raw));
+  HIPCHK(spans({{O.rho, (size_t)(cplx ? 3 : 2) * d4 * 8}, {hdev, hdev ? (size_t)d4 * 8 : 0},
                 {O.vals + 4, 3 * 8}}, "rdm finalize"));
-  if (!dry_run())
-    hipLaunchKernelGGL(rdm_finalize_kernel, dim3(1), dim3(256), 0, s, O.rho + (int64_t)d * d * d * d, d, d,
-                       O.rho, hdev, O.vals + 4);
+  if (!dry_run()) {
+    if (cplx)
+      hipLaunchKernelGGL(rdm_cplx_finalize_kernel, dim3(1), dim3(256), 0, s, raw, d, O.rho, hdev, O.vals + 4);
+    else
+      hipLaunchKernelGGL(rdm_finalize_kernel, dim3(1), dim3(256), 0, s, raw, d, d, O.rho, hdev, O.vals + 4);
+  }
   HIPCHK(last_err());
   return CTM_OK;
 }
@@ -2544,18 +2639,26 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
   for (int i = 0; i < x->ninst; ++i) {
     Inst& I = x->inst[i];
     const size_t t5 = (size_t)I.d * I.D2 * I.D2;
+    const bool cplx = x->cfg.complex_tensors != 0;
     for (int t = 0; t < x->ntens; ++t) {
       const double* a = A_dev[i * x->ntens + t];
       const double* b = B_dev ? B_dev[i * x->ntens + t] : a;
       if (!a || !b) return cleanup(fail(CTM_E_INVALID, "null tensor pointer"));
+      if (cplx) {
+        // the bra of a complex ket is its conjugate
+        if (b != a) return cleanup(fail(CTM_E_INVALID, "complex tensors: pass no bra tensors (the bra is the conjugate)"));
+        if (d2d(I.Ac[t], a, 2 * t5 * 8, x->stream) != hipSuccess) return cleanup(fail(CTM_E_HIP, "tensor copy failed"));
+        continue;
+      }
       if (d2d(I.A[t], a, t5 * 8, x->stream) != hipSuccess ||
           d2d(I.B[t], b, t5 * 8, x->stream) != hipSuccess)
         return cleanup(fail(CTM_E_HIP, "tensor copy failed"));
     }
     if (dmemset(I.flag, 0, 16, x->stream) != hipSuccess) return cleanup(fail(CTM_E_HIP, "memset"));
     for (int t = 0; t < x->ntens; ++t) {
-      if (nonfinite(x->stream, I.A[t], (int64_t)t5, I.flag) != hipSuccess ||
-          nonfinite(x->stream, I.B[t], (int64_t)t5, I.flag) != hipSuccess)
+      if (cplx ? nonfinite(x->stream, I.Ac[t], (int64_t)(2 * t5), I.flag) != hipSuccess
+               : (nonfinite(x->stream, I.A[t], (int64_t)t5, I.flag) != hipSuccess ||
+                  nonfinite(x->stream, I.B[t], (int64_t)t5, I.flag) != hipSuccess))
         return cleanup(fail(CTM_E_HIP, "nonfinite check"));
     }
     int hflag = 0;
@@ -2564,7 +2667,8 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
       return cleanup(fail(CTM_E_HIP, "flag readback"));
     if (hflag) return cleanup(fail(CTM_E_NONFINITE, "non-finite entry in a PEPS tensor"));
     for (int t = 0; t < x->ntens; ++t) {
-      if (double_layer(x->stream, I.A[t], I.B[t], I.d, I.D, I.b64[t], 0) != hipSuccess)
+      if ((cplx ? double_layer_cplx(x->stream, I.Ac[t], I.d, I.D, -1, I.b64[t])
+                : double_layer(x->stream, I.A[t], I.B[t], I.d, I.D, I.b64[t], 0)) != hipSuccess)
         return cleanup(fail(CTM_E_HIP, "double layer"));
       if (x->wt != F64 && !x->cfg.single_layer)
         for (int r = 0; r < 4; ++r)
@@ -2853,12 +2957,29 @@ ctm_status ctm_norm(ctm_ctx x, int32_t inst, double* kap) {
 ctm_status ctm_rdm(ctm_ctx x, int32_t inst, int32_t sx, int32_t sy, int32_t vertical, double* rho_host,
                    double* herm) {
   if (!x || !rho_host || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  if (x->cfg.complex_tensors) return fail(CTM_E_INVALID, "complex tensors: the density matrix is complex (ctm_rdm_complex)");
   RegGuard guard(&x->reg);
   Inst& I = x->inst[inst];
   CHK(rdm(*x, I, pmod(sx, x->Lx), pmod(sy, x->Ly), vertical ? 1 : 0, nullptr));
   const int m = I.d * I.d;
   double v3[3];
   HIPCHK(d2h(rho_host, x->obs.rho, (size_t)m * m * 8, x->stream));
+  HIPCHK(d2h(v3, x->obs.vals + 4, 3 * 8, x->stream));
+  HIPCHK(ssync(x->stream));
+  if (herm) *herm = v3[0];
+  return CTM_OK;
+}
+
+ctm_status ctm_rdm_complex(ctm_ctx x, int32_t inst, int32_t sx, int32_t sy, int32_t vertical, double* rho_host,
+                           double* herm) {
+  if (!x || !rho_host || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  if (!x->cfg.complex_tensors) return fail(CTM_E_INVALID, "real tensors: use ctm_rdm");
+  RegGuard guard(&x->reg);
+  Inst& I = x->inst[inst];
+  CHK(rdm(*x, I, pmod(sx, x->Lx), pmod(sy, x->Ly), vertical ? 1 : 0, nullptr));
+  const int m = I.d * I.d;
+  double v3[3];
+  HIPCHK(d2h(rho_host, x->obs.rho, (size_t)m * m * 16, x->stream));
   HIPCHK(d2h(v3, x->obs.vals + 4, 3 * 8, x->stream));
   HIPCHK(ssync(x->stream));
   if (herm) *herm = v3[0];
@@ -3103,6 +3224,8 @@ ctm_status ctm_fidelity(const ctm_config* cfg, const double* const* A_dev, const
                         double* d_out, double* ln_d_out, int32_t* sweeps_out) {
   if (!cfg || !A_dev || !B_dev || !d_out) return fail(CTM_E_INVALID, "args");
   if (cfg->n_inst != 1) return fail(CTM_E_INVALID, "fidelity needs n_inst == 1");
+  // the mixed network <B|A> of complex states has no real form
+  if (cfg->complex_tensors) return fail(CTM_E_INVALID, "fidelity needs real tensors");
   double kap[3];
   const double* const* kets[3] = {A_dev, B_dev, A_dev};
   const double* const* bras[3] = {A_dev, B_dev, B_dev};
@@ -3170,6 +3293,7 @@ ctm_status ctm_fidelity_noalloc(const ctm_config* cfg, const double* const* A_de
                                 void* stream, double tol, int32_t max_sweeps, double* d_out, double* ln_d_out,
                                 int32_t* sweeps_out) {
   if (!cfg || !A_dev || !B_dev || !d_out) return fail(CTM_E_INVALID, "args");
+  if (cfg->complex_tensors) return fail(CTM_E_INVALID, "fidelity needs real tensors");
   // no graph instantiation and no tile timing (both create runtime objects)
   ctm_config c = *cfg;
   c.use_graph = 0;
@@ -3396,6 +3520,9 @@ ctm_status ctm_internal_fail(ctm_status s, const char* msg) { return fail(s, msg
 
 ctm_status ctm_internal_edge_ring(ctm_ctx x, int inst, int column, CtmEdgeRing* out) {
   if (!x || !out || inst < 0 || inst >= x->ninst) return fail(CTM_E_INVALID, "args");
+  // the boundary operators act on the ket and bra bond indices separately;
+  // with complex kets the edges hold them in the real pair basis
+  if (x->cfg.complex_tensors) return fail(CTM_E_INVALID, "the boundary operator needs real tensors");
   Inst& I = x->inst[inst];
   out->stream = x->stream;
   out->chi = I.chi;

@@ -207,6 +207,12 @@ hipError_t convert(hipStream_t s, int tin, const void* in, int tout, void* out, 
 hipError_t double_layer(hipStream_t s, const double* A, const double* B, int d,
                         int D, double* out_rot[4], int64_t out_layout);
 
+// Real form of the double layer of a complex ket Ac ([d][D^4] complex,
+// interleaved; the bra is its conjugate) in the basis V-bar (up, left), V
+// (down, right) of the doubled legs (see kernels.hip); sigma >= 0 gives the
+// open double layer of physical slot sigma (physical pair in basis V).
+hipError_t double_layer_cplx(hipStream_t s, const double* Ac, int d, int D, int sigma, double* out_rot[4]);
+
 // Sum of squares of n float64 into *out (deterministic two-pass).
 hipError_t sumsq(hipStream_t s, const double* x, int64_t n, double* partial, double* out);
 // x *= 1/sqrt(*nrm2) (if > 0) for n float64.

@@ -713,6 +713,127 @@ hipError_t double_layer(hipStream_t s, const double* A, const double* B, int d, 
 }
 
 // ---------------------------------------------------------------------------
+// Real form of the double layer of a complex ket (bra = its conjugate).
+// a = sum_s A_s (x) conj(A_s) satisfies conj(a) = S a S, S swapping ket and
+// bra on every leg.  On each doubled leg (x, x') the unitary basis change V
+//   slot (x, x)            <- e_(x,x)
+//   slot (x, x'), x < x'   <- (e_(x,x') + e_(x',x)) / sqrt 2
+//   slot (x', x), x < x'   <- i (e_(x,x') - e_(x',x)) / sqrt 2
+// (V-bar: the conjugate coefficients) maps such tensors to real ones.  The
+// right and down legs take V, the left and up legs V-bar: a bond pairs a V
+// leg with a V-bar leg and V^T V-bar = 1, so every contraction of the network
+// keeps its value and the whole CTM runs on real tensors.
+//   sigma < 0: out = real part of (V-bar_u V-bar_l V_d V_r) a (the imaginary
+//              part vanishes up to rounding);
+//   sigma >= 0: the open double layer of physical slot sigma for the density
+//              matrices: sum over the physical pairs (s, s') of slot sigma
+//              (basis V on the physical pair) of A_s (x) conj(A_s'), legs
+//              transformed as above (real as well).
+// Ac is [d][D][D][D][D] complex (real, imaginary interleaved).  Rotations as
+// in double_layer.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double A_cr(const double* Ac, int64_t i) { return Ac[2 * i]; }
+__device__ __forceinline__ double A_ci(const double* Ac, int64_t i) { return Ac[2 * i + 1]; }
+
+struct PairTerms {
+  int n;
+  int k[2], b[2];      // ket and bra index of each term
+  double cr[2], ci[2];  // complex coefficient
+};
+
+__device__ __forceinline__ PairTerms pair_terms(int slot, int D, bool conj_basis) {
+  const double h = 0.70710678118654752440;
+  const int p = slot / D, q = slot - p * D;
+  PairTerms t;
+  if (p == q) {
+    t.n = 1; t.k[0] = p; t.b[0] = p; t.cr[0] = 1.0; t.ci[0] = 0.0;
+  } else if (p < q) {
+    t.n = 2;
+    t.k[0] = p; t.b[0] = q; t.cr[0] = h; t.ci[0] = 0.0;
+    t.k[1] = q; t.b[1] = p; t.cr[1] = h; t.ci[1] = 0.0;
+  } else {
+    // lower slot of the pair (q, p), q < p: i (e_(q,p) - e_(p,q)) / sqrt 2
+    const double sg = conj_basis ? -1.0 : 1.0;
+    t.n = 2;
+    t.k[0] = q; t.b[0] = p; t.cr[0] = 0.0; t.ci[0] = sg * h;
+    t.k[1] = p; t.b[1] = q; t.cr[1] = 0.0; t.ci[1] = -sg * h;
+  }
+  return t;
+}
+
+__global__ void double_layer_cplx_kernel(const double* __restrict__ Ac, int d, int D, int sigma, double* o0,
+                                         double* o1, double* o2, double* o3) {
+  const int D2 = D * D;
+  const int64_t n = (int64_t)D2 * D2 * D2 * D2;
+  const int k = blockIdx.y;
+  double* out = k == 0 ? o0 : (k == 1 ? o1 : (k == 2 ? o2 : o3));
+  const int64_t sR = 1, sDn = D, sL = (int64_t)D * D, sU = (int64_t)D * D * D, sS = (int64_t)D * D * D * D;
+  PairTerms ph;
+  if (sigma >= 0) ph = pair_terms(sigma, d, false);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = e;
+    const int Rp = rem % D2; rem /= D2;
+    const int Dp = rem % D2; rem /= D2;
+    const int Up = rem % D2; rem /= D2;
+    const int Lp = (int)rem;
+    int U, L, Dn, R;
+    if (k == 0) { U = Up; L = Lp; Dn = Dp; R = Rp; }
+    else if (k == 1) { U = Lp; L = Dp; Dn = Rp; R = Up; }
+    else if (k == 2) { U = Dp; L = Rp; Dn = Up; R = Lp; }
+    else { U = Rp; L = Up; Dn = Lp; R = Dp; }
+    const PairTerms tu = pair_terms(U, D, true), tl = pair_terms(L, D, true);
+    const PairTerms td = pair_terms(Dn, D, false), tr = pair_terms(R, D, false);
+    double ar = 0.0, ai = 0.0;
+    for (int a0 = 0; a0 < tu.n; ++a0)
+      for (int a1 = 0; a1 < tl.n; ++a1)
+        for (int a2 = 0; a2 < td.n; ++a2)
+          for (int a3 = 0; a3 < tr.n; ++a3) {
+            // coefficient product
+            double cr = tu.cr[a0], ci = tu.ci[a0], xr, xi;
+            xr = cr * tl.cr[a1] - ci * tl.ci[a1]; xi = cr * tl.ci[a1] + ci * tl.cr[a1]; cr = xr; ci = xi;
+            xr = cr * td.cr[a2] - ci * td.ci[a2]; xi = cr * td.ci[a2] + ci * td.cr[a2]; cr = xr; ci = xi;
+            xr = cr * tr.cr[a3] - ci * tr.ci[a3]; xi = cr * tr.ci[a3] + ci * tr.cr[a3]; cr = xr; ci = xi;
+            const int64_t oa = tu.k[a0] * sU + tl.k[a1] * sL + td.k[a2] * sDn + tr.k[a3] * sR;
+            const int64_t ob = tu.b[a0] * sU + tl.b[a1] * sL + td.b[a2] * sDn + tr.b[a3] * sR;
+            // v = sum over physical pairs of A_s[oa] conj(A_s'[ob])
+            double vr = 0.0, vi = 0.0;
+            const int np = sigma >= 0 ? ph.n : d;
+            for (int j = 0; j < np; ++j) {
+              const int s1 = sigma >= 0 ? ph.k[j] : j, s2 = sigma >= 0 ? ph.b[j] : j;
+              const double pr = A_cr(Ac, s1 * sS + oa), pi = A_ci(Ac, s1 * sS + oa);
+              const double qr = A_cr(Ac, s2 * sS + ob), qi = -A_ci(Ac, s2 * sS + ob);
+              double tr_ = pr * qr - pi * qi, ti_ = pr * qi + pi * qr;
+              if (sigma >= 0) {
+                const double wr = ph.cr[j], wi = ph.ci[j];
+                const double yr = wr * tr_ - wi * ti_, yi = wr * ti_ + wi * tr_;
+                tr_ = yr; ti_ = yi;
+              }
+              vr += tr_; vi += ti_;
+            }
+            ar += cr * vr - ci * vi;
+            ai += cr * vi + ci * vr;
+          }
+    (void)ai;
+    out[e] = ar;
+  }
+}
+
+hipError_t double_layer_cplx(hipStream_t s, const double* Ac, int d, int D, int sigma, double* out_rot[4]) {
+  const int64_t n = (int64_t)D * D * D * D * D * D * D * D;
+  const size_t t5 = (size_t)d * D * D * D * D * 16;
+  if (sigma >= d * d) return hipErrorInvalidValue;
+  if (!span_ok(Ac, t5, "complex double layer A")) return hipErrorInvalidValue;
+  for (int r = 0; r < 4; ++r)
+    if (!span_ok(out_rot[r], n * 8, "complex double layer out")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(double_layer_cplx_kernel, dim3((unsigned)blocks, 4), dim3(256), 0, s, Ac, d, D, sigma,
+                     out_rot[0], out_rot[1], out_rot[2], out_rot[3]);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

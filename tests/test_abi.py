@@ -97,7 +97,8 @@ for case in %(cases)r:
     eh = (ctypes.c_char * eb)()
     st.append(lib.ctm_env_export(ctx, 0, eh, eb))
     st.append(lib.ctm_env_import(ctx, 0, eh, eb))
-    if bnv or (Ly in (1, 2) and D[0] <= 4):
+    cx = extra.get("complex_tensors", False)
+    if not cx and (bnv or (Ly in (1, 2) and D[0] <= 4)):
         nv = bnv or 2 * Ly
         kry = min(D[0] ** nv, 12)
         wsb = ctypes.c_size_t()
@@ -108,9 +109,9 @@ for case in %(cases)r:
                                             kry, ev, rs, ctypes.byref(ent), ctypes.byref(wt)))
     if True:
         st.append(lib.ctm_norm(ctx, 0, ctypes.byref(k)))
-        rho = (ctypes.c_double * (d[0] ** 4))(); h = ctypes.c_double()
+        rho = (ctypes.c_double * (2 * d[0] ** 4))(); h = ctypes.c_double()
         for v in (0, 1):
-            st.append(lib.ctm_rdm(ctx, 0, 1, 0, v, rho, ctypes.byref(h)))
+            st.append((lib.ctm_rdm_complex if cx else lib.ctm_rdm)(ctx, 0, 1, 0, v, rho, ctypes.byref(h)))
     spec = (ctypes.c_double * (Lx * Ly * 4 * chi[0]))()
     st.append(lib.ctm_spectra(ctx, 0, spec))
     out[name] = [st, lib.ctm_last_error().decode(), n]
@@ -138,6 +139,9 @@ CASES = [
     # the cylinder of Sec. V's entropies: D = 8, chi = 80, N_v = 6 (ring
     # state of 1.7e9 doubles, its GEMMs in several launches)
     ("boundary_D8", 2, 2, [0, 1, 1, 0], 2, [8], [8], [80], "bf16", {"single_layer": True, "boundary_nv": 6}),
+    # complex kets on the real form of the double layer
+    ("complex_fp64", 2, 2, [0, 1, 1, 0], 2, [2], [3], [24], "fp64", {"complex_tensors": True}),
+    ("complex_bf16", 2, 2, [0, 1, 1, 0], 2, [8], [6], [144], "bf16", {"complex_tensors": True}),
 ]
 
 
@@ -152,6 +156,27 @@ def test_dry_run_orchestration(lib_path):
         assert all(s == 0 for s in st), (name, st, err)
     # the c2 workspace fits comfortably in one MI355X's HBM
     assert res["c2_bf16"][2] < 16e9
+
+
+def test_complex_rejections(lib_path):
+    """Complex kets: not with the single-layer route, not for the fidelity
+    (the mixed network has no real form), not for the boundary operator."""
+    from paper_1711_04798_amd import binding as b
+    lib = b.load()
+    cfg, keep = b.make_config(1, 1, [0], 1, [2], [2], [8], complex_tensors=True, single_layer=True)
+    with pytest.raises(b.CtmError) as e:
+        b.workspace_size(cfg)
+    assert e.value.status == b.CTM_E_INVALID
+    cfg, keep = b.make_config(1, 1, [0], 1, [2], [2], [8], complex_tensors=True)
+    assert b.workspace_size(cfg) > 0
+    dv, lv = ctypes.c_double(), ctypes.c_double()
+    sw = (ctypes.c_int32 * 3)()
+    ptrs = (ctypes.c_void_p * 1)(1 << 30)
+    pp = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+    st = lib.ctm_fidelity(ctypes.byref(cfg), pp, pp, None, 0, None, 1e-8, 10, ctypes.byref(dv), ctypes.byref(lv), sw)
+    assert st == b.CTM_E_INVALID and b"real tensors" in lib.ctm_last_error()
+    with pytest.raises(ValueError):
+        b.fidelity([np.zeros((2, 2, 2, 2, 2), dtype=complex)], [np.zeros((2, 2, 2, 2, 2))])
 
 
 def test_invalid_configs_rejected(lib_path):
