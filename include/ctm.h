@@ -380,8 +380,9 @@ ctm_status ctm_get_timing(ctm_ctx ctx, double* v);
  * Launch-variant table (process-wide): per kernel family and operand shape,
  * the tile of the generic GEMM, the split counts of the tall-skinny and
  * split-K products ("gemm", "ts", "splitk"), and the rows per work-group of
- * the bf16 enlarged-corner product ("corner": 256, 192 or 128 for variants
- * 0, 1, 2; bitwise-equal results).  The project's tuner (paper_1711_04798_amd/tune.py) runs
+ * the bf16 products with float32 output, the enlarged corners' and the
+ * absorption's ("corner": 256, 192 or 128 for variants 0, 1, 2; ak / bk mark
+ * packed operands; bitwise-equal results).  The project's tuner (paper_1711_04798_amd/tune.py) runs
  * the benchmark workloads with tuning on and saves the table; a later
  * process loads it (ctm_init loads the file named by the environment
  * variable CTM_TILE_TABLE once; the Python binding loads the committed

@@ -446,11 +446,18 @@ void launch(const Launch& l) {
                      l.g, l.mt, l.nt, l.tiles, l.per_xcd, l.aux);
 }
 
-// the packed-operand product in float32 with 64 rt rows per work-group
+// the float32-output product with 64 RT rows per work-group, operands
+// packed (BF, AF) or row-major
+template <bool BF, bool AF, int RT>
+void launch_f32(const Launch& l, bool v4) {
+  if (v4) launch<float, OUT_V4, BF, AF, RT>(l);
+  else launch<float, OUT_PLAIN, BF, AF, RT>(l);
+}
 template <int RT>
-void launch_packed(const Launch& l, bool v4) {
-  if (v4) launch<float, OUT_V4, true, true, RT>(l);
-  else launch<float, OUT_PLAIN, true, true, RT>(l);
+void launch_f32_rt(const Launch& l, bool v4, bool b_packed, bool a_packed) {
+  if (b_packed && a_packed) launch_f32<true, true, RT>(l, v4);
+  else if (b_packed) launch_f32<true, false, RT>(l, v4);
+  else launch_f32<false, false, RT>(l, v4);
 }
 
 }  // namespace
@@ -538,39 +545,39 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K) {
   return M > 0 && N > 0 && K > 0 && (K % 8) == 0 && M <= INT32_MAX && N <= INT32_MAX;
 }
 
-// The packed-operand float32 product with 64 rt rows per work-group (the
-// variants compute every element with the same K order: bitwise equal).
-static hipError_t launch_packed_rt(hipStream_t s, int64_t M, int64_t N, int64_t K, const OutView& ov, bool v4,
-                                   const GemmGroup& g, int groups, int rt) {
+// The float32-output product with 64 rt rows per work-group (the variants
+// compute every element with the same K order: bitwise equal).
+static hipError_t launch_rt(hipStream_t s, int64_t M, int64_t N, int64_t K, const OutView& ov, bool v4,
+                            const GemmGroup& g, int groups, int rt, bool b_packed, bool a_packed) {
   const int64_t bm = 64 * rt;
   const int64_t mt = (M + bm - 1) / bm, nt = (N + BN - 1) / BN, tiles = mt * nt * groups;
   if (tiles > INT32_MAX / 2) return hipErrorInvalidValue;
   const int64_t per_xcd = (tiles + 7) / 8;
   const Launch L{dim3((unsigned)(8 * per_xcd)), s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt,
                  (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd, Aux{0, 0, 0, 0}};
-  if (rt == 2) launch_packed<2>(L, v4);
-  else if (rt == 3) launch_packed<3>(L, v4);
-  else launch_packed<4>(L, v4);
+  if (rt == 2) launch_f32_rt<2>(L, v4, b_packed, a_packed);
+  else if (rt == 3) launch_f32_rt<3>(L, v4, b_packed, a_packed);
+  else launch_f32_rt<4>(L, v4, b_packed, a_packed);
   return hipGetLastError();
 }
 
 // TK_CORNER variant v -> rows per work-group 64 rt: v = 0, 1, 2 -> rt = 4, 3, 2
 static int rt_of(int v) { return v == 2 ? 2 : v == 1 ? 3 : 4; }
 
-// Rows per work-group of the packed product: the tile table's entry; else,
+// Rows per work-group of a float32-output product: the tile table's entry; else,
 // while table tuning is on (outside capture), the fastest variant timed on
 // the call's own operands (each overwrites C); else 256 rows, or 128 when
 // 256-row tiles would not fill two rounds of two work-groups per CU (the
 // tail round of a small live extent).
 static int corner_rows(hipStream_t s, int64_t M, int64_t N, int64_t K, const OutView& ov, bool v4,
-                       const GemmGroup& g, int groups) {
+                       const GemmGroup& g, int groups, bool b_packed, bool a_packed) {
   static const int forced = [] {  // CTM_CORNER_ROWS=256|192|128 overrides the choice
     const char* e = std::getenv("CTM_CORNER_ROWS");
     const int r = e ? std::atoi(e) : 0;
     return r == 256 ? 4 : r == 192 ? 3 : r == 128 ? 2 : 0;
   }();
   if (forced) return forced;
-  const TileKey key{TK_CORNER, BF16, F32, 1, 1, groups, M, N, K};
+  const TileKey key{TK_CORNER, BF16, F32, a_packed ? 1 : 0, b_packed ? 1 : 0, groups, M, N, K};
   int v = tile_lookup(key, -1);
   if (v >= 0 && v < TILE_VARIANTS[TK_CORNER]) return rt_of(v);
   if (tile_tuning_on() && !dry_run()) {
@@ -583,8 +590,8 @@ static int corner_rows(hipStream_t s, int64_t M, int64_t N, int64_t K, const Out
       for (int t = 0; t < TILE_VARIANTS[TK_CORNER]; ++t) {
         float ms_min = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
-          if (hipEventRecord(e0, s) != hipSuccess || launch_packed_rt(s, M, N, K, ov, v4, g, groups, rt_of(t)) !=
-                                                         hipSuccess ||
+          if (hipEventRecord(e0, s) != hipSuccess ||
+              launch_rt(s, M, N, K, ov, v4, g, groups, rt_of(t), b_packed, a_packed) != hipSuccess ||
               hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
             break;
           float ms = 0;
@@ -636,12 +643,9 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   if (tout == BF16 && split_stride > 0) launch<__bf16, OUT_SPLIT, false, false>(L);
   else if (tout == BF16 && v4) launch<__bf16, OUT_V4, false, false>(L);
   else if (tout == BF16) launch<__bf16, OUT_PLAIN, false, false>(L);
-  else if (b_packed && a_packed)
-    return launch_packed_rt(s, M, N, K, ov, v4, g, groups, corner_rows(s, M, N, K, ov, v4, g, groups));
-  else if (b_packed && v4) launch<float, OUT_V4, true, false>(L);
-  else if (b_packed) launch<float, OUT_PLAIN, true, false>(L);
-  else if (v4) launch<float, OUT_V4, false, false>(L);
-  else if (use_dma) launch<float, OUT_PLAIN, false, false>(L);
+  else if (use_dma)
+    return launch_rt(s, M, N, K, ov, v4, g, groups, corner_rows(s, M, N, K, ov, v4, g, groups, b_packed, a_packed),
+                     b_packed, a_packed);
   else
     hipLaunchKernelGGL(corner_bf16_kernel, grid, dim3(256), 0, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g,
                        (int32_t)mt, (int32_t)nt, (int32_t)tiles, (int32_t)per_xcd);

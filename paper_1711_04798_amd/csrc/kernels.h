@@ -159,8 +159,9 @@ int tuned_entries();
 // summation order (results differ at the rounding level); a process that
 // uses one table is deterministic.
 // ---------------------------------------------------------------------------
-//   TK_CORNER: the packed-operand bf16 corner product, rows per work-group
-//              (v = 0, 1, 2: 256, 192, 128; bitwise-equal results)
+//   TK_CORNER: the bf16 corner kernel with float32 output (ak, bk: operands
+//              packed), rows per work-group (v = 0, 1, 2: 256, 192, 128;
+//              bitwise-equal results)
 enum TileKernel : int { TK_GEMM = 0, TK_TS = 1, TK_SPLITK = 2, TK_CORNER = 3 };
 constexpr int TILE_KINDS = 4;
 constexpr int TILE_VARIANTS[TILE_KINDS] = {4, 5, 4, 3};
