@@ -101,6 +101,15 @@ ctm_status ctm_debug_set_width(ctm_ctx ctx, int32_t width, int32_t* live_out);
  */
 ctm_status ctm_debug_set_ring_rows(int64_t rows);
 
+/*
+ * The host eigensolver of the boundary operator's projected Lanczos matrix
+ * (Householder tridiagonalisation and the implicit symmetric QR algorithm):
+ * A host float64 n x n symmetric (row-major, read only), w host [n] the
+ * eigenvalues descending, V (may be NULL) host n x n with the eigenvectors
+ * in its columns.  No GPU work.
+ */
+ctm_status ctm_debug_sym_eig(int32_t n, const double* A, double* w, double* V);
+
 #ifdef __cplusplus
 }
 #endif

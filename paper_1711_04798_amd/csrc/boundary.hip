@@ -257,62 +257,142 @@ ctm_status ring_apply(const Ctx& c, double* const* W, const double* x, double* o
   return CTM_OK;
 }
 
-// Eigen-decomposition of the symmetric n x n matrix A (row-major, destroyed)
-// by cyclic Jacobi rotations: each rotation zeroes one off-diagonal pair
-// (tan of the angle t = sign(theta) / (|theta| + sqrt(theta^2 + 1)) with
-// theta = (a_qq - a_pp) / (2 a_pq)); sweeps until the off-diagonal part is
-// below 1e-15 of the diagonal.  Eigenvalues descending in w, eigenvectors in
-// the columns of V.
-void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& V) {
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const double a = A[(size_t)i * n + j];
-        if (i == j) dia += a * a; else off += a * a;
+// Eigen-decomposition of the symmetric n x n matrix A (row-major, destroyed):
+// Householder reduction to tridiagonal form T = Q^T A Q, then the implicit
+// symmetric QR algorithm with Wilkinson shifts on T (Golub & Van Loan,
+// Matrix Computations, Algorithms 8.3.1 and 8.3.3), the Givens rotations
+// accumulated into Q when vectors are wanted.  4/3 n^3 + O(n^2) flops for
+// the values (about 4 n^3 more with vectors) instead of about 3 n^3 per
+// sweep of cyclic Jacobi.  Eigenvalues descending in w; with want_vectors
+// the eigenvectors in the columns of V (row-major n x n).
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& V, bool want_vectors) {
+  w.assign(n, 0.0);
+  // Qt = Q^T (row i = column i of Q), so that every update below touches
+  // whole contiguous rows
+  std::vector<double> Qt;
+  if (want_vectors) {
+    Qt.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Qt[(size_t)i * n + i] = 1.0;
+  }
+  if (n == 0) return;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  std::vector<double> v(n), pv(n), q(n), d(n), e(n > 1 ? n - 1 : 1, 0.0);
+  // Householder: column k below the subdiagonal -> alpha e_(k+1)
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m0 = k + 1;
+    double xn = 0.0;
+    for (int i = m0; i < n; ++i) xn += a(i, k) * a(i, k);
+    xn = std::sqrt(xn);
+    double tail = 0.0;
+    for (int i = m0 + 1; i < n; ++i) tail += a(i, k) * a(i, k);
+    if (tail == 0.0) continue;  // already tridiagonal in this column
+    const double alpha = a(m0, k) >= 0.0 ? -xn : xn;
+    double vn = 0.0;
+    for (int i = m0; i < n; ++i) {
+      v[i] = a(i, k) - (i == m0 ? alpha : 0.0);
+      vn += v[i] * v[i];
+    }
+    vn = std::sqrt(vn);
+    for (int i = m0; i < n; ++i) v[i] /= vn;
+    // trailing block B <- H B H with H = I - 2 v v^T: p = B v, K = v.p,
+    // q = p - K v, B <- B - 2 (v q^T + q v^T)
+    double K = 0.0;
+    for (int i = m0; i < n; ++i) {
+      double t = 0.0;
+      for (int j = m0; j < n; ++j) t += a(i, j) * v[j];
+      pv[i] = t;
+      K += v[i] * t;
+    }
+    for (int i = m0; i < n; ++i) q[i] = pv[i] - K * v[i];
+    for (int i = m0; i < n; ++i)
+      for (int j = m0; j < n; ++j) a(i, j) -= 2.0 * (v[i] * q[j] + q[i] * v[j]);
+    a(m0, k) = a(k, m0) = alpha;
+    for (int i = m0 + 1; i < n; ++i) a(i, k) = a(k, i) = 0.0;
+    if (want_vectors) {
+      // Q <- Q H, i.e. Qt <- H Qt: rows m0.. of Qt minus 2 v (v^T Qt)
+      std::fill(pv.begin(), pv.end(), 0.0);
+      for (int j = m0; j < n; ++j) {
+        const double* row = &Qt[(size_t)j * n];
+        for (int r = 0; r < n; ++r) pv[r] += v[j] * row[r];
       }
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (apq == 0.0) continue;
-        const double theta = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = c * akp - sn * akq;
-          A[(size_t)k * n + q] = sn * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = c * apk - sn * aqk;
-          A[(size_t)q * n + k] = sn * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = c * vkp - sn * vkq;
-          V[(size_t)k * n + q] = sn * vkp + c * vkq;
+      for (int j = m0; j < n; ++j) {
+        double* row = &Qt[(size_t)j * n];
+        for (int r = 0; r < n; ++r) row[r] -= 2.0 * v[j] * pv[r];
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+  // implicit symmetric QR on (d, e): deflate from the bottom
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1, guard = 0;
+  while (hi > 0 && guard < 60 * n) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    ++guard;
+    // Wilkinson shift from the trailing 2 x 2 block
+    const double dd = 0.5 * (d[hi - 1] - d[hi]), b2 = e[hi - 1] * e[hi - 1];
+    const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::sqrt(dd * dd + b2);
+    const double mu = den != 0.0 ? d[hi] - b2 / den : d[hi];
+    double x = d[lo] - mu, z = e[lo], bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      // rotation on rows / columns k, k+1 that zeroes z against x
+      const double r = std::hypot(x, z);
+      const double c = r != 0.0 ? x / r : 1.0, s_ = r != 0.0 ? z / r : 0.0;
+      if (k > lo) e[k - 1] = r;
+      const double ak = d[k], bk = e[k], ck = d[k + 1];
+      d[k] = c * c * ak + 2.0 * c * s_ * bk + s_ * s_ * ck;
+      d[k + 1] = s_ * s_ * ak - 2.0 * c * s_ * bk + c * c * ck;
+      e[k] = c * s_ * (ck - ak) + (c * c - s_ * s_) * bk;
+      if (k + 1 < hi) {
+        const double t = e[k + 1];
+        bulge = s_ * t;
+        e[k + 1] = c * t;
+        x = e[k];
+        z = bulge;
+      }
+      if (want_vectors) {
+        // Q <- Q G: columns k, k+1 of Q are rows k, k+1 of Qt
+        double* rk = &Qt[(size_t)k * n];
+        double* rk1 = &Qt[(size_t)(k + 1) * n];
+        for (int r2 = 0; r2 < n; ++r2) {
+          const double vk = rk[r2], vk1 = rk1[r2];
+          rk[r2] = c * vk + s_ * vk1;
+          rk1[r2] = -s_ * vk + c * vk1;
         }
       }
+    }
   }
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[(size_t)a * n + a] > A[(size_t)b * n + b]; });
-  std::vector<double> V2((size_t)n * n);
-  w.resize(n);
-  for (int j = 0; j < n; ++j) {
-    w[j] = A[(size_t)idx[j] * n + idx[j]];
-    for (int k = 0; k < n; ++k) V2[(size_t)k * n + j] = V[(size_t)k * n + idx[j]];
+  std::sort(idx.begin(), idx.end(), [&](int x1, int x2) { return d[x1] > d[x2]; });
+  for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
+  if (want_vectors) {
+    V.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+      const double* row = &Qt[(size_t)idx[j] * n];
+      for (int r = 0; r < n; ++r) V[(size_t)r * n + j] = row[r];
+    }
   }
-  V.swap(V2);
 }
 
 }  // namespace
 
 extern "C" {
+
+ctm_status ctm_debug_sym_eig(int32_t n, const double* A, double* w, double* V) {
+  if (n < 1 || !A || !w) return ctm_internal_fail(CTM_E_INVALID, "args");
+  std::vector<double> a(A, A + (size_t)n * n), wv, vv;
+  sym_eig(n, a, wv, vv, V != nullptr);
+  std::copy(wv.begin(), wv.end(), w);
+  if (V) std::copy(vv.begin(), vv.end(), V);
+  return CTM_OK;
+}
 
 ctm_status ctm_debug_set_ring_rows(int64_t rows) {
   g_ring_rows = rows <= 0 ? kRingRowsDefault : std::min(rows, kRingRowsDefault);
@@ -498,7 +578,8 @@ ctm_status ctm_boundary_spectrum(ctm_ctx x, int32_t inst, int32_t column, int32_
     for (int j = 0; j < ns; ++j)
       Hs[(size_t)i * ns + j] = 0.5 * (H[(size_t)i * m + j] + H[(size_t)j * m + i]);
   std::vector<double> ev, V;
-  jacobi_eig(ns, Hs, ev, V);
+  // vectors only for the residuals of a partial basis
+  sym_eig(ns, Hs, ev, V, ns < n);
   double S = 0.0, wsum = 0.0;
   for (int i = 0; i < nev; ++i) {
     const double v = i < ns ? ev[i] / tr : 0.0;
