@@ -345,6 +345,41 @@ def boundary_oracle_rate():
     return {"D": f["D"], "chi": f["chi"], "nv": f["nv"], "s_per_spectrum": time.perf_counter() - t0}
 
 
+def complex_leg(steps=5, warm=2):
+    """Complex kets (i.i.d. complex normal tensors, the benchmark's shapes)
+    against real ones: column steps per second of the benchmark workload in
+    bf16.  The complex state runs on the real form of the double layer, so
+    the two should cost the same."""
+    import torch
+    from paper_1711_04798_amd import CTM
+    w = WORKLOAD
+    rng = np.random.default_rng(5)
+    out = {}
+    for kind in ("real", "complex"):
+        tens = []
+        for _ in range(2):
+            A = rng.standard_normal((w["d"], w["D"], w["D"], w["D"], w["D"]))
+            if kind == "complex":
+                A = A + 1j * rng.standard_normal(A.shape)
+            tens.append(A / np.linalg.norm(A))
+        log("bench: complex leg %s" % kind)
+        g = CTM([tens], Lx=w["Lx"], Ly=w["Ly"], pattern=w["pattern"], chi=w["chi"], prec="bf16",
+                **solver_opts("bf16"))
+        for _ in range(warm):
+            g.converge(tol=0.0, max_sweeps=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.converge(tol=0.0, max_sweeps=1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[kind] = {"moves_per_s": 8 * steps / el, "ms_per_sweep": 1e3 * el / steps}
+        g.close()
+    out["ratio"] = out["complex"]["moves_per_s"] / out["real"]["moves_per_s"]
+    out["note"] = "2x2 d=8 D=6 chi=144 bf16, random tensors (seed 5), complex kets on the real form of the double layer"
+    return out
+
+
 BATCHED = dict(n_inst=256, d=8, Ds=(3, 4, 5), chis=(32, 64, 100), seed=0, max_sweeps=60)
 # float64 contractions reach Delta < 1e-6; float32 contractions do not (their
 # corner spectra keep changing by ~1e-5 .. 1e-4 per sweep), so the float32
@@ -516,6 +551,7 @@ def main():
     ap.add_argument("--no-su", action="store_true", help="skip the simple-update leg")
     ap.add_argument("--su-only", action="store_true", help="only the simple-update leg")
     ap.add_argument("--no-boundary", action="store_true", help="skip the boundary-operator leg")
+    ap.add_argument("--no-complex", action="store_true", help="skip the complex-tensor leg")
     ap.add_argument("--boundary-only", action="store_true", help="only the boundary-operator leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
@@ -644,6 +680,8 @@ def main():
         out["simple_update"] = su_leg()
     if not args.no_boundary:
         out["boundary"] = boundary_leg()
+    if not args.no_complex:
+        out["complex"] = complex_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(BATCHED_FORMS[0])
         out["batched"]["sequential_class_branches"] = batched_leg(BATCHED_FORMS[1])
