@@ -1135,8 +1135,12 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
         M.p[r] = R->Rm; U.p[r] = R->WR; S.p[r] = R->S; W.p[r] = R->UR; J.p[r] = R->jw;
         stj.p[r] = R->st;
       }
-      // directions 100x below the cutoff can never be kept
-      HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P, true, true, &stj, 1e-2 * c.svd_cutoff));
+      // directions 100x below the cutoff can never be kept.  With reduced-
+      // precision contractions and a fixed iteration count the rotations
+      // stop at a column cosine of 1e-8, far below the contractions' own
+      // rounding, instead of float64 orthogonality (about one sweep less)
+      const double rot_rel = (x.qt != F64 && !adaptive) ? 1e-8 : 0.0;
+      HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P, true, true, &stj, 1e-2 * c.svd_cutoff, rot_rel));
     }
     {
       // three products of one shape per row, one grouped launch

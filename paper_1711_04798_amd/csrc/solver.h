@@ -57,11 +57,14 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
 // With transpose_in the rotations act on the columns of M^T (the rows of M):
 // M^T W = U S, i.e. M = W S U^T.  Columns whose norm stays below noise_rel
 // (at least 4 u) times the largest are left unrotated; their singular values
-// and vectors are then only bounds.
+// and vectors are then only bounds.  A pair of columns is rotated while the
+// cosine between them exceeds max(k u, rot_rel): rot_rel = 0 runs to full
+// float64 orthogonality, a larger value stops once the columns are that
+// close to orthogonal (the rotations themselves stay exactly orthogonal).
 hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U,
                       const PtrSet& S, const PtrSet& W, const PtrSet& work, int nprob,
                       bool want_vectors = true, bool transpose_in = false,
-                      const StatSet* st = nullptr, double noise_rel = 0.0);
+                      const StatSet* st = nullptr, double noise_rel = 0.0, double rot_rel = 0.0);
 
 // Residuals r_i = ||Z_i - S_i V_i|| of the columns of the n x k row-major
 // blocks; sets chi_eff (from S, chi, cutoff), converged (tol), sigma0,

@@ -449,7 +449,7 @@ extern __shared__ double jsm[];  // dynamic LDS of the Jacobi kernel
 // pair's columns are plain LDS (or global) loads issued together.  Returns the
 // number of sweeps.
 template <int NRL, bool IN_LDS>
-__device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, double nr,
+__device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, double nr, double rot_rel,
                              double* s_cn, double* s_amax, int* s_rot) {
   constexpr int ld = 16 * NRL;
   double* A = IN_LDS ? jsm : gA;
@@ -457,7 +457,9 @@ __device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, doubl
   const int tid = threadIdx.x, ql = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
   const int kk = (kc + 1) & ~1;  // even number of players; player kc (if odd) is a dummy
   const int half = kk / 2;
-  const double eps = 2.220446049250313e-16 * (double)k;
+  // a pair is rotated while the cosine of its columns exceeds k u (or the
+  // caller's coarser rot_rel)
+  const double eps = fmax(2.220446049250313e-16 * (double)k, rot_rel);
   const double eps2 = eps * eps;
   int sweeps_done = 0;
   for (int sweep = 0; sweep < 60 && kc > 1; ++sweep) {
@@ -556,7 +558,7 @@ __device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, doubl
 
 __global__ void __launch_bounds__(1024)
 jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, PtrSet work, int want_vectors,
-                  int transpose_in, StatSet st, double noise_rel, size_t lds_cap) {
+                  int transpose_in, StatSet st, double noise_rel, double rot_rel, size_t lds_cap) {
   const int pb = blockIdx.x;
   const double* M = Min.p[pb];
   const int tid = threadIdx.x, nt = blockDim.x, ql = tid & 15, grp = tid >> 4, ngrp = nt >> 4;
@@ -627,30 +629,30 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
   const bool wv = want_vectors != 0;
   int sweeps_done = 0;
   switch (in_lds ? nrl : nrl + 16) {
-    case 1: sweeps_done = jacobi_sweeps<1, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 2: sweeps_done = jacobi_sweeps<2, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 3: sweeps_done = jacobi_sweeps<3, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 4: sweeps_done = jacobi_sweeps<4, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 5: sweeps_done = jacobi_sweeps<5, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 6: sweeps_done = jacobi_sweeps<6, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 7: sweeps_done = jacobi_sweeps<7, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 8: sweeps_done = jacobi_sweeps<8, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 9: sweeps_done = jacobi_sweeps<9, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 10: sweeps_done = jacobi_sweeps<10, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 11: sweeps_done = jacobi_sweeps<11, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 12: sweeps_done = jacobi_sweeps<12, true>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 17: sweeps_done = jacobi_sweeps<1, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 18: sweeps_done = jacobi_sweeps<2, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 19: sweeps_done = jacobi_sweeps<3, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 20: sweeps_done = jacobi_sweeps<4, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 21: sweeps_done = jacobi_sweeps<5, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 22: sweeps_done = jacobi_sweeps<6, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 23: sweeps_done = jacobi_sweeps<7, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 24: sweeps_done = jacobi_sweeps<8, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 25: sweeps_done = jacobi_sweeps<9, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 26: sweeps_done = jacobi_sweeps<10, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 27: sweeps_done = jacobi_sweeps<11, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
-    case 28: sweeps_done = jacobi_sweeps<12, false>(k, kc, A, wv, nr, s_cn, &s_amax, &s_rot); break;
+    case 1: sweeps_done = jacobi_sweeps<1, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 2: sweeps_done = jacobi_sweeps<2, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 3: sweeps_done = jacobi_sweeps<3, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 4: sweeps_done = jacobi_sweeps<4, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 5: sweeps_done = jacobi_sweeps<5, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 6: sweeps_done = jacobi_sweeps<6, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 7: sweeps_done = jacobi_sweeps<7, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 8: sweeps_done = jacobi_sweeps<8, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 9: sweeps_done = jacobi_sweeps<9, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 10: sweeps_done = jacobi_sweeps<10, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 11: sweeps_done = jacobi_sweeps<11, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 12: sweeps_done = jacobi_sweeps<12, true>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 17: sweeps_done = jacobi_sweeps<1, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 18: sweeps_done = jacobi_sweeps<2, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 19: sweeps_done = jacobi_sweeps<3, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 20: sweeps_done = jacobi_sweeps<4, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 21: sweeps_done = jacobi_sweeps<5, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 22: sweeps_done = jacobi_sweeps<6, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 23: sweeps_done = jacobi_sweeps<7, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 24: sweeps_done = jacobi_sweeps<8, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 25: sweeps_done = jacobi_sweeps<9, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 26: sweeps_done = jacobi_sweeps<10, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 27: sweeps_done = jacobi_sweeps<11, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
+    case 28: sweeps_done = jacobi_sweeps<12, false>(k, kc, A, wv, nr, rot_rel, s_cn, &s_amax, &s_rot); break;
     default: break;  // kr == 0: an all-zero input
   }
   // singular values = column norms (zero for the dropped part), sorted
@@ -693,7 +695,7 @@ jacobi_svd_kernel(int k, CPtrSet Min, PtrSet Uout, PtrSet Sout, PtrSet Wout, Ptr
 
 hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, const PtrSet& S,
                       const PtrSet& W, const PtrSet& work, int nprob, bool want_vectors, bool transpose_in,
-                      const StatSet* st, double noise_rel) {
+                      const StatSet* st, double noise_rel, double rot_rel) {
   if (nprob < 0 || nprob > MAXP) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   if (k < 1 || k > JMAX) return hipErrorInvalidValue;
@@ -726,7 +728,7 @@ hipError_t jacobi_svd(hipStream_t s, int k, const CPtrSet& M, const PtrSet& U, c
   int waves = (half + 3) / 4;
   waves = waves < 2 ? 2 : (waves > 16 ? 16 : waves);
   hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nprob), dim3(64 * waves), kJMaxDyn, s, k, M, U, S, W, work,
-                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel, kJMaxDyn);
+                     want_vectors ? 1 : 0, transpose_in ? 1 : 0, st ? *st : none, noise_rel, rot_rel, kJMaxDyn);
   return hipGetLastError();
 }
 
