@@ -38,6 +38,15 @@ ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_
                             void* scratch, int64_t scratch_bytes, void* stream);
 
 /*
+ * The float32 form of ctm_debug_tsgemm ((ta, tc) = (1, 1)) with a second
+ * output: C2 (float64, M x N row-major) receives the same sums as C, written
+ * by the same reduction.
+ */
+ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A, int32_t transA,
+                                 const float* B, float* C, double* C2, void* scratch,
+                                 int64_t scratch_bytes, void* stream);
+
+/*
  * C = A Bt^T on the bf16 enlarged-corner kernel: A bf16 M x K row-major, Bt
  * bf16 N x K row-major (both 16-byte aligned, K a multiple of 8), C float32
  * M x N row-major.

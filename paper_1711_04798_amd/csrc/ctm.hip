@@ -996,19 +996,31 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
     }
     return CTM_OK;
   }
-  // reduced precision: cast in, apply in the Q type, mid and out back to float64
+  // reduced precision: cast in, apply in the Q type, mid and out in float64.
+  // Where the float32 tall-skinny kernel takes the second product, its
+  // reduction writes mid beside the float32 result; elsewhere a conversion.
   {
     Xfer cv;
     for (size_t r = 0; r < P; ++r) cv.add(in[r], rows[r].R->qin, (int64_t)n * k);
     CHK(xfer_run(s, F64, qt, cv));
   }
+  const bool ts_mid = qt == F32 && n >= 1024 && ts_gemm_supported(F32, F32, n, k, n, vq, vb, vb);
   for (int f = 0; f < nfac; ++f) {
-    G g;
+    G g, gm;
     for (size_t r = 0; r < P; ++r) {
       Row* R = rows[r].R;
       const void* src = f == 0 ? R->qin : (f == 1 ? R->q1 : (f == 2 ? R->q2 : R->q1));
       void* dst = f == 0 ? R->q1 : (f == 1 ? R->q2 : (f == 2 ? R->q1 : (void*)out[r]));
       g.add(rows[r].Q[ord[f]], src, dst);
+      gm.add(nullptr, nullptr, mid[r]);
+    }
+    if (f == 1 && ts_mid) {
+      for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
+        const int cnt = std::min(MAXG, g.size() - j0);
+        const GemmGroup g2 = gm.group(j0, cnt);
+        HIPCHK(ts_gemm(s, F32, F32, n, k, n, vq, vb, vb, g.group(j0, cnt), cnt, x.ts_scratch, x.ts_bytes, &g2));
+      }
+      continue;
     }
     CHK(gemm_long(x, qt, f == 3 ? F64 : qt, n, k, n, vq, vb, vb, g));
     if (f == 1) {
@@ -3388,6 +3400,24 @@ ctm_status ctm_debug_corner_bf16_packed(int64_t M, int64_t N, int64_t K, const v
   g.C[0] = C;
   hipError_t e = corner_bf16(s, M, N, K, rowmajor(N), g, 1, F32, 0, true);
   if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "alignment");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A, int32_t transA, const float* B,
+                                 float* C, double* C2, void* scratch, int64_t scratch_bytes, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  View va = transA ? transposed(rowmajor(M)) : rowmajor(K);
+  if (!ts_gemm_supported(F32, F32, M, N, K, va, rowmajor(N), rowmajor(N)) || !A || !B || !C || !C2 || !scratch)
+    return fail(CTM_E_INVALID, "sizes");
+  GemmGroup g{}, g2{};
+  g.A[0] = A;
+  g.B[0] = B;
+  g.C[0] = C;
+  g2.C[0] = C2;
+  hipError_t e = ts_gemm(s, F32, F32, M, N, K, va, rowmajor(N), rowmajor(N), g, 1, scratch, scratch_bytes, &g2);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "scratch too small");
   HIPCHK(e);
   HIPCHK(ssync(s));
   return CTM_OK;

@@ -81,8 +81,11 @@ hipError_t gemm_splitk(hipStream_t s, int64_t M, int64_t N, int64_t K, double al
 // f32 -> f32/f64 and f64 -> f64.  `scratch` holds the K-chunk partials.
 bool ts_gemm_supported(int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                        const View& vc);
+// c2, when given (ta = tc = F32 only): a second output, float64 through the
+// same view, written by the same reduction as C
 hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
-                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes);
+                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes,
+                   const GemmGroup* c2 = nullptr);
 
 // out[b][c][r] = in[b][r][c], float32, nb matrices R x C.
 hipError_t transpose_batched(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, float* out);

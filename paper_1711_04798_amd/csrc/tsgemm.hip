@@ -331,6 +331,23 @@ __global__ void ts_reduce_kernel(const T* __restrict__ part, int32_t M, int32_t 
   }
 }
 
+// the same, float32 partials into a float32 output and a float64 copy
+__global__ void ts_reduce2_kernel(const float* __restrict__ part, int32_t M, int32_t N, int32_t nsplit, int64_t ldc,
+                                  GemmGroup g, GemmGroup g2) {
+  const int gi = blockIdx.y;
+  const float* __restrict__ p = part + (int64_t)gi * nsplit * M * N;
+  float* __restrict__ C = (float*)g.C[gi];
+  double* __restrict__ C2 = (double*)g2.C[gi];
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0;
+    for (int s = 0; s < nsplit; ++s) acc += p[(int64_t)s * MN + e];
+    const int64_t m = e / N, n = e - m * N;
+    C[m * ldc + n] = acc;
+    C2[m * ldc + n] = (double)acc;
+  }
+}
+
 template <typename T, bool AK, bool VEC>
 hipError_t launch_partial(hipStream_t s, int nt, dim3 grid, int32_t M, int32_t N, int32_t K, int64_t lda,
                           int64_t ldb, int32_t kchunk, int32_t nsplit, int32_t mtiles, const GemmGroup& g,
@@ -378,11 +395,13 @@ int64_t ts_gemm_scratch_elems(int64_t M, int64_t N, int groups, int nsplit) {
 
 static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
                             const View& vb, const View& vc, const GemmGroup& g, int groups, void* scratch,
-                            int64_t scratch_bytes, int64_t target);
+                            int64_t scratch_bytes, int64_t target, const GemmGroup* c2);
 
 hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
-                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes) {
+                   const View& vc, const GemmGroup& g, int groups, void* scratch, int64_t scratch_bytes,
+                   const GemmGroup* c2) {
   if (groups < 1 || groups > MAXG || !ts_gemm_supported(ta, tc, M, N, K, va, vb, vc)) return hipErrorInvalidValue;
+  if (c2 && (ta != F32 || tc != F32)) return hipErrorInvalidValue;
   // split count target from the tile table (about 2048 wave tasks by default)
   const TileKey key{TK_TS, ta, tc, va.c_ls == 1, 1, groups, M, N, K};
   int v = tile_lookup(key, -1);
@@ -398,8 +417,8 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
           float ms_min = 1e30f;
           for (int rep = 0; rep < 3; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess ||
-                ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << t) !=
-                    hipSuccess ||
+                ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << t,
+                          c2) != hipSuccess ||
                 hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
               break;
             float ms = 0;
@@ -415,19 +434,20 @@ hipError_t ts_gemm(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t 
     }
   }
   if (v < 0 || v >= TILE_VARIANTS[TK_TS]) v = 3;
-  return ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << v);
+  return ts_gemm_v(s, ta, tc, M, N, K, va, vb, vc, g, groups, scratch, scratch_bytes, (int64_t)256 << v, c2);
 }
 
 static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N, int64_t K, const View& va,
                             const View& vb, const View& vc, const GemmGroup& g, int groups, void* scratch,
-                            int64_t scratch_bytes, int64_t target) {
+                            int64_t scratch_bytes, int64_t target, const GemmGroup* c2) {
   const bool ak = va.c_ls == 1;
   const int64_t lda = ak ? va.r_ls : va.c_ls, ldb = vb.r_ls, ldc = vc.r_ls;
   const size_t ea = dtype_size(ta), ec = dtype_size(tc);
   const size_t sa = (size_t)(view_max(va, M, K) + 1) * ea, sb = (size_t)(view_max(vb, K, N) + 1) * ea,
                sc = (size_t)(view_max(vc, M, N) + 1) * ec;
   for (int i = 0; i < groups; ++i)
-    if (!span_ok(g.A[i], sa, "ts A") || !span_ok(g.B[i], sb, "ts B") || !span_ok(g.C[i], sc, "ts C"))
+    if (!span_ok(g.A[i], sa, "ts A") || !span_ok(g.B[i], sb, "ts B") || !span_ok(g.C[i], sc, "ts C") ||
+        (c2 && !span_ok(c2->C[i], (size_t)(view_max(vc, M, N) + 1) * 8, "ts C2")))
       return hipErrorInvalidValue;
   // enough work-groups to fill the chip several times over, K chunks of at
   // least 8 steps, and partials that fit the scratch
@@ -501,7 +521,10 @@ static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N,
 reduce:
   const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (M * N + 255) / 256));
   dim3 rg((unsigned)blocks, (unsigned)groups);
-  if (ta == F32 && tc == F32)
+  if (c2)
+    hipLaunchKernelGGL(ts_reduce2_kernel, rg, dim3(256), 0, s, (const float*)scratch, (int32_t)M, (int32_t)N,
+                       (int32_t)nsplit, ldc, g, *c2);
+  else if (ta == F32 && tc == F32)
     hipLaunchKernelGGL((ts_reduce_kernel<float, float>), rg, dim3(256), 0, s, (const float*)scratch, (int32_t)M,
                        (int32_t)N, (int32_t)nsplit, ldc, g);
   else if (ta == F32)

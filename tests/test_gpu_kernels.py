@@ -22,6 +22,9 @@ def _lib():
                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.ctm_debug_tsgemm.restype = ctypes.c_int
+    lib.ctm_debug_tsgemm_dual.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int32] + \
+        [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_void_p]
+    lib.ctm_debug_tsgemm_dual.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
     lib.ctm_debug_corner_bf16.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16_packed.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 5
@@ -63,6 +66,35 @@ def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
     if tc == 2:
         tol = max(tol, 1e-2 * np.abs(ref).max())
     assert np.abs(got - ref).max() <= tol + 1e-300
+
+
+@pytest.mark.parametrize("M,N,K,transA", [(1728, 48, 1728, 0), (1728, 48, 1728, 1), (67, 45, 1030, 0),
+                                          (700, 192, 2500, 1), (4, 3, 8, 0)])
+def test_tsgemm_dual_output(gpu, M, N, K, transA):
+    """The float32 product with a float64 second output: the first output
+    within the float32 bound of the float64 product, the second equal to it
+    bit for bit after widening (both forms: N <= 64 streams, N = 192 takes
+    the tiled form)."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(3 * M + N + K)
+    A = rng.standard_normal((K, M) if transA else (M, K))
+    B = rng.standard_normal((K, N))
+    At = torch.tensor(A, dtype=torch.float32, device="cuda")
+    Bt = torch.tensor(B, dtype=torch.float32, device="cuda")
+    Ct = torch.full((M, N), 7.0, dtype=torch.float32, device="cuda")
+    C2 = torch.full((M, N), 7.0, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    print("tsgemm dual case", M, N, K, transA, flush=True)
+    st = lib.ctm_debug_tsgemm_dual(M, N, K, At.data_ptr(), transA, Bt.data_ptr(), Ct.data_ptr(), C2.data_ptr(),
+                                   scratch.data_ptr(), scratch.numel(), torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    Ar = At.to(torch.float64).cpu().numpy()
+    Br = Bt.to(torch.float64).cpu().numpy()
+    ref = (Ar.T if transA else Ar) @ Br
+    got = Ct.to(torch.float64).cpu().numpy()
+    assert np.abs(got - ref).max() <= 2e-6 * np.abs(Ar).max() * np.abs(Br).max() * K
+    assert np.array_equal(C2.cpu().numpy(), got)
 
 
 @pytest.mark.parametrize("ta,tc", [(0, 0), (1, 1), (1, 0)])
