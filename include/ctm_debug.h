@@ -38,6 +38,17 @@ ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_
                             void* scratch, int64_t scratch_bytes, void* stream);
 
 /*
+ * Shifted Cholesky factor of the solver's Cholesky-QR: R upper triangular
+ * (row-major k x k, positive diagonal) with R^T R = G + s I, s = shift_coef
+ * * trace(G), for a symmetric k x k row-major G whose upper triangle is read
+ * (1 <= k <= 64; all three buffers on the device, work >= 256 bytes).
+ * *fail_out is 1 when a pivot was not positive (it is then replaced by
+ * 1e-300 trace(G) and the factorisation goes on), else 0.
+ */
+ctm_status ctm_debug_chol(int32_t k, double shift_coef, const double* G, double* R, void* work,
+                          int32_t* fail_out, void* stream);
+
+/*
  * The float32 form of ctm_debug_tsgemm ((ta, tc) = (1, 1)) with a second
  * output: C2 (float64, M x N row-major) receives the same sums as C, written
  * by the same reduction.

@@ -3423,6 +3423,25 @@ ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A
   return CTM_OK;
 }
 
+ctm_status ctm_debug_chol(int32_t k, double shift_coef, const double* G, double* R, void* work, int32_t* fail_out,
+                          void* stream) {
+  if (k < 1 || k > CHOL_WAVE_MAX || !G || !R || !work || !fail_out) return fail(CTM_E_INVALID, "args");
+  hipStream_t s = (hipStream_t)stream;
+  CPtrSet g{};
+  PtrSet r{};
+  StatSet st{};
+  g.p[0] = G;
+  r.p[0] = R;
+  st.p[0] = (SolveStatus*)work;
+  HIPCHK(hipMemsetAsync(work, 0, sizeof(SolveStatus), s));
+  HIPCHK(chol_shift_inv(s, k, shift_coef, g, r, st, 1, false));
+  SolveStatus h{};
+  HIPCHK(hipMemcpyAsync(&h, work, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(ssync(s));
+  *fail_out = h.chol_fail;
+  return CTM_OK;
+}
+
 ctm_status ctm_debug_svd(int32_t k, const double* M, double* U, double* S, double* W, double* work,
                          void* stream) {
   if (k < 1 || k > 192) return fail(CTM_E_INVALID, "k");

@@ -40,7 +40,7 @@ struct StatSet {
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob, bool want_inverse = true);
 
-// Largest k of the one-wave Cholesky and of trsm_rows.
+// Largest k of the four-wave Cholesky (R alone) and of trsm_rows.
 constexpr int CHOL_WAVE_MAX = 64;
 
 // Y <- Y R^{-1} in place, Y n x k row-major, R k x k upper triangular

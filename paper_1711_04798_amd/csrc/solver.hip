@@ -92,20 +92,7 @@ chol_shift_inv_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet 
   if (fail && tid == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
 }
 
-// ---------------------------------------------------------------------------
-// The same factorisation and inverse for k <= 64 with one wave per problem.
-// Left-looking (Cholesky-Crout) order in blocks of four columns: lane i owns
-// row i of L = R^T.  For a block j0..j0+3 each lane first subtracts the
-// finished columns l < j0 from its four entries (one read of its own row
-// serves four dot products; rows j0..j0+3 are LDS broadcasts), then the 4 x 4
-// diagonal block is finished in registers, the entries of rows j0..j0+3
-// coming from their owner lanes by readlane.  Then lane c forms column c of
-// L^{-1} by forward substitution in the same blocking, with reciprocal
-// pivots; that column is row c of R^{-1} = (L^{-1})^T.
-// ---------------------------------------------------------------------------
-constexpr int CW = CHOL_WAVE_MAX;  // largest k of the one-wave form
-constexpr int CWL = CW + 4;  // LDS row stride (a block may read 3 entries past column k-1)
-
+// a double of lane l (a wave-uniform lane index)
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
@@ -113,147 +100,116 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// s[b] -= sum_{l < n} x[l] * y[b * CWL + l], b = 0..3, n a multiple of 4;
-// eight columns of loads are issued before their products, which go to two
-// partial sums per b (even and odd columns) to halve the dependent chain
-__device__ __forceinline__ void dot4_lds(const double* x, const double* y, int n, double s[4]) {
-  int l = 0;
-  double s2[4] = {0.0, 0.0, 0.0, 0.0};
-  for (; l + 8 <= n; l += 8) {
-    double xv[8], yv[4][8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = x[l + u];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) yv[b][u] = y[b * CWL + l + u];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int u = 0; u < 8; u += 2) {
-        s[b] -= xv[u] * yv[b][u];
-        s2[b] -= xv[u + 1] * yv[b][u + 1];
-      }
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b) s[b] += s2[b];
-  if (l < n) {  // n - l == 4
-    double xv[4], yv[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xv[u] = x[l + u];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) yv[b][u] = y[b * CWL + l + u];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) s[b] -= xv[u] * yv[b][u];
-  }
-}
-
-__global__ void __launch_bounds__(64)
-chol_wave_kernel(int k, double shift_coef, CPtrSet G, PtrSet Rinv, StatSet st, int want_inverse) {
-  __shared__ double L[CW * CWL];  // row i at L + i*CWL; G + sI (lower part) in, L out, zero elsewhere
-  __shared__ double X[CW * CWL];  // row c at X + c*CWL: column c of L^{-1}
-  __shared__ double rpiv[CW];     // 1 / L_jj
-  const int pb = blockIdx.x, lane = threadIdx.x;
+// ---------------------------------------------------------------------------
+// R alone for k <= 64 with four waves per problem: right-looking in blocks of
+// four columns with a lookahead of one block.  Wave w owns the column blocks
+// w, w + 4, w + 8, w + 12 and keeps them in registers (lane = row; a column of
+// L is one double per lane).  A finished block is published row-major in LDS
+// (entry (r, t) of block B at r * 4 + t), so a lane reads its own row of the
+// block, and every lane of a wave the row c of a column it reduces, as one
+// 32-byte load (the latter a broadcast).  Two panels alternate: while the
+// other waves read block jb from one, the owner of block jb + 1 subtracts
+// block jb from it, finishes it (the 4 x 4 diagonal block in registers, rows
+// of the pivots through readlane) and publishes it in the other; then every
+// wave subtracts block jb from its later blocks.  One barrier per block.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+chol_quad_kernel(int k, double shift_coef, CPtrSet G, PtrSet R, StatSet st) {
+  __shared__ double4 P[2][64];  // P[buf][r]: row r of the published block
+  __shared__ int s_fail;
+  const int pb = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_fail = 0;  // ordered before other waves' writes by the first barrier
   const double* g = G.p[pb];
-  double* ri = Rinv.p[pb];
-  // lane c reads column c of G (coalesced rows, every load in flight at
-  // once; indices clamped so that no load leaves the k x k block)
-  const int cc = lane < k ? lane : k - 1;
-  double col[CW];
-#pragma unroll
-  for (int r = 0; r < CW; ++r) col[r] = g[(r < k ? r : k - 1) * k + cc];
-  double tr = 0.0;
-#pragma unroll
-  for (int r = 0; r < CW; ++r)
-    if (r == lane && r < k) tr = col[r];
+  double* ro = R.p[pb];
+  // the trace, by every wave in the same order
+  double tr = lane < k ? g[lane * k + lane] : 0.0;
   for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
   const double shift = shift_coef * tr;
-  // the upper triangle of G is the input (as in the wide form): row c of the
-  // lower factor's input is L_cr = G_rc (r <= c), zero elsewhere
-  double* li = L + lane * CWL;
-#pragma unroll
-  for (int r = 0; r < CW; ++r) li[r] = (r <= lane && lane < k) ? col[r] + (r == lane ? shift : 0.0) : 0.0;
-#pragma unroll
-  for (int r = CW; r < CWL; ++r) li[r] = 0.0;
-  __syncthreads();
   const double floor_v = (tr > 0.0 ? tr : 1.0) * 1e-300;
+  // v[i][t]: entry (lane, c) of column c = 4 (w + 4 i) + t; column c of the
+  // lower input is row c of G's upper triangle
+  double v[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 4 * (w + 4 * i) + t;
+      v[i][t] = (c < k && lane < k && lane >= c) ? g[c * k + lane] + (lane == c ? shift : 0.0) : 0.0;
+    }
   int fail = 0;
-  for (int j0 = 0; j0 < k; j0 += 4) {
-    double sv[4] = {li[j0], li[j0 + 1], li[j0 + 2], li[j0 + 3]};
-    dot4_lds(li, L + j0 * CWL, j0, sv);
+  // finish owned block i (already reduced by every earlier block), publish it
+  auto finish = [&](int i, double4* out) {
+    const int c0 = 4 * (w + 4 * i);
     double lb[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = j0 + b;
-      lb[b] = 0.0;
+    for (int t = 0; t < 4; ++t) {
+      const int j = c0 + t;
+      lb[t] = 0.0;
       if (j < k) {
-        double sb = sv[b];
+        double sb = v[i][t];
 #pragma unroll
-        for (int m = 0; m < b; ++m) sb -= lb[m] * readlane_f64(lb[m], j);
+        for (int m = 0; m < t; ++m) sb -= lb[m] * readlane_f64(lb[m], j);
         double d = readlane_f64(sb, j);
         if (!(d > floor_v)) { d = floor_v; fail = 1; }
         const double rinv = rsqrt(d), r = d * rinv;
-        lb[b] = lane == j ? r : (lane > j ? sb * rinv : 0.0);
-        if (lane == 0) rpiv[j] = rinv;
+        lb[t] = lane == j ? r : (lane > j ? sb * rinv : 0.0);
       }
+      v[i][t] = lb[t];
     }
-    if (lane < k) {
+    out[lane] = make_double4(lb[0], lb[1], lb[2], lb[3]);
+  };
+  // owned block i minus the published block (lr: this lane's row of it)
+  auto reduce = [&](int i, const double4& lr, const double4* pub) {
+    const int c0 = 4 * (w + 4 * i);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (j0 + b < k) li[j0 + b] = lb[b];
+    for (int t = 0; t < 4; ++t) {
+      const double4 lc = pub[c0 + t];
+      double x = v[i][t];
+      x = fma(-lr.x, lc.x, x);
+      x = fma(-lr.y, lc.y, x);
+      x = fma(-lr.z, lc.z, x);
+      x = fma(-lr.w, lc.w, x);
+      v[i][t] = x;
+    }
+  };
+  if (w == 0) finish(0, P[0]);
+  __syncthreads();
+  const int nblk = (k + 3) / 4;
+  for (int jb = 0; jb + 1 < nblk; ++jb) {
+    const int nb = jb + 1;
+    const double4* pub = P[jb & 1];
+    const double4 lr = pub[lane];
+    if ((nb & 3) == w) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (w + 4 * i == nb) {
+          reduce(i, lr, pub);
+          finish(i, P[nb & 1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int B = w + 4 * i;
+      if (B > nb && B < nblk) reduce(i, lr, pub);
     }
     __syncthreads();
   }
-  if (!want_inverse) {
-    // R itself (upper triangular, row-major): R_rc = L_cr
-    if (lane < k) {
+  // R_rc = L_cr: row c of R is column c of L
 #pragma unroll
-      for (int r = 0; r < CW; ++r)
-        if (r < k) ri[r * k + lane] = r <= lane ? li[r] : 0.0;
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 4 * (w + 4 * i) + t;
+      if (c < k && lane < k) ro[c * k + lane] = lane >= c ? v[i][t] : 0.0;
     }
-    if (fail && lane == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
-    return;
-  }
-  // forward substitution, rows in blocks of four:
-  //   x_i = (delta_ic - sum_{l<i} L_il x_l) / L_ii
-  double* xc = X + lane * CWL;
-  for (int i0 = 0; i0 < k; i0 += 4) {
-    double sv[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) sv[b] = lane == i0 + b ? 1.0 : 0.0;
-    dot4_lds(xc, L + i0 * CWL, i0, sv);
-    double xb[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      xb[b] = 0.0;
-      if (i0 + b < k) {
-        double sb = sv[b];
-#pragma unroll
-        for (int m = 0; m < b; ++m) sb -= L[(i0 + b) * CWL + i0 + m] * xb[m];
-        xb[b] = sb * rpiv[i0 + b];
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (i0 + b < k) xc[i0 + b] = xb[b];
-  }
+  if (fail) s_fail = 1;
   __syncthreads();
-  // lane c writes column c of R^{-1} (row r of R^{-1} is X's row r)
-  if (lane < k) {
-#pragma unroll
-    for (int r = 0; r < CW; ++r)
-      if (r < k) ri[r * k + lane] = X[r * CWL + lane];
-  }
-  if (fail && lane == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
+  if (s_fail && tid == 0 && st.p[pb]) st.p[pb]->chol_fail = 1;
 }
 
 hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet& G,
                           const PtrSet& Rinv, const StatSet& st, int nprob, bool want_inverse) {
-  if (!want_inverse && k > CW) return hipErrorInvalidValue;
+  if (!want_inverse && k > CHOL_WAVE_MAX) return hipErrorInvalidValue;
   if (nprob < 0 || nprob > MAXP || k < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   // dynamic LDS: packed R plus 16 columns of the inverse; 8 KiB of the CU's
@@ -266,9 +222,8 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
         !span_ok(st.p[i], sizeof(SolveStatus), "chol status"))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
-  if (k <= CW) {
-    hipLaunchKernelGGL(chol_wave_kernel, dim3(nprob), dim3(64), 0, s, k, shift_coef, G, Rinv, st,
-                       want_inverse ? 1 : 0);
+  if (!want_inverse) {
+    hipLaunchKernelGGL(chol_quad_kernel, dim3(nprob), dim3(256), 0, s, k, shift_coef, G, Rinv, st);
     return hipGetLastError();
   }
   static bool attr_set = false;
@@ -373,7 +328,7 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
 }
 
 hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob) {
-  if (nprob < 0 || nprob > MAXP || k < 1 || k > CW || n < 1) return hipErrorInvalidValue;
+  if (nprob < 0 || nprob > MAXP || k < 1 || k > CHOL_WAVE_MAX || n < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R"))

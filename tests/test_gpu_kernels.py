@@ -25,6 +25,8 @@ def _lib():
     lib.ctm_debug_tsgemm_dual.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int32] + \
         [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_void_p]
     lib.ctm_debug_tsgemm_dual.restype = ctypes.c_int
+    lib.ctm_debug_chol.argtypes = [ctypes.c_int32, ctypes.c_double] + [ctypes.c_void_p] * 5
+    lib.ctm_debug_chol.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
     lib.ctm_debug_corner_bf16.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16_packed.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 5
@@ -66,6 +68,60 @@ def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
     if tc == 2:
         tol = max(tol, 1e-2 * np.abs(ref).max())
     assert np.abs(got - ref).max() <= tol + 1e-300
+
+
+def _chol(lib, G, coef):
+    import torch
+    k = G.shape[0]
+    Gt = torch.tensor(G, dtype=torch.float64, device="cuda")
+    Rt = torch.full((k, k), 7.0, dtype=torch.float64, device="cuda")
+    work = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    fail = ctypes.c_int32(-1)
+    st = lib.ctm_debug_chol(k, coef, Gt.data_ptr(), Rt.data_ptr(), work.data_ptr(), ctypes.byref(fail),
+                            torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    return Rt.cpu().numpy(), fail.value
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 5, 17, 48, 63, 64])
+def test_chol_factor(gpu, k):
+    """Shifted Cholesky of the Cholesky-QR step against numpy's factor: a
+    well-conditioned Gram matrix without shift (only the upper triangle is
+    read: the strict lower one holds NaN), and a rank-deficient Gram matrix
+    with the first pass's shift, where R^T R must reproduce G + sI."""
+    lib = _lib()
+    rng = np.random.default_rng(100 + k)
+    print("chol case", k, flush=True)
+    Y = rng.standard_normal((300, k))
+    G = Y.T @ Y
+    Gn = G.copy()
+    Gn[np.tril_indices(k, -1)] = np.nan
+    R, fail = _chol(lib, Gn, 0.0)
+    assert fail == 0
+    Rnp = np.linalg.cholesky(np.triu(G) + np.triu(G, 1).T).T
+    assert np.array_equal(R, np.triu(R)) and (np.diag(R) > 0).all()
+    assert np.abs(R - Rnp).max() <= 1e-13 * np.abs(Rnp).max()
+    # rank k // 2 + 1: the shift keeps every pivot positive
+    Y2 = rng.standard_normal((300, k // 2 + 1)) @ rng.standard_normal((k // 2 + 1, k))
+    G2 = Y2.T @ Y2
+    G2 = np.triu(G2) + np.triu(G2, 1).T
+    u = 2.0 ** -53
+    coef = 11.0 * (300 * k + k * (k + 1)) * u
+    R2, fail2 = _chol(lib, G2, coef)
+    assert fail2 == 0
+    S = G2 + coef * np.trace(G2) * np.eye(k)
+    assert np.abs(R2.T @ R2 - S).max() <= 64 * k * u * np.trace(G2)
+
+
+def test_chol_reports_failure(gpu):
+    """A negative pivot sets the failure flag and the factor stays finite."""
+    lib = _lib()
+    k = 40
+    G = np.eye(k)
+    G[7, 7] = -1.0
+    R, fail = _chol(lib, G, 0.0)
+    assert fail == 1
+    assert np.isfinite(R).all()
 
 
 @pytest.mark.parametrize("M,N,K,transA", [(1728, 48, 1728, 0), (1728, 48, 1728, 1), (67, 45, 1030, 0),
