@@ -38,6 +38,14 @@ ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_
                             void* scratch, int64_t scratch_bytes, void* stream);
 
 /*
+ * Gram matrix of the solver's Cholesky-QR: G = Y^T Y (k x k row-major) for a
+ * row-major n x k float64 Y, 1 <= k <= 64, through part_elems doubles of
+ * device scratch `part` (at least k * k).  All buffers on the device.
+ */
+ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* Y, double* G, double* part,
+                          int64_t part_elems, void* stream);
+
+/*
  * Shifted Cholesky factor of the solver's Cholesky-QR: R upper triangular
  * (row-major k x k, positive diagonal) with R^T R = G + s I, s = shift_coef
  * * trace(G), for a symmetric k x k row-major G whose upper triangle is read

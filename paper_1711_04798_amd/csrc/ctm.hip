@@ -1052,7 +1052,14 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
       Ri.p[r] = rows[r].R->Rinv;
       st.p[r] = rows[r].R->st;
     }
-    CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
+    if (k <= 64) {
+      CPtrSet Ys{};
+      PtrSet Gp{};
+      for (size_t r = 0; r < P; ++r) { Ys.p[r] = Y[r]; Gp.p[r] = rows[r].R->G; }
+      HIPCHK(gram_small(s, n, k, Ys, Gp, (int)P, x.splitk, x.splitk_elems));
+    } else {
+      CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
+    }
     if (k <= CHOL_WAVE_MAX) {
       // R itself, then Y <- Y R^{-1} by substitution in place
       HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P, false));
@@ -3417,6 +3424,21 @@ ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A
   g.C[0] = C;
   g2.C[0] = C2;
   hipError_t e = ts_gemm(s, F32, F32, M, N, K, va, rowmajor(N), rowmajor(N), g, 1, scratch, scratch_bytes, &g2);
+  if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "scratch too small");
+  HIPCHK(e);
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
+ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* Y, double* G, double* part, int64_t part_elems,
+                          void* stream) {
+  if (n < 1 || k < 1 || k > 64 || !Y || !G || !part) return fail(CTM_E_INVALID, "args");
+  hipStream_t s = (hipStream_t)stream;
+  CPtrSet y{};
+  PtrSet g{};
+  y.p[0] = Y;
+  g.p[0] = G;
+  hipError_t e = gram_small(s, n, k, y, g, 1, part, part_elems);
   if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "scratch too small");
   HIPCHK(e);
   HIPCHK(ssync(s));

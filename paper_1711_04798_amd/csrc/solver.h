@@ -43,6 +43,12 @@ hipError_t chol_shift_inv(hipStream_t s, int k, double shift_coef, const CPtrSet
 // Largest k of the four-wave Cholesky (R alone) and of trsm_rows.
 constexpr int CHOL_WAVE_MAX = 64;
 
+// G = Y^T Y (k x k row-major) for each problem's n x k row-major float64 Y,
+// k <= 64.  part: device scratch of part_elems doubles for the per-chunk
+// partial sums (at least k * k * nprob; more allows shorter chunks).
+hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
+                      int64_t part_elems);
+
 // Y <- Y R^{-1} in place, Y n x k row-major, R k x k upper triangular
 // row-major (k <= 64), for each problem.
 hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob);

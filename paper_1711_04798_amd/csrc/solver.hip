@@ -343,6 +343,127 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
 }
 
 // ---------------------------------------------------------------------------
+// Gram matrix of a tall block, k <= 64: G = Y^T Y.  A work-group takes a
+// chunk of 4 rpw rows, wave w the rows w rpw .. (w + 1) rpw - 1 of it.  Four
+// rows of Y are one K step of the float64 MFMA for both operands: lane l
+// loads Y[r + l / 16][16 b + l % 16] once per column block b, which is the
+// A operand of the tiles (b, .) (A = Y^T) and the B operand of the tiles
+// (., b).  Only the tiles on and above the block diagonal are formed; wave 0
+// adds the other waves' tiles (through LDS) in wave order and writes them
+// with their mirror images as the chunk's partial k x k sum.  A second kernel adds the
+// chunks in order (64 entries per work-group, a quarter of the chunks per
+// wave, the four quarter sums in order).
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KB>
+__global__ void __launch_bounds__(256)
+gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet Y, double* __restrict__ part, int nchunks) {
+  constexpr int NTL = KB * (KB + 1) / 2;
+  __shared__ v4d red[3][NTL][64];  // waves 1..3
+  const int pb = blockIdx.y, chunk = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lg = lane >> 4;
+  const double* __restrict__ y = Y.p[pb];
+  v4d acc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = ((int64_t)chunk * 4 + w) * rpw;
+  for (int s0 = 0; s0 < rpw; s0 += 16) {
+    // four K steps: every load first, then the products
+    double f[4][KB];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t r = r0 + s0 + 4 * st + lg;
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int c = 16 * b + lr;
+        f[st][b] = (r < n && c < k) ? y[r * k + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      int t = 0;
+#pragma unroll
+      for (int i = 0; i < KB; ++i)
+#pragma unroll
+        for (int j = i; j < KB; ++j) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[st][i], f[st][j], acc[t], 0, 0, 0);
+          ++t;
+        }
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) red[w - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (w != 0) return;
+  // tile t = (i, j): lane l, value q is entry (16 i + l / 16 + 4 q, 16 j + l % 16)
+  double* __restrict__ P = part + ((int64_t)pb * nchunks + chunk) * k * k;
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < KB; ++i)
+#pragma unroll
+    for (int j = i; j < KB; ++j) {
+      const v4d v = ((acc[t] + red[0][t][lane]) + red[1][t][lane]) + red[2][t][lane];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = 16 * i + lg + 4 * q, b = 16 * j + lr;
+        if (a < k && b < k) {
+          P[a * k + b] = v[q];
+          if (i != j) P[b * k + a] = v[q];
+        }
+      }
+      ++t;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+gram_reduce_kernel(const double* __restrict__ part, int nchunks, int k, PtrSet G) {
+  __shared__ double q4[4][64];
+  const int pb = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kk = k * k, e = blockIdx.x * 64 + lane;
+  const double* __restrict__ p = part + (int64_t)pb * nchunks * kk;
+  const int per = (nchunks + 3) / 4, c0 = w * per, c1 = min(nchunks, c0 + per);
+  double acc = 0.0;
+  if (e < kk)
+    for (int c = c0; c < c1; ++c) acc += p[(int64_t)c * kk + e];
+  q4[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < kk) G.p[pb][e] = ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
+}
+
+hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
+                      int64_t part_elems) {
+  if (nprob < 0 || nprob > MAXP || k < 1 || k > 64 || n < 1) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
+  const int64_t kk = (int64_t)k * k;
+  const int64_t cap = part_elems / (kk * nprob);  // chunks the scratch holds
+  if (cap < 1) return hipErrorInvalidValue;
+  // rows per wave: multiples of 16, as few as the scratch allows
+  const int64_t rpw = 16 * std::max<int64_t>(1, (n + 64 * cap - 1) / (64 * cap));
+  const int64_t nchunks = (n + 4 * rpw - 1) / (4 * rpw);
+  if (nchunks > cap || rpw > INT32_MAX) return hipErrorInvalidValue;
+  for (int i = 0; i < nprob; ++i)
+    if (!span_ok(Y.p[i], (size_t)n * k * 8, "gram Y") || !span_ok(G.p[i], (size_t)kk * 8, "gram G"))
+      return hipErrorInvalidValue;
+  if (!span_ok(part, (size_t)nchunks * kk * nprob * 8, "gram partials")) return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const dim3 g1((unsigned)nchunks, (unsigned)nprob);
+  switch ((k + 15) / 16) {
+    case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
+    case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
+    case 3: hipLaunchKernelGGL(gram_partial_kernel<3>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
+    default: hipLaunchKernelGGL(gram_partial_kernel<4>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((kk + 63) / 64), (unsigned)nprob), dim3(256), 0, s, part,
+                     (int)nchunks, k, G);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of a k x k matrix, one workgroup per
 // problem (Golub & Van Loan, Sec. 8.6.3; Hestenes 1958).  Columns are kept
 // column-major (in LDS when they fit) and rotated in pairs of the round-robin

@@ -27,6 +27,9 @@ def _lib():
     lib.ctm_debug_tsgemm_dual.restype = ctypes.c_int
     lib.ctm_debug_chol.argtypes = [ctypes.c_int32, ctypes.c_double] + [ctypes.c_void_p] * 5
     lib.ctm_debug_chol.restype = ctypes.c_int
+    lib.ctm_debug_gram.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_void_p] * 3 + \
+        [ctypes.c_int64, ctypes.c_void_p]
+    lib.ctm_debug_gram.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
     lib.ctm_debug_corner_bf16.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16_packed.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 5
@@ -68,6 +71,30 @@ def test_gemm(gpu, ta, tc, M, N, K, transA, transB):
     if tc == 2:
         tol = max(tol, 1e-2 * np.abs(ref).max())
     assert np.abs(got - ref).max() <= tol + 1e-300
+
+
+@pytest.mark.parametrize("n,k,part", [(1728, 48, 64), (5184, 64, 64), (100, 17, 64), (4, 1, 64), (65, 64, 64),
+                                        (1, 3, 64), (1728, 48, 1), (5184, 33, 3), (37, 16, 64)])
+def test_gram_small(gpu, n, k, part):
+    """Gram matrix of a tall block against numpy: chunks of 64 rows (and of
+    more rows per wave when the scratch holds fewer chunks: part = partial
+    sums the scratch holds), ragged row and column blocks, k from 1 to 64;
+    the result is exactly symmetric."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(n + 3 * k)
+    Y = rng.standard_normal((n, k))
+    Yt = torch.tensor(Y, dtype=torch.float64, device="cuda")
+    Gt = torch.full((k, k), 7.0, dtype=torch.float64, device="cuda")
+    P = torch.full((part * k * k,), float("nan"), dtype=torch.float64, device="cuda")
+    print("gram case", n, k, part, flush=True)
+    st = lib.ctm_debug_gram(n, k, Yt.data_ptr(), Gt.data_ptr(), P.data_ptr(), P.numel(),
+                            torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    G = Gt.cpu().numpy()
+    ref = Y.T @ Y
+    assert np.abs(G - ref).max() <= 4 * n * 2.0 ** -53 * np.abs(Y).max() ** 2
+    assert np.array_equal(G, G.T)
 
 
 def _chol(lib, G, coef):
