@@ -228,4 +228,21 @@ hipError_t nonfinite(hipStream_t s, const double* x, int64_t n, int* flag);
 // (splitmix64 of seed + index, Box-Muller).
 hipError_t randn(hipStream_t s, double* out, int64_t n, uint64_t seed);
 
+// sum_{i < count} p[i * stride], added in order i = 0, 1, ... from zero, with
+// eight loads in flight (a loop of dependent load-add steps would wait for
+// memory once per term)
+template <typename T>
+__device__ __forceinline__ T ordered_sum(const T* __restrict__ p, int count, int64_t stride) {
+  T acc = 0;
+  for (int i0 = 0; i0 < count; i0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i0 + u < count ? p[(int64_t)(i0 + u) * stride] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < count) acc += v[u];
+  }
+  return acc;
+}
+
 }  // namespace ctmk

@@ -311,9 +311,8 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int ksplit
   const int64_t per = (int64_t)gridDim.x * (blockDim.x >> 3);
   for (int64_t e0 = (int64_t)blockIdx.x * (blockDim.x >> 3); e0 < MN; e0 += per) {
     const int64_t e = e0 + (threadIdx.x >> 3);  // uniform trip count over the block: all lanes shuffle
-    double acc = 0.0;
-    if (e < MN)
-      for (int sp = t; sp < ksplit; sp += 8) acc += p[(int64_t)sp * MN + e];
+    double acc = (e < MN && t < ksplit) ? ordered_sum(p + (int64_t)t * MN + e, (ksplit - t + 7) / 8, 8 * MN)
+                                         : 0.0;
     acc += __shfl_xor(acc, 1, 8);
     acc += __shfl_xor(acc, 2, 8);
     acc += __shfl_xor(acc, 4, 8);

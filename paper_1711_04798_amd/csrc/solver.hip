@@ -425,9 +425,7 @@ gram_reduce_kernel(const double* __restrict__ part, int nchunks, int k, PtrSet G
   const int kk = k * k, e = blockIdx.x * 64 + lane;
   const double* __restrict__ p = part + (int64_t)pb * nchunks * kk;
   const int per = (nchunks + 3) / 4, c0 = w * per, c1 = min(nchunks, c0 + per);
-  double acc = 0.0;
-  if (e < kk)
-    for (int c = c0; c < c1; ++c) acc += p[(int64_t)c * kk + e];
+  const double acc = e < kk ? ordered_sum(p + (int64_t)c0 * kk + e, c1 - c0, kk) : 0.0;
   q4[w][lane] = acc;
   __syncthreads();
   if (w == 0 && e < kk) G.p[pb][e] = ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
@@ -850,8 +848,7 @@ residual_final_kernel(int64_t n, int k, int nb, int chi, double cutoff, double t
   __shared__ double s_res[256];
   const double* p = nb > 0 ? part + (size_t)pb * nb * k : nullptr;
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += p[(size_t)b * k + c];
+    const double t = nb > 0 ? ordered_sum(p + c, nb, k) : 0.0;
     s_res[c] = sqrt(t);
   }
   __syncthreads();

@@ -324,8 +324,7 @@ __global__ void ts_reduce_kernel(const T* __restrict__ part, int32_t M, int32_t 
   TO* __restrict__ C = (TO*)g.C[gi];
   const int64_t MN = (int64_t)M * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
-    T acc = 0;
-    for (int s = 0; s < nsplit; ++s) acc += p[(int64_t)s * MN + e];
+    const T acc = ordered_sum(p + e, nsplit, MN);
     const int64_t m = e / N, n = e - m * N;
     C[m * ldc + n] = (TO)acc;
   }
@@ -340,8 +339,7 @@ __global__ void ts_reduce2_kernel(const float* __restrict__ part, int32_t M, int
   double* __restrict__ C2 = (double*)g2.C[gi];
   const int64_t MN = (int64_t)M * N;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
-    float acc = 0;
-    for (int s = 0; s < nsplit; ++s) acc += p[(int64_t)s * MN + e];
+    const float acc = ordered_sum(p + e, nsplit, MN);
     const int64_t m = e / N, n = e - m * N;
     C[m * ldc + n] = acc;
     C2[m * ldc + n] = (double)acc;
