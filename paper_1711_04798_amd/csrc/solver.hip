@@ -594,11 +594,18 @@ __device__ int jacobi_sweeps(int k, int kc, double* gA, bool want_vectors, doubl
         b = sum16(b);
         g = sum16(g);
         if (fmin(a, b) > noise && g * g > eps2 * (a * b)) {
-          // tangent of the smaller angle that zeroes g (Rutishauser's form of
-          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g)
-          const double d = b - a;
-          const double tn = (d >= 0 ? 2.0 * g : -2.0 * g) / (fabs(d) + sqrt(d * d + 4.0 * g * g));
-          const double c = rsqrt(1.0 + tn * tn), sn = c * tn;
+          // the smaller angle that zeroes g (Rutishauser's form of the
+          // tangent, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta =
+          // (b - a) / 2g), without a division: with d = b - a, h =
+          // sqrt(d^2 + 4 g^2) and e = |d| + h, t = 2 g sign(d) / e, so
+          // c = 1 / sqrt(1 + t^2) = e / sqrt(e^2 + 4 g^2) and s = c t =
+          // 2 g sign(d) / sqrt(e^2 + 4 g^2).  Both square roots come from
+          // reciprocal square roots, the second exactly normalising (c, s).
+          const double d = b - a, g2 = 2.0 * g;
+          const double h2 = fma(d, d, g2 * g2);
+          const double e = fabs(d) + h2 * rsqrt(h2);
+          const double r = rsqrt(fma(e, e, g2 * g2));
+          const double c = e * r, sn = (d >= 0 ? g2 : -g2) * r;
 #pragma unroll
           for (int t = 0; t < NRL; ++t) {
             cp[ql + 16 * t] = c * xp[t] - sn * xq[t];
