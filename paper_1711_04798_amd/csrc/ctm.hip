@@ -177,6 +177,7 @@ struct Inst {
   bool staleT[4][MAXPOS] = {};
   void* bT3[MAXT][4] = {};       // bf16 mode: [hi | lo | hi] split of bT, N x 3K
   void* bTp[MAXT][4] = {};       // bf16 mode: bT in the corner kernel's packed fragment layout
+  void* bT3p[MAXT][4] = {};      // bf16 mode: bT3 in that layout (the absorption's B operand)
   double* Ac[MAXT] = {};         // complex kets (real, imaginary interleaved)
   // single-layer mode: the ket (Sk) and bra (Sb) tensor of each rotation in
   // the working type, legs [L'][U'][s][D'][R'] of the rotated frame
@@ -386,7 +387,10 @@ void plan(ctm_ctx_s& x, Arena& ar) {
           I.bT[t][r] = ar.take_bytes(a8 * dtype_size(BF16));
           I.bT3[t][r] = ar.take_bytes(3 * a8 * dtype_size(BF16));
           const int64_t K4 = (int64_t)I.D2 * I.D2;
-          if (K4 % 8 == 0) I.bTp[t][r] = ar.take_bytes((size_t)corner_bf16_packed_b_elems(K4, K4) * 2);
+          if (K4 % 8 == 0) {
+            I.bTp[t][r] = ar.take_bytes((size_t)corner_bf16_packed_b_elems(K4, K4) * 2);
+            I.bT3p[t][r] = ar.take_bytes((size_t)corner_bf16_packed_b_elems(K4, 3 * K4) * 2);
+          }
         }
       }
     }
@@ -1349,6 +1353,11 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
     // below reads it that way: element (m, n) at (m / c) K4 c + m % c + n c
     // (four consecutive c2 per 16-byte store)
     const bool to_t = at == F32 && D2 >= 2 && I0.rows[0].W2t;
+    // the double layer's split in the packed fragment layout when every
+    // instance of the class has it
+    bool b3p = corner_packed_b();
+    for (Inst* I : insts)
+      for (int t = 0; t < MAXT; ++t) b3p = b3p && (I->bT3[t][0] == nullptr || I->bT3p[t][0] != nullptr);
     G g3x;
     for (Inst* I : insts) {
       Roles ro{&x, I, k};
@@ -1356,13 +1365,14 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
         Row& R = I->rows[yp];
         // W1 as c matrices [(l,u)][c2] -> A3[(g,c2)][hi | hi | lo over (l,u)]
         if (!a3_done) HIPCHK(split3_transpose_bf16(s, (const float*)R.W1, c, K4, c, true, R.A3));
-        g3x.add(R.A3, I->bT3[ro.tid(xp, yp)][(k + 0) % 4], to_t ? R.W2t : R.W2);
+        const int tt = ro.tid(xp, yp), rr = (k + 0) % 4;
+        g3x.add(R.A3, b3p ? I->bT3p[tt][rr] : I->bT3[tt][rr], to_t ? R.W2t : R.W2);
       }
     }
     const View vw2 = to_t ? View{c, 1, K4 * c, INT64_MAX / 4, c, 0} : rowmajor(K4);
     for (int j0 = 0; j0 < g3x.size(); j0 += MAXG) {
       int cnt = std::min(MAXG, g3x.size() - j0);
-      HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, vw2, g3x.group(j0, cnt), cnt, F32));
+      HIPCHK(corner_bf16(s, c * c, K4, 3 * K4, vw2, g3x.group(j0, cnt), cnt, F32, 0, b3p));
     }
     w2t_done = to_t;
   } else {
@@ -2736,6 +2746,8 @@ static ctm_status init_impl(const ctm_config* cfg, const double* const* A_dev, c
           if (split3_bf16(x->stream, F64, I.b64[t][r], transposed(rowmajor(K4)), K4, K4, false, I.bT3[t][r]) !=
               hipSuccess)
             return cleanup(fail(CTM_E_HIP, "split double layer"));
+          if (I.bT3p[t][r] && corner_bf16_pack_b(x->stream, I.bT3[t][r], K4, 3 * K4, I.bT3p[t][r]) != hipSuccess)
+            return cleanup(fail(CTM_E_HIP, "pack split double layer"));
         }
     }
     st = init_env(*x, I, i, init, spectrum_host);
