@@ -640,7 +640,16 @@ hipError_t corner_bf16(hipStream_t s, int64_t M, int64_t N, int64_t K, const Vie
   Aux aux{split_stride, 0, 0, 0};
   const Launch L{grid, s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt, (int32_t)nt, (int32_t)tiles,
                  (int32_t)per_xcd, aux};
-  if (tout == BF16 && split_stride > 0) launch<__bf16, OUT_SPLIT, false, false>(L);
+  if (tout == BF16 && use_dma && tiles < 256) {
+    // fewer 256-row tiles than CUs: 128 rows per work-group (the same K
+    // order per element, bitwise equal)
+    const int64_t mt2 = (M + 127) / 128, tiles2 = mt2 * nt * groups, px2 = (tiles2 + 7) / 8;
+    const Launch L2{dim3((unsigned)(8 * px2)), s, (int32_t)M, (int32_t)N, (int32_t)K, ov, g, (int32_t)mt2,
+                    (int32_t)nt, (int32_t)tiles2, (int32_t)px2, aux};
+    if (split_stride > 0) launch<__bf16, OUT_SPLIT, false, false, 2>(L2);
+    else if (v4) launch<__bf16, OUT_V4, false, false, 2>(L2);
+    else launch<__bf16, OUT_PLAIN, false, false, 2>(L2);
+  } else if (tout == BF16 && split_stride > 0) launch<__bf16, OUT_SPLIT, false, false>(L);
   else if (tout == BF16 && v4) launch<__bf16, OUT_V4, false, false>(L);
   else if (tout == BF16) launch<__bf16, OUT_PLAIN, false, false>(L);
   else if (use_dma)

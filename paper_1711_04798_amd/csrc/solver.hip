@@ -270,6 +270,14 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
   __shared__ double rdq[KP];  // 1 / R_jj (1 past k)
   const int pb = blockIdx.y, tid = threadIdx.x;
   const double* __restrict__ r = R.p[pb];
+  // this lane's part of its row of Y, loaded before R is staged so that the
+  // two loads' latencies overlap
+  const int lane = tid & 63, s = lane & 3;
+  const int64_t row = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + (lane >> 2);
+  double* __restrict__ yr = Y.p[pb] + min<int64_t>(row, n - 1) * k;
+  double tv[NT4];
+#pragma unroll
+  for (int t = 0; t < NT4; ++t) tv[t] = yr[min(4 * t + s, k - 1)];
   {
     constexpr int PER = (KP * KP + 255) / 256;
     double rv[PER];
@@ -293,17 +301,9 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
     }
   }
   __syncthreads();
-  const int lane = tid & 63, s = lane & 3;
-  const int64_t row = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + (lane >> 2);
-  double* __restrict__ yr = Y.p[pb] + min<int64_t>(row, n - 1) * k;
   double y[NT4];
-  {
-    double tv[NT4];
 #pragma unroll
-    for (int t = 0; t < NT4; ++t) tv[t] = yr[min(4 * t + s, k - 1)];
-#pragma unroll
-    for (int t = 0; t < NT4; ++t) y[t] = 4 * t + s < k ? tv[t] : 0.0;
-  }
+  for (int t = 0; t < NT4; ++t) y[t] = 4 * t + s < k ? tv[t] : 0.0;
   const double* rq = Rq + s * NT4;
 #pragma unroll
   for (int j = 0; j < KP; ++j) {
