@@ -1215,8 +1215,8 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     for (int it = 0; it + 1 < maxit; ++it) {
       CHK(napply(x, n, k, rows, V, Yb, LV, false));
       CHK(orthonormalize(x, n, k, rows, Yb, 1));
-      CHK(napply(x, n, k, rows, Yb, Z, UU, true));
-      CHK(copy_blocks(V, Z));
+      // V is not read again before it is replaced: N^T orth(N V) goes there
+      CHK(napply(x, n, k, rows, Yb, V, UU, true));
       CHK(orthonormalize(x, n, k, rows, V, ortho_passes));
     }
     CHK(rr_iteration(x.resid_step));
