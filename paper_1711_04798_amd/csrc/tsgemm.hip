@@ -190,11 +190,14 @@ __device__ __forceinline__ float comp(const float4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-template <int NT, bool AK>
+// R row blocks of 16 per wave (R = 2: twice the waves for the same K
+// chunks).  m-fast A: lane l reads R consecutive rows per K step (16 or 8
+// bytes), value q feeding row block q, which holds rows m0 + R r' + q.
+template <int NT, bool AK, int R = 4>
 __global__ void __launch_bounds__(256, 2)
 ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int32_t kchunk, int32_t nsplit,
                  int32_t mtiles, int32_t ntasks, GemmGroup g, float* __restrict__ part) {
-  constexpr int R = 4;
+  static_assert(R == 4 || R == 2, "row blocks per wave");
   const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= ntasks) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -208,7 +211,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   const float* arow[R];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb)
-    arow[rb] = AK ? A + (int64_t)min(m0 + rb * 16 + lr, M - 1) * lda : A + min(m0 + 4 * lr, M - 4);
+    arow[rb] = AK ? A + (int64_t)min(m0 + rb * 16 + lr, M - 1) * lda : A + min(m0 + R * lr, M - R);
   int ncol[NT];
 #pragma unroll
   for (int cb = 0; cb < NT; ++cb) ncol[cb] = min(cb * 16 + lr, N - 1);
@@ -217,7 +220,8 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   for (int rb = 0; rb < R; ++rb)
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
-  float4 a[3][R];
+  constexpr int NA = AK ? R : 4;  // A loads per K block
+  float4 a[3][NA];
   float b[3][NT][4];
   // K block t of the chunk into ring slot st.  Addresses are clamped to the
   // chunk's last four columns, so the loads carry no condition and no select
@@ -227,8 +231,14 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   auto load = [&](int st, int t) {
     const int kc = min(kbeg + t * 16 + 4 * lg, kend - 4);  // kend - kbeg >= 4, multiples of 4
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-      a[st][j] = *reinterpret_cast<const float4*>(AK ? arow[j] + kc : arow[0] + (int64_t)(kc + j) * lda);
+    for (int j = 0; j < NA; ++j) {
+      if constexpr (AK || R == 4) {
+        a[st][j] = *reinterpret_cast<const float4*>(AK ? arow[j] + kc : arow[0] + (int64_t)(kc + j) * lda);
+      } else {
+        const float2 v = *reinterpret_cast<const float2*>(arow[0] + (int64_t)(kc + j) * lda);
+        a[st][j] = make_float4(v.x, v.y, 0.f, 0.f);
+      }
+    }
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
@@ -237,8 +247,8 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   // ragged last block: lane groups past the chunk end contribute zeros
   auto mask = [&](int st, bool kin) {
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb)
-      if (!kin) a[st][rb] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < NA; ++j)
+      if (!kin) a[st][j] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int cb = 0; cb < NT; ++cb)
 #pragma unroll
@@ -258,7 +268,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
   // following block, the loads spread evenly among its MFMAs: issued in a
   // burst between MFMA blocks, the same loads leave the matrix cores idle
   // about half the time
-  constexpr int NL = R + 4 * NT;                  // loads per block
+  constexpr int NL = NA + 4 * NT;                 // loads per block
   constexpr int NM = 4 * R * NT;                  // MFMAs per block
   auto region = [&](int ls, int lt, int cs) {
     load(ls, lt);
@@ -310,7 +320,7 @@ ts_stream_kernel(int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int3
       const int n = cb * 16 + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = AK ? m0 + rb * 16 + 4 * lg + q : m0 + 16 * lg + 4 * q + rb;
+        const int m = AK ? m0 + rb * 16 + 4 * lg + q : m0 + R * (4 * lg + q) + rb;
         if (m < M && n < N) P[(int64_t)m * N + n] = acc[rb][cb][q];
       }
     }
@@ -372,6 +382,26 @@ static bool stream_form() {
   static const bool v = [] {
     const char* e = std::getenv("CTM_TS_FORM");
     return !(e && std::strcmp(e, "lds") == 0);
+  }();
+  return v;
+}
+
+// rows per wave of the register-streaming form for k-fast and m-fast A:
+// 32 (CTM_TS_ROWS=64, CTM_TS_ROWS_M=64 select 64).  With about one wave per
+// SIMD at the split counts the tuner picks, a 64-row wave spent half its
+// time waiting for its loads; 32-row waves double the waves per SIMD for the
+// same K chunks and partials
+static int ts_rows_ak() {
+  static const int v = [] {
+    const char* e = std::getenv("CTM_TS_ROWS");
+    return e && std::atoi(e) == 64 ? 64 : 32;
+  }();
+  return v;
+}
+static int ts_rows_mk() {
+  static const int v = [] {
+    const char* e = std::getenv("CTM_TS_ROWS_M");
+    return e && std::atoi(e) == 64 ? 64 : 32;
   }();
   return v;
 }
@@ -470,9 +500,10 @@ static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N,
   const int32_t M32 = (int32_t)M, N32 = (int32_t)N, K32 = (int32_t)K, kc32 = (int32_t)kchunk,
                 ns32 = (int32_t)nsplit, mt32 = (int32_t)mtiles;
   if (ta == F32 && vec && N <= 64 && stream_form()) {
-    // register-streaming form: 64 rows per wave, K chunks of whole
-    // three-block groups, about 2048 waves
-    const int64_t mt64 = (M + 63) / 64;
+    // register-streaming form: 32 or 64 rows per wave, K chunks of whole
+    // three-block groups, about target waves
+    const int rows = ak ? ts_rows_ak() : ts_rows_mk();
+    const int64_t mt64 = (M + rows - 1) / rows;
     int64_t ns2 = std::max<int64_t>(1, std::min<int64_t>((target + mt64 * groups - 1) / (mt64 * groups), K / 48));
     while (ns2 > 1 && ts_gemm_scratch_elems(M, N, groups, (int)ns2) * 4 > scratch_bytes) ns2 /= 2;
     int64_t kc2 = ((K + ns2 - 1) / ns2 + 47) / 48 * 48;
@@ -482,20 +513,22 @@ static hipError_t ts_gemm_v(hipStream_t s, int ta, int tc, int64_t M, int64_t N,
       const int64_t ntasks = mt64 * ns2 * groups;
       dim3 g2((unsigned)((ntasks + 3) / 4));
       const int nt2 = (int)((N + 15) / 16);
+#define TS2_LAUNCH(NTV, AKV, RV)                                                                           \
+  hipLaunchKernelGGL((ts_stream_kernel<NTV, AKV, RV>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb,         \
+                     (int32_t)kc2, (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch)
 #define TS2_CASE(NTV)                                                                                        \
   case NTV:                                                                                                  \
-    if (ak)                                                                                                  \
-      hipLaunchKernelGGL((ts_stream_kernel<NTV, true>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb,          \
-                         (int32_t)kc2, (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);        \
-    else                                                                                                     \
-      hipLaunchKernelGGL((ts_stream_kernel<NTV, false>), g2, dim3(256), 0, s, M32, N32, K32, lda, ldb,         \
-                         (int32_t)kc2, (int32_t)ns2, (int32_t)mt64, (int32_t)ntasks, g, (float*)scratch);        \
+    if (ak && rows == 32) TS2_LAUNCH(NTV, true, 2);                                                          \
+    else if (ak) TS2_LAUNCH(NTV, true, 4);                                                                   \
+    else if (rows == 32) TS2_LAUNCH(NTV, false, 2);                                                          \
+    else TS2_LAUNCH(NTV, false, 4);                                                                          \
     break;
       switch (nt2) {
         TS2_CASE(1) TS2_CASE(2) TS2_CASE(3) TS2_CASE(4)
         default: return hipErrorInvalidValue;
       }
 #undef TS2_CASE
+#undef TS2_LAUNCH
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       nsplit = ns2;
