@@ -975,9 +975,11 @@ struct SolveRow {
 // false) or N^T = Q3 Q4 Q1 Q2 (true).  `mid` receives the product after the
 // first two factors (Lh^T in, or Uh in).  in/out/mid float64 n x k.  With
 // nfac = 2 only mid is formed.
+// in_cast false: the rows' float32 input (qin) already holds `in` rounded
+// (written by the orthonormalisation that produced it).
 ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
                   const std::vector<double*>& in, const std::vector<double*>& out,
-                  const std::vector<double*>& mid, bool transposeN, int nfac = 4) {
+                  const std::vector<double*>& mid, bool transposeN, int nfac = 4, bool in_cast = true) {
   hipStream_t s = x.stream;
   const int qt = x.qt;
   const View vq = transposeN ? rowmajor(n) : transposed(rowmajor(n));
@@ -1003,7 +1005,7 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
   // reduced precision: cast in, apply in the Q type, mid and out in float64.
   // Where the float32 tall-skinny kernel takes the second product, its
   // reduction writes mid beside the float32 result; elsewhere a conversion.
-  {
+  if (in_cast) {
     Xfer cv;
     for (size_t r = 0; r < P; ++r) cv.add(in[r], rows[r].R->qin, (int64_t)n * k);
     CHK(xfer_run(s, F64, qt, cv));
@@ -1039,8 +1041,10 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
 // Y <- Y R^{-1} `passes` times with R from the shifted Cholesky factor of Y^T Y
 // (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020); up to
 // 64 columns by substitution with R, otherwise through R^{-1} and a product.
+// With to_qin (k <= 64 only), the last pass also writes Y rounded to float32
+// into each row's N-apply input (what napply's cast would write).
 ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
-                          const std::vector<double*>& Y, int passes = 3) {
+                          const std::vector<double*>& Y, int passes = 3, bool to_qin = false) {
   hipStream_t s = x.stream;
   const size_t P = rows.size();
   const double u = 1.1102230246251565e-16;
@@ -1070,7 +1074,9 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
       PtrSet Ys{};
       CPtrSet Rs{};
       for (size_t r = 0; r < P; ++r) { Ys.p[r] = Y[r]; Rs.p[r] = rows[r].R->Rinv; }
-      HIPCHK(trsm_rows(s, n, k, Ys, Rs, (int)P));
+      PtrSet q32{};
+      for (size_t r = 0; r < P; ++r) q32.p[r] = (double*)rows[r].R->qin;
+      HIPCHK(trsm_rows(s, n, k, Ys, Rs, (int)P, (to_qin && pass + 1 == passes) ? &q32 : nullptr));
       continue;
     }
     HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P));
@@ -1126,7 +1132,10 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   // well conditioned: Cholesky-QR twice orthonormalises it to rounding level.
   // The fixed-count iteration only takes its span (the first application of
   // N is orthonormalised afresh), so one pass is enough there
-  CHK(orthonormalize(x, n, k, rows, V, adaptive ? 2 : 1));
+  // the orthonormalisations that feed an N-application write its float32
+  // input themselves (k <= 64, float32 Q), and that application skips its cast
+  const bool q32 = x.qt == F32 && k <= CHOL_WAVE_MAX;
+  CHK(orthonormalize(x, n, k, rows, V, adaptive ? 2 : 1, q32));
   std::vector<SolveStatus> hst(P);
   auto copy_blocks = [&](std::vector<double*>& dst, const std::vector<double*>& src) -> ctm_status {
     Xfer cp;
@@ -1137,7 +1146,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   // left vectors U = Q U_R, right vectors V' = V W_R, Z = N^T U and the
   // residuals |Z_i - S_i V'_i|.
   auto rr_iteration = [&](bool want_resid) -> ctm_status {
-    CHK(napply(x, n, k, rows, V, Yb, LV, false));          // Y = N V, LV = Lh^T V
+    CHK(napply(x, n, k, rows, V, Yb, LV, false, 4, !q32));  // Y = N V, LV = Lh^T V
     CHK(copy_blocks(Qb, Yb));
     CHK(orthonormalize(x, n, k, rows, Qb, ortho_passes));  // Q = orth(Y)
     {
@@ -1203,7 +1212,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       for (size_t r = 0; r < P; ++r) all = all && hst[r].converged;
       if (all) break;
       CHK(copy_blocks(V, Z));
-      CHK(orthonormalize(x, n, k, rows, V));
+      CHK(orthonormalize(x, n, k, rows, V, 3, q32));
     }
   } else {
     // fixed count: plain subspace iterations V <- orth(N^T orth(N V)), then
@@ -1213,11 +1222,11 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     // here; they are formed on the last column step of a sweep (and of every
     // single move) as the accuracy record of the solver.
     for (int it = 0; it + 1 < maxit; ++it) {
-      CHK(napply(x, n, k, rows, V, Yb, LV, false));
-      CHK(orthonormalize(x, n, k, rows, Yb, 1));
+      CHK(napply(x, n, k, rows, V, Yb, LV, false, 4, !q32));
+      CHK(orthonormalize(x, n, k, rows, Yb, 1, q32));
       // V is not read again before it is replaced: N^T orth(N V) goes there
-      CHK(napply(x, n, k, rows, Yb, V, UU, true));
-      CHK(orthonormalize(x, n, k, rows, V, ortho_passes));
+      CHK(napply(x, n, k, rows, Yb, V, UU, true, 4, !q32));
+      CHK(orthonormalize(x, n, k, rows, V, ortho_passes, q32));
     }
     CHK(rr_iteration(x.resid_step));
   }

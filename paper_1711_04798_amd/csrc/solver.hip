@@ -263,7 +263,7 @@ __device__ __forceinline__ double dpp_f64(double v) {
 
 template <int KP>
 __global__ void __launch_bounds__(256)
-trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
+trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R, PtrSet Y32, int w32) {
   constexpr int NT4 = KP / 4;
   // Rq[(4 j + s) NT4 + t] = R[j][4 t + s] for j < 4 t + s < k, else 0
   __shared__ __attribute__((aligned(16))) double Rq[KP * KP];
@@ -324,21 +324,31 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R) {
 #pragma unroll
     for (int t = 0; t < NT4; ++t)
       if (4 * t + s < k) yr[4 * t + s] = y[t];
+    if (w32) {
+      float* __restrict__ y32 = (float*)Y32.p[pb] + row * k;
+#pragma unroll
+      for (int t = 0; t < NT4; ++t)
+        if (4 * t + s < k) y32[4 * t + s] = (float)y[t];
+    }
   }
 }
 
-hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob) {
+hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob,
+                     const PtrSet* Y32) {
   if (nprob < 0 || nprob > MAXP || k < 1 || k > CHOL_WAVE_MAX || n < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
-    if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R"))
+    if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R") ||
+        (Y32 && (!Y32->p[i] || !span_ok(Y32->p[i], (size_t)n * k * 4, "trsm Y32"))))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
+  const PtrSet y32 = Y32 ? *Y32 : PtrSet{};
+  const int w32 = Y32 ? 1 : 0;
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)nprob);
-  if (k <= 16) hipLaunchKernelGGL(trsm_quad_kernel<16>, grid, dim3(256), 0, s, n, k, Y, R);
-  else if (k <= 32) hipLaunchKernelGGL(trsm_quad_kernel<32>, grid, dim3(256), 0, s, n, k, Y, R);
-  else if (k <= 48) hipLaunchKernelGGL(trsm_quad_kernel<48>, grid, dim3(256), 0, s, n, k, Y, R);
-  else hipLaunchKernelGGL(trsm_quad_kernel<64>, grid, dim3(256), 0, s, n, k, Y, R);
+  if (k <= 16) hipLaunchKernelGGL(trsm_quad_kernel<16>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
+  else if (k <= 32) hipLaunchKernelGGL(trsm_quad_kernel<32>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
+  else if (k <= 48) hipLaunchKernelGGL(trsm_quad_kernel<48>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
+  else hipLaunchKernelGGL(trsm_quad_kernel<64>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
   return hipGetLastError();
 }
 
