@@ -1339,16 +1339,18 @@ ctm_status absorb_rows(ctm_ctx_s& x, const std::vector<Inst*>& insts, int k, int
       // at (g c + c2) 3 K4 + l D2 + u, the copies K4 apart; with u the fast
       // output column, 16 lanes store 16 consecutive entries
       G g3b;
+      std::vector<Split3Job> sj;
       for (Inst* I : insts) {
         Roles ro{&x, I, k};
         for (int yp = 0; yp < ly; ++yp) {
           Row& R = I->rows[yp];
           Row& Rp = I->rows[pmod(yp - 1, ly)];
-          HIPCHK(split3_bf16(s, F64, ro.T(3, xp, yp), rowmajor(c), c * D2, c, true, R.T3s));
-          HIPCHK(split3_bf16(s, F64, Rp.P2T, view2(D2, c, 1, BIG, D2 * c, 0), D2 * c, c, false, R.P3s));
+          sj.push_back(Split3Job{ro.T(3, xp, yp), rowmajor(c), true, R.T3s});
+          sj.push_back(Split3Job{Rp.P2T, view2(D2, c, 1, BIG, D2 * c, 0), false, R.P3s});
           g3b.add(R.T3s, R.P3s, R.A3);
         }
       }
+      HIPCHK(split3_bf16_group(s, sj.data(), (int)sj.size(), c * D2, c));
       const View va3 = view2(D2, D2, c * 3 * K4, D2, 1, 3 * K4);
       for (int j0 = 0; j0 < g3b.size(); j0 += MAXG) {
         int cnt = std::min(MAXG, g3b.size() - j0);

@@ -99,6 +99,14 @@ bool corner_bf16_supported(int64_t M, int64_t N, int64_t K);
 // row-major rows x 3K.  tin = F32 or F64.
 hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, int64_t rows, int64_t K, bool a_side,
                        void* out);
+// Several float64 splits of one shape (rows x K) in grouped launches.
+struct Split3Job {
+  const void* in;
+  View view;
+  bool a_side;
+  void* out;
+};
+hipError_t split3_bf16_group(hipStream_t s, const Split3Job* jobs, int njobs, int64_t rows, int64_t K);
 // The same for float32 `in` = nb matrices [R][C] (row-major, batch-major),
 // transposed on the way: out row (b, c) = split of in[b][.][c], length 3R.
 hipError_t split3_transpose_bf16(hipStream_t s, const float* in, int64_t nb, int64_t R, int64_t C, bool a_side,

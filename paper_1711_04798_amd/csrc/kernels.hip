@@ -1037,20 +1037,70 @@ hipError_t normalize_group(hipStream_t s, const NormSet& x, int njobs, double* p
 // ---------------------------------------------------------------------------
 // three-term bf16 split (see kernels.h)
 // ---------------------------------------------------------------------------
+// one element: o[0], o[K], o[2K] of its output row
+__device__ __forceinline__ void split3_store(double x, int a_side, __bf16* o, int64_t K) {
+  const __bf16 hi = (__bf16)(float)x;
+  const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+  o[0] = hi;
+  o[K] = a_side ? hi : lo;
+  o[2 * K] = a_side ? lo : hi;
+}
+
 template <typename TI>
 __global__ void split3_kernel(const TI* __restrict__ in, DevView v, int64_t rows, int64_t K, int a_side,
                               __bf16* __restrict__ out) {
   const int64_t n = rows * K;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / K, k = e - r * K;
-    const double x = (double)in[row_off(v, (int32_t)r) + col_off(v, (int32_t)k)];
-    const __bf16 hi = (__bf16)(float)x;
-    const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
-    __bf16* o = out + r * 3 * K + k;
-    o[0] = hi;
-    o[K] = a_side ? hi : lo;
-    o[2 * K] = a_side ? lo : hi;
+    split3_store((double)in[row_off(v, (int32_t)r) + col_off(v, (int32_t)k)], a_side, out + r * 3 * K + k, K);
   }
+}
+
+// several float64 splits of one shape, job = blockIdx.y
+constexpr int MAXJ3 = 8;
+struct Split3Set {
+  const double* in[MAXJ3];
+  __bf16* out[MAXJ3];
+  DevView v[MAXJ3];
+  int a_side[MAXJ3];
+};
+
+__global__ void split3_group_kernel(Split3Set j, int64_t rows, int64_t K) {
+  const int q = blockIdx.y;
+  const double* __restrict__ in = j.in[q];
+  __bf16* __restrict__ out = j.out[q];
+  const DevView v = j.v[q];
+  const int a_side = j.a_side[q];
+  const int64_t n = rows * K;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / K, k = e - r * K;
+    split3_store(in[row_off(v, (int32_t)r) + col_off(v, (int32_t)k)], a_side, out + r * 3 * K + k, K);
+  }
+}
+
+hipError_t split3_bf16_group(hipStream_t s, const Split3Job* jobs, int njobs, int64_t rows, int64_t K) {
+  if (njobs < 0 || rows <= 0 || K <= 0 || rows > INT32_MAX || K > INT32_MAX) return hipErrorInvalidValue;
+  for (int i = 0; i < njobs; ++i)
+    if (!span_ok(jobs[i].in, (size_t)(view_max(jobs[i].view, rows, K) + 1) * 8, "split3 in") ||
+        !span_ok(jobs[i].out, (size_t)rows * 3 * K * 2, "split3 out"))
+      return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(8192, (rows * K + 255) / 256);
+  for (int j0 = 0; j0 < njobs; j0 += MAXJ3) {
+    const int cnt = std::min(MAXJ3, njobs - j0);
+    Split3Set set{};
+    for (int i = 0; i < cnt; ++i) {
+      const Split3Job& jb = jobs[j0 + i];
+      set.in[i] = (const double*)jb.in;
+      set.out[i] = (__bf16*)jb.out;
+      set.v[i] = dev_view(jb.view, rows, K);
+      set.a_side[i] = jb.a_side ? 1 : 0;
+    }
+    hipLaunchKernelGGL(split3_group_kernel, dim3((unsigned)blocks, (unsigned)cnt), dim3(256), 0, s, set, rows, K);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t split3_bf16(hipStream_t s, int tin, const void* in, const View& vin, int64_t rows, int64_t K, bool a_side,
