@@ -39,10 +39,12 @@ ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_
 
 /*
  * Gram matrix of the solver's Cholesky-QR: G = Y^T Y (k x k row-major) for a
- * row-major n x k float64 Y, 1 <= k <= 64, through part_elems doubles of
- * device scratch `part` (at least k * k).  All buffers on the device.
+ * row-major n x k float64 Y, 1 <= k <= 64 (X null); or the Rayleigh-Ritz
+ * product G = X^T Y of two such blocks, 1 <= k <= 48.  Through part_elems
+ * doubles of device scratch `part` (at least k * k).  All buffers on the
+ * device.
  */
-ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* Y, double* G, double* part,
+ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* X, const double* Y, double* G, double* part,
                           int64_t part_elems, void* stream);
 
 /*

@@ -1149,7 +1149,12 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
     CHK(napply(x, n, k, rows, V, Yb, LV, false, 4, !q32));  // Y = N V, LV = Lh^T V
     CHK(copy_blocks(Qb, Yb));
     CHK(orthonormalize(x, n, k, rows, Qb, ortho_passes));  // Q = orth(Y)
-    {
+    if (k <= 48) {
+      CPtrSet Qs{}, Ys{};
+      PtrSet Rs{};
+      for (size_t r = 0; r < P; ++r) { Qs.p[r] = Qb[r]; Ys.p[r] = Yb[r]; Rs.p[r] = rows[r].R->Rm; }
+      HIPCHK(gram_cross_small(s, n, k, Qs, Ys, Rs, (int)P, x.splitk, x.splitk_elems));
+    } else {
       G g;
       for (size_t r = 0; r < P; ++r) g.add(Qb[r], Yb[r], rows[r].R->Rm);
       CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), g));
@@ -3453,15 +3458,16 @@ ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A
   return CTM_OK;
 }
 
-ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* Y, double* G, double* part, int64_t part_elems,
-                          void* stream) {
-  if (n < 1 || k < 1 || k > 64 || !Y || !G || !part) return fail(CTM_E_INVALID, "args");
+ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* X, const double* Y, double* G, double* part,
+                          int64_t part_elems, void* stream) {
+  if (n < 1 || k < 1 || k > (X ? 48 : 64) || !Y || !G || !part) return fail(CTM_E_INVALID, "args");
   hipStream_t s = (hipStream_t)stream;
-  CPtrSet y{};
+  CPtrSet x{}, y{};
   PtrSet g{};
+  x.p[0] = X;
   y.p[0] = Y;
   g.p[0] = G;
-  hipError_t e = gram_small(s, n, k, y, g, 1, part, part_elems);
+  hipError_t e = X ? gram_cross_small(s, n, k, x, y, g, 1, part, part_elems) : gram_small(s, n, k, y, g, 1, part, part_elems);
   if (e == hipErrorInvalidValue) return fail(CTM_E_INVALID, "scratch too small");
   HIPCHK(e);
   HIPCHK(ssync(s));

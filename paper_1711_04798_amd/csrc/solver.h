@@ -48,6 +48,9 @@ constexpr int CHOL_WAVE_MAX = 64;
 // partial sums (at least k * k * nprob; more allows shorter chunks).
 hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
                       int64_t part_elems);
+// G = X^T Y for two n x k row-major float64 blocks, k <= 48, the same way.
+hipError_t gram_cross_small(hipStream_t s, int64_t n, int k, const CPtrSet& X, const CPtrSet& Y, const PtrSet& G,
+                            int nprob, double* part, int64_t part_elems);
 
 // Y <- Y R^{-1} in place, Y n x k row-major, R k x k upper triangular
 // row-major (k <= 64), for each problem; with Y32, the result rounded to

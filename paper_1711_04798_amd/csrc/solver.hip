@@ -353,7 +353,8 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
 }
 
 // ---------------------------------------------------------------------------
-// Gram matrix of a tall block, k <= 64: G = Y^T Y.  A work-group takes a
+// Gram matrix of a tall block, k <= 64: G = Y^T Y (and the cross form
+// G = X^T Y of two blocks, k <= 48).  A work-group takes a
 // chunk of 4 rpw rows, wave w the rows w rpw .. (w + 1) rpw - 1 of it.  Four
 // rows of Y are one K step of the float64 MFMA for both operands: lane l
 // loads Y[r + l / 16][16 b + l % 16] once per column block b, which is the
@@ -366,13 +367,17 @@ hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPt
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KB>
+// SYM: G = Y^T Y (X = Y, tiles on and above the block diagonal, mirrored);
+// otherwise G = X^T Y (every tile; k <= 48 so that the LDS of the three
+// waves' tiles stays within 64 KiB)
+template <int KB, bool SYM>
 __global__ void __launch_bounds__(256)
-gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet Y, double* __restrict__ part, int nchunks) {
-  constexpr int NTL = KB * (KB + 1) / 2;
+gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet X, CPtrSet Y, double* __restrict__ part, int nchunks) {
+  constexpr int NTL = SYM ? KB * (KB + 1) / 2 : KB * KB;
   __shared__ v4d red[3][NTL][64];  // waves 1..3
   const int pb = blockIdx.y, chunk = blockIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 15, lg = lane >> 4;
+  const double* __restrict__ x = X.p[pb];
   const double* __restrict__ y = Y.p[pb];
   v4d acc[NTL];
 #pragma unroll
@@ -380,14 +385,16 @@ gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet Y, double* __restrict__ p
   const int64_t r0 = ((int64_t)chunk * 4 + w) * rpw;
   for (int s0 = 0; s0 < rpw; s0 += 16) {
     // four K steps: every load first, then the products
-    double f[4][KB];
+    double fx[4][KB], fy[4][KB];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const int64_t r = r0 + s0 + 4 * st + lg;
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int c = 16 * b + lr;
-        f[st][b] = (r < n && c < k) ? y[r * k + c] : 0.0;
+        const bool in = r < n && c < k;
+        fx[st][b] = in ? x[r * k + c] : 0.0;
+        if constexpr (!SYM) fy[st][b] = in ? y[r * k + c] : 0.0;
       }
     }
 #pragma unroll
@@ -396,8 +403,8 @@ gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet Y, double* __restrict__ p
 #pragma unroll
       for (int i = 0; i < KB; ++i)
 #pragma unroll
-        for (int j = i; j < KB; ++j) {
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[st][i], f[st][j], acc[t], 0, 0, 0);
+        for (int j = SYM ? i : 0; j < KB; ++j) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fx[st][i], SYM ? fx[st][j] : fy[st][j], acc[t], 0, 0, 0);
           ++t;
         }
     }
@@ -414,14 +421,14 @@ gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet Y, double* __restrict__ p
 #pragma unroll
   for (int i = 0; i < KB; ++i)
 #pragma unroll
-    for (int j = i; j < KB; ++j) {
+    for (int j = SYM ? i : 0; j < KB; ++j) {
       const v4d v = ((acc[t] + red[0][t][lane]) + red[1][t][lane]) + red[2][t][lane];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int a = 16 * i + lg + 4 * q, b = 16 * j + lr;
         if (a < k && b < k) {
           P[a * k + b] = v[q];
-          if (i != j) P[b * k + a] = v[q];
+          if (SYM && i != j) P[b * k + a] = v[q];
         }
       }
       ++t;
@@ -441,9 +448,10 @@ gram_reduce_kernel(const double* __restrict__ part, int nchunks, int k, PtrSet G
   if (w == 0 && e < kk) G.p[pb][e] = ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
 }
 
-hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
-                      int64_t part_elems) {
-  if (nprob < 0 || nprob > MAXP || k < 1 || k > 64 || n < 1) return hipErrorInvalidValue;
+// X == nullptr: the symmetric form (G = Y^T Y, k <= 64); else G = X^T Y (k <= 48)
+static hipError_t gram_launch(hipStream_t s, int64_t n, int k, const CPtrSet* X, const CPtrSet& Y, const PtrSet& G,
+                              int nprob, double* part, int64_t part_elems) {
+  if (nprob < 0 || nprob > MAXP || k < 1 || k > (X ? 48 : 64) || n < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   const int64_t kk = (int64_t)k * k;
   const int64_t cap = part_elems / (kk * nprob);  // chunks the scratch holds
@@ -453,22 +461,39 @@ hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const P
   const int64_t nchunks = (n + 4 * rpw - 1) / (4 * rpw);
   if (nchunks > cap || rpw > INT32_MAX) return hipErrorInvalidValue;
   for (int i = 0; i < nprob; ++i)
-    if (!span_ok(Y.p[i], (size_t)n * k * 8, "gram Y") || !span_ok(G.p[i], (size_t)kk * 8, "gram G"))
+    if (!span_ok(Y.p[i], (size_t)n * k * 8, "gram Y") || !span_ok(G.p[i], (size_t)kk * 8, "gram G") ||
+        (X && !span_ok(X->p[i], (size_t)n * k * 8, "gram X")))
       return hipErrorInvalidValue;
   if (!span_ok(part, (size_t)nchunks * kk * nprob * 8, "gram partials")) return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   const dim3 g1((unsigned)nchunks, (unsigned)nprob);
+  const CPtrSet Xs = X ? *X : Y;
+  const int r = (int)rpw, nc = (int)nchunks;
+#define GRAM_CASE(KBV)                                                                                      \
+  case KBV:                                                                                                 \
+    if (X) hipLaunchKernelGGL((gram_partial_kernel<KBV, false>), g1, dim3(256), 0, s, n, k, r, Xs, Y, part, nc); \
+    else hipLaunchKernelGGL((gram_partial_kernel<KBV, true>), g1, dim3(256), 0, s, n, k, r, Xs, Y, part, nc);    \
+    break;
   switch ((k + 15) / 16) {
-    case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
-    case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
-    case 3: hipLaunchKernelGGL(gram_partial_kernel<3>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
-    default: hipLaunchKernelGGL(gram_partial_kernel<4>, g1, dim3(256), 0, s, n, k, (int)rpw, Y, part, (int)nchunks); break;
+    GRAM_CASE(1) GRAM_CASE(2) GRAM_CASE(3)
+    default: hipLaunchKernelGGL((gram_partial_kernel<4, true>), g1, dim3(256), 0, s, n, k, r, Xs, Y, part, nc); break;
   }
+#undef GRAM_CASE
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((kk + 63) / 64), (unsigned)nprob), dim3(256), 0, s, part,
                      (int)nchunks, k, G);
   return hipGetLastError();
+}
+
+hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
+                      int64_t part_elems) {
+  return gram_launch(s, n, k, nullptr, Y, G, nprob, part, part_elems);
+}
+
+hipError_t gram_cross_small(hipStream_t s, int64_t n, int k, const CPtrSet& X, const CPtrSet& Y, const PtrSet& G,
+                            int nprob, double* part, int64_t part_elems) {
+  return gram_launch(s, n, k, &X, Y, G, nprob, part, part_elems);
 }
 
 // ---------------------------------------------------------------------------

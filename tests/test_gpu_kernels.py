@@ -27,7 +27,7 @@ def _lib():
     lib.ctm_debug_tsgemm_dual.restype = ctypes.c_int
     lib.ctm_debug_chol.argtypes = [ctypes.c_int32, ctypes.c_double] + [ctypes.c_void_p] * 5
     lib.ctm_debug_chol.restype = ctypes.c_int
-    lib.ctm_debug_gram.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_void_p] * 3 + \
+    lib.ctm_debug_gram.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_void_p] * 4 + \
         [ctypes.c_int64, ctypes.c_void_p]
     lib.ctm_debug_gram.restype = ctypes.c_int
     lib.ctm_debug_corner_bf16.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p] * 4
@@ -79,7 +79,8 @@ def test_gram_small(gpu, n, k, part):
     """Gram matrix of a tall block against numpy: chunks of 64 rows (and of
     more rows per wave when the scratch holds fewer chunks: part = partial
     sums the scratch holds), ragged row and column blocks, k from 1 to 64;
-    the result is exactly symmetric."""
+    the result is exactly symmetric.  For k <= 48 also the cross form X^T Y
+    of the Rayleigh-Ritz step."""
     import torch
     lib = _lib()
     rng = np.random.default_rng(n + 3 * k)
@@ -88,13 +89,24 @@ def test_gram_small(gpu, n, k, part):
     Gt = torch.full((k, k), 7.0, dtype=torch.float64, device="cuda")
     P = torch.full((part * k * k,), float("nan"), dtype=torch.float64, device="cuda")
     print("gram case", n, k, part, flush=True)
-    st = lib.ctm_debug_gram(n, k, Yt.data_ptr(), Gt.data_ptr(), P.data_ptr(), P.numel(),
+    st = lib.ctm_debug_gram(n, k, None, Yt.data_ptr(), Gt.data_ptr(), P.data_ptr(), P.numel(),
                             torch.cuda.current_stream().cuda_stream)
     assert st == 0
     G = Gt.cpu().numpy()
     ref = Y.T @ Y
     assert np.abs(G - ref).max() <= 4 * n * 2.0 ** -53 * np.abs(Y).max() ** 2
     assert np.array_equal(G, G.T)
+    if k <= 48:
+        # the cross form X^T Y (every tile formed)
+        X = rng.standard_normal((n, k))
+        Xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+        Gt.fill_(7.0)
+        P.fill_(float("nan"))
+        st = lib.ctm_debug_gram(n, k, Xt.data_ptr(), Yt.data_ptr(), Gt.data_ptr(), P.data_ptr(), P.numel(),
+                                torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        ref = X.T @ Y
+        assert np.abs(Gt.cpu().numpy() - ref).max() <= 4 * n * 2.0 ** -53 * np.abs(X).max() * np.abs(Y).max()
 
 
 def _chol(lib, G, coef):
