@@ -617,6 +617,24 @@ ctm_status gemm_long(ctm_ctx_s& x, int ta, int tc, int64_t M, int64_t N, int64_t
   return CTM_OK;
 }
 
+// C = A B, (n x K)(K x N) float64 row-major, for every problem of g: the
+// small-matrix kernel for K, N <= 64, the generic GEMM otherwise
+ctm_status rmul_run(ctm_ctx_s& x, int64_t n, int K, int N, const G& g) {
+  if (K > 64 || N > 64) return gemm_run(x.stream, F64, F64, n, N, K, rowmajor(K), rowmajor(N), rowmajor(N), g);
+  for (int j0 = 0; j0 < g.size(); j0 += MAXP) {
+    const int cnt = std::min(MAXP, g.size() - j0);
+    CPtrSet a{}, b{};
+    PtrSet c{};
+    for (int i = 0; i < cnt; ++i) {
+      a.p[i] = (const double*)g.A[j0 + i];
+      b.p[i] = (const double*)g.B[j0 + i];
+      c.p[i] = (double*)g.C[j0 + i];
+    }
+    HIPCHK(rmul_small(x.stream, n, K, N, a, b, c, cnt));
+  }
+  return CTM_OK;
+}
+
 ctm_status gemm_sk(ctm_ctx_s& x, int64_t M, int64_t N, int64_t K, const View& va, const View& vb,
                    const View& vc, const G& g) {
   for (int j0 = 0; j0 < g.size(); j0 += MAXG) {
@@ -1188,7 +1206,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
         gq.add(V[r], R->WR, Vpv[r]);   // V' = V W_R
         gq.add(LV[r], R->WR, R->tmp);  // Lh^T V' = (Lh^T V) W_R
       }
-      CHK(gemm_run(s, F64, F64, n, k, k, rowmajor(k), rowmajor(k), rowmajor(k), gq));
+      CHK(rmul_run(x, n, k, k, gq));
       Xfer cp;
       for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
       CHK(xfer_run(s, F64, F64, cp));
@@ -1256,7 +1274,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       gp.add(LV[r], R->Wp, R->P1);
       gp.add(UU[r], R->Up, R->P2T);
     }
-    CHK(gemm_run(s, F64, F64, n, chi, k, rowmajor(k), rowmajor(chi), rowmajor(chi), gp));
+    CHK(rmul_run(x, n, k, chi, gp));
     // keep the right vectors and status for the next solve on the same cut
     static_assert(sizeof(SolveStatus) % 8 == 0, "status copied as 8-byte words");
     Xfer cp;

@@ -435,6 +435,83 @@ gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet X, CPtrSet Y, double* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// C = A B for row-major float64 A (n x K), B (K x N), C (n x N), K and N up to
+// 64: one wave per 16 rows of C, every fragment loaded straight from memory
+// (lane l: A[r + l % 16][4 s + l / 16] for K step s, B[4 s + l / 16][16 j +
+// l % 16] for column block j), all loads issued before the products.
+// ---------------------------------------------------------------------------
+template <int KS, int NB>
+__global__ void __launch_bounds__(256)
+rmul_small_kernel(int64_t n, int K, int N, CPtrSet A, CPtrSet B, PtrSet C) {
+  const int pb = blockIdx.y, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (r0 >= n) return;  // whole wave
+  const double* __restrict__ a = A.p[pb];
+  const double* __restrict__ b = B.p[pb];
+  double* __restrict__ c = C.p[pb];
+  const int64_t ra = r0 + lr;
+  double fa[KS], fb[KS][NB];
+#pragma unroll
+  for (int st = 0; st < KS; ++st) {
+    const int ka = 4 * st + lg;
+    fa[st] = (ra < n && ka < K) ? a[ra * K + ka] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int cb = 16 * j + lr;
+      fb[st][j] = (ka < K && cb < N) ? b[ka * N + cb] : 0.0;
+    }
+  }
+  v4d acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st], fb[st][j], acc[j], 0, 0, 0);
+  // lane l, value q: row r0 + l / 16 + 4 q, column 16 j + l % 16
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int cb = 16 * j + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + lg + 4 * q;
+      if (r < n && cb < N) c[r * N + cb] = acc[j][q];
+    }
+  }
+}
+
+hipError_t rmul_small(hipStream_t s, int64_t n, int K, int N, const CPtrSet& A, const CPtrSet& B, const PtrSet& C,
+                      int nprob) {
+  if (nprob < 0 || nprob > MAXP || n < 1 || K < 1 || K > 64 || N < 1 || N > 64) return hipErrorInvalidValue;
+  if (nprob == 0) return hipSuccess;
+  for (int i = 0; i < nprob; ++i)
+    if (!span_ok(A.p[i], (size_t)n * K * 8, "rmul A") || !span_ok(B.p[i], (size_t)K * N * 8, "rmul B") ||
+        !span_ok(C.p[i], (size_t)n * N * 8, "rmul C"))
+      return hipErrorInvalidValue;
+  if (dry_run()) return hipSuccess;
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)nprob);
+  const int ks = (K + 15) / 16, nb = (N + 15) / 16;
+#define RMUL(KSV, NBV) \
+  hipLaunchKernelGGL((rmul_small_kernel<4 * KSV, NBV>), grid, dim3(256), 0, s, n, K, N, A, B, C)
+#define RMUL_N(KSV)                  \
+  switch (nb) {                      \
+    case 1: RMUL(KSV, 1); break;     \
+    case 2: RMUL(KSV, 2); break;     \
+    case 3: RMUL(KSV, 3); break;     \
+    default: RMUL(KSV, 4); break;    \
+  }
+  switch (ks) {
+    case 1: RMUL_N(1); break;
+    case 2: RMUL_N(2); break;
+    case 3: RMUL_N(3); break;
+    default: RMUL_N(4); break;
+  }
+#undef RMUL_N
+#undef RMUL
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256)
 gram_reduce_kernel(const double* __restrict__ part, int nchunks, int k, PtrSet G) {
   __shared__ double q4[4][64];
