@@ -38,6 +38,14 @@ ctm_status ctm_debug_tsgemm(int32_t ta, int32_t tc, int64_t M, int64_t N, int64_
                             void* scratch, int64_t scratch_bytes, void* stream);
 
 /*
+ * C = A B for row-major float64 A (n x K), B (K x N), C (n x N) on the
+ * solver's small right-multiplication kernel (1 <= K, N <= 64; device
+ * buffers).
+ */
+ctm_status ctm_debug_rmul(int64_t n, int32_t K, int32_t N, const double* A, const double* B, double* C,
+                          void* stream);
+
+/*
  * Gram matrix of the solver's Cholesky-QR: G = Y^T Y (k x k row-major) for a
  * row-major n x k float64 Y, 1 <= k <= 64 (X null); or the Rayleigh-Ritz
  * product G = X^T Y of two such blocks, 1 <= k <= 48.  Through part_elems

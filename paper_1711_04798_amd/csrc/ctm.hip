@@ -3476,6 +3476,19 @@ ctm_status ctm_debug_tsgemm_dual(int64_t M, int64_t N, int64_t K, const float* A
   return CTM_OK;
 }
 
+ctm_status ctm_debug_rmul(int64_t n, int32_t K, int32_t N, const double* A, const double* B, double* C, void* stream) {
+  if (n < 1 || K < 1 || K > 64 || N < 1 || N > 64 || !A || !B || !C) return fail(CTM_E_INVALID, "args");
+  hipStream_t s = (hipStream_t)stream;
+  CPtrSet a{}, b{};
+  PtrSet c{};
+  a.p[0] = A;
+  b.p[0] = B;
+  c.p[0] = C;
+  HIPCHK(rmul_small(s, n, K, N, a, b, c, 1));
+  HIPCHK(ssync(s));
+  return CTM_OK;
+}
+
 ctm_status ctm_debug_gram(int64_t n, int32_t k, const double* X, const double* Y, double* G, double* part,
                           int64_t part_elems, void* stream) {
   if (n < 1 || k < 1 || k > (X ? 48 : 64) || !Y || !G || !part) return fail(CTM_E_INVALID, "args");

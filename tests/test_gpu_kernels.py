@@ -25,6 +25,8 @@ def _lib():
     lib.ctm_debug_tsgemm_dual.argtypes = [ctypes.c_int64] * 3 + [ctypes.c_void_p, ctypes.c_int32] + \
         [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_void_p]
     lib.ctm_debug_tsgemm_dual.restype = ctypes.c_int
+    lib.ctm_debug_rmul.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32] + [ctypes.c_void_p] * 4
+    lib.ctm_debug_rmul.restype = ctypes.c_int
     lib.ctm_debug_chol.argtypes = [ctypes.c_int32, ctypes.c_double] + [ctypes.c_void_p] * 5
     lib.ctm_debug_chol.restype = ctypes.c_int
     lib.ctm_debug_gram.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_void_p] * 4 + \
@@ -107,6 +109,26 @@ def test_gram_small(gpu, n, k, part):
         assert st == 0
         ref = X.T @ Y
         assert np.abs(Gt.cpu().numpy() - ref).max() <= 4 * n * 2.0 ** -53 * np.abs(X).max() * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("n,K,N", [(1728, 48, 48), (5184, 64, 64), (100, 17, 33), (7, 1, 1), (65, 64, 5),
+                                   (16, 3, 64)])
+def test_rmul_small(gpu, n, K, N):
+    """The solver's right-multiplication by a small matrix against numpy:
+    ragged row, K and column blocks."""
+    import torch
+    lib = _lib()
+    rng = np.random.default_rng(n + 5 * K + 11 * N)
+    A = rng.standard_normal((n, K))
+    B = rng.standard_normal((K, N))
+    At = torch.tensor(A, dtype=torch.float64, device="cuda")
+    Bt = torch.tensor(B, dtype=torch.float64, device="cuda")
+    Ct = torch.full((n, N), 7.0, dtype=torch.float64, device="cuda")
+    print("rmul case", n, K, N, flush=True)
+    st = lib.ctm_debug_rmul(n, K, N, At.data_ptr(), Bt.data_ptr(), Ct.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    assert np.abs(Ct.cpu().numpy() - A @ B).max() <= 4 * K * 2.0 ** -53 * np.abs(A).max() * np.abs(B).max()
 
 
 def _chol(lib, G, coef):
