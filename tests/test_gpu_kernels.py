@@ -185,6 +185,53 @@ def test_chol_reports_failure(gpu):
     assert np.isfinite(R).all()
 
 
+TS64_RUN = r"""
+import ctypes, sys
+import numpy as np
+import torch
+sys.path.insert(0, %(root)r)
+from paper_1711_04798_amd import binding
+lib = binding.load()
+lib.ctm_debug_tsgemm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_int64, ctypes.c_void_p]
+worst = 0.0
+for M, N, K, transA in ((1728, 48, 1728, 0), (1728, 48, 1728, 1), (68, 45, 1036, 0), (68, 45, 1036, 1),
+                        (1000, 64, 772, 1)):
+    rng = np.random.default_rng(M + N + K + transA)
+    A = rng.standard_normal((K, M) if transA else (M, K))
+    B = rng.standard_normal((K, N))
+    At = torch.tensor(A, dtype=torch.float32, device="cuda")
+    Bt = torch.tensor(B, dtype=torch.float32, device="cuda")
+    Ct = torch.full((M, N), 7.0, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    assert lib.ctm_debug_tsgemm(1, 1, M, N, K, At.data_ptr(), transA, Bt.data_ptr(), Ct.data_ptr(),
+                                scratch.data_ptr(), scratch.numel(), torch.cuda.current_stream().cuda_stream) == 0
+    Ar = At.double().cpu().numpy(); Br = Bt.double().cpu().numpy()
+    ref = (Ar.T if transA else Ar) @ Br
+    err = np.abs(Ct.double().cpu().numpy() - ref).max() / (np.abs(Ar).max() * np.abs(Br).max() * K)
+    worst = max(worst, err)
+print(worst)
+"""
+
+
+def test_tsgemm_64_rows(gpu):
+    """The streaming form with 64 rows per wave (CTM_TS_ROWS=64 and
+    CTM_TS_ROWS_M=64: four row blocks, m-fast A in 16-byte loads) against
+    numpy, both layouts of A, ragged K blocks (the default runs 32 rows)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    env.update({"CTM_TS_ROWS": "64", "CTM_TS_ROWS_M": "64"})
+    print("tsgemm 64-row run", flush=True)
+    r = subprocess.run([sys.executable, "-c", TS64_RUN % {"root": root}], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert float(r.stdout.strip().splitlines()[-1]) <= 2e-6
+
+
 @pytest.mark.parametrize("M,N,K,transA", [(1728, 48, 1728, 0), (1728, 48, 1728, 1), (67, 45, 1030, 0),
                                           (700, 192, 2500, 1), (4, 3, 8, 0)])
 def test_tsgemm_dual_output(gpu, M, N, K, transA):
