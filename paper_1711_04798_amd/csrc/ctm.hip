@@ -1729,8 +1729,12 @@ ctm_status corner_spectra(ctm_ctx_s& x, const std::vector<Inst*>& insts, bool fi
       W.p[j] = x.spec_tmp_W + (size_t)j * c2;
       J.p[j] = x.spec_tmp_J + (size_t)j * 2 * chi * ((chi + 15) / 16 * 16);
     }
-    // corner singular values far below the solver cutoff carry no information
-    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, cnt, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff));
+    // corner singular values far below the solver cutoff carry no information;
+    // with reduced-precision contractions the rotations stop at a column
+    // cosine of 1e-8, far below the spectra's own rounding (as in the
+    // solver's Rayleigh-Ritz step)
+    HIPCHK(jacobi_svd(s, chi, M, U, S, W, J, cnt, false, false, nullptr, 1e-2 * x.cfg.svd_cutoff,
+                      x.qt != F64 ? 1e-8 : 0.0));
   }
   for (size_t i0 = 0; i0 < insts.size(); i0 += MAXP) {
     int cnt = (int)std::min<size_t>(MAXP, insts.size() - i0);
