@@ -1198,18 +1198,22 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
       HIPCHK(jacobi_svd(s, k, M, U, S, W, J, (int)P, true, true, &stj, 1e-2 * c.svd_cutoff, rot_rel));
     }
     {
-      // three products of one shape per row, one grouped launch
+      // three products of one shape per row, one grouped launch; the small
+      // kernel (k <= 64) may write in place, so Lh^T V' replaces Lh^T V there
+      const bool in_place = k <= 64;
       G gq;
       for (size_t r = 0; r < P; ++r) {
         Row* R = rows[r].R;
         gq.add(Qb[r], R->UR, Ub[r]);   // U  = Q U_R
         gq.add(V[r], R->WR, Vpv[r]);   // V' = V W_R
-        gq.add(LV[r], R->WR, R->tmp);  // Lh^T V' = (Lh^T V) W_R
+        gq.add(LV[r], R->WR, in_place ? (void*)LV[r] : R->tmp);  // Lh^T V' = (Lh^T V) W_R
       }
       CHK(rmul_run(x, n, k, k, gq));
-      Xfer cp;
-      for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
-      CHK(xfer_run(s, F64, F64, cp));
+      if (!in_place) {
+        Xfer cp;
+        for (size_t r = 0; r < P; ++r) cp.add(rows[r].R->tmp, LV[r], (int64_t)n * k);
+        CHK(xfer_run(s, F64, F64, cp));
+      }
     }
     // UU = Uh U (the projector's factor), and Z = N^T U for the residuals
     CHK(napply(x, n, k, rows, Ub, Z, UU, true, want_resid ? 4 : 2));

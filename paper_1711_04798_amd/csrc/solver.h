@@ -49,7 +49,8 @@ constexpr int CHOL_WAVE_MAX = 64;
 hipError_t gram_small(hipStream_t s, int64_t n, int k, const CPtrSet& Y, const PtrSet& G, int nprob, double* part,
                       int64_t part_elems);
 // C = A B for row-major float64 A (n x K), B (K x N), C (n x N) per problem,
-// K, N <= 64, on the float64 MFMA with fragments loaded straight from memory.
+// K, N <= 64, on the float64 MFMA with fragments loaded straight from memory;
+// C may be A (in place, N == K).
 hipError_t rmul_small(hipStream_t s, int64_t n, int K, int N, const CPtrSet& A, const CPtrSet& B, const PtrSet& C,
                       int nprob);
 // G = X^T Y for two n x k row-major float64 blocks, k <= 48, the same way.

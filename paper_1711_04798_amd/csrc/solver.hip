@@ -439,7 +439,9 @@ gram_partial_kernel(int64_t n, int k, int rpw, CPtrSet X, CPtrSet Y, double* __r
 // C = A B for row-major float64 A (n x K), B (K x N), C (n x N), K and N up to
 // 64: one wave per 16 rows of C, every fragment loaded straight from memory
 // (lane l: A[r + l % 16][4 s + l / 16] for K step s, B[4 s + l / 16][16 j +
-// l % 16] for column block j), all loads issued before the products.
+// l % 16] for column block j), all loads issued before the products.  A wave
+// reads its rows of A whole before it writes the same rows of C, so C may be
+// A (no restrict on either).
 // ---------------------------------------------------------------------------
 template <int KS, int NB>
 __global__ void __launch_bounds__(256)
@@ -447,9 +449,9 @@ rmul_small_kernel(int64_t n, int K, int N, CPtrSet A, CPtrSet B, PtrSet C) {
   const int pb = blockIdx.y, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
   if (r0 >= n) return;  // whole wave
-  const double* __restrict__ a = A.p[pb];
+  const double* a = A.p[pb];
   const double* __restrict__ b = B.p[pb];
-  double* __restrict__ c = C.p[pb];
+  double* c = C.p[pb];
   const int64_t ra = r0 + lr;
   double fa[KS], fb[KS][NB];
 #pragma unroll

@@ -115,7 +115,8 @@ def test_gram_small(gpu, n, k, part):
                                    (16, 3, 64)])
 def test_rmul_small(gpu, n, K, N):
     """The solver's right-multiplication by a small matrix against numpy:
-    ragged row, K and column blocks."""
+    ragged row, K and column blocks; in place (C = A) bit for bit equal to
+    the out-of-place result."""
     import torch
     lib = _lib()
     rng = np.random.default_rng(n + 5 * K + 11 * N)
@@ -129,6 +130,12 @@ def test_rmul_small(gpu, n, K, N):
                             torch.cuda.current_stream().cuda_stream)
     assert st == 0
     assert np.abs(Ct.cpu().numpy() - A @ B).max() <= 4 * K * 2.0 ** -53 * np.abs(A).max() * np.abs(B).max()
+    if K == N:
+        # in place: C = A
+        st = lib.ctm_debug_rmul(n, K, N, At.data_ptr(), Bt.data_ptr(), At.data_ptr(),
+                                torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        assert np.array_equal(At.cpu().numpy(), Ct.cpu().numpy())
 
 
 def _chol(lib, G, coef):
