@@ -1060,18 +1060,29 @@ ctm_status napply(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
 // (Cholesky-QR with shifts; Fukaya et al., SIAM J. Sci. Comput. 2020); up to
 // 64 columns by substitution with R, otherwise through R^{-1} and a product.
 // With to_qin (k <= 64 only), the last pass also writes Y rounded to float32
-// into each row's N-apply input (what napply's cast would write).
+// into each row's N-apply input (what napply's cast would write).  With Yin
+// (k <= 64 only), the first pass starts from Yin instead of Y's contents
+// (Yin is read, Y written).
 ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow>& rows,
-                          const std::vector<double*>& Y, int passes = 3, bool to_qin = false) {
+                          const std::vector<double*>& Y, int passes = 3, bool to_qin = false,
+                          const std::vector<double*>* Yin = nullptr) {
   hipStream_t s = x.stream;
   const size_t P = rows.size();
   const double u = 1.1102230246251565e-16;
+  if (Yin && k > CHOL_WAVE_MAX) {  // the product form works in place: copy first
+    Xfer cp;
+    for (size_t r = 0; r < P; ++r) cp.add((*Yin)[r], Y[r], (int64_t)n * k);
+    CHK(xfer_run(s, F64, F64, cp));
+    Yin = nullptr;
+  }
   for (int pass = 0; pass < passes; ++pass) {
     double coef = pass == 0 ? 11.0 * ((double)n * k + (double)k * (k + 1)) * u : 4.0 * u;
     G gg;
     CPtrSet Gs{};
     PtrSet Ri{};
     StatSet st{};
+    // the first pass reads Yin when given
+    const bool from_in = Yin && pass == 0;
     for (size_t r = 0; r < P; ++r) {
       gg.add(Y[r], Y[r], rows[r].R->G);
       Gs.p[r] = rows[r].R->G;
@@ -1081,7 +1092,7 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
     if (k <= 64) {
       CPtrSet Ys{};
       PtrSet Gp{};
-      for (size_t r = 0; r < P; ++r) { Ys.p[r] = Y[r]; Gp.p[r] = rows[r].R->G; }
+      for (size_t r = 0; r < P; ++r) { Ys.p[r] = from_in ? (*Yin)[r] : Y[r]; Gp.p[r] = rows[r].R->G; }
       HIPCHK(gram_small(s, n, k, Ys, Gp, (int)P, x.splitk, x.splitk_elems));
     } else {
       CHK(gemm_sk(x, k, k, n, transposed(rowmajor(k)), rowmajor(k), rowmajor(k), gg));
@@ -1093,8 +1104,13 @@ ctm_status orthonormalize(ctm_ctx_s& x, int n, int k, const std::vector<SolveRow
       CPtrSet Rs{};
       for (size_t r = 0; r < P; ++r) { Ys.p[r] = Y[r]; Rs.p[r] = rows[r].R->Rinv; }
       PtrSet q32{};
-      for (size_t r = 0; r < P; ++r) q32.p[r] = (double*)rows[r].R->qin;
-      HIPCHK(trsm_rows(s, n, k, Ys, Rs, (int)P, (to_qin && pass + 1 == passes) ? &q32 : nullptr));
+      CPtrSet yin{};
+      for (size_t r = 0; r < P; ++r) {
+        q32.p[r] = (double*)rows[r].R->qin;
+        yin.p[r] = from_in ? (*Yin)[r] : nullptr;
+      }
+      HIPCHK(trsm_rows(s, n, k, Ys, Rs, (int)P, (to_qin && pass + 1 == passes) ? &q32 : nullptr,
+                       from_in ? &yin : nullptr));
       continue;
     }
     HIPCHK(chol_shift_inv(s, k, coef, Gs, Ri, st, (int)P));
@@ -1165,8 +1181,7 @@ ctm_status solve_projectors(ctm_ctx_s& x, Inst& I, std::vector<SolveRow>& rows, 
   // residuals |Z_i - S_i V'_i|.
   auto rr_iteration = [&](bool want_resid) -> ctm_status {
     CHK(napply(x, n, k, rows, V, Yb, LV, false, 4, !q32));  // Y = N V, LV = Lh^T V
-    CHK(copy_blocks(Qb, Yb));
-    CHK(orthonormalize(x, n, k, rows, Qb, ortho_passes));  // Q = orth(Y)
+    CHK(orthonormalize(x, n, k, rows, Qb, ortho_passes, false, &Yb));  // Q = orth(Y), Y kept
     if (k <= 48) {
       CPtrSet Qs{}, Ys{};
       PtrSet Rs{};

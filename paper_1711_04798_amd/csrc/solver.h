@@ -59,9 +59,10 @@ hipError_t gram_cross_small(hipStream_t s, int64_t n, int k, const CPtrSet& X, c
 
 // Y <- Y R^{-1} in place, Y n x k row-major, R k x k upper triangular
 // row-major (k <= 64), for each problem; with Y32, the result rounded to
-// float32 is also written there (n x k row-major).
+// float32 is also written there (n x k row-major); with Yin, Y <- Yin R^{-1}
+// (Yin read, Y written).
 hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob,
-                     const PtrSet* Y32 = nullptr);
+                     const PtrSet* Y32 = nullptr, const CPtrSet* Yin = nullptr);
 
 // One-sided Jacobi SVD of the k x k row-major matrix M (k <= 192): M W = U S with singular
 // values in descending order.  U, W row-major k x k; S length k.  Columns of U

@@ -263,7 +263,7 @@ __device__ __forceinline__ double dpp_f64(double v) {
 
 template <int KP>
 __global__ void __launch_bounds__(256)
-trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R, PtrSet Y32, int w32) {
+trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R, PtrSet Y32, int w32, CPtrSet Yin, int r_in) {
   constexpr int NT4 = KP / 4;
   // Rq[(4 j + s) NT4 + t] = R[j][4 t + s] for j < 4 t + s < k, else 0
   __shared__ __attribute__((aligned(16))) double Rq[KP * KP];
@@ -274,10 +274,11 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R, PtrSet Y32, int w32) {
   // two loads' latencies overlap
   const int lane = tid & 63, s = lane & 3;
   const int64_t row = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + (lane >> 2);
-  double* __restrict__ yr = Y.p[pb] + min<int64_t>(row, n - 1) * k;
+  double* yr = Y.p[pb] + min<int64_t>(row, n - 1) * k;
+  const double* yi = (r_in ? Yin.p[pb] : Y.p[pb]) + min<int64_t>(row, n - 1) * k;
   double tv[NT4];
 #pragma unroll
-  for (int t = 0; t < NT4; ++t) tv[t] = yr[min(4 * t + s, k - 1)];
+  for (int t = 0; t < NT4; ++t) tv[t] = yi[min(4 * t + s, k - 1)];
   {
     constexpr int PER = (KP * KP + 255) / 256;
     double rv[PER];
@@ -334,21 +335,23 @@ trsm_quad_kernel(int64_t n, int k, PtrSet Y, CPtrSet R, PtrSet Y32, int w32) {
 }
 
 hipError_t trsm_rows(hipStream_t s, int64_t n, int k, const PtrSet& Y, const CPtrSet& R, int nprob,
-                     const PtrSet* Y32) {
+                     const PtrSet* Y32, const CPtrSet* Yin) {
   if (nprob < 0 || nprob > MAXP || k < 1 || k > CHOL_WAVE_MAX || n < 1) return hipErrorInvalidValue;
   if (nprob == 0) return hipSuccess;
   for (int i = 0; i < nprob; ++i)
     if (!span_ok(Y.p[i], (size_t)n * k * 8, "trsm Y") || !span_ok(R.p[i], (size_t)k * k * 8, "trsm R") ||
-        (Y32 && (!Y32->p[i] || !span_ok(Y32->p[i], (size_t)n * k * 4, "trsm Y32"))))
+        (Y32 && (!Y32->p[i] || !span_ok(Y32->p[i], (size_t)n * k * 4, "trsm Y32"))) ||
+        (Yin && (!Yin->p[i] || !span_ok(Yin->p[i], (size_t)n * k * 8, "trsm Yin"))))
       return hipErrorInvalidValue;
   if (dry_run()) return hipSuccess;
   const PtrSet y32 = Y32 ? *Y32 : PtrSet{};
-  const int w32 = Y32 ? 1 : 0;
+  const CPtrSet yin = Yin ? *Yin : CPtrSet{};
+  const int w32 = Y32 ? 1 : 0, r_in = Yin ? 1 : 0;
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)nprob);
-  if (k <= 16) hipLaunchKernelGGL(trsm_quad_kernel<16>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
-  else if (k <= 32) hipLaunchKernelGGL(trsm_quad_kernel<32>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
-  else if (k <= 48) hipLaunchKernelGGL(trsm_quad_kernel<48>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
-  else hipLaunchKernelGGL(trsm_quad_kernel<64>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32);
+  if (k <= 16) hipLaunchKernelGGL(trsm_quad_kernel<16>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32, yin, r_in);
+  else if (k <= 32) hipLaunchKernelGGL(trsm_quad_kernel<32>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32, yin, r_in);
+  else if (k <= 48) hipLaunchKernelGGL(trsm_quad_kernel<48>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32, yin, r_in);
+  else hipLaunchKernelGGL(trsm_quad_kernel<64>, grid, dim3(256), 0, s, n, k, Y, R, y32, w32, yin, r_in);
   return hipGetLastError();
 }
 
